@@ -1,0 +1,207 @@
+"""Benchmark: frames/s of the MI355X Gaussian-splatting rasterizer.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2]
+
+A step is one forward render (preprocess, scan, duplicate, sort, ranges,
+blend) of the configuration's synthetic scene, inputs resident in HBM.  The
+same run also times forward+backward steps (forward, L1 loss gradient,
+backward) and reports per-stage times from HIP events recorded on the render
+stream, the roofline position of the dominant kernel, and the CPU oracle timed
+on the host cores.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, GB/s
+FP32_VALU_PEAK_TFLOPS = 157.3  # MI355X FP32 vector (packed), TFLOP/s
+SORT_BYTES_PER_KEY_PASS = 24  # read key+value (12 B) and write key+value (12 B)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "room"])
+    ap.add_argument("--blend-variant", type=int, default=0)
+    ap.add_argument("--no-backward", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--cpu-budget-s", type=float, default=40.0)
+    return ap.parse_args()
+
+
+def cpu_baseline(scene, cam, budget_s):
+    """The FP64 oracle, as it is, on the host cores: one full forward frame of
+    the same scene and camera (the oracle's projection, keys, sort, ranges and
+    blend).  Falls back to a 1/8 Gaussian subsample when a full frame would
+    exceed the budget; the sample is stated in the output."""
+    from oracle import oracle as O
+    import multiprocessing
+    cores = int(os.environ.get("OMP_NUM_THREADS", multiprocessing.cpu_count()))
+    n = scene["n"]
+    # estimate from a 1/64 subsample first
+    def sub(frac):
+        m = max(1, int(n * frac))
+        idx = np.random.default_rng(0).choice(n, m, replace=False)
+        idx.sort()
+        s = {k: (np.ascontiguousarray(v[..., idx]) if isinstance(v, np.ndarray) else v)
+             for k, v in scene.items()}
+        s["n"] = m
+        return s
+    t0 = time.perf_counter()
+    O.render(sub(1 / 64), cam)
+    t_small = time.perf_counter() - t0
+    frac, label = 1.0, "one full frame"
+    if t_small * 64 > budget_s:
+        frac, label = 1 / 8, "one frame of a 1/8 random subsample of the Gaussians"
+    s = scene if frac == 1.0 else sub(frac)
+    t0 = time.perf_counter()
+    O.render(s, cam)
+    dt = time.perf_counter() - t0
+    return {"value": round(1.0 / dt, 5), "unit": "frames/s", "cores": cores, "kind": "oracle",
+            "sample": f"{label} ({s['n']} Gaussians, {cam.width}x{cam.height}), FP64 C oracle, "
+                      f"OpenMP over Gaussians and pixels, single-threaded stable sort; {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for {args.gpus}).",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2509_25626_amd import scenes as S
+    from paper_2509_25626_amd.render import GaussianScene, Renderer
+
+    scene_np, cam = S.config_scene(args.config)
+    dev = torch.device("cuda", 0)
+    scene = GaussianScene.from_numpy(scene_np, device=dev)
+    R = Renderer(0)
+    frame = R.acquire_frame()
+    H, W = cam.height, cam.width
+    out = (torch.empty((3, H, W), device=dev), torch.empty((H, W), device=dev),
+           torch.empty((H, W), dtype=torch.int32, device=dev))
+
+    def fwd(timing=False):
+        return R.forward(scene, cam, frame=frame, blend_variant=args.blend_variant, out=out, timing=timing)
+
+    for _ in range(args.warmup):
+        fwd()
+    torch.cuda.synchronize()
+    stage_acc = {}
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        fwd(timing=True)
+        for k, v in frame.stage_times().items():
+            stage_acc[k] = stage_acc.get(k, 0.0) + v
+    torch.cuda.synchronize()
+    t_fwd = (time.perf_counter() - t0) / args.steps
+    stages = {k: v / args.steps for k, v in stage_acc.items() if not k.endswith("backward_ms")}
+    info = frame.info()
+    K, passes = int(info.num_keys), int(info.sort_passes)
+
+    result_extra = {}
+    if not args.no_backward:
+        target = torch.from_numpy(S.target_image(40, W, H)).to(dev)
+        grads = {k: torch.empty_like(getattr(scene, k)) for k in
+                 ("means", "log_scales", "quats", "opacity_logits", "sh")}
+        dl = torch.empty((3, H, W), device=dev)
+        loss = torch.empty(1, device=dev)
+
+        def fwdbwd(timing=False):
+            rgb, T, nc, _ = fwd(timing)
+            R.l1_loss_grad(rgb, target, dl, loss)
+            R.backward(frame, scene, cam, T, nc, dl, grads)
+
+        for _ in range(max(1, args.warmup // 2)):
+            fwdbwd()
+        torch.cuda.synchronize()
+        bw_acc = {}
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fwdbwd(timing=True)
+            for k, v in frame.stage_times().items():
+                bw_acc[k] = bw_acc.get(k, 0.0) + v
+        torch.cuda.synchronize()
+        t_fb = (time.perf_counter() - t0) / args.steps
+        result_extra["fwd_bwd_fps"] = round(1.0 / t_fb, 3)
+        result_extra["fwd_bwd_ms"] = round(t_fb * 1e3, 4)
+        result_extra["backward_stage_ms"] = {k: round(v / args.steps, 4) for k, v in bw_acc.items()
+                                             if k.endswith("backward_ms")}
+
+    # roofline of the dominant forward kernel (largest stage)
+    dom = max(stages, key=stages.get)
+    if dom == "sort_ms":
+        per_launch_ms = stages["sort_ms"] / max(passes, 1)
+        traffic_bytes = SORT_BYTES_PER_KEY_PASS * K
+        achieved = traffic_bytes / (per_launch_ms * 1e-3) / 1e9
+        roof = {"kernel": "k_onesweep (one 8-bit radix pass)", "bound": "hbm", "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None, "algorithmic_bytes_per_launch": traffic_bytes,
+                "avg_launch_ms": round(per_launch_ms, 4)}
+    elif dom == "preprocess_ms":
+        bpg = 4 * (3 + 3 + 4 + 1 + 3 * (scene.sh_degree + 1) ** 2) + 61
+        traffic_bytes = bpg * scene.n
+        achieved = traffic_bytes / (stages[dom] * 1e-3) / 1e9
+        roof = {"kernel": "k_preprocess", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "algorithmic_bytes_per_launch": traffic_bytes, "avg_launch_ms": round(stages[dom], 4)}
+    else:
+        roof = {"kernel": dom.replace("_ms", ""), "bound": "alu", "achieved": None,
+                "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": None, "traffic": None,
+                "avg_launch_ms": round(stages[dom], 4)}
+
+    serving = None
+    if not args.no_serving:
+        try:
+            from paper_2509_25626_amd import serve
+            serving = serve.bench_serving(quick=True)
+        except Exception as e:  # serving is reported when available
+            serving = {"error": str(e)[:200]}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(scene_np, cam, args.cpu_budget_s)
+
+    fps = 1.0 / t_fwd
+    line = {
+        "metric": "frames/s at 3M Gaussians 1.3MP (fwd, fwd+bwd); p50/p99 batched-serve ms",
+        "value": round(fps, 3),
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_fwd * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: {scene.n} Gaussians SH{scene.sh_degree}, {W}x{H}, 16x16 tiles, "
+                               "forward render", "gaussians": scene.n, "width": W, "height": H,
+                   "keys": K, "sort_passes": passes, "parallelism": "single GPU"},
+        "stage_ms": {k: round(v, 4) for k, v in stages.items()},
+        **result_extra,
+        "serving": serving,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    R.release_frame(frame)
+    R.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,292 @@
+/*
+ * cdnasplat.h -- C ABI of the MI355X (gfx950) 3D Gaussian-splatting rasterizer.
+ *
+ * The library renders a set of 3D Gaussians for a pinhole camera with the
+ * pipeline the paper describes in Section II-B ("Structure of Gaussian
+ * Splatting Rendering Pipeline") and Algorithm 1:
+ *
+ *   preprocess  per Gaussian: visibility, projection to a 2D splat (mean,
+ *               conic, screen radius), colour from spherical harmonics, depth
+ *   duplicate   one (tile | depth) key per covered 16x16 tile
+ *   sort        stable radix sort of the 64-bit keys (ties by Gaussian index)
+ *   ranges      [start, end) of every tile in the sorted list
+ *   blend       per pixel, front to back alpha blending with early stop when
+ *               the transmittance falls below 1e-4 (Eq. (1), Algorithm 1)
+ *
+ * plus the exact backward pass of all of it (gradients for every raw
+ * parameter) and a continuous-batching server for many resident scenes.
+ *
+ * Conventions shared by every call:
+ *  - Device pointers are plain HIP device addresses on the context's device;
+ *    host pointers are ordinary process memory.  Every pointer argument says
+ *    which it is.
+ *  - Work is enqueued on the caller's HIP stream (`stream`, a hipStream_t
+ *    passed as void*; NULL is the legacy default stream).  Calls return once
+ *    the work is enqueued unless stated otherwise.
+ *  - No call throws or aborts.  Every fallible call returns a cds_status;
+ *    cds_last_error() gives a human-readable message for the calling thread.
+ *  - Arguments are validated before any device work is enqueued; an invalid
+ *    argument returns CDS_ERR_INVALID_ARG and changes nothing.
+ *  - A context (and every frame or server made from it) may be used by one
+ *    host thread at a time.
+ */
+#ifndef CDNASPLAT_H
+#define CDNASPLAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CDS_TILE 16          /* tile edge in pixels (Section II-B: 16 x 16 tiles) */
+#define CDS_MAX_SH_DEGREE 3  /* spherical-harmonics degree 0..3 (16 coefficients) */
+
+typedef enum cds_status {
+    CDS_OK = 0,
+    CDS_ERR_INVALID_ARG = 1, /* bad pointer, size or option; nothing was enqueued */
+    CDS_ERR_OOM = 2,         /* the allocator returned NULL; outputs unspecified, no leak */
+    CDS_ERR_CAPACITY = 3,    /* a size limit of the library was exceeded (e.g. > 2^32-1 keys) */
+    CDS_ERR_DEVICE = 4,      /* a HIP call or a device-side check failed (message has details) */
+    CDS_ERR_BUSY = 5         /* the server has no free slot / budget for the request right now */
+} cds_status;
+
+/* Device-memory allocator.  alloc returns a device pointer aligned to at least
+ * 256 bytes, or NULL on failure; free releases it.  Memory may be reused by
+ * the library for later stream-ordered work only through these calls.  Pass
+ * NULL to cds_create to use hipMalloc / hipFree. */
+typedef struct cds_allocator {
+    void* (*alloc)(size_t bytes, void* user);
+    void (*free)(void* ptr, void* user);
+    void* user;
+} cds_allocator;
+
+/* A scene: n Gaussians as structure-of-arrays float32 planes in DEVICE memory,
+ * owned by the caller and only read by the library.
+ *   means          [3][n]              world-space centres
+ *   log_scales     [3][n]              log of the per-axis standard deviation
+ *   quats          [4][n]              rotation (w, x, y, z); need not be normalised
+ *   opacity_logits [n]                 opacity = 1 / (1 + exp(-logit))
+ *   sh             [(deg+1)^2][3][n]   spherical-harmonics coefficients,
+ *                                      coefficient-major, then colour channel */
+typedef struct cds_scene {
+    int64_t n;
+    int32_t sh_degree;
+    int32_t reserved;
+    const float* means;
+    const float* log_scales;
+    const float* quats;
+    const float* opacity_logits;
+    const float* sh;
+} cds_scene;
+
+/* Gradients with the same layouts as cds_scene, DEVICE memory, caller-owned.
+ * Every element is overwritten by cds_render_backward. */
+typedef struct cds_scene_grad {
+    float* means;
+    float* log_scales;
+    float* quats;
+    float* opacity_logits;
+    float* sh;
+} cds_scene_grad;
+
+/* Pinhole camera (HOST struct, copied by value).  `view` is the world->camera
+ * transform [R | t], row-major 3 x 4; the camera looks down +z, image x to
+ * the right and y down; pixel (x, y) is sampled at integer coordinates.
+ * Gaussians with camera-space z <= near_plane are culled.  bg is the
+ * background colour composited behind the splats. */
+typedef struct cds_camera {
+    int32_t width, height;
+    float fx, fy, cx, cy;
+    float view[12];
+    float near_plane;
+    float bg[3];
+} cds_camera;
+
+/* Render options (HOST struct; NULL means all defaults). */
+#define CDS_OPT_DEFAULT 0u
+#define CDS_OPT_STAGE_TIMING 1u  /* record HIP events around every stage (forward and backward) */
+typedef struct cds_render_opts {
+    uint32_t flags;         /* CDS_OPT_* bits */
+    int32_t blend_variant;  /* 0 = default; 1, 2, 4 = pixels per thread of the blend kernel */
+    int32_t sort_variant;   /* 0 = default: depth digits sorted per Gaussian, tile digits per key;
+                               1 = every digit of the 64-bit keys sorted per key.  Same result. */
+    int32_t reserved;
+} cds_render_opts;
+
+typedef struct cds_ctx cds_ctx;
+typedef struct cds_frame cds_frame;
+typedef struct cds_server cds_server;
+
+/* Library version string (static storage). */
+const char* cds_version(void);
+
+/* Message describing the last non-OK status returned to this thread. */
+const char* cds_last_error(void);
+
+/* Create a context on HIP device `device`.  `alloc` (HOST struct, copied) may
+ * be NULL for hipMalloc/hipFree.  *out receives the context. */
+cds_status cds_create(cds_ctx** out, int device, const cds_allocator* alloc);
+
+/* Destroy a context; frames and servers made from it must be released first.
+ * Waits for the context's outstanding work.  NULL is ignored. */
+void cds_destroy(cds_ctx* ctx);
+
+/* Per-render state: the per-Gaussian projected splats, the keys and tile
+ * lists of the last forward render, kept for the backward pass and for
+ * inspection.  A frame grows its buffers as needed and reuses them; it must
+ * not be used by two renders in flight at once. */
+cds_status cds_frame_create(cds_ctx* ctx, cds_frame** out);
+void cds_frame_release(cds_frame* frame);
+
+/*
+ * Forward render (Section II-B, Algorithm 1).
+ *   out_rgb      DEVICE float [3][H][W]  colour, planar, C + T * bg
+ *   out_T        DEVICE float [H][W]     final transmittance T
+ *   out_ncontrib DEVICE u32   [H][W]     1-based position, in the pixel's tile
+ *                                        list, of the last Gaussian blended
+ *                                        (0 if none); skipped entries count
+ * All three outputs are caller-owned and fully overwritten.  The call
+ * synchronises the stream once to learn the number of keys (the only host
+ * wait of a render).  Returns CDS_ERR_CAPACITY when the number of keys
+ * exceeds 2^30 - 1.
+ */
+cds_status cds_render_forward(cds_ctx* ctx, cds_frame* frame, const cds_scene* scene,
+                              const cds_camera* cam, const cds_render_opts* opts,
+                              float* out_rgb, float* out_T, uint32_t* out_ncontrib,
+                              void* stream);
+
+/*
+ * Backward pass of the last forward render of `frame`: the exact derivative
+ * of the forward with every discrete decision (culls, tile lists, skipped and
+ * terminated blending steps, colour and alpha clamps, Jacobian guard band)
+ * held fixed.  The transmittance of each step is recomputed by division from
+ * the final T, walking each pixel's list backwards.
+ *   out_T, out_ncontrib  DEVICE, the forward's outputs (unchanged since)
+ *   dL_drgb              DEVICE float [3][H][W]  gradient of the loss w.r.t. out_rgb
+ *   grads                DEVICE, caller-owned, cds_scene layouts, overwritten
+ * `scene` and `cam` must be those of the forward.
+ */
+cds_status cds_render_backward(cds_ctx* ctx, cds_frame* frame, const cds_scene* scene,
+                               const cds_camera* cam, const float* out_T,
+                               const uint32_t* out_ncontrib, const float* dL_drgb,
+                               const cds_scene_grad* grads, void* stream);
+
+/* L1 image loss helper: dL_drgb[i] = sign(rgb[i] - target[i]) / count and,
+ * if loss_out is not NULL, loss_out[0] = mean |rgb - target| (DEVICE float,
+ * overwritten).  All pointers DEVICE, count elements. */
+cds_status cds_l1_loss_grad(cds_ctx* ctx, const float* rgb, const float* target, int64_t count,
+                            float* dL_drgb, float* loss_out, void* stream);
+
+/* Device pointers into a frame's state after cds_render_forward (read-only,
+ * owned by the frame, valid until the frame's next render or release).  The
+ * caller must have synchronised with the render; building the 64-bit sorted
+ * keys on first request synchronises the device. */
+typedef struct cds_frame_info {
+    int64_t n;                     /* Gaussians of the last render */
+    int64_t num_keys;              /* K: duplicated (tile | depth) keys */
+    int32_t width, height, tiles_x, tiles_y;
+    int32_t sort_passes;           /* 8-bit radix passes over the 64-bit key (depth + tile digits) */
+    int32_t reserved;
+    const float* mean2d;           /* [n] float2 (x, y), pixels */
+    const float* conic_opacity;    /* [n] float4 (A, B, C, opacity): power = -A dx^2/2 - B dx dy - C dy^2/2 */
+    const float* rgb;              /* [n] float4 (r, g, b, 0) after the clamp at 0 */
+    const uint32_t* depth_bits;    /* [n] IEEE bits of the float32 view depth (0 if culled) */
+    const int32_t* radius;         /* [n] screen radius in pixels, 0 if culled */
+    const uint32_t* tile_rect;     /* [n] uint2: (tx0 | ty0 << 16, tx1 | ty1 << 16), inclusive */
+    const uint32_t* tiles_touched; /* [n] number of covered tiles */
+    const uint32_t* offsets;       /* [n] exclusive prefix sum of tiles_touched */
+    const uint64_t* keys;          /* [K] sorted (tile << 32 | depth bits) */
+    const uint32_t* values;        /* [K] Gaussian index of each sorted key */
+    const uint32_t* ranges;        /* [tiles_x * tiles_y] uint2 [start, end), (0, 0) if empty */
+    const uint8_t* clamp_flags;    /* [n] bit 0..2 colour channel clamped, 3/4 Jacobian x/y clamped */
+} cds_frame_info;
+
+cds_status cds_frame_get_info(cds_frame* frame, cds_frame_info* out);
+
+/* Per-stage device time of the frame's last forward (and backward) render,
+ * in milliseconds, from HIP events recorded on the render's stream when the
+ * forward ran with CDS_OPT_STAGE_TIMING.  Waits for those events.  `scan_ms`
+ * includes the host read-back of the key count; backward fields are 0 until a
+ * backward pass has run. */
+typedef struct cds_stage_times {
+    float preprocess_ms, scan_ms, duplicate_ms, sort_ms, ranges_ms, blend_ms;
+    float blend_backward_ms, preprocess_backward_ms;
+} cds_stage_times;
+
+cds_status cds_frame_stage_times(cds_frame* frame, cds_stage_times* out);
+
+/*
+ * Stand-alone stable LSD radix sort of (key, value) pairs on key bits
+ * [0, end_bit), the sort the forward render uses.  All arrays DEVICE,
+ * `count` elements; the inputs are not modified; outputs may not alias
+ * inputs.  Equal keys keep their input order.
+ */
+cds_status cds_sort_pairs(cds_ctx* ctx, const uint64_t* keys_in, const uint32_t* values_in,
+                          int64_t count, int32_t end_bit, uint64_t* keys_out,
+                          uint32_t* values_out, void* stream);
+
+/*
+ * Stand-alone exclusive prefix sum of `count` uint32 (DEVICE in/out, may not
+ * alias); the total is written to DEVICE *total (uint64).  Used by the
+ * forward render for key offsets.
+ */
+cds_status cds_exclusive_scan_u32(cds_ctx* ctx, const uint32_t* in, int64_t count, uint32_t* out,
+                                  uint64_t* total, void* stream);
+
+/* Synchronise `stream` and report device-side errors raised since the last
+ * check (a bounded wait that gave up, a capacity overrun): CDS_OK or
+ * CDS_ERR_DEVICE with a message. */
+cds_status cds_check_device(cds_ctx* ctx, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Serving: continuous batching of render requests over resident scenes.    */
+/* ------------------------------------------------------------------------ */
+
+typedef struct cds_server_opts {
+    int32_t max_slots;          /* requests in flight at once (1..64) */
+    int32_t max_batch;          /* requests fused into one batched launch (1..max_slots) */
+    int64_t hbm_budget_bytes;   /* workspace budget for admitted requests; 0 = free HBM at create */
+} cds_server_opts;
+
+typedef struct cds_server_stats {
+    int64_t submitted, completed, rejected;
+    int64_t batches;            /* batched launches issued */
+    int64_t workspace_bytes;    /* workspace currently reserved by admitted requests */
+    int64_t peak_workspace_bytes;
+} cds_server_stats;
+
+/* Create a server on a context.  The server owns one HIP stream pair and a
+ * host scheduler thread. */
+cds_status cds_server_create(cds_ctx* ctx, const cds_server_opts* opts, cds_server** out);
+
+/* Register a resident scene (DEVICE arrays, caller-owned; they must stay
+ * valid and unchanged until the server is destroyed).  *scene_id (HOST)
+ * receives its id. */
+cds_status cds_server_add_scene(cds_server* srv, const cds_scene* scene, int32_t* scene_id);
+
+/* Queue a render of `scene_id` for `cam`.  out_rgb (DEVICE, caller-owned,
+ * [3][H][W]) becomes valid when cds_server_poll reports the ticket done.
+ * Returns CDS_ERR_BUSY if the request could never fit the budget. */
+cds_status cds_server_submit(cds_server* srv, int32_t scene_id, const cds_camera* cam,
+                             float* out_rgb, uint64_t* ticket);
+
+/* *done (HOST) = 1 when the ticket's image is complete on the device, else 0.
+ * If latency_ms is not NULL it receives submit-to-completion time in ms
+ * (valid when done). */
+cds_status cds_server_poll(cds_server* srv, uint64_t ticket, int32_t* done, double* latency_ms);
+
+/* Block until every queued request is complete. */
+cds_status cds_server_drain(cds_server* srv);
+
+cds_status cds_server_get_stats(cds_server* srv, cds_server_stats* out);
+
+/* Drain and destroy the server.  NULL is ignored. */
+void cds_server_destroy(cds_server* srv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CDNASPLAT_H */

@@ -1,0 +1,348 @@
+// Per-pixel front-to-back alpha blending (paper Section II-B(2), Eq. (1) with
+// the splat alpha, Algorithm 1) and its backward pass.
+//
+// One workgroup per 16x16 tile.  The tile's sorted splats are staged through
+// LDS in batches of 256 (the shared-memory staging the paper measures at
+// +11.3%), the colour included (the coalesced-RGB point).  Each lane blends
+// PPT vertically adjacent pixels (PPT = 1, 2, 4), so every LDS read of a splat
+// serves PPT pixel evaluations and the column-dependent terms of the
+// quadratic form are computed once per lane.  The conic is pre-scaled by
+// -log2(e)/2, -log2(e), -log2(e)/2 when staged so the hot loop needs one
+// hardware exp2 (v_exp_f32, the gfx950 counterpart of the paper's __expf).
+// The loop has no data-dependent trip count (per-pixel "done" masks only),
+// an early exit is voted block-wide once per batch, and a wave whose pixels
+// are all done leaves the batch early.
+//
+// Tiles are assigned in XCD-contiguous bands so neighbouring tiles, which
+// share most of their splats, hit the same L2.
+#include "device_utils.h"
+#include "internal.h"
+
+namespace cds {
+namespace {
+
+constexpr int kBatch = 256;
+constexpr float kLn2 = 0.69314718055994531f;
+constexpr float kAlphaMax = 0.99f;
+constexpr float kAlphaMin = 1.0f / 255.0f;
+constexpr float kTMin = 0.0001f;
+
+// Staged splat, one LDS slot per splat:
+//   s_q  double4 (mean x, mean y, A', B')   s_c double C'   s_f float4 (opacity, r, g, b)
+// with A' = -log2(e)/2 A, B' = -log2(e) B, C' = -log2(e)/2 C, so that
+// A' dx^2 + B' dx dy + C' dy^2 = log2(e) * power.
+__device__ __forceinline__ void stage_splat(const float2* __restrict__ mean2d,
+                                            const float4* __restrict__ conic_opacity,
+                                            const float4* __restrict__ rgb, uint32_t id, double4* s_q,
+                                            double* s_c, float4* s_f, int k) {
+    const double L = 1.4426950408889634;  // log2(e)
+    const float2 m = mean2d[id];
+    const float4 co = conic_opacity[id];
+    const float4 c = rgb[id];
+    s_q[k] = make_double4((double)m.x, (double)m.y, -0.5 * L * (double)co.x, -L * (double)co.y);
+    s_c[k] = -0.5 * L * (double)co.z;
+    s_f[k] = make_float4(co.w, c.x, c.y, c.z);
+}
+
+// The blending decision of one (pixel, splat) pair, shared by the forward
+// and the backward pass so both take bit-identical decisions.
+//   adx2 = A' dx^2, bdx = B' dx (column terms), dy = mean_y - pixel_y.
+// The quadratic form is evaluated in float64: for thin splats its terms
+// cancel and float32 would lose the digits that decide alpha.  Float64 FMA
+// runs at the float32 (non-packed) rate on CDNA4, so this costs one
+// conversion per pair.  Returns false when the splat is skipped
+// (power > 0 or alpha < 1/255).
+__device__ __forceinline__ bool splat_alpha(double adx2, double bdx, double c2, double dy, float opacity,
+                                            float& alpha, float& G) {
+    const double power = fma(dy, fma(c2, dy, bdx), adx2);  // log2(e) * power
+    if (power > 0.0) return false;
+    G = __builtin_amdgcn_exp2f((float)power);
+    alpha = fminf(kAlphaMax, opacity * G);
+    return !(alpha < kAlphaMin);
+}
+
+template <int PPT>
+__global__ __launch_bounds__(256 / PPT) void k_blend(BlendArgs a, uint32_t per_xcd) {
+    constexpr int NT = 256 / PPT;
+    __shared__ double4 s_q[kBatch];
+    __shared__ double s_c[kBatch];
+    __shared__ float4 s_f[kBatch];
+
+    const uint32_t tile = xcd_band(blockIdx.x, per_xcd);
+    if (tile >= (uint32_t)(a.tiles_x * a.tiles_y)) return;  // whole block: padding
+    const int t = threadIdx.x;
+    const int tx = (int)(tile % (uint32_t)a.tiles_x), ty = (int)(tile / (uint32_t)a.tiles_x);
+    const int px = tx * kTile + (t & 15);
+    const int py0 = ty * kTile + (t >> 4) * PPT;
+    const double fpx = (double)px;
+
+    float T[PPT], C0[PPT], C1[PPT], C2[PPT];
+    double fpy[PPT];
+    uint32_t last[PPT];
+    bool done[PPT];
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        T[p] = 1.0f;
+        C0[p] = C1[p] = C2[p] = 0.0f;
+        last[p] = 0;
+        fpy[p] = (double)(py0 + p);
+        done[p] = !(px < a.width && py0 + p < a.height);
+    }
+
+    const uint2 range = a.ranges[tile];
+    const int todo = (int)(range.y - range.x);
+    for (int base = 0; base < todo; base += kBatch) {
+        int alive = 0;
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) alive |= done[p] ? 0 : 1;
+        if (__syncthreads_count(alive) == 0) break;
+        for (int k = t; k < kBatch; k += NT) {
+            const int idx = base + k;
+            if (idx < todo)
+                stage_splat(a.mean2d, a.conic_opacity, a.rgb, a.point_list[range.x + idx], s_q, s_c, s_f, k);
+        }
+        __syncthreads();
+        const int cnt = min(kBatch, todo - base);
+        for (int j = 0; j < cnt; ++j) {
+            if ((j & 31) == 0) {
+                int live = 0;
+#pragma unroll
+                for (int p = 0; p < PPT; ++p) live |= done[p] ? 0 : 1;
+                if (!__any(live)) break;  // wave-uniform: this wave's pixels are all done
+            }
+            const double4 q = s_q[j];
+            const double c2 = s_c[j];
+            const float4 f = s_f[j];
+            const double dx = q.x - fpx;
+            const double adx2 = (q.z * dx) * dx;
+            const double bdx = q.w * dx;
+#pragma unroll
+            for (int p = 0; p < PPT; ++p) {
+                if (done[p]) continue;
+                float alpha, G;
+                if (!splat_alpha(adx2, bdx, c2, q.y - fpy[p], f.x, alpha, G)) continue;
+                const float test_T = T[p] * (1.0f - alpha);
+                if (test_T < kTMin) {
+                    done[p] = true;
+                    continue;
+                }
+                const float wgt = alpha * T[p];
+                C0[p] = fmaf(f.y, wgt, C0[p]);
+                C1[p] = fmaf(f.z, wgt, C1[p]);
+                C2[p] = fmaf(f.w, wgt, C2[p]);
+                T[p] = test_T;
+                last[p] = (uint32_t)(base + j + 1);
+            }
+        }
+    }
+
+    const int64_t npix = (int64_t)a.width * a.height;
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        const int py = py0 + p;
+        if (px < a.width && py < a.height) {
+            const int64_t pix = (int64_t)py * a.width + px;
+            a.out_T[pix] = T[p];
+            a.out_ncontrib[pix] = last[p];
+            a.out_rgb[pix] = fmaf(T[p], a.bg[0], C0[p]);
+            a.out_rgb[npix + pix] = fmaf(T[p], a.bg[1], C1[p]);
+            a.out_rgb[2 * npix + pix] = fmaf(T[p], a.bg[2], C2[p]);
+        }
+    }
+}
+
+// Backward: each pixel walks its list from its last blended splat down to
+// the first, recovering the transmittance before each splat by division
+// (T_i = T_{i+1} / (1 - alpha_i)) from the stored final T, and carrying the
+// colour S_i composited behind splat i (background included):
+//   dL/drgb_i  = alpha_i T_i dL/dC
+//   dL/dalpha_i = T_i (rgb_i - S_i) . dL/dC,   S_{i-1} = alpha_i rgb_i + (1 - alpha_i) S_i
+// alpha = min(0.99, o G): when unclamped dalpha/do = G and dalpha/dpower = alpha.
+// Per-splat sums over the wave are reduced with cross-lane shuffles and
+// added to the per-Gaussian 2D gradients with one atomic per value.
+template <int PPT>
+__global__ __launch_bounds__(256 / PPT) void k_blend_bwd(BlendBwdArgs a, uint32_t per_xcd) {
+    constexpr int NT = 256 / PPT;
+    __shared__ double4 s_q[kBatch];
+    __shared__ double s_c[kBatch];
+    __shared__ float4 s_f[kBatch];
+    __shared__ uint32_t s_id[kBatch];
+    __shared__ uint32_t s_max;
+
+    const uint32_t tile = xcd_band(blockIdx.x, per_xcd);
+    if (tile >= (uint32_t)(a.tiles_x * a.tiles_y)) return;
+    const int t = threadIdx.x;
+    const int tx = (int)(tile % (uint32_t)a.tiles_x), ty = (int)(tile / (uint32_t)a.tiles_x);
+    const int px = tx * kTile + (t & 15);
+    const int py0 = ty * kTile + (t >> 4) * PPT;
+    const double fpx = (double)px;
+    const int64_t npix = (int64_t)a.width * a.height;
+
+    float T[PPT], S0[PPT], S1[PPT], S2[PPT], D0[PPT], D1[PPT], D2[PPT];
+    double fpy[PPT];
+    uint32_t last[PPT];
+    uint32_t mylast = 0;
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        const int py = py0 + p;
+        fpy[p] = (double)py;
+        S0[p] = a.bg[0];
+        S1[p] = a.bg[1];
+        S2[p] = a.bg[2];
+        if (px < a.width && py < a.height) {
+            const int64_t pix = (int64_t)py * a.width + px;
+            T[p] = a.final_T[pix];
+            last[p] = a.ncontrib[pix];
+            D0[p] = a.dL_drgb[pix];
+            D1[p] = a.dL_drgb[npix + pix];
+            D2[p] = a.dL_drgb[2 * npix + pix];
+        } else {
+            T[p] = 1.0f;
+            last[p] = 0;
+            D0[p] = D1[p] = D2[p] = 0.0f;
+        }
+        mylast = last[p] > mylast ? last[p] : mylast;
+    }
+    if (t == 0) s_max = 0;
+    __syncthreads();
+    mylast = wave_max(mylast);
+    if (lane_id() == 0) atomicMax(&s_max, mylast);
+    __syncthreads();
+    const uint2 range = a.ranges[tile];
+    // n_contrib can never exceed the tile's list length; clamp so a stale or
+    // foreign n_contrib cannot walk past the list
+    const uint32_t len = range.y - range.x;
+    const int maxlast = (int)(s_max < len ? s_max : len);
+    const int64_t n = a.n;
+    for (int end = maxlast; end > 0; end -= kBatch) {
+        const int begin = end - kBatch > 0 ? end - kBatch : 0;
+        __syncthreads();  // the previous batch is fully consumed
+        for (int k = t; k < end - begin; k += NT) {
+            const uint32_t id = a.point_list[range.x + begin + k];
+            s_id[k] = id;
+            stage_splat(a.mean2d, a.conic_opacity, a.rgb, id, s_q, s_c, s_f, k);
+        }
+        __syncthreads();
+        for (int j = end - 1; j >= begin; --j) {
+            const int k = j - begin;
+            const double4 q = s_q[k];
+            const double c2 = s_c[k];
+            const float4 f = s_f[k];
+            const double dx = q.x - fpx;
+            const double adx2 = (q.z * dx) * dx;
+            const double bdx = q.w * dx;
+            const float dxf = (float)dx;
+            float gmx = 0.f, gmy = 0.f, gA = 0.f, gB = 0.f, gC = 0.f, go = 0.f, gr = 0.f, gg = 0.f,
+                  gb = 0.f;
+            bool any = false;
+#pragma unroll
+            for (int p = 0; p < PPT; ++p) {
+                if ((uint32_t)j >= last[p]) continue;
+                const double dy = q.y - fpy[p];
+                float alpha, G;
+                if (!splat_alpha(adx2, bdx, c2, dy, f.x, alpha, G)) continue;
+                any = true;
+                const float dyf = (float)dy;
+                const float one_m = 1.0f - alpha;
+                T[p] = T[p] / one_m;
+                const float Tp = T[p];
+                const float dLda = Tp * ((f.y - S0[p]) * D0[p] + (f.z - S1[p]) * D1[p] +
+                                         (f.w - S2[p]) * D2[p]);
+                S0[p] = alpha * f.y + one_m * S0[p];
+                S1[p] = alpha * f.z + one_m * S1[p];
+                S2[p] = alpha * f.w + one_m * S2[p];
+                const float wgt = alpha * Tp;
+                gr += wgt * D0[p];
+                gg += wgt * D1[p];
+                gb += wgt * D2[p];
+                if (!(f.x * G > kAlphaMax)) {
+                    go += dLda * G;
+                    const float dLdp = dLda * alpha;
+                    // power = (A' dx^2 + B' dx dy + C' dy^2) / log2(e), dx = mean_x - pixel_x
+                    gmx += dLdp * (2.0f * (float)q.z * dxf + (float)q.w * dyf);
+                    gmy += dLdp * (2.0f * (float)c2 * dyf + (float)q.w * dxf);
+                    gA += dLdp * (-0.5f * dxf * dxf);
+                    gB += dLdp * (-dxf * dyf);
+                    gC += dLdp * (-0.5f * dyf * dyf);
+                }
+            }
+            if (__any(any)) {
+                gmx = wave_sum(gmx); gmy = wave_sum(gmy);
+                gA = wave_sum(gA); gB = wave_sum(gB); gC = wave_sum(gC);
+                go = wave_sum(go);
+                gr = wave_sum(gr); gg = wave_sum(gg); gb = wave_sum(gb);
+                if (lane_id() == 0) {
+                    const uint32_t id = s_id[k];
+                    float* g = a.grad2d;
+                    atomicAdd(g + id, gmx * kLn2);
+                    atomicAdd(g + n + id, gmy * kLn2);
+                    atomicAdd(g + 2 * n + id, gA);
+                    atomicAdd(g + 3 * n + id, gB);
+                    atomicAdd(g + 4 * n + id, gC);
+                    atomicAdd(g + 5 * n + id, go);
+                    atomicAdd(g + 6 * n + id, gr);
+                    atomicAdd(g + 7 * n + id, gg);
+                    atomicAdd(g + 8 * n + id, gb);
+                }
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_l1_loss_grad(const float* __restrict__ rgb,
+                                                      const float* __restrict__ target, int64_t count,
+                                                      float* __restrict__ grad, float* loss) {
+    float acc = 0.0f;
+    const float inv = 1.0f / (float)count;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const float d = rgb[i] - target[i];
+        grad[i] = d > 0.0f ? inv : (d < 0.0f ? -inv : 0.0f);
+        acc += fabsf(d);
+    }
+    if (loss) {
+        acc = wave_sum(acc);
+        if (lane_id() == 0) atomicAdd(loss, acc * inv);
+    }
+}
+
+}  // namespace
+
+static uint32_t xcd_per(int64_t tiles) { return (uint32_t)((tiles + 7) / 8); }
+
+hipError_t launch_blend(const BlendArgs& a, int variant, hipStream_t stream) {
+    const int64_t tiles = (int64_t)a.tiles_x * a.tiles_y;
+    if (tiles == 0) return hipSuccess;
+    const uint32_t per = xcd_per(tiles);
+    const dim3 grid(8 * per);
+    switch (variant) {
+        case 1: hipLaunchKernelGGL(k_blend<1>, grid, dim3(256), 0, stream, a, per); break;
+        case 4: hipLaunchKernelGGL(k_blend<4>, grid, dim3(64), 0, stream, a, per); break;
+        default: hipLaunchKernelGGL(k_blend<2>, grid, dim3(128), 0, stream, a, per); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_blend_backward(const BlendBwdArgs& a, hipStream_t stream) {
+    const int64_t tiles = (int64_t)a.tiles_x * a.tiles_y;
+    if (tiles == 0) return hipSuccess;
+    const uint32_t per = xcd_per(tiles);
+    hipLaunchKernelGGL(k_blend_bwd<1>, dim3(8 * per), dim3(256), 0, stream, a, per);
+    return hipGetLastError();
+}
+
+hipError_t launch_l1_loss_grad(const float* rgb, const float* target, int64_t count, float* grad,
+                               float* loss, hipStream_t stream) {
+    if (count <= 0) return hipSuccess;
+    if (loss) {
+        hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(loss), 1, 0u, stream);
+        if (e != hipSuccess) return e;
+    }
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_l1_loss_grad, dim3((unsigned)blocks), dim3(256), 0, stream, rgb, target,
+                       count, grad, loss);
+    return hipGetLastError();
+}
+
+}  // namespace cds

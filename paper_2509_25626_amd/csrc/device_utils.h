@@ -1,0 +1,88 @@
+// Device-side helpers for gfx950 (CDNA4, wave64): lane masks, wave and block
+// scans, bounded-spin atomics.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cds {
+
+constexpr int kWave = 64;
+constexpr int kTile = 16;
+
+__device__ __forceinline__ uint32_t lane_id() {
+    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+// Number of set bits of `mask` in lanes strictly below this lane.
+__device__ __forceinline__ uint32_t count_below(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+// Inclusive prefix sum across the 64 lanes of a wave.
+__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t v) {
+    const uint32_t l = lane_id();
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        uint32_t t = __shfl_up(v, (unsigned)o, kWave);
+        if (l >= (uint32_t)o) v += t;
+    }
+    return v;
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        uint32_t t = __shfl_xor(v, o, kWave);
+        v = t > v ? t : v;
+    }
+    return v;
+}
+
+// Exclusive prefix sum over a block of NT threads (NT a multiple of 64).
+// `scratch` holds NT/64 words of LDS.  Every thread of the block must call.
+template <int NT>
+__device__ __forceinline__ uint32_t block_excl_sum(uint32_t v, uint32_t* scratch, uint32_t* total) {
+    static_assert(NT % kWave == 0, "block must be whole waves");
+    constexpr int NW = NT / kWave;
+    const uint32_t inc = wave_incl_sum(v);
+    const int w = threadIdx.x / kWave;
+    if (lane_id() == kWave - 1) scratch[w] = inc;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+        uint32_t s = scratch[k];
+        before += (k < w) ? s : 0u;
+        all += s;
+    }
+    __syncthreads();
+    if (total) *total = all;
+    return before + inc - v;
+}
+
+__device__ __forceinline__ uint32_t atomic_load_agent(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void atomic_store_agent(uint32_t* p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// XCD-aware block -> work-item map.  Consecutive workgroup ids are spread
+// round-robin over the 8 XCDs of the chip; this sends a contiguous band of
+// work items (neighbouring tiles) to each XCD so they share its L2.
+// `grid` must be 8 * per_xcd; returns >= count for padding blocks.
+__device__ __forceinline__ uint32_t xcd_band(uint32_t bid, uint32_t per_xcd) {
+    return (bid & 7u) * per_xcd + (bid >> 3);
+}
+
+}  // namespace cds

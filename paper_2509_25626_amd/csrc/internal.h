@@ -1,0 +1,150 @@
+// Internal interface between the host runtime and the kernel translation
+// units.  Each launcher enqueues its kernels on `stream` and returns the HIP
+// status of the launch.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cds {
+
+// Camera and per-frame constants of the projection (double precision: the
+// projection decides tile coverage and depth keys in float64).
+struct ProjParams {
+    int64_t n;
+    int32_t sh_degree;
+    int32_t width, height, tiles_x, tiles_y;
+    int32_t pad;
+    double R[9];        // world -> camera rotation, row-major
+    double t[3];        // world -> camera translation
+    double campos[3];   // camera centre in world space, -R^T t
+    double fx, fy, cx, cy;
+    double near_plane;
+    double limx, limy;  // 1.3 x half field of view tangents (Jacobian guard band)
+};
+
+struct SceneParams {
+    const float* means;
+    const float* log_scales;
+    const float* quats;
+    const float* opacity_logits;
+    const float* sh;
+};
+
+// Per-Gaussian projected state (the paper's points_xy_image, conic_opacity,
+// features and depths, plus tile bookkeeping).
+struct SplatBuffers {
+    float2* mean2d;
+    float4* conic_opacity;
+    float4* rgb;
+    uint32_t* depth_bits;
+    int32_t* radius;
+    uint2* rect;
+    uint32_t* touched;
+    uint8_t* clamp_flags;
+};
+
+struct GradBuffers2D {  // [9][n]: mean x, mean y, conic A, B, C, opacity, r, g, b
+    float* g;
+};
+
+hipError_t launch_preprocess(const ProjParams& p, const SceneParams& s, const SplatBuffers& out,
+                             hipStream_t stream);
+
+// Exclusive scan of n uint32 values (read as in[gather[i]] when gather is
+// not null); the total (uint64, device) is written too.  `block_sums` needs
+// scan_block_sums_size(n) uint64 elements.
+int64_t scan_block_sums_size(int64_t n);
+hipError_t launch_exclusive_scan(const uint32_t* in, const uint32_t* gather, uint32_t* out, int64_t n,
+                                 uint64_t* block_sums, uint64_t* total, hipStream_t stream);
+
+// Key duplication over the visit order `order` (identity when null): writes
+// 64-bit keys and/or 32-bit tile ids plus values, and (if hist is not null)
+// the digit histograms: `depth_passes` depth-digit passes then `tile_passes`
+// tile-digit passes ([passes][256], zero on entry).
+hipError_t launch_duplicate(int64_t n, const uint32_t* order, const uint32_t* offsets, const uint32_t* touched,
+                            const uint2* rect, const uint32_t* depth_bits, int tiles_x, uint64_t* keys64,
+                            uint32_t* tiles32, uint32_t* values, uint32_t* hist, int depth_passes,
+                            int tile_passes, hipStream_t stream);
+hipError_t launch_make_keys(const uint32_t* tiles, const uint32_t* values, const uint32_t* depth_bits,
+                            int64_t count, uint64_t* keys, hipStream_t stream);
+
+// Stable LSD radix sort, 8-bit digits from bit shift0.  Pass 0 reads (kin,
+// vin) -- vin null means value = input position -- and the passes ping-pong
+// between (ka, va) and (kb, vb): the result is in (ka, va) after an odd
+// number of passes, in (kb, vb) after an even number.  kin may alias kb.
+struct SortWorkspace {
+    uint32_t* hist;      // [passes][256]
+    uint32_t* status;    // [passes][partitions][256]
+    uint32_t* counters;  // [passes]
+    uint32_t* err;       // device error word
+};
+constexpr int kSortThreads = 256;
+constexpr int kSortKeysPerThread = 16;
+constexpr int64_t kSortPartition = (int64_t)kSortThreads * kSortKeysPerThread;
+constexpr int64_t kSortMaxCount = (int64_t(1) << 30) - 1;
+inline int64_t sort_partitions(int64_t count) { return (count + kSortPartition - 1) / kSortPartition; }
+hipError_t launch_sort_histogram(const uint64_t* keys, int64_t count, int passes, int shift0, uint32_t* hist,
+                                 hipStream_t stream);
+hipError_t launch_sort_histogram(const uint32_t* keys, int64_t count, int passes, int shift0, uint32_t* hist,
+                                 hipStream_t stream);
+hipError_t launch_sort_prepare(const SortWorkspace& ws, int64_t count, int passes, bool clear_hist,
+                               hipStream_t stream);
+hipError_t launch_sort_passes(const uint64_t* kin, const uint32_t* vin, uint64_t* ka, uint32_t* va,
+                              uint64_t* kb, uint32_t* vb, int64_t count, int passes, int shift0,
+                              const SortWorkspace& ws, hipStream_t stream);
+hipError_t launch_sort_passes(const uint32_t* kin, const uint32_t* vin, uint32_t* ka, uint32_t* va,
+                              uint32_t* kb, uint32_t* vb, int64_t count, int passes, int shift0,
+                              const SortWorkspace& ws, hipStream_t stream);
+
+hipError_t launch_fill_u32(uint32_t* p, int64_t count, uint32_t value, hipStream_t stream);
+
+hipError_t launch_ranges(const uint32_t* tile_words, int stride, int64_t count, uint2* ranges,
+                         int64_t ntiles, hipStream_t stream);
+
+struct BlendArgs {
+    const uint2* ranges;
+    const uint32_t* point_list;
+    const float2* mean2d;
+    const float4* conic_opacity;
+    const float4* rgb;
+    int32_t width, height, tiles_x, tiles_y;
+    float bg[3];
+    float* out_rgb;
+    float* out_T;
+    uint32_t* out_ncontrib;
+};
+hipError_t launch_blend(const BlendArgs& a, int variant, hipStream_t stream);
+
+struct BlendBwdArgs {
+    const uint2* ranges;
+    const uint32_t* point_list;
+    const float2* mean2d;
+    const float4* conic_opacity;
+    const float4* rgb;
+    int32_t width, height, tiles_x, tiles_y;
+    float bg[3];
+    const float* final_T;
+    const uint32_t* ncontrib;
+    const float* dL_drgb;
+    int64_t n;
+    float* grad2d;  // [9][n], zero on entry
+};
+hipError_t launch_blend_backward(const BlendBwdArgs& a, hipStream_t stream);
+
+struct PreBwdArgs {
+    const int32_t* radius;
+    const uint8_t* clamp_flags;
+    const float* grad2d;  // [9][n]
+    float* g_means;
+    float* g_log_scales;
+    float* g_quats;
+    float* g_opacity_logits;
+    float* g_sh;
+};
+hipError_t launch_preprocess_backward(const ProjParams& p, const SceneParams& s, const PreBwdArgs& a,
+                                      hipStream_t stream);
+
+hipError_t launch_l1_loss_grad(const float* rgb, const float* target, int64_t count, float* grad,
+                               float* loss, hipStream_t stream);
+
+}  // namespace cds

@@ -1,0 +1,208 @@
+// Per-Gaussian preprocessing (paper Section II-B(1)): visibility, projection
+// of each 3D Gaussian to a 2D splat (mean, conic, screen radius, covered tile
+// rectangle), depth, and colour from spherical harmonics (degree <= 3).
+//
+// The geometry runs in float64: it decides the discrete outputs (near cull,
+// radius, covered tiles, depth-key bits), and float64 is what makes those
+// decisions reproducible by an independent implementation.  The kernel reads
+// ~236 B and writes ~61 B per Gaussian, so the float64 arithmetic (full rate
+// on CDNA4 vector units) stays below the HBM time.  Colour is float32.
+//
+// Loads are coalesced structure-of-arrays planes, one Gaussian per lane.
+#include "device_utils.h"
+#include "internal.h"
+
+namespace cds {
+namespace {
+
+// Real spherical-harmonics normalisation constants (orthonormal basis with
+// the Condon-Shortley phase), written from their closed forms:
+// 1/(2 sqrt(pi)), sqrt(3/(4 pi)), sqrt(15/(4 pi)), sqrt(5/(16 pi)),
+// sqrt(15/(16 pi)), sqrt(35/(32 pi)), sqrt(105/(4 pi)), sqrt(21/(32 pi)),
+// sqrt(7/(16 pi)), sqrt(105/(16 pi)).
+constexpr float kY00 = 0.28209479177387814f;
+constexpr float kY1 = 0.48860251190291992f;
+constexpr float kY2a = 1.0925484305920792f;
+constexpr float kY2b = 0.31539156525252005f;
+constexpr float kY2c = 0.54627421529603959f;
+constexpr float kY3a = 0.59004358992664352f;
+constexpr float kY3b = 2.8906114426405538f;
+constexpr float kY3c = 0.45704579946446572f;
+constexpr float kY3d = 0.3731763325901154f;
+constexpr float kY3e = 1.4453057213202769f;
+
+__device__ __forceinline__ void sh_basis_f32(float x, float y, float z, int degree, float b[16]) {
+    b[0] = kY00;
+    if (degree < 1) return;
+    b[1] = -kY1 * y;
+    b[2] = kY1 * z;
+    b[3] = -kY1 * x;
+    if (degree < 2) return;
+    const float xx = x * x, yy = y * y, zz = z * z;
+    b[4] = kY2a * (x * y);
+    b[5] = -kY2a * (y * z);
+    b[6] = kY2b * (2.0f * zz - xx - yy);
+    b[7] = -kY2a * (x * z);
+    b[8] = kY2c * (xx - yy);
+    if (degree < 3) return;
+    b[9] = -kY3a * y * (3.0f * xx - yy);
+    b[10] = kY3b * (x * y) * z;
+    b[11] = -kY3c * y * (4.0f * zz - xx - yy);
+    b[12] = kY3d * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+    b[13] = -kY3c * x * (4.0f * zz - xx - yy);
+    b[14] = kY3e * z * (xx - yy);
+    b[15] = -kY3a * x * (xx - 3.0f * yy);
+}
+
+__global__ __launch_bounds__(256) void k_preprocess(ProjParams P, SceneParams S, SplatBuffers O) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P.n) return;
+    const int64_t n = P.n;
+
+    const double m0 = S.means[i], m1 = S.means[n + i], m2 = S.means[2 * n + i];
+    const double tx = P.R[0] * m0 + P.R[1] * m1 + P.R[2] * m2 + P.t[0];
+    const double ty = P.R[3] * m0 + P.R[4] * m1 + P.R[5] * m2 + P.t[1];
+    const double tz = P.R[6] * m0 + P.R[7] * m1 + P.R[8] * m2 + P.t[2];
+
+    bool visible = tz > P.near_plane;
+    double A = 0, B = 0, C = 0, mx = 0, my = 0;
+    int radius = 0;
+    uint32_t tx0 = 0, ty0 = 0, tx1 = 0, ty1 = 0;
+    uint8_t flags = 0;
+    float mxf = 0.f, myf = 0.f;
+
+    if (visible) {
+        // 3D covariance Sigma = Rq diag(s^2) Rq^T, s = exp(log_scale)
+        const double s0 = exp(2.0 * (double)S.log_scales[i]);
+        const double s1 = exp(2.0 * (double)S.log_scales[n + i]);
+        const double s2 = exp(2.0 * (double)S.log_scales[2 * n + i]);
+        double qw = S.quats[i], qx = S.quats[n + i], qy = S.quats[2 * n + i], qz = S.quats[3 * n + i];
+        const double qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+        qw /= qn; qx /= qn; qy /= qn; qz /= qn;
+        const double r00 = 1.0 - 2.0 * (qy * qy + qz * qz), r01 = 2.0 * (qx * qy - qw * qz),
+                     r02 = 2.0 * (qx * qz + qw * qy);
+        const double r10 = 2.0 * (qx * qy + qw * qz), r11 = 1.0 - 2.0 * (qx * qx + qz * qz),
+                     r12 = 2.0 * (qy * qz - qw * qx);
+        const double r20 = 2.0 * (qx * qz - qw * qy), r21 = 2.0 * (qy * qz + qw * qx),
+                     r22 = 1.0 - 2.0 * (qx * qx + qy * qy);
+        const double S00 = r00 * r00 * s0 + r01 * r01 * s1 + r02 * r02 * s2;
+        const double S01 = r00 * r10 * s0 + r01 * r11 * s1 + r02 * r12 * s2;
+        const double S02 = r00 * r20 * s0 + r01 * r21 * s1 + r02 * r22 * s2;
+        const double S11 = r10 * r10 * s0 + r11 * r11 * s1 + r12 * r12 * s2;
+        const double S12 = r10 * r20 * s0 + r11 * r21 * s1 + r12 * r22 * s2;
+        const double S22 = r20 * r20 * s0 + r21 * r21 * s1 + r22 * r22 * s2;
+
+        // EWA Jacobian of the perspective projection, ratios limited to the guard band
+        double ux = tx / tz, uy = ty / tz;
+        if (ux > P.limx) { ux = P.limx; flags |= 8; }
+        if (ux < -P.limx) { ux = -P.limx; flags |= 8; }
+        if (uy > P.limy) { uy = P.limy; flags |= 16; }
+        if (uy < -P.limy) { uy = -P.limy; flags |= 16; }
+        const double j00 = P.fx / tz, j02 = -P.fx * ux / tz;
+        const double j11 = P.fy / tz, j12 = -P.fy * uy / tz;
+        // M = J * Rcam (2 x 3)
+        const double a0 = j00 * P.R[0] + j02 * P.R[6], a1 = j00 * P.R[1] + j02 * P.R[7],
+                     a2 = j00 * P.R[2] + j02 * P.R[8];
+        const double b0 = j11 * P.R[3] + j12 * P.R[6], b1 = j11 * P.R[4] + j12 * P.R[7],
+                     b2 = j11 * P.R[5] + j12 * P.R[8];
+        // v = Sigma M0^T, w = Sigma M1^T
+        const double v0 = S00 * a0 + S01 * a1 + S02 * a2;
+        const double v1 = S01 * a0 + S11 * a1 + S12 * a2;
+        const double v2 = S02 * a0 + S12 * a1 + S22 * a2;
+        const double w0 = S00 * b0 + S01 * b1 + S02 * b2;
+        const double w1 = S01 * b0 + S11 * b1 + S12 * b2;
+        const double w2 = S02 * b0 + S12 * b1 + S22 * b2;
+        const double ca = a0 * v0 + a1 * v1 + a2 * v2 + 0.3;
+        const double cb = b0 * v0 + b1 * v1 + b2 * v2;
+        const double cc = b0 * w0 + b1 * w1 + b2 * w2 + 0.3;
+        const double det = ca * cc - cb * cb;
+        if (!(det > 0.0)) {
+            visible = false;
+        } else {
+            A = cc / det;
+            B = -cb / det;
+            C = ca / det;
+            const double mid = 0.5 * (ca + cc);
+            const double disc = mid * mid - det;
+            const double lam = mid + sqrt(disc > 0.1 ? disc : 0.1);
+            const double rr = ceil(3.0 * sqrt(lam));
+            mx = P.fx * tx / tz + P.cx;
+            my = P.fy * ty / tz + P.cy;
+            mxf = (float)mx;
+            myf = (float)my;
+            // covered pixels |p - mean| <= r per axis (mean as stored, float32)
+            double lox = ceil((double)mxf - rr), hix = floor((double)mxf + rr);
+            double loy = ceil((double)myf - rr), hiy = floor((double)myf + rr);
+            lox = lox < 0.0 ? 0.0 : lox;
+            loy = loy < 0.0 ? 0.0 : loy;
+            hix = hix > P.width - 1 ? (double)(P.width - 1) : hix;
+            hiy = hiy > P.height - 1 ? (double)(P.height - 1) : hiy;
+            if (lox > hix || loy > hiy) {
+                visible = false;
+            } else {
+                radius = rr > 2147483647.0 ? 2147483647 : (int)rr;
+                tx0 = (uint32_t)lox / kTile; tx1 = (uint32_t)hix / kTile;
+                ty0 = (uint32_t)loy / kTile; ty1 = (uint32_t)hiy / kTile;
+            }
+        }
+    }
+
+    if (!visible) {
+        O.mean2d[i] = make_float2(0.f, 0.f);
+        O.conic_opacity[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        O.rgb[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        O.depth_bits[i] = 0u;
+        O.radius[i] = 0;
+        O.rect[i] = make_uint2(0u, 0u);
+        O.touched[i] = 0u;
+        O.clamp_flags[i] = 0;
+        return;
+    }
+
+    const float opacity = (float)(1.0 / (1.0 + exp(-(double)S.opacity_logits[i])));
+
+    // colour: view direction from the camera centre, SH up to degree 3
+    double dx = m0 - P.campos[0], dy = m1 - P.campos[1], dz = m2 - P.campos[2];
+    const double dl = sqrt(dx * dx + dy * dy + dz * dz);
+    float basis[16];
+    sh_basis_f32((float)(dx / dl), (float)(dy / dl), (float)(dz / dl), P.sh_degree, basis);
+    const int nb = (P.sh_degree + 1) * (P.sh_degree + 1);
+    float col[3] = {0.f, 0.f, 0.f};
+    for (int k = 0; k < nb; ++k) {
+        const float* c = S.sh + (int64_t)k * 3 * n + i;
+        col[0] += basis[k] * c[0];
+        col[1] += basis[k] * c[n];
+        col[2] += basis[k] * c[2 * n];
+    }
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        col[ch] += 0.5f;
+        if (col[ch] < 0.0f) {
+            col[ch] = 0.0f;
+            flags |= (uint8_t)(1u << ch);
+        }
+    }
+
+    const float dzf = (float)tz;
+    O.mean2d[i] = make_float2(mxf, myf);
+    O.conic_opacity[i] = make_float4((float)A, (float)B, (float)C, opacity);
+    O.rgb[i] = make_float4(col[0], col[1], col[2], 0.f);
+    O.depth_bits[i] = __float_as_uint(dzf);
+    O.radius[i] = radius;
+    O.rect[i] = make_uint2(tx0 | (ty0 << 16), tx1 | (ty1 << 16));
+    O.touched[i] = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+    O.clamp_flags[i] = flags;
+}
+
+}  // namespace
+
+hipError_t launch_preprocess(const ProjParams& p, const SceneParams& s, const SplatBuffers& out,
+                             hipStream_t stream) {
+    if (p.n == 0) return hipSuccess;
+    const int nt = 256;
+    const int64_t nb = (p.n + nt - 1) / nt;
+    hipLaunchKernelGGL(k_preprocess, dim3((unsigned)nb), dim3(nt), 0, stream, p, s, out);
+    return hipGetLastError();
+}
+
+}  // namespace cds

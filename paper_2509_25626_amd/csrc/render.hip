@@ -1,0 +1,295 @@
+// The stream-ordered launch sequence of one forward render and one backward
+// pass (paper Section II-B: preprocessing -> duplication -> sort -> ranges ->
+// alpha blending).  The only host wait is the read-back of the key count K
+// after the prefix sum; every other step is enqueued on the caller's stream.
+#include <cstring>
+
+#include "runtime_internal.h"
+
+namespace cds {
+
+void release_frame_events(cds_frame* f) {
+    for (hipEvent_t& e : f->ev)
+        if (e) {
+            (void)hipEventDestroy(e);
+            e = nullptr;
+        }
+}
+
+void release_frame_buffers(cds_frame* f) {
+    cds_ctx* c = f->ctx;
+    DevBuf* bufs[] = {&f->mean2d, &f->conic, &f->rgb, &f->depth, &f->radius, &f->rect, &f->touched,
+                      &f->offsets, &f->clampf, &f->blocksums, &f->total, &f->order0, &f->order1,
+                      &f->dkey0, &f->dkey1, &f->sort_d.hist, &f->sort_d.status, &f->sort_d.counters,
+                      &f->keys0, &f->keys1, &f->tk0, &f->tk1, &f->vals0, &f->vals1, &f->sort.hist,
+                      &f->sort.status, &f->sort.counters, &f->ranges, &f->grad2d};
+    for (DevBuf* b : bufs) release(c, *b);
+    f->valid = false;
+}
+
+#define CDS_HIP(expr, what)                          \
+    do {                                             \
+        hipError_t _e = (expr);                      \
+        if (_e != hipSuccess) return hip_fail(_e, what); \
+    } while (0)
+#define CDS_TRY(expr)                   \
+    do {                                \
+        cds_status _s = (expr);         \
+        if (_s != CDS_OK) return _s;    \
+    } while (0)
+
+int tile_bits_for(int64_t ntiles) {
+    int bits = 0;
+    while (bits < 32 && (int64_t(1) << bits) < ntiles) ++bits;
+    return bits;
+}
+
+/*
+ * Sort variant 0 (default): the 32 depth bits of every key of a Gaussian are
+ * that Gaussian's depth, so the four depth-digit LSD passes are run once over
+ * the N Gaussians (stable, ties by index) instead of over the K keys; keys are
+ * then generated in that order, which is exactly the sequence the four depth
+ * passes would have produced, and the remaining tile-digit passes run over
+ * 32-bit tile ids.  The sorted (key, value) list is bit-identical to the
+ * direct sort of the 64-bit keys (variant 1), at a third of the key traffic.
+ */
+cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scene, const cds_camera* cam,
+                               int blend_variant, int sort_variant, float* out_rgb, float* out_T,
+                               uint32_t* out_ncontrib, hipStream_t stream) {
+    const int64_t n = scene->n;
+    f->timed_backward = false;
+    CDS_TRY(f->record(0, stream));
+    const ProjParams P = make_proj(scene, cam);
+    const int64_t ntiles = (int64_t)P.tiles_x * P.tiles_y;
+    const size_t nn = (size_t)(n > 0 ? n : 1);
+    const int tile_passes = (tile_bits_for(ntiles) + 7) / 8;
+
+    CDS_TRY(ensure(ctx, f->mean2d, sizeof(float2) * nn, 1.1));
+    CDS_TRY(ensure(ctx, f->conic, sizeof(float4) * nn, 1.1));
+    CDS_TRY(ensure(ctx, f->rgb, sizeof(float4) * nn, 1.1));
+    CDS_TRY(ensure(ctx, f->depth, sizeof(uint32_t) * nn, 1.1));
+    CDS_TRY(ensure(ctx, f->radius, sizeof(int32_t) * nn, 1.1));
+    CDS_TRY(ensure(ctx, f->rect, sizeof(uint2) * nn, 1.1));
+    CDS_TRY(ensure(ctx, f->touched, sizeof(uint32_t) * nn, 1.1));
+    CDS_TRY(ensure(ctx, f->offsets, sizeof(uint32_t) * nn, 1.1));
+    CDS_TRY(ensure(ctx, f->clampf, nn, 1.1));
+    CDS_TRY(ensure(ctx, f->blocksums, sizeof(uint64_t) * scan_block_sums_size(n), 1.1));
+    CDS_TRY(ensure(ctx, f->total, 256));
+    CDS_TRY(ensure(ctx, f->ranges, sizeof(uint2) * (size_t)ntiles, 1.1));
+    if (sort_variant == 0) {
+        CDS_TRY(ensure(ctx, f->order0, sizeof(uint32_t) * nn, 1.1));
+        CDS_TRY(ensure(ctx, f->order1, sizeof(uint32_t) * nn, 1.1));
+        CDS_TRY(ensure(ctx, f->dkey0, sizeof(uint32_t) * nn, 1.1));
+        CDS_TRY(ensure(ctx, f->dkey1, sizeof(uint32_t) * nn, 1.1));
+        CDS_TRY(ensure_sort_workspace(ctx, f->sort_d, n, 4));
+    }
+
+    SplatBuffers sb;
+    sb.mean2d = (float2*)f->mean2d.p;
+    sb.conic_opacity = (float4*)f->conic.p;
+    sb.rgb = (float4*)f->rgb.p;
+    sb.depth_bits = (uint32_t*)f->depth.p;
+    sb.radius = (int32_t*)f->radius.p;
+    sb.rect = (uint2*)f->rect.p;
+    sb.touched = (uint32_t*)f->touched.p;
+    sb.clamp_flags = (uint8_t*)f->clampf.p;
+    CDS_HIP(launch_preprocess(P, make_scene(scene), sb, stream), "preprocess kernel");
+    CDS_TRY(f->record(1, stream));
+
+    // depth order of the Gaussians (variant 0): 4 passes, result in (dkey1, order1)
+    const uint32_t* order = nullptr;
+    if (sort_variant == 0 && n > 0) {
+        SortWorkspace wd = sort_ws(ctx, f->sort_d);
+        CDS_HIP(launch_sort_prepare(wd, n, 4, true, stream), "depth sort prepare");
+        CDS_HIP(launch_sort_histogram(sb.depth_bits, n, 4, 0, wd.hist, stream), "depth sort histogram");
+        CDS_HIP(launch_sort_passes(sb.depth_bits, nullptr, (uint32_t*)f->dkey0.p, (uint32_t*)f->order0.p,
+                                   (uint32_t*)f->dkey1.p, (uint32_t*)f->order1.p, n, 4, 0, wd, stream),
+                "depth sort");
+        order = (const uint32_t*)f->order1.p;
+    }
+    uint64_t* d_total = (uint64_t*)f->total.p;
+    CDS_HIP(launch_exclusive_scan(sb.touched, order, (uint32_t*)f->offsets.p, n, (uint64_t*)f->blocksums.p,
+                                  d_total, stream),
+            "scan kernels");
+    CDS_HIP(hipMemcpyAsync(ctx->host_pinned, d_total, sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
+            "hipMemcpyAsync(key count)");
+    CDS_HIP(hipStreamSynchronize(stream), "hipStreamSynchronize(key count)");
+    CDS_TRY(f->record(2, stream));
+    const uint64_t K = ctx->host_pinned[0];
+    if (K > (uint64_t)kSortMaxCount)
+        return fail(CDS_ERR_CAPACITY, "render needs " + std::to_string(K) +
+                                          " tile keys; the radix sort supports at most 2^30-1");
+    const int passes = sort_variant == 0 ? tile_passes : 4 + tile_passes;
+    const size_t kk = (size_t)(K > 0 ? K : 1);
+    CDS_TRY(ensure(ctx, f->vals0, sizeof(uint32_t) * kk, 1.25));
+    CDS_TRY(ensure(ctx, f->vals1, sizeof(uint32_t) * kk, 1.25));
+    if (sort_variant == 0) {
+        CDS_TRY(ensure(ctx, f->tk0, sizeof(uint32_t) * kk, 1.25));
+        CDS_TRY(ensure(ctx, f->tk1, sizeof(uint32_t) * kk, 1.25));
+    } else {
+        CDS_TRY(ensure(ctx, f->keys0, sizeof(uint64_t) * kk, 1.25));
+        CDS_TRY(ensure(ctx, f->keys1, sizeof(uint64_t) * kk, 1.25));
+    }
+    CDS_TRY(ensure_sort_workspace(ctx, f->sort, (int64_t)K, passes > 0 ? passes : 1));
+
+    SortWorkspace ws = sort_ws(ctx, f->sort);
+    if (K > 0) {
+        CDS_HIP(launch_sort_prepare(ws, (int64_t)K, passes, true, stream), "sort prepare");
+        if (sort_variant == 0)
+            CDS_HIP(launch_duplicate(n, order, (const uint32_t*)f->offsets.p, sb.touched, sb.rect, sb.depth_bits,
+                                     P.tiles_x, nullptr, (uint32_t*)f->tk0.p, (uint32_t*)f->vals0.p, ws.hist, 0,
+                                     tile_passes, stream),
+                    "duplicate kernel");
+        else
+            CDS_HIP(launch_duplicate(n, nullptr, (const uint32_t*)f->offsets.p, sb.touched, sb.rect,
+                                     sb.depth_bits, P.tiles_x, (uint64_t*)f->keys0.p, nullptr,
+                                     (uint32_t*)f->vals0.p, ws.hist, 4, tile_passes, stream),
+                    "duplicate kernel");
+    }
+    CDS_TRY(f->record(3, stream));
+    const bool odd = (passes & 1) != 0;
+    if (sort_variant == 0) {
+        if (K > 0)
+            CDS_HIP(launch_sort_passes((const uint32_t*)f->tk0.p, (const uint32_t*)f->vals0.p, (uint32_t*)f->tk1.p,
+                                       (uint32_t*)f->vals1.p, (uint32_t*)f->tk0.p, (uint32_t*)f->vals0.p,
+                                       (int64_t)K, passes, 0, ws, stream),
+                    "tile sort");
+        f->res_tiles = (const uint32_t*)(odd ? f->tk1.p : f->tk0.p);
+        f->res_tile_stride = 1;
+        f->res_keys = nullptr;
+    } else {
+        if (K > 0)
+            CDS_HIP(launch_sort_passes((const uint64_t*)f->keys0.p, (const uint32_t*)f->vals0.p,
+                                       (uint64_t*)f->keys1.p, (uint32_t*)f->vals1.p, (uint64_t*)f->keys0.p,
+                                       (uint32_t*)f->vals0.p, (int64_t)K, passes, 0, ws, stream),
+                    "key sort");
+        f->res_keys = (const uint64_t*)(odd ? f->keys1.p : f->keys0.p);
+        f->res_tiles = reinterpret_cast<const uint32_t*>(f->res_keys) + 1;  // high words
+        f->res_tile_stride = 2;
+    }
+    f->res_values = (const uint32_t*)(odd ? f->vals1.p : f->vals0.p);
+    CDS_TRY(f->record(4, stream));
+    f->n = n;
+    f->K = (int64_t)K;
+    f->width = cam->width;
+    f->height = cam->height;
+    f->tiles_x = P.tiles_x;
+    f->tiles_y = P.tiles_y;
+    f->passes = sort_variant == 0 ? 4 + tile_passes : passes;
+    f->sort_variant = sort_variant;
+    CDS_HIP(launch_ranges(f->res_tiles, f->res_tile_stride, (int64_t)K, (uint2*)f->ranges.p, ntiles, stream),
+            "ranges kernel");
+    CDS_TRY(f->record(5, stream));
+
+    BlendArgs ba;
+    ba.ranges = (const uint2*)f->ranges.p;
+    ba.point_list = f->res_values;
+    ba.mean2d = sb.mean2d;
+    ba.conic_opacity = sb.conic_opacity;
+    ba.rgb = sb.rgb;
+    ba.width = cam->width;
+    ba.height = cam->height;
+    ba.tiles_x = P.tiles_x;
+    ba.tiles_y = P.tiles_y;
+    for (int k = 0; k < 3; ++k) ba.bg[k] = cam->bg[k];
+    ba.out_rgb = out_rgb;
+    ba.out_T = out_T;
+    ba.out_ncontrib = out_ncontrib;
+    CDS_HIP(launch_blend(ba, blend_variant, stream), "blend kernel");
+    CDS_TRY(f->record(6, stream));
+    f->valid = true;
+    return CDS_OK;
+}
+
+// Build the 64-bit sorted keys of a variant-0 render (for inspection).
+cds_status frame_build_keys(cds_frame* f) {
+    if (f->res_keys || f->K == 0) return CDS_OK;
+    CDS_TRY(ensure(f->ctx, f->keys0, sizeof(uint64_t) * (size_t)f->K, 1.25));
+    CDS_HIP(launch_make_keys(f->res_tiles, f->res_values, (const uint32_t*)f->depth.p, f->K,
+                             (uint64_t*)f->keys0.p, nullptr),
+            "make keys");
+    CDS_HIP(hipStreamSynchronize(nullptr), "hipStreamSynchronize");
+    f->res_keys = (const uint64_t*)f->keys0.p;
+    return CDS_OK;
+}
+
+cds_status render_backward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scene, const cds_camera* cam,
+                                const float* out_T, const uint32_t* out_ncontrib, const float* dL_drgb,
+                                const cds_scene_grad* g, hipStream_t stream) {
+    const int64_t n = scene->n;
+    if (n == 0) return CDS_OK;
+    const ProjParams P = make_proj(scene, cam);
+    CDS_TRY(ensure(ctx, f->grad2d, sizeof(float) * 9 * (size_t)n, 1.1));
+    CDS_TRY(f->record(7, stream));
+    CDS_HIP(launch_fill_u32((uint32_t*)f->grad2d.p, 9 * n, 0u, stream), "fill");
+    BlendBwdArgs b;
+    b.ranges = (const uint2*)f->ranges.p;
+    b.point_list = f->res_values;
+    b.mean2d = (const float2*)f->mean2d.p;
+    b.conic_opacity = (const float4*)f->conic.p;
+    b.rgb = (const float4*)f->rgb.p;
+    b.width = f->width;
+    b.height = f->height;
+    b.tiles_x = f->tiles_x;
+    b.tiles_y = f->tiles_y;
+    for (int k = 0; k < 3; ++k) b.bg[k] = cam->bg[k];
+    b.final_T = out_T;
+    b.ncontrib = out_ncontrib;
+    b.dL_drgb = dL_drgb;
+    b.n = n;
+    b.grad2d = (float*)f->grad2d.p;
+    CDS_HIP(launch_blend_backward(b, stream), "blend backward kernel");
+    CDS_TRY(f->record(8, stream));
+    PreBwdArgs pa;
+    pa.radius = (const int32_t*)f->radius.p;
+    pa.clamp_flags = (const uint8_t*)f->clampf.p;
+    pa.grad2d = (const float*)f->grad2d.p;
+    pa.g_means = g->means;
+    pa.g_log_scales = g->log_scales;
+    pa.g_quats = g->quats;
+    pa.g_opacity_logits = g->opacity_logits;
+    pa.g_sh = g->sh;
+    CDS_HIP(launch_preprocess_backward(P, make_scene(scene), pa, stream), "preprocess backward kernel");
+    CDS_TRY(f->record(9, stream));
+    f->timed_backward = f->timing;
+    return CDS_OK;
+}
+
+}  // namespace cds
+
+void cds_frame::release_all() {
+    cds::release_frame_buffers(this);
+    cds::release_frame_events(this);
+}
+
+cds_status cds_frame::record(int i, hipStream_t s) {
+    if (!timing) return CDS_OK;
+    hipError_t e;
+    if (!ev[i] && (e = hipEventCreate(&ev[i])) != hipSuccess) return cds::hip_fail(e, "hipEventCreate");
+    if ((e = hipEventRecord(ev[i], s)) != hipSuccess) return cds::hip_fail(e, "hipEventRecord");
+    return CDS_OK;
+}
+
+extern "C" cds_status cds_frame_stage_times(cds_frame* f, cds_stage_times* out) {
+    if (!f || !out) return cds::fail(CDS_ERR_INVALID_ARG, "NULL argument");
+    if (!f->valid || !f->timing) return cds::fail(CDS_ERR_INVALID_ARG, "frame has no timed render");
+    hipError_t e = hipSetDevice(f->ctx->device);
+    if (e != hipSuccess) return cds::hip_fail(e, "hipSetDevice");
+    const int last = f->timed_backward ? 9 : 6;
+    if ((e = hipEventSynchronize(f->ev[last])) != hipSuccess) return cds::hip_fail(e, "hipEventSynchronize");
+    float ms[9] = {};
+    for (int i = 0; i < last; ++i) {
+        if (i == 6) continue;  // gap between the forward and the backward
+        if ((e = hipEventElapsedTime(&ms[i], f->ev[i], f->ev[i + 1])) != hipSuccess)
+            return cds::hip_fail(e, "hipEventElapsedTime");
+    }
+    out->preprocess_ms = ms[0];
+    out->scan_ms = ms[1];
+    out->duplicate_ms = ms[2];
+    out->sort_ms = ms[3];
+    out->ranges_ms = ms[4];
+    out->blend_ms = ms[5];
+    out->blend_backward_ms = f->timed_backward ? ms[7] : 0.f;
+    out->preprocess_backward_ms = f->timed_backward ? ms[8] : 0.f;
+    return CDS_OK;
+}

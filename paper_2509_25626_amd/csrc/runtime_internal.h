@@ -1,0 +1,86 @@
+// Host-side state shared by the runtime translation units.
+#pragma once
+#include <string>
+
+#include "cdnasplat.h"
+#include "internal.h"
+
+namespace cds {
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+struct SortState {
+    DevBuf hist, status, counters;
+};
+
+}  // namespace cds
+
+struct cds_ctx {
+    int device = 0;
+    cds_allocator alloc{};
+    bool has_alloc = false;
+    uint64_t* host_pinned = nullptr;  // pinned host words for the per-render key count
+    uint32_t* d_err = nullptr;        // device-side error word
+    cds_frame* scratch = nullptr;     // buffers of the stand-alone sort / scan calls
+};
+
+struct cds_frame {
+    cds_ctx* ctx = nullptr;
+    // per Gaussian
+    cds::DevBuf mean2d, conic, rgb, depth, radius, rect, touched, offsets, clampf;
+    cds::DevBuf blocksums, total;
+    cds::DevBuf order0, order1, dkey0, dkey1;  // per-Gaussian depth sort (sort variant 0)
+    cds::SortState sort_d;
+    // per key
+    cds::DevBuf keys0, keys1;                  // 64-bit keys (variant 1; variant 0: rebuilt on request)
+    cds::DevBuf tk0, tk1;                      // 32-bit tile ids (variant 0)
+    cds::DevBuf vals0, vals1;
+    cds::SortState sort;
+    // per tile
+    cds::DevBuf ranges;
+    // backward
+    cds::DevBuf grad2d;
+    int64_t n = 0, K = 0;
+    int32_t width = 0, height = 0, tiles_x = 0, tiles_y = 0, passes = 0, sort_variant = 0;
+    bool valid = false;
+    // where the last render left its sorted list
+    const uint32_t* res_values = nullptr;
+    const uint32_t* res_tiles = nullptr;  // tile id words, stride res_tile_stride
+    int res_tile_stride = 1;
+    const uint64_t* res_keys = nullptr;   // 64-bit keys, null until built (variant 0)
+    // stage timing: events 0..6 bracket the forward stages, 7..9 the backward
+    bool timing = false, timed_backward = false;
+    hipEvent_t ev[10] = {};
+    cds_status record(int i, hipStream_t s);
+    void release_all();
+};
+
+namespace cds {
+
+extern thread_local std::string g_last_error;
+cds_status fail(cds_status s, const std::string& msg);
+cds_status hip_fail(hipError_t e, const char* what);
+void* ctx_alloc(cds_ctx* c, size_t bytes);
+void ctx_free(cds_ctx* c, void* p);
+cds_status ensure(cds_ctx* c, DevBuf& b, size_t bytes, double grow = 1.0);
+void release(cds_ctx* c, DevBuf& b);
+cds_status validate_scene(const cds_scene* s);
+cds_status validate_camera(const cds_camera* c);
+ProjParams make_proj(const cds_scene* s, const cds_camera* c);
+SceneParams make_scene(const cds_scene* s);
+cds_status ensure_sort_workspace(cds_ctx* ctx, SortState& s, int64_t count, int passes);
+SortWorkspace sort_ws(cds_ctx* ctx, SortState& s);
+
+cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scene, const cds_camera* cam,
+                               int blend_variant, int sort_variant, float* out_rgb, float* out_T,
+                               uint32_t* out_ncontrib, hipStream_t stream);
+int tile_bits_for(int64_t ntiles);
+cds_status frame_build_keys(cds_frame* f);
+cds_status render_backward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scene, const cds_camera* cam,
+                                const float* out_T, const uint32_t* out_ncontrib, const float* dL_drgb,
+                                const cds_scene_grad* g, hipStream_t stream);
+
+}  // namespace cds

@@ -1,0 +1,114 @@
+// Exclusive prefix sum of per-Gaussian tile counts -> key offsets and the
+// total number of keys ("bounds and ranges" preparation, paper Section II-B).
+// The input may be read through a gather index (tile counts in depth order).
+// Reduce-then-scan over 4096-element tiles: per-tile sums, a single-block
+// scan of the sums, then a rescan that adds each tile's prefix.  Totals are
+// kept in 64 bits so an overflow of the 32-bit key space is detected.
+#include "device_utils.h"
+#include "internal.h"
+
+namespace cds {
+namespace {
+
+constexpr int kNT = 256;
+constexpr int kIPT = 16;
+constexpr int64_t kTileItems = (int64_t)kNT * kIPT;
+
+// in[gather[i]] when `gather` is given, else in[i]
+__device__ __forceinline__ uint32_t scan_in(const uint32_t* __restrict__ in, const uint32_t* __restrict__ gather,
+                                            int64_t i) {
+    return gather ? in[gather[i]] : in[i];
+}
+
+__global__ __launch_bounds__(kNT) void k_scan_reduce(const uint32_t* __restrict__ in,
+                                                     const uint32_t* __restrict__ gather, int64_t n,
+                                                     uint64_t* __restrict__ sums) {
+    __shared__ uint32_t scratch[kNT / kWave];
+    const int64_t base = (int64_t)blockIdx.x * kTileItems;
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kIPT; ++k) {
+        const int64_t idx = base + (int64_t)k * kNT + threadIdx.x;
+        if (idx < n) s += scan_in(in, gather, idx);
+    }
+    uint32_t total;
+    block_excl_sum<kNT>(s, scratch, &total);
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// One block scans the tile sums (exclusive, in place) and writes the total.
+__global__ __launch_bounds__(1024) void k_scan_sums(uint64_t* __restrict__ sums, int64_t count,
+                                                    uint64_t* __restrict__ total) {
+    __shared__ uint64_t wsum[1024 / kWave];
+    __shared__ uint64_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < count; base += 1024) {
+        const int64_t idx = base + threadIdx.x;
+        const uint64_t v = idx < count ? sums[idx] : 0;
+        // inclusive wave scan in 64 bits
+        uint64_t inc = v;
+        const uint32_t l = lane_id();
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            uint64_t t = __shfl_up(inc, (unsigned)o, kWave);
+            if (l >= (uint32_t)o) inc += t;
+        }
+        const int w = threadIdx.x / kWave;
+        if (l == kWave - 1) wsum[w] = inc;
+        __syncthreads();
+        uint64_t before = 0, all = 0;
+        for (int k = 0; k < 1024 / kWave; ++k) {
+            before += (k < w) ? wsum[k] : 0;
+            all += wsum[k];
+        }
+        const uint64_t c = carry;
+        if (idx < count) sums[idx] = c + before + inc - v;
+        __syncthreads();
+        if (threadIdx.x == 0) carry = c + all;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ __launch_bounds__(kNT) void k_scan_down(const uint32_t* __restrict__ in,
+                                                   const uint32_t* __restrict__ gather, int64_t n,
+                                                   const uint64_t* __restrict__ sums,
+                                                   uint32_t* __restrict__ out) {
+    __shared__ uint32_t scratch[kNT / kWave];
+    // blocked arrangement: thread t owns items [t*kIPT, (t+1)*kIPT) of the tile
+    const int64_t base = (int64_t)blockIdx.x * kTileItems + (int64_t)threadIdx.x * kIPT;
+    uint32_t v[kIPT];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kIPT; ++k) {
+        v[k] = (base + k < n) ? scan_in(in, gather, base + k) : 0u;
+        s += v[k];
+    }
+    uint32_t run = block_excl_sum<kNT>(s, scratch, nullptr) + (uint32_t)sums[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kIPT; ++k) {
+        if (base + k < n) out[base + k] = run;
+        run += v[k];
+    }
+}
+
+}  // namespace
+
+int64_t scan_block_sums_size(int64_t n) { return (n + kTileItems - 1) / kTileItems + 1; }
+
+hipError_t launch_exclusive_scan(const uint32_t* in, const uint32_t* gather, uint32_t* out, int64_t n,
+                                 uint64_t* block_sums, uint64_t* total, hipStream_t stream) {
+    const int64_t tiles = (n + kTileItems - 1) / kTileItems;
+    if (tiles > 0) {
+        hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)tiles), dim3(kNT), 0, stream, in, gather, n, block_sums);
+    }
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, stream, block_sums, tiles, total);
+    if (tiles > 0) {
+        hipLaunchKernelGGL(k_scan_down, dim3((unsigned)tiles), dim3(kNT), 0, stream, in, gather, n, block_sums,
+                           out);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace cds

@@ -1,0 +1,298 @@
+// Stable LSD radix sort of (64-bit key, 32-bit value) pairs, 8-bit digits,
+// one "onesweep" kernel per digit (the per-tile depth sort of paper
+// Section II-B(1), done as one global sort of (tile | depth) keys).
+//
+// Per pass, each workgroup (256 threads, 4096 keys) takes the next partition
+// id from an atomic counter (so every lower id belongs to a workgroup that is
+// already running), ranks its keys stably in LDS, publishes its per-digit
+// counts, and finds the per-digit count of all earlier partitions by
+// decoupled look-back over a status word per (partition, digit):
+//   bits 31..30 = 0 not ready, 1 partition count only, 2 inclusive prefix
+//   bits 29..0  = the count
+// Keys are then reordered in LDS by digit and written out so each digit run
+// is a contiguous, coalesced store.  Global digit offsets come from a
+// histogram of all keys computed before the first pass.
+//
+// Ranking is wave64-native: keys are held "wave-striped" (round r of a wave
+// covers 64 consecutive input keys), peers with the same digit are found
+// with eight ballots, and a per-wave, per-digit counter in LDS gives each key
+// its rank; processing rounds in order keeps the sort stable.
+//
+// The look-back wait is bounded: after ~2^22 polls a workgroup records an
+// error in the device error word and proceeds, so a logic error can only
+// corrupt the output, never hang the device.
+#include "device_utils.h"
+#include "internal.h"
+
+namespace cds {
+namespace {
+
+constexpr int kNT = kSortThreads;
+constexpr int kKPT = kSortKeysPerThread;
+constexpr int kP = kNT * kKPT;
+constexpr int kWaves = kNT / kWave;
+constexpr uint32_t kFlagAgg = 1u << 30;
+constexpr uint32_t kFlagIncl = 2u << 30;
+constexpr uint32_t kValueMask = (1u << 30) - 1;
+constexpr uint32_t kSpinLimit = 1u << 22;
+
+__global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, int64_t count,
+                                                  uint32_t value) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+// Digit histograms of `passes` 8-bit digits (starting at bit `shift0`) over all keys.
+template <typename Key>
+__global__ __launch_bounds__(256) void k_sort_histogram(const Key* __restrict__ keys, int64_t count,
+                                                        int passes, int shift0,
+                                                        uint32_t* __restrict__ hist) {
+    __shared__ uint32_t s_hist[8 * 256];
+    for (int k = threadIdx.x; k < passes * 256; k += blockDim.x) s_hist[k] = 0;
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const Key key = keys[i];
+        for (int p = 0; p < passes; ++p)
+            atomicAdd(&s_hist[p * 256 + (uint32_t)((key >> (shift0 + 8 * p)) & 255u)], 1u);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < passes * 256; k += blockDim.x) {
+        const uint32_t c = s_hist[k];
+        if (c) atomicAdd(&hist[k], c);
+    }
+}
+
+template <typename Key>
+struct PassArgs {
+    const Key* kin;
+    const uint32_t* vin;  // null: the value of input position i is i
+    Key* kout;
+    uint32_t* vout;
+    int64_t count;
+    int shift;
+    const uint32_t* hist;  // [256] digit counts of all keys
+    uint32_t* status;      // [partitions][256]
+    uint32_t* counter;     // partition-id counter
+    uint32_t* err;
+};
+
+template <typename Key>
+__global__ __launch_bounds__(kNT) void k_onesweep(PassArgs<Key> a) {
+    __shared__ Key s_keys[kP];                  // reorder buffer (keys, then values)
+    __shared__ uint32_t s_whist[kWaves][256];   // per-wave digit counters, then offsets
+    __shared__ uint32_t s_gbase[256];
+    __shared__ uint32_t s_scan[kWaves];
+    __shared__ uint32_t s_pid;
+
+    const int t = threadIdx.x;
+    const int w = t / kWave;
+    const uint32_t l = lane_id();
+    if (t == 0) s_pid = atomicAdd(a.counter, 1u);
+    for (int k = t; k < kWaves * 256; k += kNT) (&s_whist[0][0])[k] = 0;
+    __syncthreads();
+    const uint32_t pid = s_pid;
+    const int64_t base = (int64_t)pid * kP;
+    const int64_t wbase = base + (int64_t)w * (kWave * kKPT);
+
+    Key key[kKPT];
+    uint32_t val[kKPT];
+#pragma unroll
+    for (int r = 0; r < kKPT; ++r) {
+        const int64_t idx = wbase + r * kWave + l;
+        const bool valid = idx < a.count;
+        key[r] = valid ? a.kin[idx] : (Key)0;
+        val[r] = valid ? (a.vin ? a.vin[idx] : (uint32_t)idx) : 0u;
+    }
+
+    // stable wave-level ranking
+    uint32_t rank[kKPT];
+#pragma unroll
+    for (int r = 0; r < kKPT; ++r) {
+        const bool valid = (wbase + r * kWave + l) < a.count;
+        const uint32_t d = (uint32_t)(key[r] >> a.shift) & 255u;
+        uint64_t peers = ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t m = ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const uint32_t below = count_below(peers);
+        const uint32_t cnt = (uint32_t)__popcll(peers);
+        uint32_t pre = 0;
+        if (valid) pre = s_whist[w][d];
+        if (valid && below == 0) s_whist[w][d] = pre + cnt;
+        rank[r] = pre + below;
+    }
+    __syncthreads();
+
+    // thread t owns digit t
+    const uint32_t c0 = s_whist[0][t], c1 = s_whist[1][t], c2 = s_whist[2][t], c3 = s_whist[3][t];
+    static_assert(kWaves == 4, "digit bookkeeping assumes 4 waves");
+    const uint32_t tot = c0 + c1 + c2 + c3;
+    uint32_t* st = a.status + (size_t)pid * 256;
+    atomic_store_agent(st + t, (pid == 0 ? kFlagIncl : kFlagAgg) | tot);
+
+    const uint32_t bstart = block_excl_sum<kNT>(tot, s_scan, nullptr);
+    const uint32_t gstart = block_excl_sum<kNT>(a.hist[t], s_scan, nullptr);
+
+    uint32_t excl = 0;
+    if (pid > 0) {
+        int64_t p = (int64_t)pid - 1;
+        uint32_t spins = 0;
+        while (p >= 0) {
+            const uint32_t s = atomic_load_agent(a.status + (size_t)p * 256 + t);
+            const uint32_t f = s & ~kValueMask;
+            if (f == 0u) {
+                if (++spins > kSpinLimit) {
+                    atomicOr(a.err, 1u);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+                continue;
+            }
+            excl += s & kValueMask;
+            if (f == kFlagIncl) break;
+            --p;
+        }
+        atomic_store_agent(st + t, kFlagIncl | ((excl + tot) & kValueMask));
+    }
+    s_whist[0][t] = bstart;
+    s_whist[1][t] = bstart + c0;
+    s_whist[2][t] = bstart + c0 + c1;
+    s_whist[3][t] = bstart + c0 + c1 + c2;
+    s_gbase[t] = gstart + excl - bstart;
+    __syncthreads();
+
+    // reorder keys by digit in LDS
+#pragma unroll
+    for (int r = 0; r < kKPT; ++r) {
+        const bool valid = (wbase + r * kWave + l) < a.count;
+        if (valid) {
+            const uint32_t d = (uint32_t)(key[r] >> a.shift) & 255u;
+            const uint32_t pos = s_whist[w][d] + rank[r];
+            if (pos < (uint32_t)kP) s_keys[pos] = key[r];
+        }
+    }
+    __syncthreads();
+    const int64_t rem = a.count - base;
+    const uint32_t nvalid = rem < kP ? (uint32_t)rem : (uint32_t)kP;
+    uint32_t gpos[kKPT];
+#pragma unroll
+    for (int r = 0; r < kKPT; ++r) {
+        const uint32_t i = (uint32_t)(r * kNT + t);
+        gpos[r] = 0;
+        if (i < nvalid) {
+            const Key k = s_keys[i];
+            const uint32_t d = (uint32_t)(k >> a.shift) & 255u;
+            const uint32_t g = s_gbase[d] + i;
+            // a position outside the output can only come from an inconsistent
+            // histogram or look-back; record it instead of writing out of bounds
+            if ((int64_t)g < a.count) a.kout[g] = k;
+            else atomicOr(a.err, 2u);
+            gpos[r] = g;
+        }
+    }
+    __syncthreads();
+    // the values follow the same permutation
+    uint32_t* s_vals = reinterpret_cast<uint32_t*>(s_keys);
+#pragma unroll
+    for (int r = 0; r < kKPT; ++r) {
+        const bool valid = (wbase + r * kWave + l) < a.count;
+        if (valid) {
+            const uint32_t d = (uint32_t)(key[r] >> a.shift) & 255u;
+            const uint32_t pos = s_whist[w][d] + rank[r];
+            if (pos < (uint32_t)kP) s_vals[pos] = val[r];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kKPT; ++r) {
+        const uint32_t i = (uint32_t)(r * kNT + t);
+        if (i < nvalid && (int64_t)gpos[r] < a.count) a.vout[gpos[r]] = s_vals[i];
+    }
+}
+
+template <typename Key>
+hipError_t sort_histogram_impl(const Key* keys, int64_t count, int passes, int shift0, uint32_t* hist,
+                               hipStream_t stream) {
+    if (count <= 0) return hipSuccess;
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(k_sort_histogram<Key>, dim3((unsigned)blocks), dim3(256), 0, stream, keys, count,
+                       passes, shift0, hist);
+    return hipGetLastError();
+}
+
+template <typename Key>
+hipError_t sort_passes_impl(const Key* kin, const uint32_t* vin, Key* ka, uint32_t* va, Key* kb,
+                            uint32_t* vb, int64_t count, int passes, int shift0, const SortWorkspace& ws,
+                            hipStream_t stream) {
+    if (count <= 0 || passes <= 0) return hipSuccess;
+    if (count > kSortMaxCount) return hipErrorInvalidValue;
+    const int64_t parts = sort_partitions(count);
+    for (int p = 0; p < passes; ++p) {
+        PassArgs<Key> a;
+        a.kin = p == 0 ? kin : ((p & 1) ? ka : kb);
+        a.vin = p == 0 ? vin : ((p & 1) ? va : vb);
+        a.kout = (p & 1) ? kb : ka;
+        a.vout = (p & 1) ? vb : va;
+        a.count = count;
+        a.shift = shift0 + 8 * p;
+        a.hist = ws.hist + (size_t)p * 256;
+        a.status = ws.status + (size_t)p * parts * 256;
+        a.counter = ws.counters + p;
+        a.err = ws.err;
+        hipLaunchKernelGGL(k_onesweep<Key>, dim3((unsigned)parts), dim3(kNT), 0, stream, a);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t launch_fill_u32(uint32_t* p, int64_t count, uint32_t value, hipStream_t stream) {
+    if (count <= 0) return hipSuccess;
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, stream, p, count, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_sort_histogram(const uint64_t* keys, int64_t count, int passes, int shift0, uint32_t* hist,
+                                 hipStream_t stream) {
+    return sort_histogram_impl<uint64_t>(keys, count, passes, shift0, hist, stream);
+}
+
+hipError_t launch_sort_histogram(const uint32_t* keys, int64_t count, int passes, int shift0, uint32_t* hist,
+                                 hipStream_t stream) {
+    return sort_histogram_impl<uint32_t>(keys, count, passes, shift0, hist, stream);
+}
+
+hipError_t launch_sort_prepare(const SortWorkspace& ws, int64_t count, int passes, bool clear_hist,
+                               hipStream_t stream) {
+    const int64_t parts = sort_partitions(count);
+    hipError_t e = launch_fill_u32(ws.status, (int64_t)passes * parts * 256, 0u, stream);
+    if (e != hipSuccess) return e;
+    e = launch_fill_u32(ws.counters, passes, 0u, stream);
+    if (e != hipSuccess) return e;
+    if (clear_hist) e = launch_fill_u32(ws.hist, (int64_t)passes * 256, 0u, stream);
+    return e;
+}
+
+hipError_t launch_sort_passes(const uint64_t* kin, const uint32_t* vin, uint64_t* ka, uint32_t* va,
+                              uint64_t* kb, uint32_t* vb, int64_t count, int passes, int shift0,
+                              const SortWorkspace& ws, hipStream_t stream) {
+    return sort_passes_impl<uint64_t>(kin, vin, ka, va, kb, vb, count, passes, shift0, ws, stream);
+}
+
+hipError_t launch_sort_passes(const uint32_t* kin, const uint32_t* vin, uint32_t* ka, uint32_t* va,
+                              uint32_t* kb, uint32_t* vb, int64_t count, int passes, int shift0,
+                              const SortWorkspace& ws, hipStream_t stream) {
+    return sort_passes_impl<uint32_t>(kin, vin, ka, va, kb, vb, count, passes, shift0, ws, stream);
+}
+
+}  // namespace cds
