@@ -106,7 +106,9 @@ typedef struct cds_camera {
 
 /* Render options (HOST struct; NULL means all defaults). */
 #define CDS_OPT_DEFAULT 0u
-#define CDS_OPT_STAGE_TIMING 1u  /* record HIP events around every stage (forward and backward) */
+#define CDS_OPT_STAGE_TIMING 1u      /* record HIP events around every stage (forward and backward) */
+#define CDS_OPT_SORT_ONESWEEP 2u      /* radix-sort passes by decoupled look-back (default: by size) */
+#define CDS_OPT_SORT_REDUCE_SCAN 4u   /* radix-sort passes by reduce-then-scan (default: by size) */
 typedef struct cds_render_opts {
     uint32_t flags;         /* CDS_OPT_* bits */
     int32_t blend_variant;  /* 0 = default; 1, 2, 4 = pixels per thread of the blend kernel */
@@ -221,11 +223,12 @@ cds_status cds_frame_stage_times(cds_frame* frame, cds_stage_times* out);
  * Stand-alone stable LSD radix sort of (key, value) pairs on key bits
  * [0, end_bit), the sort the forward render uses.  All arrays DEVICE,
  * `count` elements; the inputs are not modified; outputs may not alias
- * inputs.  Equal keys keep their input order.
+ * inputs.  Equal keys keep their input order.  `flags`: 0 or one of
+ * CDS_OPT_SORT_ONESWEEP / CDS_OPT_SORT_REDUCE_SCAN.
  */
 cds_status cds_sort_pairs(cds_ctx* ctx, const uint64_t* keys_in, const uint32_t* values_in,
                           int64_t count, int32_t end_bit, uint64_t* keys_out,
-                          uint32_t* values_out, void* stream);
+                          uint32_t* values_out, uint32_t flags, void* stream);
 
 /*
  * Stand-alone exclusive prefix sum of `count` uint32 (DEVICE in/out, may not

@@ -61,17 +61,20 @@ __device__ __forceinline__ bool splat_alpha(double adx2, double bdx, double c2, 
     return !(alpha < kAlphaMin);
 }
 
+// One 16x16 tile: stage its sorted splats through LDS in batches and blend
+// each pixel front to back.  Shared by the single-render kernel and the
+// persistent batched kernel so a request renders bit-identically in both.
+// Every thread of the workgroup must call it (it contains barriers).
 template <int PPT>
-__global__ __launch_bounds__(256 / PPT) void k_blend(BlendArgs a, uint32_t per_xcd) {
+__device__ __forceinline__ void blend_tile(int tx, int ty, int width, int height, uint2 range,
+                                           const uint32_t* __restrict__ point_list,
+                                           const float2* __restrict__ mean2d,
+                                           const float4* __restrict__ conic_opacity,
+                                           const float4* __restrict__ rgb, float bg0, float bg1, float bg2,
+                                           float* out_rgb, float* out_T, uint32_t* out_ncontrib, double4* s_q,
+                                           double* s_c, float4* s_f) {
     constexpr int NT = 256 / PPT;
-    __shared__ double4 s_q[kBatch];
-    __shared__ double s_c[kBatch];
-    __shared__ float4 s_f[kBatch];
-
-    const uint32_t tile = xcd_band(blockIdx.x, per_xcd);
-    if (tile >= (uint32_t)(a.tiles_x * a.tiles_y)) return;  // whole block: padding
     const int t = threadIdx.x;
-    const int tx = (int)(tile % (uint32_t)a.tiles_x), ty = (int)(tile / (uint32_t)a.tiles_x);
     const int px = tx * kTile + (t & 15);
     const int py0 = ty * kTile + (t >> 4) * PPT;
     const double fpx = (double)px;
@@ -86,10 +89,9 @@ __global__ __launch_bounds__(256 / PPT) void k_blend(BlendArgs a, uint32_t per_x
         C0[p] = C1[p] = C2[p] = 0.0f;
         last[p] = 0;
         fpy[p] = (double)(py0 + p);
-        done[p] = !(px < a.width && py0 + p < a.height);
+        done[p] = !(px < width && py0 + p < height);
     }
 
-    const uint2 range = a.ranges[tile];
     const int todo = (int)(range.y - range.x);
     for (int base = 0; base < todo; base += kBatch) {
         int alive = 0;
@@ -98,8 +100,7 @@ __global__ __launch_bounds__(256 / PPT) void k_blend(BlendArgs a, uint32_t per_x
         if (__syncthreads_count(alive) == 0) break;
         for (int k = t; k < kBatch; k += NT) {
             const int idx = base + k;
-            if (idx < todo)
-                stage_splat(a.mean2d, a.conic_opacity, a.rgb, a.point_list[range.x + idx], s_q, s_c, s_f, k);
+            if (idx < todo) stage_splat(mean2d, conic_opacity, rgb, point_list[range.x + idx], s_q, s_c, s_f, k);
         }
         __syncthreads();
         const int cnt = min(kBatch, todo - base);
@@ -136,18 +137,60 @@ __global__ __launch_bounds__(256 / PPT) void k_blend(BlendArgs a, uint32_t per_x
         }
     }
 
-    const int64_t npix = (int64_t)a.width * a.height;
+    const int64_t npix = (int64_t)width * height;
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
         const int py = py0 + p;
-        if (px < a.width && py < a.height) {
-            const int64_t pix = (int64_t)py * a.width + px;
-            a.out_T[pix] = T[p];
-            a.out_ncontrib[pix] = last[p];
-            a.out_rgb[pix] = fmaf(T[p], a.bg[0], C0[p]);
-            a.out_rgb[npix + pix] = fmaf(T[p], a.bg[1], C1[p]);
-            a.out_rgb[2 * npix + pix] = fmaf(T[p], a.bg[2], C2[p]);
+        if (px < width && py < height) {
+            const int64_t pix = (int64_t)py * width + px;
+            if (out_T) out_T[pix] = T[p];
+            if (out_ncontrib) out_ncontrib[pix] = last[p];
+            out_rgb[pix] = fmaf(T[p], bg0, C0[p]);
+            out_rgb[npix + pix] = fmaf(T[p], bg1, C1[p]);
+            out_rgb[2 * npix + pix] = fmaf(T[p], bg2, C2[p]);
         }
+    }
+}
+
+template <int PPT>
+__global__ __launch_bounds__(256 / PPT) void k_blend(BlendArgs a, uint32_t per_xcd) {
+    __shared__ double4 s_q[kBatch];
+    __shared__ double s_c[kBatch];
+    __shared__ float4 s_f[kBatch];
+    const uint32_t tile = xcd_band(blockIdx.x, per_xcd);
+    if (tile >= (uint32_t)(a.tiles_x * a.tiles_y)) return;  // whole block: padding
+    const int tx = (int)(tile % (uint32_t)a.tiles_x), ty = (int)(tile / (uint32_t)a.tiles_x);
+    blend_tile<PPT>(tx, ty, a.width, a.height, a.ranges[tile], a.point_list, a.mean2d, a.conic_opacity, a.rgb,
+                    a.bg[0], a.bg[1], a.bg[2], a.out_rgb, a.out_T, a.out_ncontrib, s_q, s_c, s_f);
+}
+
+// Persistent blend over every tile of a batch of renders: each workgroup
+// takes the next global tile id from an atomic counter until none is left
+// (every wave reaches the exit), finds the owning request by binary search
+// over the tile bases, and blends that tile.
+template <int PPT>
+__global__ __launch_bounds__(256 / PPT) void k_blend_batch(const BatchItem* __restrict__ items, int nitems,
+                                                           int64_t total_tiles, const uint2* __restrict__ ranges,
+                                                           const uint32_t* __restrict__ point_list,
+                                                           const float2* __restrict__ mean2d,
+                                                           const float4* __restrict__ conic_opacity,
+                                                           const float4* __restrict__ rgb, uint32_t* counter) {
+    __shared__ double4 s_q[kBatch];
+    __shared__ double s_c[kBatch];
+    __shared__ float4 s_f[kBatch];
+    __shared__ uint32_t s_tile;
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1u);
+        __syncthreads();
+        const uint32_t g = s_tile;
+        __syncthreads();  // every thread has read s_tile before it is overwritten
+        if ((int64_t)g >= total_tiles) break;
+        const int r = find_item_by_tile(items, nitems, g);
+        const BatchItem& it = items[r];
+        const uint32_t local = g - (uint32_t)it.tile_base;
+        const int tx = (int)(local % (uint32_t)it.P.tiles_x), ty = (int)(local / (uint32_t)it.P.tiles_x);
+        blend_tile<PPT>(tx, ty, it.P.width, it.P.height, ranges[g], point_list, mean2d, conic_opacity, rgb,
+                        it.bg[0], it.bg[1], it.bg[2], it.out_rgb, it.out_T, it.out_ncontrib, s_q, s_c, s_f);
     }
 }
 
@@ -320,6 +363,17 @@ hipError_t launch_blend(const BlendArgs& a, int variant, hipStream_t stream) {
         case 4: hipLaunchKernelGGL(k_blend<4>, grid, dim3(64), 0, stream, a, per); break;
         default: hipLaunchKernelGGL(k_blend<2>, grid, dim3(128), 0, stream, a, per); break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_blend_batch(const BatchItem* items, int nitems, int64_t total_tiles, const uint2* ranges,
+                              const uint32_t* point_list, const float2* mean2d, const float4* conic_opacity,
+                              const float4* rgb, uint32_t* counter, int grid, hipStream_t stream) {
+    if (total_tiles == 0) return hipSuccess;
+    hipError_t e = launch_fill_u32(counter, 1, 0u, stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_blend_batch<2>, dim3((unsigned)grid), dim3(128), 0, stream, items, nitems, total_tiles,
+                       ranges, point_list, mean2d, conic_opacity, rgb, counter);
     return hipGetLastError();
 }
 

@@ -8,11 +8,11 @@
 // latter case only the 32-bit tile ids are written (the depth digits are
 // already sorted) and the 64-bit keys can be rebuilt from the values.
 //
-// Load balance: a workgroup takes 256 consecutive visit positions and spreads
-// their combined output evenly over its 256 lanes (lane e writes outputs
-// e, e+256, ...; the owner of an output is found by binary search over the
-// group's offsets in LDS), so a Gaussian covering thousands of tiles costs
-// the group the same as many small ones and every store is coalesced.
+// Work split: each wave takes 64 consecutive visit positions and emits their
+// Gaussians one after another, each Gaussian's keys spread over the 64 lanes
+// (lane c writes keys c, c+64, ...), so stores are coalesced and a Gaussian
+// covering thousands of tiles keeps the whole wave busy; the Gaussian's
+// rectangle and offset are broadcast from its lane with readlane.
 //
 // The same pass builds the radix-sort digit histograms without touching each
 // key: depth digits are per Gaussian (weight = tiles touched), and the tile
@@ -42,6 +42,8 @@ struct DupArgs {
     uint32_t* hist;            // [passes][256] or null
     int depth_passes;          // leading depth-digit passes in hist (0 or 4)
     int tile_passes;           // following tile-digit passes
+    const BatchItem* items;    // batched render: per-scene tile layout (null: one scene)
+    int nitems;
 };
 
 // +1 for every value v in [v0, v0 + len) on the histogram of (v >> shift) & 255.
@@ -75,81 +77,79 @@ __device__ __forceinline__ void add_run(uint32_t* s_hist, int* s_diff, uint32_t*
 }
 
 __global__ __launch_bounds__(kNT) void k_duplicate(DupArgs A) {
-    __shared__ uint32_t s_start[kNT];
-    __shared__ uint2 s_rect[kNT];
-    __shared__ uint32_t s_depth[kNT];
-    __shared__ uint32_t s_gid[kNT];
     __shared__ uint32_t s_hist[kMaxPasses * 256];
     __shared__ int s_diff[kMaxPasses * 257];
     __shared__ uint32_t s_all[kMaxPasses];
-    __shared__ uint32_t s_range[2];
     const int t = threadIdx.x;
+    const uint32_t lane = lane_id();
     const bool do_hist = A.hist != nullptr;
     const int passes = A.depth_passes + A.tile_passes;
     if (do_hist) {
         for (int k = t; k < passes * 256; k += kNT) s_hist[k] = 0;
         for (int k = t; k < passes * 257; k += kNT) s_diff[k] = 0;
         if (t < kMaxPasses) s_all[t] = 0;
+        __syncthreads();
     }
     const int64_t n = A.n;
-    const int64_t groups = (n + kNT - 1) / kNT;
-    for (int64_t g = blockIdx.x; g < groups; g += gridDim.x) {
-        const int64_t j = g * kNT + t;
-        // positions past the end get the largest start so the binary search
-        // below never selects them
-        uint32_t off = 0xFFFFFFFFu, cnt = 0, gid = 0;
+    const uint32_t tiles_x = (uint32_t)A.tiles_x;
+    const int64_t wave = (int64_t)blockIdx.x * (kNT / kWave) + t / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * (kNT / kWave);
+    for (int64_t base = wave * kWave; base < n; base += nwaves * kWave) {
+        const int64_t j = base + lane;
+        uint32_t off = 0, cnt = 0, gid = 0, depth = 0, tx_n = tiles_x, tbase = 0;
+        uint2 r = make_uint2(0u, 0u);
         if (j < n) {
             gid = A.order ? A.order[j] : (uint32_t)j;
             off = A.offsets[j];
             cnt = A.touched[gid];
-        }
-        __syncthreads();  // the previous group finished reading the LDS arrays
-        if (t == 0) s_range[0] = off;
-        const int64_t last = (g * kNT + kNT - 1 < n) ? (g * kNT + kNT - 1) : (n - 1);
-        if (j == last) s_range[1] = off + cnt;
-        s_start[t] = off;
-        if (cnt) {
-            const uint2 r = A.rect[gid];
-            const uint32_t depth = A.depth_bits[gid];
-            s_rect[t] = r;
-            s_depth[t] = depth;
-            s_gid[t] = gid;
-            if (do_hist) {
-                for (int p = 0; p < A.depth_passes; ++p)
-                    atomicAdd(&s_hist[p * 256 + ((depth >> (8 * p)) & 255u)], cnt);
-                const uint32_t x0 = r.x & 0xFFFFu, y0 = r.x >> 16, x1 = r.y & 0xFFFFu, y1 = r.y >> 16;
-                for (uint32_t ty = y0; ty <= y1; ++ty) {
-                    const uint32_t t0 = ty * (uint32_t)A.tiles_x + x0;
-                    for (int q = 0; q < A.tile_passes; ++q)
-                        add_run(s_hist, s_diff, s_all, A.depth_passes + q, 8 * q, t0, x1 - x0 + 1);
+            if (cnt) {
+                r = A.rect[gid];
+                depth = A.depth_bits[gid];
+                if (A.items) {
+                    const int it = find_item_by_gaussian(A.items, A.nitems, gid);
+                    tx_n = (uint32_t)A.items[it].P.tiles_x;
+                    tbase = (uint32_t)A.items[it].tile_base;
                 }
             }
         }
-        __syncthreads();
-        const uint32_t gbase = s_range[0];
-        const uint32_t total = s_range[1] - gbase;
-        for (uint32_t e = t; e < total; e += kNT) {
-            const uint32_t pos = gbase + e;
-            // owner: last lane with s_start <= pos (zero-count lanes share the
-            // start of the next one and are skipped by taking the last)
-            int lo = 0, hi = kNT - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (s_start[mid] <= pos) lo = mid; else hi = mid - 1;
-            }
-            const uint2 r = s_rect[lo];
-            const uint32_t x0 = r.x & 0xFFFFu, y0 = r.x >> 16, x1 = r.y & 0xFFFFu;
+        uint64_t todo = ballot(cnt != 0);
+        while (todo) {
+            // one Gaussian at a time, its keys spread over the 64 lanes
+            const int src = __builtin_ctzll(todo);
+            todo &= todo - 1;
+            const uint32_t g_off = __builtin_amdgcn_readlane(off, src);
+            const uint32_t g_cnt = __builtin_amdgcn_readlane(cnt, src);
+            const uint32_t g_id = __builtin_amdgcn_readlane(gid, src);
+            const uint32_t g_depth = __builtin_amdgcn_readlane(depth, src);
+            const uint32_t rx = __builtin_amdgcn_readlane(r.x, src);
+            const uint32_t ry = __builtin_amdgcn_readlane(r.y, src);
+            const uint32_t g_tx = __builtin_amdgcn_readlane(tx_n, src);
+            const uint32_t g_tb = __builtin_amdgcn_readlane(tbase, src);
+            const uint32_t x0 = rx & 0xFFFFu, y0 = rx >> 16, x1 = ry & 0xFFFFu, y1 = ry >> 16;
             const uint32_t w = x1 - x0 + 1;
-            const uint32_t local = pos - s_start[lo];
-            // local / w via a float estimate and an exact integer fix-up
-            uint32_t q = (uint32_t)((float)local * __frcp_rn((float)w));
-            int32_t rem = (int32_t)local - (int32_t)(q * w);
-            while (rem < 0) { --q; rem += (int32_t)w; }
-            while (rem >= (int32_t)w) { ++q; rem -= (int32_t)w; }
-            const uint32_t tile = (y0 + q) * (uint32_t)A.tiles_x + (x0 + (uint32_t)rem);
-            if (A.keys64) A.keys64[pos] = ((uint64_t)tile << 32) | (uint64_t)s_depth[lo];
-            if (A.tiles32) A.tiles32[pos] = tile;
-            A.values[pos] = s_gid[lo];
+            const float inv_w = __frcp_rn((float)w);
+            for (uint32_t c = lane; c < g_cnt; c += kWave) {
+                // c / w via a float estimate and an exact integer fix-up
+                uint32_t q = (uint32_t)((float)c * inv_w);
+                int32_t rem = (int32_t)c - (int32_t)(q * w);
+                while (rem < 0) { --q; rem += (int32_t)w; }
+                while (rem >= (int32_t)w) { ++q; rem -= (int32_t)w; }
+                const uint32_t tile = g_tb + (y0 + q) * g_tx + (x0 + (uint32_t)rem);
+                const uint32_t pos = g_off + c;
+                if (A.keys64) A.keys64[pos] = ((uint64_t)tile << 32) | (uint64_t)g_depth;
+                if (A.tiles32) A.tiles32[pos] = tile;
+                A.values[pos] = g_id;
+            }
+            if (do_hist) {
+                if (lane == 0)
+                    for (int p = 0; p < A.depth_passes; ++p)
+                        atomicAdd(&s_hist[p * 256 + ((g_depth >> (8 * p)) & 255u)], g_cnt);
+                for (uint32_t ty = y0 + lane; ty <= y1; ty += kWave) {
+                    const uint32_t t0 = g_tb + ty * g_tx + x0;
+                    for (int q = 0; q < A.tile_passes; ++q)
+                        add_run(s_hist, s_diff, s_all, A.depth_passes + q, 8 * q, t0, w);
+                }
+            }
         }
     }
     if (do_hist) {
@@ -192,7 +192,7 @@ __global__ __launch_bounds__(256) void k_make_keys(const uint32_t* __restrict__ 
 hipError_t launch_duplicate(int64_t n, const uint32_t* order, const uint32_t* offsets, const uint32_t* touched,
                             const uint2* rect, const uint32_t* depth_bits, int tiles_x, uint64_t* keys64,
                             uint32_t* tiles32, uint32_t* values, uint32_t* hist, int depth_passes,
-                            int tile_passes, hipStream_t stream) {
+                            int tile_passes, hipStream_t stream, const BatchItem* items, int nitems) {
     if (n == 0) return hipSuccess;
     if (depth_passes + tile_passes > kMaxPasses) return hipErrorInvalidValue;
     DupArgs A;
@@ -209,6 +209,8 @@ hipError_t launch_duplicate(int64_t n, const uint32_t* order, const uint32_t* of
     A.hist = hist;
     A.depth_passes = depth_passes;
     A.tile_passes = tile_passes;
+    A.items = items;
+    A.nitems = nitems;
     const int64_t groups = (n + kNT - 1) / kNT;
     const int64_t grid = groups < 2048 ? groups : 2048;
     hipLaunchKernelGGL(k_duplicate, dim3((unsigned)grid), dim3(kNT), 0, stream, A);

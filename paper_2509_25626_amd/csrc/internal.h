@@ -50,6 +50,40 @@ struct GradBuffers2D {  // [9][n]: mean x, mean y, conic A, B, C, opacity, r, g,
 hipError_t launch_preprocess(const ProjParams& p, const SceneParams& s, const SplatBuffers& out,
                              hipStream_t stream);
 
+// One request of a batched render: a scene, its camera, and where its
+// Gaussians and tiles sit in the batch's concatenated index spaces.
+struct BatchItem {
+    ProjParams P;
+    SceneParams S;
+    int64_t gauss_base;  // first global Gaussian index of this item
+    int64_t tile_base;   // first global tile id of this item
+    float bg[3];
+    float* out_rgb;
+    float* out_T;            // may be null
+    uint32_t* out_ncontrib;  // may be null
+};
+
+// Item owning global Gaussian g / global tile t (items sorted by base).
+__device__ __forceinline__ int find_item_by_gaussian(const BatchItem* items, int nitems, int64_t g) {
+    int lo = 0, hi = nitems - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (items[mid].gauss_base <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+__device__ __forceinline__ int find_item_by_tile(const BatchItem* items, int nitems, int64_t t) {
+    int lo = 0, hi = nitems - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (items[mid].tile_base <= t) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+hipError_t launch_preprocess_batch(const BatchItem* items, int nitems, int64_t total, const SplatBuffers& out,
+                                   hipStream_t stream);
+
 // Exclusive scan of n uint32 values (read as in[gather[i]] when gather is
 // not null); the total (uint64, device) is written too.  `block_sums` needs
 // scan_block_sums_size(n) uint64 elements.
@@ -64,7 +98,8 @@ hipError_t launch_exclusive_scan(const uint32_t* in, const uint32_t* gather, uin
 hipError_t launch_duplicate(int64_t n, const uint32_t* order, const uint32_t* offsets, const uint32_t* touched,
                             const uint2* rect, const uint32_t* depth_bits, int tiles_x, uint64_t* keys64,
                             uint32_t* tiles32, uint32_t* values, uint32_t* hist, int depth_passes,
-                            int tile_passes, hipStream_t stream);
+                            int tile_passes, hipStream_t stream, const BatchItem* items = nullptr,
+                            int nitems = 0);
 hipError_t launch_make_keys(const uint32_t* tiles, const uint32_t* values, const uint32_t* depth_bits,
                             int64_t count, uint64_t* keys, hipStream_t stream);
 
@@ -72,17 +107,24 @@ hipError_t launch_make_keys(const uint32_t* tiles, const uint32_t* values, const
 // vin) -- vin null means value = input position -- and the passes ping-pong
 // between (ka, va) and (kb, vb): the result is in (ka, va) after an odd
 // number of passes, in (kb, vb) after an even number.  kin may alias kb.
+enum class SortAlgo { kAuto, kOnesweep, kReduceScan };
 struct SortWorkspace {
-    uint32_t* hist;      // [passes][256]
-    uint32_t* status;    // [passes][partitions][256]
-    uint32_t* counters;  // [passes]
-    uint32_t* err;       // device error word
+    uint32_t* hist;       // onesweep: [passes][256] digit counts of all keys
+    uint32_t* status;     // onesweep: [passes][partitions][256]
+    uint32_t* counters;   // onesweep: [passes]
+    uint32_t* part_hist;  // reduce-then-scan: [256][partitions]
+    uint32_t* bases;      // reduce-then-scan: [256][partitions]
+    uint64_t* scan_sums;  // reduce-then-scan: scan_block_sums_size(256 * partitions)
+    uint64_t* scan_total;
+    uint32_t* err;        // device error word
 };
 constexpr int kSortThreads = 256;
 constexpr int kSortKeysPerThread = 16;
 constexpr int64_t kSortPartition = (int64_t)kSortThreads * kSortKeysPerThread;
 constexpr int64_t kSortMaxCount = (int64_t(1) << 30) - 1;
+constexpr int64_t kSortRtsMinPartitions = int64_t(1) << 40;  // auto: onesweep (measured faster at 80M keys)
 inline int64_t sort_partitions(int64_t count) { return (count + kSortPartition - 1) / kSortPartition; }
+bool sort_uses_onesweep(int64_t count, SortAlgo algo);
 hipError_t launch_sort_histogram(const uint64_t* keys, int64_t count, int passes, int shift0, uint32_t* hist,
                                  hipStream_t stream);
 hipError_t launch_sort_histogram(const uint32_t* keys, int64_t count, int passes, int shift0, uint32_t* hist,
@@ -91,10 +133,10 @@ hipError_t launch_sort_prepare(const SortWorkspace& ws, int64_t count, int passe
                                hipStream_t stream);
 hipError_t launch_sort_passes(const uint64_t* kin, const uint32_t* vin, uint64_t* ka, uint32_t* va,
                               uint64_t* kb, uint32_t* vb, int64_t count, int passes, int shift0,
-                              const SortWorkspace& ws, hipStream_t stream);
+                              const SortWorkspace& ws, SortAlgo algo, hipStream_t stream);
 hipError_t launch_sort_passes(const uint32_t* kin, const uint32_t* vin, uint32_t* ka, uint32_t* va,
                               uint32_t* kb, uint32_t* vb, int64_t count, int passes, int shift0,
-                              const SortWorkspace& ws, hipStream_t stream);
+                              const SortWorkspace& ws, SortAlgo algo, hipStream_t stream);
 
 hipError_t launch_fill_u32(uint32_t* p, int64_t count, uint32_t value, hipStream_t stream);
 
@@ -114,6 +156,12 @@ struct BlendArgs {
     uint32_t* out_ncontrib;
 };
 hipError_t launch_blend(const BlendArgs& a, int variant, hipStream_t stream);
+
+// Persistent blend over the tiles of a batch: workgroups pull global tile
+// ids from `counter` (zero on entry) until all `total_tiles` are done.
+hipError_t launch_blend_batch(const BatchItem* items, int nitems, int64_t total_tiles, const uint2* ranges,
+                              const uint32_t* point_list, const float2* mean2d, const float4* conic_opacity,
+                              const float4* rgb, uint32_t* counter, int grid, hipStream_t stream);
 
 struct BlendBwdArgs {
     const uint2* ranges;

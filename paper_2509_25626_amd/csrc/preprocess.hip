@@ -54,9 +54,9 @@ __device__ __forceinline__ void sh_basis_f32(float x, float y, float z, int degr
     b[15] = -kY3a * x * (xx - 3.0f * yy);
 }
 
-__global__ __launch_bounds__(256) void k_preprocess(ProjParams P, SceneParams S, SplatBuffers O) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= P.n) return;
+// Gaussian i of a scene with P.n Gaussians; outputs go to slot `o` of O.
+__device__ __forceinline__ void preprocess_one(const ProjParams& P, const SceneParams& S, int64_t i,
+                                               const SplatBuffers& O, int64_t o) {
     const int64_t n = P.n;
 
     const double m0 = S.means[i], m1 = S.means[n + i], m2 = S.means[2 * n + i];
@@ -148,14 +148,14 @@ __global__ __launch_bounds__(256) void k_preprocess(ProjParams P, SceneParams S,
     }
 
     if (!visible) {
-        O.mean2d[i] = make_float2(0.f, 0.f);
-        O.conic_opacity[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-        O.rgb[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-        O.depth_bits[i] = 0u;
-        O.radius[i] = 0;
-        O.rect[i] = make_uint2(0u, 0u);
-        O.touched[i] = 0u;
-        O.clamp_flags[i] = 0;
+        O.mean2d[o] = make_float2(0.f, 0.f);
+        O.conic_opacity[o] = make_float4(0.f, 0.f, 0.f, 0.f);
+        O.rgb[o] = make_float4(0.f, 0.f, 0.f, 0.f);
+        O.depth_bits[o] = 0u;
+        O.radius[o] = 0;
+        O.rect[o] = make_uint2(0u, 0u);
+        O.touched[o] = 0u;
+        O.clamp_flags[o] = 0;
         return;
     }
 
@@ -184,17 +184,41 @@ __global__ __launch_bounds__(256) void k_preprocess(ProjParams P, SceneParams S,
     }
 
     const float dzf = (float)tz;
-    O.mean2d[i] = make_float2(mxf, myf);
-    O.conic_opacity[i] = make_float4((float)A, (float)B, (float)C, opacity);
-    O.rgb[i] = make_float4(col[0], col[1], col[2], 0.f);
-    O.depth_bits[i] = __float_as_uint(dzf);
-    O.radius[i] = radius;
-    O.rect[i] = make_uint2(tx0 | (ty0 << 16), tx1 | (ty1 << 16));
-    O.touched[i] = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
-    O.clamp_flags[i] = flags;
+    O.mean2d[o] = make_float2(mxf, myf);
+    O.conic_opacity[o] = make_float4((float)A, (float)B, (float)C, opacity);
+    O.rgb[o] = make_float4(col[0], col[1], col[2], 0.f);
+    O.depth_bits[o] = __float_as_uint(dzf);
+    O.radius[o] = radius;
+    O.rect[o] = make_uint2(tx0 | (ty0 << 16), tx1 | (ty1 << 16));
+    O.touched[o] = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+    O.clamp_flags[o] = flags;
+}
+
+__global__ __launch_bounds__(256) void k_preprocess(ProjParams P, SceneParams S, SplatBuffers O) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P.n) return;
+    preprocess_one(P, S, i, O, i);
+}
+
+// Several scenes at once: global index g over the concatenated scenes of a
+// batch; each lane finds its scene by binary search over the item bases.
+__global__ __launch_bounds__(256) void k_preprocess_batch(const BatchItem* __restrict__ items, int nitems,
+                                                          int64_t total, SplatBuffers O) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    const int r = find_item_by_gaussian(items, nitems, g);
+    preprocess_one(items[r].P, items[r].S, g - items[r].gauss_base, O, g);
 }
 
 }  // namespace
+
+hipError_t launch_preprocess_batch(const BatchItem* items, int nitems, int64_t total, const SplatBuffers& out,
+                                   hipStream_t stream) {
+    if (total == 0) return hipSuccess;
+    const int64_t nb = (total + 255) / 256;
+    hipLaunchKernelGGL(k_preprocess_batch, dim3((unsigned)nb), dim3(256), 0, stream, items, nitems, total, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_preprocess(const ProjParams& p, const SceneParams& s, const SplatBuffers& out,
                              hipStream_t stream) {

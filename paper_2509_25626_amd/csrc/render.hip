@@ -54,7 +54,7 @@ int tile_bits_for(int64_t ntiles) {
  * direct sort of the 64-bit keys (variant 1), at a third of the key traffic.
  */
 cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scene, const cds_camera* cam,
-                               int blend_variant, int sort_variant, float* out_rgb, float* out_T,
+                               int blend_variant, int sort_variant, SortAlgo algo, float* out_rgb, float* out_T,
                                uint32_t* out_ncontrib, hipStream_t stream) {
     const int64_t n = scene->n;
     f->timed_backward = false;
@@ -100,10 +100,12 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
     const uint32_t* order = nullptr;
     if (sort_variant == 0 && n > 0) {
         SortWorkspace wd = sort_ws(ctx, f->sort_d);
-        CDS_HIP(launch_sort_prepare(wd, n, 4, true, stream), "depth sort prepare");
-        CDS_HIP(launch_sort_histogram(sb.depth_bits, n, 4, 0, wd.hist, stream), "depth sort histogram");
+        if (sort_uses_onesweep(n, algo)) {
+            CDS_HIP(launch_sort_prepare(wd, n, 4, true, stream), "depth sort prepare");
+            CDS_HIP(launch_sort_histogram(sb.depth_bits, n, 4, 0, wd.hist, stream), "depth sort histogram");
+        }
         CDS_HIP(launch_sort_passes(sb.depth_bits, nullptr, (uint32_t*)f->dkey0.p, (uint32_t*)f->order0.p,
-                                   (uint32_t*)f->dkey1.p, (uint32_t*)f->order1.p, n, 4, 0, wd, stream),
+                                   (uint32_t*)f->dkey1.p, (uint32_t*)f->order1.p, n, 4, 0, wd, algo, stream),
                 "depth sort");
         order = (const uint32_t*)f->order1.p;
     }
@@ -134,16 +136,20 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
 
     SortWorkspace ws = sort_ws(ctx, f->sort);
     if (K > 0) {
-        CDS_HIP(launch_sort_prepare(ws, (int64_t)K, passes, true, stream), "sort prepare");
+        // onesweep passes need the digit histograms of all keys; the duplicate
+        // pass builds them per Gaussian and per rectangle row
+        const bool need_hist = sort_uses_onesweep((int64_t)K, algo) && passes > 0;
+        if (need_hist) CDS_HIP(launch_sort_prepare(ws, (int64_t)K, passes, true, stream), "sort prepare");
+        uint32_t* hist = need_hist ? ws.hist : nullptr;
         if (sort_variant == 0)
             CDS_HIP(launch_duplicate(n, order, (const uint32_t*)f->offsets.p, sb.touched, sb.rect, sb.depth_bits,
-                                     P.tiles_x, nullptr, (uint32_t*)f->tk0.p, (uint32_t*)f->vals0.p, ws.hist, 0,
+                                     P.tiles_x, nullptr, (uint32_t*)f->tk0.p, (uint32_t*)f->vals0.p, hist, 0,
                                      tile_passes, stream),
                     "duplicate kernel");
         else
             CDS_HIP(launch_duplicate(n, nullptr, (const uint32_t*)f->offsets.p, sb.touched, sb.rect,
                                      sb.depth_bits, P.tiles_x, (uint64_t*)f->keys0.p, nullptr,
-                                     (uint32_t*)f->vals0.p, ws.hist, 4, tile_passes, stream),
+                                     (uint32_t*)f->vals0.p, hist, 4, tile_passes, stream),
                     "duplicate kernel");
     }
     CDS_TRY(f->record(3, stream));
@@ -152,7 +158,7 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
         if (K > 0)
             CDS_HIP(launch_sort_passes((const uint32_t*)f->tk0.p, (const uint32_t*)f->vals0.p, (uint32_t*)f->tk1.p,
                                        (uint32_t*)f->vals1.p, (uint32_t*)f->tk0.p, (uint32_t*)f->vals0.p,
-                                       (int64_t)K, passes, 0, ws, stream),
+                                       (int64_t)K, passes, 0, ws, algo, stream),
                     "tile sort");
         f->res_tiles = (const uint32_t*)(odd ? f->tk1.p : f->tk0.p);
         f->res_tile_stride = 1;
@@ -161,7 +167,7 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
         if (K > 0)
             CDS_HIP(launch_sort_passes((const uint64_t*)f->keys0.p, (const uint32_t*)f->vals0.p,
                                        (uint64_t*)f->keys1.p, (uint32_t*)f->vals1.p, (uint64_t*)f->keys0.p,
-                                       (uint32_t*)f->vals0.p, (int64_t)K, passes, 0, ws, stream),
+                                       (uint32_t*)f->vals0.p, (int64_t)K, passes, 0, ws, algo, stream),
                     "key sort");
         f->res_keys = (const uint64_t*)(odd ? f->keys1.p : f->keys0.p);
         f->res_tiles = reinterpret_cast<const uint32_t*>(f->res_keys) + 1;  // high words

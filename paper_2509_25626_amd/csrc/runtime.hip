@@ -128,13 +128,17 @@ SceneParams make_scene(const cds_scene* s) {
 }
 
 cds_status ensure_sort_workspace(cds_ctx* ctx, SortState& s, int64_t count, int passes) {
-    const int64_t parts = sort_partitions(count);
+    const int64_t parts = std::max<int64_t>(sort_partitions(count), 1);
     cds_status st;
     if ((st = ensure(ctx, s.hist, sizeof(uint32_t) * 256 * 8)) != CDS_OK) return st;
     if ((st = ensure(ctx, s.counters, sizeof(uint32_t) * 8)) != CDS_OK) return st;
-    if ((st = ensure(ctx, s.status, sizeof(uint32_t) * 256 * (size_t)std::max<int64_t>(parts, 1) * passes,
-                     1.25)) != CDS_OK)
+    if ((st = ensure(ctx, s.status, sizeof(uint32_t) * 256 * (size_t)parts * passes, 1.25)) != CDS_OK) return st;
+    if ((st = ensure(ctx, s.part_hist, sizeof(uint32_t) * 256 * (size_t)parts, 1.25)) != CDS_OK) return st;
+    if ((st = ensure(ctx, s.bases, sizeof(uint32_t) * 256 * (size_t)parts, 1.25)) != CDS_OK) return st;
+    if ((st = ensure(ctx, s.scan_sums, sizeof(uint64_t) * (size_t)scan_block_sums_size(256 * parts), 1.25)) !=
+        CDS_OK)
         return st;
+    if ((st = ensure(ctx, s.scan_total, 256)) != CDS_OK) return st;
     return CDS_OK;
 }
 
@@ -143,8 +147,18 @@ SortWorkspace sort_ws(cds_ctx* ctx, SortState& s) {
     ws.hist = (uint32_t*)s.hist.p;
     ws.status = (uint32_t*)s.status.p;
     ws.counters = (uint32_t*)s.counters.p;
+    ws.part_hist = (uint32_t*)s.part_hist.p;
+    ws.bases = (uint32_t*)s.bases.p;
+    ws.scan_sums = (uint64_t*)s.scan_sums.p;
+    ws.scan_total = (uint64_t*)s.scan_total.p;
     ws.err = ctx->d_err;
     return ws;
+}
+
+SortAlgo sort_algo_from_flags(uint32_t flags) {
+    if (flags & CDS_OPT_SORT_ONESWEEP) return SortAlgo::kOnesweep;
+    if (flags & CDS_OPT_SORT_REDUCE_SCAN) return SortAlgo::kReduceScan;
+    return SortAlgo::kAuto;
 }
 
 }  // namespace cds
@@ -233,9 +247,14 @@ cds_status cds_render_forward(cds_ctx* ctx, cds_frame* f, const cds_scene* scene
     if (!out_rgb || !out_T || !out_ncontrib) return fail(CDS_ERR_INVALID_ARG, "output pointer is NULL");
     int variant = 0, sort_variant = 0;
     bool timing = false;
+    SortAlgo algo = SortAlgo::kAuto;
     if (opts) {
-        if (opts->flags & ~CDS_OPT_STAGE_TIMING) return fail(CDS_ERR_INVALID_ARG, "unknown option flags");
+        if (opts->flags & ~(CDS_OPT_STAGE_TIMING | CDS_OPT_SORT_ONESWEEP | CDS_OPT_SORT_REDUCE_SCAN))
+            return fail(CDS_ERR_INVALID_ARG, "unknown option flags");
+        if ((opts->flags & CDS_OPT_SORT_ONESWEEP) && (opts->flags & CDS_OPT_SORT_REDUCE_SCAN))
+            return fail(CDS_ERR_INVALID_ARG, "choose one radix-sort pass algorithm");
         timing = (opts->flags & CDS_OPT_STAGE_TIMING) != 0;
+        algo = sort_algo_from_flags(opts->flags);
         variant = opts->blend_variant;
         if (variant != 0 && variant != 1 && variant != 2 && variant != 4)
             return fail(CDS_ERR_INVALID_ARG, "blend_variant must be 0, 1, 2 or 4");
@@ -248,7 +267,8 @@ cds_status cds_render_forward(cds_ctx* ctx, cds_frame* f, const cds_scene* scene
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     f->valid = false;
     f->timing = timing;
-    return render_forward_impl(ctx, f, scene, cam, variant, sort_variant, out_rgb, out_T, out_ncontrib, stream);
+    return render_forward_impl(ctx, f, scene, cam, variant, sort_variant, algo, out_rgb, out_T, out_ncontrib,
+                               stream);
 }
 
 cds_status cds_render_backward(cds_ctx* ctx, cds_frame* f, const cds_scene* scene, const cds_camera* cam,
@@ -310,8 +330,13 @@ cds_status cds_frame_get_info(cds_frame* f, cds_frame_info* o) {
 }
 
 cds_status cds_sort_pairs(cds_ctx* ctx, const uint64_t* keys_in, const uint32_t* values_in, int64_t count,
-                          int32_t end_bit, uint64_t* keys_out, uint32_t* values_out, void* stream_) {
+                          int32_t end_bit, uint64_t* keys_out, uint32_t* values_out, uint32_t flags,
+                          void* stream_) {
     if (!ctx) return fail(CDS_ERR_INVALID_ARG, "context is NULL");
+    if (flags & ~(CDS_OPT_SORT_ONESWEEP | CDS_OPT_SORT_REDUCE_SCAN) ||
+        ((flags & CDS_OPT_SORT_ONESWEEP) && (flags & CDS_OPT_SORT_REDUCE_SCAN)))
+        return fail(CDS_ERR_INVALID_ARG, "bad sort flags");
+    const SortAlgo algo = sort_algo_from_flags(flags);
     if (count < 0 || end_bit < 1 || end_bit > 64) return fail(CDS_ERR_INVALID_ARG, "bad count or end_bit");
     if (count > kSortMaxCount) return fail(CDS_ERR_CAPACITY, "sort supports at most 2^30-1 pairs");
     if (count > 0 && (!keys_in || !values_in || !keys_out || !values_out))
@@ -338,9 +363,11 @@ cds_status cds_sort_pairs(cds_ctx* ctx, const uint64_t* keys_in, const uint32_t*
     else            { ka = tmpk; va = tmpv; kb = keys_out; vb = values_out; }
     SortWorkspace ws = sort_ws(ctx, s->sort);
     if ((e = launch_sort_prepare(ws, count, passes, true, stream)) != hipSuccess) return hip_fail(e, "sort prepare");
-    if ((e = launch_sort_histogram(keys_in, count, passes, 0, ws.hist, stream)) != hipSuccess)
+    if (sort_uses_onesweep(count, algo) &&
+        (e = launch_sort_histogram(keys_in, count, passes, 0, ws.hist, stream)) != hipSuccess)
         return hip_fail(e, "sort histogram");
-    if ((e = launch_sort_passes(keys_in, values_in, ka, va, kb, vb, count, passes, 0, ws, stream)) != hipSuccess)
+    if ((e = launch_sort_passes(keys_in, values_in, ka, va, kb, vb, count, passes, 0, ws, algo, stream)) !=
+        hipSuccess)
         return hip_fail(e, "sort passes");
     return CDS_OK;
 }

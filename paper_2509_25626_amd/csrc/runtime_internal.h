@@ -13,7 +13,7 @@ struct DevBuf {
 };
 
 struct SortState {
-    DevBuf hist, status, counters;
+    DevBuf hist, status, counters, part_hist, bases, scan_sums, scan_total;
 };
 
 }  // namespace cds
@@ -75,8 +75,9 @@ cds_status ensure_sort_workspace(cds_ctx* ctx, SortState& s, int64_t count, int 
 SortWorkspace sort_ws(cds_ctx* ctx, SortState& s);
 
 cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scene, const cds_camera* cam,
-                               int blend_variant, int sort_variant, float* out_rgb, float* out_T,
+                               int blend_variant, int sort_variant, SortAlgo algo, float* out_rgb, float* out_T,
                                uint32_t* out_ncontrib, hipStream_t stream);
+SortAlgo sort_algo_from_flags(uint32_t flags);
 int tile_bits_for(int64_t ntiles);
 cds_status frame_build_keys(cds_frame* f);
 cds_status render_backward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scene, const cds_camera* cam,

@@ -1,26 +1,29 @@
-// Stable LSD radix sort of (64-bit key, 32-bit value) pairs, 8-bit digits,
-// one "onesweep" kernel per digit (the per-tile depth sort of paper
-// Section II-B(1), done as one global sort of (tile | depth) keys).
+// Stable LSD radix sort of (32- or 64-bit key, 32-bit value) pairs with
+// 8-bit digits: the per-tile depth order of paper Section II-B(1), done as a
+// global sort of (tile | depth) keys.
 //
-// Per pass, each workgroup (256 threads, 4096 keys) takes the next partition
-// id from an atomic counter (so every lower id belongs to a workgroup that is
-// already running), ranks its keys stably in LDS, publishes its per-digit
-// counts, and finds the per-digit count of all earlier partitions by
-// decoupled look-back over a status word per (partition, digit):
-//   bits 31..30 = 0 not ready, 1 partition count only, 2 inclusive prefix
-//   bits 29..0  = the count
-// Keys are then reordered in LDS by digit and written out so each digit run
-// is a contiguous, coalesced store.  Global digit offsets come from a
-// histogram of all keys computed before the first pass.
+// Every pass is a partitioned counting sort.  A workgroup (256 threads,
+// 4096 keys) ranks its keys stably in LDS, reorders them by digit and writes
+// each digit run as one contiguous, coalesced store.  Ranking is wave64
+// native: keys are held "wave-striped" (round r of a wave covers 64
+// consecutive input keys), lanes with the same digit are found with eight
+// ballots, and a per-wave per-digit counter in LDS gives each key its rank;
+// processing rounds in order keeps the sort stable.
 //
-// Ranking is wave64-native: keys are held "wave-striped" (round r of a wave
-// covers 64 consecutive input keys), peers with the same digit are found
-// with eight ballots, and a per-wave, per-digit counter in LDS gives each key
-// its rank; processing rounds in order keeps the sort stable.
-//
-// The look-back wait is bounded: after ~2^22 polls a workgroup records an
-// error in the device error word and proceeds, so a logic error can only
-// corrupt the output, never hang the device.
+// Two ways give a partition the global position of its digit runs:
+//  - reduce-then-scan (default for large inputs): an upsweep kernel counts
+//    the digits of every partition into a digit-major [256][partitions]
+//    matrix, one exclusive scan of that matrix yields every (digit,
+//    partition) base, and the pass kernel reads its bases.  20 B/key for
+//    32-bit keys, and no workgroup ever waits for another.
+//  - onesweep: each partition publishes its digit counts and sums its
+//    predecessors' by decoupled look-back over a status word per (partition,
+//    digit) (bits 31..30 = 0 not ready, 1 partition count, 2 inclusive
+//    prefix).  16 B/key, but every inclusive prefix waits for a
+//    device-coherent round trip; on a chip of 8 XCDs that chain, not HBM,
+//    bounds large sorts, so it is used for small ones.  Its wait is bounded:
+//    after ~2^22 polls a workgroup records an error and proceeds, so a logic
+//    error can corrupt the output but never hang the device.
 #include "device_utils.h"
 #include "internal.h"
 
@@ -35,6 +38,7 @@ constexpr uint32_t kFlagAgg = 1u << 30;
 constexpr uint32_t kFlagIncl = 2u << 30;
 constexpr uint32_t kValueMask = (1u << 30) - 1;
 constexpr uint32_t kSpinLimit = 1u << 22;
+constexpr int kLookBack = 8;  // predecessors read per look-back step
 
 __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, int64_t count,
                                                   uint32_t value) {
@@ -64,6 +68,41 @@ __global__ __launch_bounds__(256) void k_sort_histogram(const Key* __restrict__ 
     }
 }
 
+// Lanes of the wave holding the same 8-bit digit (restricted to `valid` lanes).
+__device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
+    uint64_t peers = ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t m = ballot(bit);
+        peers &= bit ? m : ~m;
+    }
+    return peers;
+}
+
+// Per-partition digit counts, digit-major: part_hist[d * parts + p].  Each
+// distinct digit of a wave round costs one LDS atomic (equal digits would
+// otherwise serialise on one address).
+template <typename Key>
+__global__ __launch_bounds__(kNT) void k_rts_upsweep(const Key* __restrict__ keys, int64_t count, int shift,
+                                                     uint32_t* __restrict__ part_hist, int64_t parts) {
+    __shared__ uint32_t s_h[256];
+    const int t = threadIdx.x;
+    s_h[t] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kP;
+#pragma unroll 4
+    for (int r = 0; r < kKPT; ++r) {
+        const int64_t idx = base + (int64_t)r * kNT + t;
+        const bool valid = idx < count;
+        const uint32_t d = valid ? (uint32_t)(keys[idx] >> shift) & 255u : 0u;
+        const uint64_t peers = digit_peers(d, valid);
+        if (valid && count_below(peers) == 0) atomicAdd(&s_h[d], (uint32_t)__popcll(peers));
+    }
+    __syncthreads();
+    part_hist[(int64_t)t * parts + blockIdx.x] = s_h[t];
+}
+
 template <typename Key>
 struct PassArgs {
     const Key* kin;
@@ -72,14 +111,16 @@ struct PassArgs {
     uint32_t* vout;
     int64_t count;
     int shift;
-    const uint32_t* hist;  // [256] digit counts of all keys
-    uint32_t* status;      // [partitions][256]
-    uint32_t* counter;     // partition-id counter
+    const uint32_t* hist;   // onesweep: [256] digit counts of all keys
+    uint32_t* status;       // onesweep: [partitions][256]
+    uint32_t* counter;      // onesweep: partition-id counter
+    const uint32_t* bases;  // reduce-then-scan: [256][partitions] exclusive bases
+    int64_t parts;
     uint32_t* err;
 };
 
-template <typename Key>
-__global__ __launch_bounds__(kNT) void k_onesweep(PassArgs<Key> a) {
+template <typename Key, bool kOnesweep>
+__global__ __launch_bounds__(kNT) void k_sort_pass(PassArgs<Key> a) {
     __shared__ Key s_keys[kP];                  // reorder buffer (keys, then values)
     __shared__ uint32_t s_whist[kWaves][256];   // per-wave digit counters, then offsets
     __shared__ uint32_t s_gbase[256];
@@ -89,7 +130,7 @@ __global__ __launch_bounds__(kNT) void k_onesweep(PassArgs<Key> a) {
     const int t = threadIdx.x;
     const int w = t / kWave;
     const uint32_t l = lane_id();
-    if (t == 0) s_pid = atomicAdd(a.counter, 1u);
+    if (t == 0) s_pid = kOnesweep ? atomicAdd(a.counter, 1u) : blockIdx.x;
     for (int k = t; k < kWaves * 256; k += kNT) (&s_whist[0][0])[k] = 0;
     __syncthreads();
     const uint32_t pid = s_pid;
@@ -112,13 +153,7 @@ __global__ __launch_bounds__(kNT) void k_onesweep(PassArgs<Key> a) {
     for (int r = 0; r < kKPT; ++r) {
         const bool valid = (wbase + r * kWave + l) < a.count;
         const uint32_t d = (uint32_t)(key[r] >> a.shift) & 255u;
-        uint64_t peers = ballot(valid);
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t m = ballot(bit);
-            peers &= bit ? m : ~m;
-        }
+        const uint64_t peers = digit_peers(d, valid);
         const uint32_t below = count_below(peers);
         const uint32_t cnt = (uint32_t)__popcll(peers);
         uint32_t pre = 0;
@@ -132,38 +167,60 @@ __global__ __launch_bounds__(kNT) void k_onesweep(PassArgs<Key> a) {
     const uint32_t c0 = s_whist[0][t], c1 = s_whist[1][t], c2 = s_whist[2][t], c3 = s_whist[3][t];
     static_assert(kWaves == 4, "digit bookkeeping assumes 4 waves");
     const uint32_t tot = c0 + c1 + c2 + c3;
-    uint32_t* st = a.status + (size_t)pid * 256;
-    atomic_store_agent(st + t, (pid == 0 ? kFlagIncl : kFlagAgg) | tot);
-
-    const uint32_t bstart = block_excl_sum<kNT>(tot, s_scan, nullptr);
-    const uint32_t gstart = block_excl_sum<kNT>(a.hist[t], s_scan, nullptr);
-
-    uint32_t excl = 0;
-    if (pid > 0) {
-        int64_t p = (int64_t)pid - 1;
-        uint32_t spins = 0;
-        while (p >= 0) {
-            const uint32_t s = atomic_load_agent(a.status + (size_t)p * 256 + t);
-            const uint32_t f = s & ~kValueMask;
-            if (f == 0u) {
-                if (++spins > kSpinLimit) {
-                    atomicOr(a.err, 1u);
-                    break;
+    uint32_t gb;  // global position of this partition's first key with digit t
+    if constexpr (kOnesweep) {
+        uint32_t* st = a.status + (size_t)pid * 256;
+        atomic_store_agent(st + t, (pid == 0 ? kFlagIncl : kFlagAgg) | tot);
+        const uint32_t gstart = block_excl_sum<kNT>(a.hist[t], s_scan, nullptr);
+        // Look-back: read a window of predecessors' status words at once (they
+        // are device-coherent loads, a memory round trip each), consume them
+        // nearest first, stop at an inclusive prefix, re-poll from the first
+        // one not ready.
+        uint32_t excl = 0;
+        if (pid > 0) {
+            int64_t p = (int64_t)pid - 1;
+            uint32_t spins = 0;
+            while (p >= 0) {
+                uint32_t s[kLookBack];
+#pragma unroll
+                for (int k = 0; k < kLookBack; ++k)
+                    s[k] = (p - k >= 0) ? atomic_load_agent(a.status + (size_t)(p - k) * 256 + t) : kFlagIncl;
+                int consumed = 0;
+                bool found = false, stalled = false;
+#pragma unroll
+                for (int k = 0; k < kLookBack; ++k) {
+                    if (found || stalled) continue;
+                    const uint32_t f = s[k] & ~kValueMask;
+                    if (f == 0u) {
+                        stalled = true;
+                        continue;
+                    }
+                    excl += s[k] & kValueMask;
+                    ++consumed;
+                    if (f == kFlagIncl) found = true;
                 }
-                __builtin_amdgcn_s_sleep(1);
-                continue;
+                if (found) break;
+                p -= consumed;
+                if (stalled) {
+                    if (++spins > kSpinLimit) {
+                        atomicOr(a.err, 1u);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
             }
-            excl += s & kValueMask;
-            if (f == kFlagIncl) break;
-            --p;
+            atomic_store_agent(st + t, kFlagIncl | ((excl + tot) & kValueMask));
         }
-        atomic_store_agent(st + t, kFlagIncl | ((excl + tot) & kValueMask));
+        gb = gstart + excl;
+    } else {
+        gb = a.bases[(int64_t)t * a.parts + pid];
     }
+    const uint32_t bstart = block_excl_sum<kNT>(tot, s_scan, nullptr);
     s_whist[0][t] = bstart;
     s_whist[1][t] = bstart + c0;
     s_whist[2][t] = bstart + c0 + c1;
     s_whist[3][t] = bstart + c0 + c1 + c2;
-    s_gbase[t] = gstart + excl - bstart;
+    s_gbase[t] = gb - bstart;
     __syncthreads();
 
     // reorder keys by digit in LDS
@@ -188,8 +245,8 @@ __global__ __launch_bounds__(kNT) void k_onesweep(PassArgs<Key> a) {
             const Key k = s_keys[i];
             const uint32_t d = (uint32_t)(k >> a.shift) & 255u;
             const uint32_t g = s_gbase[d] + i;
-            // a position outside the output can only come from an inconsistent
-            // histogram or look-back; record it instead of writing out of bounds
+            // a position outside the output can only come from inconsistent digit
+            // counts; record it instead of writing out of bounds
             if ((int64_t)g < a.count) a.kout[g] = k;
             else atomicOr(a.err, 2u);
             gpos[r] = g;
@@ -229,10 +286,11 @@ hipError_t sort_histogram_impl(const Key* keys, int64_t count, int passes, int s
 template <typename Key>
 hipError_t sort_passes_impl(const Key* kin, const uint32_t* vin, Key* ka, uint32_t* va, Key* kb,
                             uint32_t* vb, int64_t count, int passes, int shift0, const SortWorkspace& ws,
-                            hipStream_t stream) {
+                            SortAlgo algo, hipStream_t stream) {
     if (count <= 0 || passes <= 0) return hipSuccess;
     if (count > kSortMaxCount) return hipErrorInvalidValue;
     const int64_t parts = sort_partitions(count);
+    const bool onesweep = sort_uses_onesweep(count, algo);
     for (int p = 0; p < passes; ++p) {
         PassArgs<Key> a;
         a.kin = p == 0 ? kin : ((p & 1) ? ka : kb);
@@ -244,15 +302,32 @@ hipError_t sort_passes_impl(const Key* kin, const uint32_t* vin, Key* ka, uint32
         a.hist = ws.hist + (size_t)p * 256;
         a.status = ws.status + (size_t)p * parts * 256;
         a.counter = ws.counters + p;
+        a.bases = ws.bases;
+        a.parts = parts;
         a.err = ws.err;
-        hipLaunchKernelGGL(k_onesweep<Key>, dim3((unsigned)parts), dim3(kNT), 0, stream, a);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+        hipError_t e;
+        if (onesweep) {
+            hipLaunchKernelGGL((k_sort_pass<Key, true>), dim3((unsigned)parts), dim3(kNT), 0, stream, a);
+        } else {
+            hipLaunchKernelGGL(k_rts_upsweep<Key>, dim3((unsigned)parts), dim3(kNT), 0, stream, a.kin, count,
+                               a.shift, ws.part_hist, parts);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            e = launch_exclusive_scan(ws.part_hist, nullptr, ws.bases, 256 * parts, ws.scan_sums, ws.scan_total,
+                                      stream);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL((k_sort_pass<Key, false>), dim3((unsigned)parts), dim3(kNT), 0, stream, a);
+        }
+        if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
 }  // namespace
+
+bool sort_uses_onesweep(int64_t count, SortAlgo algo) {
+    return algo == SortAlgo::kOnesweep ||
+           (algo == SortAlgo::kAuto && sort_partitions(count) < kSortRtsMinPartitions);
+}
 
 hipError_t launch_fill_u32(uint32_t* p, int64_t count, uint32_t value, hipStream_t stream) {
     if (count <= 0) return hipSuccess;
@@ -285,14 +360,14 @@ hipError_t launch_sort_prepare(const SortWorkspace& ws, int64_t count, int passe
 
 hipError_t launch_sort_passes(const uint64_t* kin, const uint32_t* vin, uint64_t* ka, uint32_t* va,
                               uint64_t* kb, uint32_t* vb, int64_t count, int passes, int shift0,
-                              const SortWorkspace& ws, hipStream_t stream) {
-    return sort_passes_impl<uint64_t>(kin, vin, ka, va, kb, vb, count, passes, shift0, ws, stream);
+                              const SortWorkspace& ws, SortAlgo algo, hipStream_t stream) {
+    return sort_passes_impl<uint64_t>(kin, vin, ka, va, kb, vb, count, passes, shift0, ws, algo, stream);
 }
 
 hipError_t launch_sort_passes(const uint32_t* kin, const uint32_t* vin, uint32_t* ka, uint32_t* va,
                               uint32_t* kb, uint32_t* vb, int64_t count, int passes, int shift0,
-                              const SortWorkspace& ws, hipStream_t stream) {
-    return sort_passes_impl<uint32_t>(kin, vin, ka, va, kb, vb, count, passes, shift0, ws, stream);
+                              const SortWorkspace& ws, SortAlgo algo, hipStream_t stream) {
+    return sort_passes_impl<uint32_t>(kin, vin, ka, va, kb, vb, count, passes, shift0, ws, algo, stream);
 }
 
 }  // namespace cds

@@ -41,6 +41,11 @@ def device_to_numpy(ptr: int, count: int, dtype) -> np.ndarray:
     return out
 
 
+def _sort_flag(algo: str) -> int:
+    return {"auto": 0, "onesweep": native.CDS_OPT_SORT_ONESWEEP,
+            "reduce_scan": native.CDS_OPT_SORT_REDUCE_SCAN}[algo]
+
+
 def _stream_handle(device) -> int:
     return torch.cuda.current_stream(device).cuda_stream
 
@@ -201,7 +206,7 @@ class Renderer:
         self._pool.append(frame)
 
     def forward(self, scene: GaussianScene, cam, frame: Frame | None = None, blend_variant: int = 0,
-                out=None, timing: bool = False, sort_variant: int = 0):
+                out=None, timing: bool = False, sort_variant: int = 0, sort_algo: str = "auto"):
         """Render; returns (rgb [3,H,W], final_T [H,W], n_contrib [H,W] int32 view of uint32, frame)."""
         cs = native.camera_struct(cam)
         H, W = cs.height, cs.width
@@ -212,8 +217,8 @@ class Renderer:
         else:
             rgb, T, nc = out
         frame = frame or self.acquire_frame()
-        opts = native.CdsRenderOpts(native.CDS_OPT_STAGE_TIMING if timing else 0, int(blend_variant),
-                                    int(sort_variant), 0)
+        flags = (native.CDS_OPT_STAGE_TIMING if timing else 0) | _sort_flag(sort_algo)
+        opts = native.CdsRenderOpts(flags, int(blend_variant), int(sort_variant), 0)
         sst = scene.struct()
         check(self.L.cds_render_forward(self.handle, frame.handle, ctypes.byref(sst), ctypes.byref(cs),
                                         ctypes.byref(opts), rgb.data_ptr(), T.data_ptr(), nc.data_ptr(),
@@ -242,12 +247,13 @@ class Renderer:
                                       grad.data_ptr(), loss.data_ptr(), _stream_handle(self.device)))
         return grad, loss
 
-    def sort_pairs(self, keys, values, end_bit=64):
+    def sort_pairs(self, keys, values, end_bit=64, algo="auto"):
         """Stable radix sort of uint64 keys (int64 tensor bits) with uint32 values (int32 bits)."""
         ko = torch.empty_like(keys)
         vo = torch.empty_like(values)
         check(self.L.cds_sort_pairs(self.handle, keys.data_ptr(), values.data_ptr(), keys.numel(),
-                                    int(end_bit), ko.data_ptr(), vo.data_ptr(), _stream_handle(self.device)))
+                                    int(end_bit), ko.data_ptr(), vo.data_ptr(), _sort_flag(algo),
+                                    _stream_handle(self.device)))
         return ko, vo
 
     def exclusive_scan(self, values):

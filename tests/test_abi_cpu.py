@@ -48,7 +48,7 @@ def test_null_arguments_rejected_without_device_work(lib):
     assert b"NULL" in lib.cds_last_error()
     assert lib.cds_render_backward(None, None, None, None, None, None, None, None, None) == \
         native.CDS_ERR_INVALID_ARG
-    assert lib.cds_sort_pairs(None, None, None, 10, 64, None, None, None) == native.CDS_ERR_INVALID_ARG
+    assert lib.cds_sort_pairs(None, None, None, 10, 64, None, None, 0, None) == native.CDS_ERR_INVALID_ARG
     assert lib.cds_exclusive_scan_u32(None, None, 10, None, None, None) == native.CDS_ERR_INVALID_ARG
     assert lib.cds_frame_create(None, ctypes.byref(P())) == native.CDS_ERR_INVALID_ARG
     assert lib.cds_frame_get_info(None, None) == native.CDS_ERR_INVALID_ARG

@@ -29,11 +29,13 @@ def R():
     r.close()
 
 
-def gpu_render(R, scene, cam, variant=0, sort_variant=0):
+def gpu_render(R, scene, cam, variant=0, sort_variant=0, sort_algo="auto"):
     from paper_2509_25626_amd.render import GaussianScene
     gs = GaussianScene.from_numpy(scene)
-    rgb, T, nc, frame = R.forward(gs, cam, blend_variant=variant, sort_variant=sort_variant)
+    rgb, T, nc, frame = R.forward(gs, cam, blend_variant=variant, sort_variant=sort_variant,
+                                  sort_algo=sort_algo)
     torch.cuda.synchronize()
+    R.check_device()
     out = dict(image=rgb.cpu().numpy(), final_T=T.cpu().numpy(),
                n_contrib=nc.cpu().numpy().view(np.uint32))
     out.update(frame.fetch())
@@ -104,8 +106,8 @@ def compare_images(g, o, max_flip_frac=2e-3):
     return int(flip.sum())
 
 
-def full_check(R, scene, cam, variant=0, sort_variant=0):
-    g = gpu_render(R, scene, cam, variant, sort_variant)
+def full_check(R, scene, cam, variant=0, sort_variant=0, sort_algo="auto"):
+    g = gpu_render(R, scene, cam, variant, sort_variant, sort_algo)
     o = O.render(scene, cam, round_f32=True)
     flagged = compare_projection(g, o)
     compare_keys(g, o, flagged, sort_variant)
@@ -115,10 +117,11 @@ def full_check(R, scene, cam, variant=0, sort_variant=0):
 
 # ---------------------------------------------------------------- whole pipeline
 
-@pytest.mark.parametrize("sort_variant", [0, 1])
-def test_c1_forward_parity(R, sort_variant):
+@pytest.mark.parametrize("sort_variant,sort_algo", [(0, "auto"), (1, "auto"), (0, "onesweep"),
+                                                     (0, "reduce_scan"), (1, "reduce_scan")])
+def test_c1_forward_parity(R, sort_variant, sort_algo):
     scene, cam = S.config_scene("c1")
-    g, o, nflip = full_check(R, scene, cam, sort_variant=sort_variant)
+    g, o, nflip = full_check(R, scene, cam, sort_variant=sort_variant, sort_algo=sort_algo)
     assert g["K"] > 30000 and g["passes"] == 5
     print(f"c1: K={g['K']} flip-eligible pixels={nflip}")
 
@@ -205,9 +208,13 @@ def test_single_gaussian_covering_whole_image(R):
 
 # ---------------------------------------------------------------- sort and scan
 
-@pytest.mark.parametrize("count", [1, 100, 4095, 4096, 4097, 123_457, 1_000_003])
-@pytest.mark.parametrize("end_bit", [64, 44, 8])
-def test_sort_pairs_matches_stable_argsort(R, count, end_bit):
+SORT_CASES = ([(c, b, "auto") for c in (1, 100, 4095, 4096, 4097, 123_457, 1_000_003) for b in (64, 44, 8)]
+              + [(c, b, a) for c in (1, 4097, 1_000_003, 9_000_001) for b in (64, 12)
+                 for a in ("onesweep", "reduce_scan")])
+
+
+@pytest.mark.parametrize("count,end_bit,algo", SORT_CASES)
+def test_sort_pairs_matches_stable_argsort(R, count, end_bit, algo):
     rng = np.random.default_rng(count + end_bit)
     # few distinct values so that ties (and therefore stability) matter
     keys = rng.integers(0, 2**63, size=count, dtype=np.uint64) & np.uint64(0xFFFF0000000F00FF)
@@ -215,7 +222,7 @@ def test_sort_pairs_matches_stable_argsort(R, count, end_bit):
     vals = np.arange(count, dtype=np.uint32)
     kt = torch.from_numpy(keys.view(np.int64)).cuda()
     vt = torch.from_numpy(vals.view(np.int32)).cuda()
-    ko, vo = R.sort_pairs(kt, vt, end_bit)
+    ko, vo = R.sort_pairs(kt, vt, end_bit, algo)
     R.check_device()
     mask = np.uint64((1 << end_bit) - 1) if end_bit < 64 else np.uint64(0xFFFFFFFFFFFFFFFF)
     order = np.argsort(keys & mask, kind="stable")
