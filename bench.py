@@ -25,7 +25,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, GB/s
 FP32_VALU_PEAK_TFLOPS = 157.3  # MI355X FP32 vector (packed), TFLOP/s
-SORT_BYTES_PER_KEY_PASS = 24  # read key+value (12 B) and write key+value (12 B)
+
+# Algorithmic HBM bytes of each forward stage's kernels (each byte the
+# computation must move once): see roofline().
 
 
 def parse():
@@ -40,6 +42,62 @@ def parse():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=40.0)
     return ap.parse_args()
+
+
+def roofline(stages, scene, K, passes, info):
+    """Roofline position of the dominant forward stage: algorithmic bytes per
+    launch of its main kernel over that kernel's average launch duration, from
+    the HIP events the library records on the render stream."""
+    n = scene.n
+    sh_bytes = 4 * 3 * (scene.sh_degree + 1) ** 2
+    tiles = int(info.tiles_x) * int(info.tiles_y)
+    tile_passes = max(int(passes) - 4, 1)
+    table = {
+        # kernel, launches per frame, algorithmic bytes per launch
+        # preprocess: 40 B of geometry + SH in, 61 B of splat state out per Gaussian
+        "preprocess_ms": ("k_preprocess", 1, (40 + sh_bytes + 61) * n),
+        # depth sort: 4 onesweep passes over (u32 depth, u32 index), 16 B per Gaussian each
+        "scan_ms": ("k_sort_pass<u32> (depth digits)", 4, 16 * n),
+        # duplicate: 8 B per key (tile id, value) + 24 B per Gaussian read
+        "duplicate_ms": ("k_duplicate", 1, 8 * K + 24 * n),
+        # tile sort: read and write (u32 tile id, u32 value), 16 B per key per pass
+        "sort_ms": ("k_sort_pass<u32> (tile digits)", tile_passes, 16 * K),
+        # ranges: read 4 B per key, write 8 B per tile
+        "ranges_ms": ("k_ranges4", 1, 4 * K + 8 * tiles),
+    }
+    dom = max(stages, key=stages.get)
+    if dom not in table:
+        return {"kernel": dom.replace("_ms", ""), "bound": "alu", "achieved": None, "peak": None,
+                "unit": None, "frac": None, "traffic": None, "stage_ms": round(stages[dom], 4)}
+    kernel, launches, nbytes = table[dom]
+    per_launch_ms = stages[dom] / launches
+    achieved = nbytes / (per_launch_ms * 1e-3) / 1e9
+    return {"kernel": kernel, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kernel),
+            "algorithmic_bytes_per_launch": int(nbytes), "launches_per_frame": launches,
+            "avg_launch_ms": round(per_launch_ms, 4)}
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when there is none for this kernel or its source changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    ent = rec.get(kernel)
+    if not ent:
+        return None
+    src = os.path.join(ROOT, ent["source"])
+    try:
+        with open(src, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    return ent["bytes_per_launch"] if sha == ent["source_sha256"] else None
 
 
 def cpu_baseline(scene, cam, budget_s):
@@ -141,27 +199,7 @@ def main():
         result_extra["backward_stage_ms"] = {k: round(v / args.steps, 4) for k, v in bw_acc.items()
                                              if k.endswith("backward_ms")}
 
-    # roofline of the dominant forward kernel (largest stage)
-    dom = max(stages, key=stages.get)
-    if dom == "sort_ms":
-        per_launch_ms = stages["sort_ms"] / max(passes, 1)
-        traffic_bytes = SORT_BYTES_PER_KEY_PASS * K
-        achieved = traffic_bytes / (per_launch_ms * 1e-3) / 1e9
-        roof = {"kernel": "k_onesweep (one 8-bit radix pass)", "bound": "hbm", "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "algorithmic_bytes_per_launch": traffic_bytes,
-                "avg_launch_ms": round(per_launch_ms, 4)}
-    elif dom == "preprocess_ms":
-        bpg = 4 * (3 + 3 + 4 + 1 + 3 * (scene.sh_degree + 1) ** 2) + 61
-        traffic_bytes = bpg * scene.n
-        achieved = traffic_bytes / (stages[dom] * 1e-3) / 1e9
-        roof = {"kernel": "k_preprocess", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "algorithmic_bytes_per_launch": traffic_bytes, "avg_launch_ms": round(stages[dom], 4)}
-    else:
-        roof = {"kernel": dom.replace("_ms", ""), "bound": "alu", "achieved": None,
-                "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": None, "traffic": None,
-                "avg_launch_ms": round(stages[dom], 4)}
+    roof = roofline(stages, scene, K, passes, info)
 
     serving = None
     if not args.no_serving:

@@ -112,8 +112,14 @@ typedef struct cds_camera {
 typedef struct cds_render_opts {
     uint32_t flags;         /* CDS_OPT_* bits */
     int32_t blend_variant;  /* 0 = default; 1, 2, 4 = pixels per thread of the blend kernel */
-    int32_t sort_variant;   /* 0 = default: depth digits sorted per Gaussian, tile digits per key;
-                               1 = every digit of the 64-bit keys sorted per key.  Same result. */
+    int32_t sort_variant;   /* how the (tile | depth) list is ordered; every variant gives the same
+                               sorted keys, values and ranges:
+                               1 = 64-bit keys radix-sorted on all their digits;
+                               2 = depth digits sorted once per Gaussian, then the tile digits of
+                                   32-bit tile ids radix-sorted per key;
+                               3 = depth digits per Gaussian, then a counting sort on the whole tile id
+                                   fused with duplication (needs at most 4096 tiles per row);
+                               0 = default: 3 when possible, else 2. */
     int32_t reserved;
 } cds_render_opts;
 
@@ -198,7 +204,9 @@ typedef struct cds_frame_info {
     const int32_t* radius;         /* [n] screen radius in pixels, 0 if culled */
     const uint32_t* tile_rect;     /* [n] uint2: (tx0 | ty0 << 16, tx1 | ty1 << 16), inclusive */
     const uint32_t* tiles_touched; /* [n] number of covered tiles */
-    const uint32_t* offsets;       /* [n] exclusive prefix sum of tiles_touched */
+    const uint32_t* offsets;       /* [n] exclusive prefix sum of tiles_touched in visit order
+                                      (index order for sort variant 1, depth order for 2);
+                                      NULL for variant 3, which does not form it */
     const uint64_t* keys;          /* [K] sorted (tile << 32 | depth bits) */
     const uint32_t* values;        /* [K] Gaussian index of each sorted key */
     const uint32_t* ranges;        /* [tiles_x * tiles_y] uint2 [start, end), (0, 0) if empty */
@@ -210,7 +218,11 @@ cds_status cds_frame_get_info(cds_frame* frame, cds_frame_info* out);
 /* Per-stage device time of the frame's last forward (and backward) render,
  * in milliseconds, from HIP events recorded on the render's stream when the
  * forward ran with CDS_OPT_STAGE_TIMING.  Waits for those events.  `scan_ms`
- * includes the host read-back of the key count; backward fields are 0 until a
+ * covers everything between preprocessing and the host read-back of the key
+ * count, read-back included: the per-Gaussian depth sort (sort variants 2,
+ * 3), the prefix sum of tiles_touched (variants 1, 2) or the tile counts and
+ * their scans (variant 3).  With sort variant 3 `duplicate_ms` is the fused
+ * placement and `sort_ms`, `ranges_ms` are 0.  Backward fields are 0 until a
  * backward pass has run. */
 typedef struct cds_stage_times {
     float preprocess_ms, scan_ms, duplicate_ms, sort_ms, ranges_ms, blend_ms;

@@ -126,19 +126,55 @@ constexpr int64_t kSortRtsMinPartitions = int64_t(1) << 40;  // auto: onesweep (
 inline int64_t sort_partitions(int64_t count) { return (count + kSortPartition - 1) / kSortPartition; }
 bool sort_uses_onesweep(int64_t count, SortAlgo algo);
 hipError_t launch_sort_histogram(const uint64_t* keys, int64_t count, int passes, int shift0, uint32_t* hist,
-                                 hipStream_t stream);
+                                 hipStream_t stream, int end_bit = 0);
 hipError_t launch_sort_histogram(const uint32_t* keys, int64_t count, int passes, int shift0, uint32_t* hist,
-                                 hipStream_t stream);
+                                 hipStream_t stream, int end_bit = 0);
 hipError_t launch_sort_prepare(const SortWorkspace& ws, int64_t count, int passes, bool clear_hist,
                                hipStream_t stream);
+// Key bits at and above end_bit (0: shift0 + 8 * passes) must be zero; a
+// pass whose digit has fewer significant bits ranks on those bits only.
 hipError_t launch_sort_passes(const uint64_t* kin, const uint32_t* vin, uint64_t* ka, uint32_t* va,
                               uint64_t* kb, uint32_t* vb, int64_t count, int passes, int shift0,
-                              const SortWorkspace& ws, SortAlgo algo, hipStream_t stream);
+                              const SortWorkspace& ws, SortAlgo algo, hipStream_t stream, int end_bit = 0);
 hipError_t launch_sort_passes(const uint32_t* kin, const uint32_t* vin, uint32_t* ka, uint32_t* va,
                               uint32_t* kb, uint32_t* vb, int64_t count, int passes, int shift0,
-                              const SortWorkspace& ws, SortAlgo algo, hipStream_t stream);
+                              const SortWorkspace& ws, SortAlgo algo, hipStream_t stream, int end_bit = 0);
 
 hipError_t launch_fill_u32(uint32_t* p, int64_t count, uint32_t value, hipStream_t stream);
+
+// Tile binning (stable counting sort by tile of Gaussians already in depth
+// order, fused with duplication).  The visit order is cut into chunks of
+// `chunk` Gaussians and the tile grid into bands of `band_rows` rows; one
+// wave handles one (chunk, band) item.
+struct BinPlan {
+    int tiles_x = 0, tiles_y = 0;
+    int band_rows = 0, bands = 0;
+    int chunk = 0;        // Gaussians per chunk
+    int64_t chunks = 0;
+    int64_t groups = 0;   // chunk groups of the column scan
+    int64_t ntiles = 0;
+};
+constexpr int kBinChunk = 2048;
+constexpr int kBinGroup = 32;
+constexpr int kBinMaxBandRows = 16;
+constexpr int kBinMaxRowTiles = 4096;  // band_rows * tiles_x <= this (16 KiB of LDS per wave)
+bool bin_supported(int tiles_x, int tiles_y);
+BinPlan bin_plan(int64_t n, int tiles_x, int tiles_y);
+// rectangles in visit order, culled splats as empty rectangles: vrect [n]
+hipError_t launch_bin_gather(int64_t n, const uint32_t* order, const uint32_t* touched, const uint2* rect,
+                             uint2* vrect, hipStream_t stream);
+// M [chunks][ntiles]: keys of each chunk in each tile
+hipError_t launch_bin_count(const BinPlan& p, int64_t n, const uint2* vrect, uint32_t* M, hipStream_t stream);
+// M -> E (first list position of each chunk's keys in each tile, in place);
+// P [groups][ntiles] and tsum [ntiles] are workspace; ranges [ntiles]; *total = K
+hipError_t launch_bin_scan(const BinPlan& p, uint32_t* M, uint32_t* P, uint32_t* tsum, uint2* ranges,
+                           uint64_t* total, hipStream_t stream);
+// values [count]: Gaussian indices in (tile, visit order); err |= 4 on an inconsistent count
+hipError_t launch_bin_place(const BinPlan& p, int64_t n, const uint32_t* order, const uint2* vrect,
+                            const uint32_t* E, uint64_t count, uint32_t* values, uint32_t* err,
+                            hipStream_t stream);
+hipError_t launch_keys_from_ranges(const uint2* ranges, int64_t ntiles, const uint32_t* values,
+                                   const uint32_t* depth_bits, uint64_t* keys, hipStream_t stream);
 
 hipError_t launch_ranges(const uint32_t* tile_words, int stride, int64_t count, uint2* ranges,
                          int64_t ntiles, hipStream_t stream);

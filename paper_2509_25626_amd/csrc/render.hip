@@ -21,8 +21,11 @@ void release_frame_buffers(cds_frame* f) {
     DevBuf* bufs[] = {&f->mean2d, &f->conic, &f->rgb, &f->depth, &f->radius, &f->rect, &f->touched,
                       &f->offsets, &f->clampf, &f->blocksums, &f->total, &f->order0, &f->order1,
                       &f->dkey0, &f->dkey1, &f->sort_d.hist, &f->sort_d.status, &f->sort_d.counters,
+                      &f->sort_d.part_hist, &f->sort_d.bases, &f->sort_d.scan_sums, &f->sort_d.scan_total,
+                      &f->vrect, &f->binM, &f->binP, &f->tsum,
                       &f->keys0, &f->keys1, &f->tk0, &f->tk1, &f->vals0, &f->vals1, &f->sort.hist,
-                      &f->sort.status, &f->sort.counters, &f->ranges, &f->grad2d};
+                      &f->sort.status, &f->sort.counters, &f->sort.part_hist, &f->sort.bases,
+                      &f->sort.scan_sums, &f->sort.scan_total, &f->ranges, &f->grad2d};
     for (DevBuf* b : bufs) release(c, *b);
     f->valid = false;
 }
@@ -45,13 +48,18 @@ int tile_bits_for(int64_t ntiles) {
 }
 
 /*
- * Sort variant 0 (default): the 32 depth bits of every key of a Gaussian are
- * that Gaussian's depth, so the four depth-digit LSD passes are run once over
- * the N Gaussians (stable, ties by index) instead of over the K keys; keys are
- * then generated in that order, which is exactly the sequence the four depth
- * passes would have produced, and the remaining tile-digit passes run over
- * 32-bit tile ids.  The sorted (key, value) list is bit-identical to the
- * direct sort of the 64-bit keys (variant 1), at a third of the key traffic.
+ * Sort variants.  Every variant yields the same sorted (tile | depth, index)
+ * list and tile ranges.
+ *  1: the 64-bit keys are generated per (Gaussian, tile) and radix-sorted on
+ *     all their digits.
+ *  2: the 32 depth bits of every key of a Gaussian are that Gaussian's depth,
+ *     so the four depth-digit LSD passes run once over the N Gaussians
+ *     (stable, ties by index); keys are generated in that order -- exactly
+ *     the sequence the depth passes would have produced -- and only the
+ *     tile-digit passes run over the keys, as 32-bit tile ids.
+ *  3: as 2, but the tile-order pass is a counting sort on the whole tile id
+ *     fused with duplication (tile binning): no per-key sort pass at all.
+ *  0: 3 when the tile grid allows it, else 2.
  */
 cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scene, const cds_camera* cam,
                                int blend_variant, int sort_variant, SortAlgo algo, float* out_rgb, float* out_T,
@@ -63,6 +71,12 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
     const int64_t ntiles = (int64_t)P.tiles_x * P.tiles_y;
     const size_t nn = (size_t)(n > 0 ? n : 1);
     const int tile_passes = (tile_bits_for(ntiles) + 7) / 8;
+    const bool can_bin = bin_supported(P.tiles_x, P.tiles_y);
+    if (sort_variant == 0) sort_variant = can_bin ? 3 : 2;
+    if (sort_variant == 3 && !can_bin)
+        return fail(CDS_ERR_INVALID_ARG, "tile binning needs at most 4096 tiles per row");
+    const bool presort = sort_variant == 2 || sort_variant == 3;
+    const bool binned = sort_variant == 3;
 
     CDS_TRY(ensure(ctx, f->mean2d, sizeof(float2) * nn, 1.1));
     CDS_TRY(ensure(ctx, f->conic, sizeof(float4) * nn, 1.1));
@@ -71,17 +85,27 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
     CDS_TRY(ensure(ctx, f->radius, sizeof(int32_t) * nn, 1.1));
     CDS_TRY(ensure(ctx, f->rect, sizeof(uint2) * nn, 1.1));
     CDS_TRY(ensure(ctx, f->touched, sizeof(uint32_t) * nn, 1.1));
-    CDS_TRY(ensure(ctx, f->offsets, sizeof(uint32_t) * nn, 1.1));
     CDS_TRY(ensure(ctx, f->clampf, nn, 1.1));
-    CDS_TRY(ensure(ctx, f->blocksums, sizeof(uint64_t) * scan_block_sums_size(n), 1.1));
     CDS_TRY(ensure(ctx, f->total, 256));
     CDS_TRY(ensure(ctx, f->ranges, sizeof(uint2) * (size_t)ntiles, 1.1));
-    if (sort_variant == 0) {
+    if (!binned) {
+        CDS_TRY(ensure(ctx, f->offsets, sizeof(uint32_t) * nn, 1.1));
+        CDS_TRY(ensure(ctx, f->blocksums, sizeof(uint64_t) * scan_block_sums_size(n), 1.1));
+    }
+    if (presort) {
         CDS_TRY(ensure(ctx, f->order0, sizeof(uint32_t) * nn, 1.1));
         CDS_TRY(ensure(ctx, f->order1, sizeof(uint32_t) * nn, 1.1));
         CDS_TRY(ensure(ctx, f->dkey0, sizeof(uint32_t) * nn, 1.1));
         CDS_TRY(ensure(ctx, f->dkey1, sizeof(uint32_t) * nn, 1.1));
         CDS_TRY(ensure_sort_workspace(ctx, f->sort_d, n, 4));
+    }
+    BinPlan bp;
+    if (binned) {
+        bp = bin_plan(n, P.tiles_x, P.tiles_y);
+        CDS_TRY(ensure(ctx, f->vrect, sizeof(uint2) * nn, 1.1));
+        CDS_TRY(ensure(ctx, f->binM, sizeof(uint32_t) * (size_t)(bp.chunks * bp.ntiles), 1.1));
+        CDS_TRY(ensure(ctx, f->binP, sizeof(uint32_t) * (size_t)(bp.groups * bp.ntiles), 1.1));
+        CDS_TRY(ensure(ctx, f->tsum, sizeof(uint32_t) * (size_t)ntiles, 1.1));
     }
 
     SplatBuffers sb;
@@ -96,9 +120,9 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
     CDS_HIP(launch_preprocess(P, make_scene(scene), sb, stream), "preprocess kernel");
     CDS_TRY(f->record(1, stream));
 
-    // depth order of the Gaussians (variant 0): 4 passes, result in (dkey1, order1)
+    // depth order of the Gaussians (variants 2, 3): 4 passes, result in (dkey1, order1)
     const uint32_t* order = nullptr;
-    if (sort_variant == 0 && n > 0) {
+    if (presort && n > 0) {
         SortWorkspace wd = sort_ws(ctx, f->sort_d);
         if (sort_uses_onesweep(n, algo)) {
             CDS_HIP(launch_sort_prepare(wd, n, 4, true, stream), "depth sort prepare");
@@ -110,9 +134,18 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
         order = (const uint32_t*)f->order1.p;
     }
     uint64_t* d_total = (uint64_t*)f->total.p;
-    CDS_HIP(launch_exclusive_scan(sb.touched, order, (uint32_t*)f->offsets.p, n, (uint64_t*)f->blocksums.p,
-                                  d_total, stream),
-            "scan kernels");
+    if (binned) {
+        // per (chunk, band) tile counts, their column scan, tile ranges and K
+        CDS_HIP(launch_bin_gather(n, order, sb.touched, sb.rect, (uint2*)f->vrect.p, stream), "bin gather");
+        CDS_HIP(launch_bin_count(bp, n, (const uint2*)f->vrect.p, (uint32_t*)f->binM.p, stream), "bin count");
+        CDS_HIP(launch_bin_scan(bp, (uint32_t*)f->binM.p, (uint32_t*)f->binP.p, (uint32_t*)f->tsum.p,
+                                (uint2*)f->ranges.p, d_total, stream),
+                "bin scan");
+    } else {
+        CDS_HIP(launch_exclusive_scan(sb.touched, order, (uint32_t*)f->offsets.p, n, (uint64_t*)f->blocksums.p,
+                                      d_total, stream),
+                "scan kernels");
+    }
     CDS_HIP(hipMemcpyAsync(ctx->host_pinned, d_total, sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
             "hipMemcpyAsync(key count)");
     CDS_HIP(hipStreamSynchronize(stream), "hipStreamSynchronize(key count)");
@@ -120,72 +153,88 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
     const uint64_t K = ctx->host_pinned[0];
     if (K > (uint64_t)kSortMaxCount)
         return fail(CDS_ERR_CAPACITY, "render needs " + std::to_string(K) +
-                                          " tile keys; the radix sort supports at most 2^30-1");
-    const int passes = sort_variant == 0 ? tile_passes : 4 + tile_passes;
+                                          " tile keys; the sorted list supports at most 2^30-1");
     const size_t kk = (size_t)(K > 0 ? K : 1);
     CDS_TRY(ensure(ctx, f->vals0, sizeof(uint32_t) * kk, 1.25));
-    CDS_TRY(ensure(ctx, f->vals1, sizeof(uint32_t) * kk, 1.25));
-    if (sort_variant == 0) {
-        CDS_TRY(ensure(ctx, f->tk0, sizeof(uint32_t) * kk, 1.25));
-        CDS_TRY(ensure(ctx, f->tk1, sizeof(uint32_t) * kk, 1.25));
-    } else {
-        CDS_TRY(ensure(ctx, f->keys0, sizeof(uint64_t) * kk, 1.25));
-        CDS_TRY(ensure(ctx, f->keys1, sizeof(uint64_t) * kk, 1.25));
-    }
-    CDS_TRY(ensure_sort_workspace(ctx, f->sort, (int64_t)K, passes > 0 ? passes : 1));
-
-    SortWorkspace ws = sort_ws(ctx, f->sort);
-    if (K > 0) {
-        // onesweep passes need the digit histograms of all keys; the duplicate
-        // pass builds them per Gaussian and per rectangle row
-        const bool need_hist = sort_uses_onesweep((int64_t)K, algo) && passes > 0;
-        if (need_hist) CDS_HIP(launch_sort_prepare(ws, (int64_t)K, passes, true, stream), "sort prepare");
-        uint32_t* hist = need_hist ? ws.hist : nullptr;
-        if (sort_variant == 0)
-            CDS_HIP(launch_duplicate(n, order, (const uint32_t*)f->offsets.p, sb.touched, sb.rect, sb.depth_bits,
-                                     P.tiles_x, nullptr, (uint32_t*)f->tk0.p, (uint32_t*)f->vals0.p, hist, 0,
-                                     tile_passes, stream),
-                    "duplicate kernel");
-        else
-            CDS_HIP(launch_duplicate(n, nullptr, (const uint32_t*)f->offsets.p, sb.touched, sb.rect,
-                                     sb.depth_bits, P.tiles_x, (uint64_t*)f->keys0.p, nullptr,
-                                     (uint32_t*)f->vals0.p, hist, 4, tile_passes, stream),
-                    "duplicate kernel");
-    }
-    CDS_TRY(f->record(3, stream));
-    const bool odd = (passes & 1) != 0;
-    if (sort_variant == 0) {
-        if (K > 0)
-            CDS_HIP(launch_sort_passes((const uint32_t*)f->tk0.p, (const uint32_t*)f->vals0.p, (uint32_t*)f->tk1.p,
-                                       (uint32_t*)f->vals1.p, (uint32_t*)f->tk0.p, (uint32_t*)f->vals0.p,
-                                       (int64_t)K, passes, 0, ws, algo, stream),
-                    "tile sort");
-        f->res_tiles = (const uint32_t*)(odd ? f->tk1.p : f->tk0.p);
-        f->res_tile_stride = 1;
-        f->res_keys = nullptr;
-    } else {
-        if (K > 0)
-            CDS_HIP(launch_sort_passes((const uint64_t*)f->keys0.p, (const uint32_t*)f->vals0.p,
-                                       (uint64_t*)f->keys1.p, (uint32_t*)f->vals1.p, (uint64_t*)f->keys0.p,
-                                       (uint32_t*)f->vals0.p, (int64_t)K, passes, 0, ws, algo, stream),
-                    "key sort");
-        f->res_keys = (const uint64_t*)(odd ? f->keys1.p : f->keys0.p);
-        f->res_tiles = reinterpret_cast<const uint32_t*>(f->res_keys) + 1;  // high words
-        f->res_tile_stride = 2;
-    }
-    f->res_values = (const uint32_t*)(odd ? f->vals1.p : f->vals0.p);
-    CDS_TRY(f->record(4, stream));
     f->n = n;
     f->K = (int64_t)K;
     f->width = cam->width;
     f->height = cam->height;
     f->tiles_x = P.tiles_x;
     f->tiles_y = P.tiles_y;
-    f->passes = sort_variant == 0 ? 4 + tile_passes : passes;
     f->sort_variant = sort_variant;
-    CDS_HIP(launch_ranges(f->res_tiles, f->res_tile_stride, (int64_t)K, (uint2*)f->ranges.p, ntiles, stream),
-            "ranges kernel");
-    CDS_TRY(f->record(5, stream));
+
+    if (binned) {
+        CDS_HIP(launch_bin_place(bp, n, order, (const uint2*)f->vrect.p, (const uint32_t*)f->binM.p, K,
+                                 (uint32_t*)f->vals0.p, ctx->d_err, stream),
+                "bin place");
+        CDS_TRY(f->record(3, stream));
+        CDS_TRY(f->record(4, stream));
+        CDS_TRY(f->record(5, stream));
+        f->res_values = (const uint32_t*)f->vals0.p;
+        f->res_tiles = nullptr;
+        f->res_tile_stride = 1;
+        f->res_keys = nullptr;
+        f->passes = 4;
+    } else {
+        const int passes = presort ? tile_passes : 4 + tile_passes;
+        CDS_TRY(ensure(ctx, f->vals1, sizeof(uint32_t) * kk, 1.25));
+        if (presort) {
+            CDS_TRY(ensure(ctx, f->tk0, sizeof(uint32_t) * kk, 1.25));
+            CDS_TRY(ensure(ctx, f->tk1, sizeof(uint32_t) * kk, 1.25));
+        } else {
+            CDS_TRY(ensure(ctx, f->keys0, sizeof(uint64_t) * kk, 1.25));
+            CDS_TRY(ensure(ctx, f->keys1, sizeof(uint64_t) * kk, 1.25));
+        }
+        CDS_TRY(ensure_sort_workspace(ctx, f->sort, (int64_t)K, passes > 0 ? passes : 1));
+        SortWorkspace ws = sort_ws(ctx, f->sort);
+        if (K > 0) {
+            // onesweep passes need the digit histograms of all keys; the duplicate
+            // pass builds them per Gaussian and per rectangle row
+            const bool need_hist = sort_uses_onesweep((int64_t)K, algo) && passes > 0;
+            if (need_hist) CDS_HIP(launch_sort_prepare(ws, (int64_t)K, passes, true, stream), "sort prepare");
+            uint32_t* hist = need_hist ? ws.hist : nullptr;
+            if (presort)
+                CDS_HIP(launch_duplicate(n, order, (const uint32_t*)f->offsets.p, sb.touched, sb.rect,
+                                         sb.depth_bits, P.tiles_x, nullptr, (uint32_t*)f->tk0.p,
+                                         (uint32_t*)f->vals0.p, hist, 0, tile_passes, stream),
+                        "duplicate kernel");
+            else
+                CDS_HIP(launch_duplicate(n, nullptr, (const uint32_t*)f->offsets.p, sb.touched, sb.rect,
+                                         sb.depth_bits, P.tiles_x, (uint64_t*)f->keys0.p, nullptr,
+                                         (uint32_t*)f->vals0.p, hist, 4, tile_passes, stream),
+                        "duplicate kernel");
+        }
+        CDS_TRY(f->record(3, stream));
+        const bool odd = (passes & 1) != 0;
+        if (presort) {
+            if (K > 0)
+                CDS_HIP(launch_sort_passes((const uint32_t*)f->tk0.p, (const uint32_t*)f->vals0.p,
+                                           (uint32_t*)f->tk1.p, (uint32_t*)f->vals1.p, (uint32_t*)f->tk0.p,
+                                           (uint32_t*)f->vals0.p, (int64_t)K, passes, 0, ws, algo, stream,
+                                           tile_bits_for(ntiles)),
+                        "tile sort");
+            f->res_tiles = (const uint32_t*)(odd ? f->tk1.p : f->tk0.p);
+            f->res_tile_stride = 1;
+            f->res_keys = nullptr;
+        } else {
+            if (K > 0)
+                CDS_HIP(launch_sort_passes((const uint64_t*)f->keys0.p, (const uint32_t*)f->vals0.p,
+                                           (uint64_t*)f->keys1.p, (uint32_t*)f->vals1.p, (uint64_t*)f->keys0.p,
+                                           (uint32_t*)f->vals0.p, (int64_t)K, passes, 0, ws, algo, stream,
+                                           32 + tile_bits_for(ntiles)),
+                        "key sort");
+            f->res_keys = (const uint64_t*)(odd ? f->keys1.p : f->keys0.p);
+            f->res_tiles = reinterpret_cast<const uint32_t*>(f->res_keys) + 1;  // high words
+            f->res_tile_stride = 2;
+        }
+        f->res_values = (const uint32_t*)(odd ? f->vals1.p : f->vals0.p);
+        CDS_TRY(f->record(4, stream));
+        f->passes = presort ? 4 + tile_passes : passes;
+        CDS_HIP(launch_ranges(f->res_tiles, f->res_tile_stride, (int64_t)K, (uint2*)f->ranges.p, ntiles, stream),
+                "ranges kernel");
+        CDS_TRY(f->record(5, stream));
+    }
 
     BlendArgs ba;
     ba.ranges = (const uint2*)f->ranges.p;
@@ -207,13 +256,18 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
     return CDS_OK;
 }
 
-// Build the 64-bit sorted keys of a variant-0 render (for inspection).
+// Build the 64-bit sorted keys of a render that did not sort them (for inspection).
 cds_status frame_build_keys(cds_frame* f) {
     if (f->res_keys || f->K == 0) return CDS_OK;
     CDS_TRY(ensure(f->ctx, f->keys0, sizeof(uint64_t) * (size_t)f->K, 1.25));
-    CDS_HIP(launch_make_keys(f->res_tiles, f->res_values, (const uint32_t*)f->depth.p, f->K,
-                             (uint64_t*)f->keys0.p, nullptr),
-            "make keys");
+    if (f->res_tiles)
+        CDS_HIP(launch_make_keys(f->res_tiles, f->res_values, (const uint32_t*)f->depth.p, f->K,
+                                 (uint64_t*)f->keys0.p, nullptr),
+                "make keys");
+    else
+        CDS_HIP(launch_keys_from_ranges((const uint2*)f->ranges.p, (int64_t)f->tiles_x * f->tiles_y, f->res_values,
+                                        (const uint32_t*)f->depth.p, (uint64_t*)f->keys0.p, nullptr),
+                "keys from ranges");
     CDS_HIP(hipStreamSynchronize(nullptr), "hipStreamSynchronize");
     f->res_keys = (const uint64_t*)f->keys0.p;
     return CDS_OK;

@@ -258,8 +258,8 @@ cds_status cds_render_forward(cds_ctx* ctx, cds_frame* f, const cds_scene* scene
         variant = opts->blend_variant;
         if (variant != 0 && variant != 1 && variant != 2 && variant != 4)
             return fail(CDS_ERR_INVALID_ARG, "blend_variant must be 0, 1, 2 or 4");
-        if (opts->sort_variant != 0 && opts->sort_variant != 1)
-            return fail(CDS_ERR_INVALID_ARG, "sort_variant must be 0 or 1");
+        if (opts->sort_variant < 0 || opts->sort_variant > 3)
+            return fail(CDS_ERR_INVALID_ARG, "sort_variant must be 0, 1, 2 or 3");
         sort_variant = opts->sort_variant;
     }
     hipStream_t stream = (hipStream_t)stream_;
@@ -321,7 +321,7 @@ cds_status cds_frame_get_info(cds_frame* f, cds_frame_info* o) {
     o->radius = (const int32_t*)f->radius.p;
     o->tile_rect = (const uint32_t*)f->rect.p;
     o->tiles_touched = (const uint32_t*)f->touched.p;
-    o->offsets = (const uint32_t*)f->offsets.p;
+    o->offsets = f->sort_variant == 3 ? nullptr : (const uint32_t*)f->offsets.p;
     o->keys = f->res_keys;
     o->values = f->res_values;
     o->ranges = (const uint32_t*)f->ranges.p;
@@ -364,9 +364,10 @@ cds_status cds_sort_pairs(cds_ctx* ctx, const uint64_t* keys_in, const uint32_t*
     SortWorkspace ws = sort_ws(ctx, s->sort);
     if ((e = launch_sort_prepare(ws, count, passes, true, stream)) != hipSuccess) return hip_fail(e, "sort prepare");
     if (sort_uses_onesweep(count, algo) &&
-        (e = launch_sort_histogram(keys_in, count, passes, 0, ws.hist, stream)) != hipSuccess)
+        (e = launch_sort_histogram(keys_in, count, passes, 0, ws.hist, stream, end_bit)) != hipSuccess)
         return hip_fail(e, "sort histogram");
-    if ((e = launch_sort_passes(keys_in, values_in, ka, va, kb, vb, count, passes, 0, ws, algo, stream)) !=
+    if ((e = launch_sort_passes(keys_in, values_in, ka, va, kb, vb, count, passes, 0, ws, algo, stream,
+                                end_bit)) !=
         hipSuccess)
         return hip_fail(e, "sort passes");
     return CDS_OK;

@@ -32,11 +32,12 @@ struct cds_frame {
     // per Gaussian
     cds::DevBuf mean2d, conic, rgb, depth, radius, rect, touched, offsets, clampf;
     cds::DevBuf blocksums, total;
-    cds::DevBuf order0, order1, dkey0, dkey1;  // per-Gaussian depth sort (sort variant 0)
+    cds::DevBuf order0, order1, dkey0, dkey1;  // per-Gaussian depth sort (sort variants 2, 3)
+    cds::DevBuf vrect, binM, binP, tsum;       // tile binning (sort variant 3)
     cds::SortState sort_d;
     // per key
-    cds::DevBuf keys0, keys1;                  // 64-bit keys (variant 1; variant 0: rebuilt on request)
-    cds::DevBuf tk0, tk1;                      // 32-bit tile ids (variant 0)
+    cds::DevBuf keys0, keys1;                  // 64-bit keys (variant 1; others: rebuilt on request)
+    cds::DevBuf tk0, tk1;                      // 32-bit tile ids (variant 2)
     cds::DevBuf vals0, vals1;
     cds::SortState sort;
     // per tile
@@ -48,9 +49,9 @@ struct cds_frame {
     bool valid = false;
     // where the last render left its sorted list
     const uint32_t* res_values = nullptr;
-    const uint32_t* res_tiles = nullptr;  // tile id words, stride res_tile_stride
+    const uint32_t* res_tiles = nullptr;  // tile id words, stride res_tile_stride (null: binned)
     int res_tile_stride = 1;
-    const uint64_t* res_keys = nullptr;   // 64-bit keys, null until built (variant 0)
+    const uint64_t* res_keys = nullptr;   // 64-bit keys, null until built (variants 2, 3)
     // stage timing: events 0..6 bracket the forward stages, 7..9 the backward
     bool timing = false, timed_backward = false;
     hipEvent_t ev[10] = {};

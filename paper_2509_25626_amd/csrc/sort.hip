@@ -24,6 +24,8 @@
 //    bounds large sorts, so it is used for small ones.  Its wait is bounded:
 //    after ~2^22 polls a workgroup records an error and proceeds, so a logic
 //    error can corrupt the output but never hang the device.
+#include <algorithm>
+
 #include "device_utils.h"
 #include "internal.h"
 
@@ -50,7 +52,7 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, int6
 // Digit histograms of `passes` 8-bit digits (starting at bit `shift0`) over all keys.
 template <typename Key>
 __global__ __launch_bounds__(256) void k_sort_histogram(const Key* __restrict__ keys, int64_t count,
-                                                        int passes, int shift0,
+                                                        int passes, int shift0, int end_bit,
                                                         uint32_t* __restrict__ hist) {
     __shared__ uint32_t s_hist[8 * 256];
     for (int k = threadIdx.x; k < passes * 256; k += blockDim.x) s_hist[k] = 0;
@@ -59,7 +61,11 @@ __global__ __launch_bounds__(256) void k_sort_histogram(const Key* __restrict__ 
          i += (int64_t)gridDim.x * blockDim.x) {
         const Key key = keys[i];
         for (int p = 0; p < passes; ++p)
-            atomicAdd(&s_hist[p * 256 + (uint32_t)((key >> (shift0 + 8 * p)) & 255u)], 1u);
+        {
+            const int sh = shift0 + 8 * p;
+            const int bits = min(8, end_bit - sh);
+            atomicAdd(&s_hist[p * 256 + ((uint32_t)(key >> sh) & ((1u << bits) - 1u))], 1u);
+        }
     }
     __syncthreads();
     for (int k = threadIdx.x; k < passes * 256; k += blockDim.x) {
@@ -68,16 +74,24 @@ __global__ __launch_bounds__(256) void k_sort_histogram(const Key* __restrict__ 
     }
 }
 
-// Lanes of the wave holding the same 8-bit digit (restricted to `valid` lanes).
-__device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
-    uint64_t peers = ballot(valid);
+// Lanes of the wave holding the same digit (restricted to `valid` lanes),
+// from one ballot per significant digit bit (`bits` <= 8, uniform).  x is
+// all ones where the bit is set, so the lanes agreeing with this lane on the
+// bit are ~(m ^ x): five VALU operations per bit.
+__device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid, int bits) {
+    const uint64_t v = ballot(valid);
+    uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
-        const bool bit = (d >> b) & 1u;
-        const uint64_t m = ballot(bit);
-        peers &= bit ? m : ~m;
+        if (b < bits) {
+            uint32_t x = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);
+            asm("" : "+v"(x));  // compare x itself rather than a re-derived shift of d
+            const uint64_t m = ballot(x != 0u);
+            lo &= ~((uint32_t)m ^ x);
+            hi &= ~((uint32_t)(m >> 32) ^ x);
+        }
     }
-    return peers;
+    return ((uint64_t)hi << 32) | lo;
 }
 
 // Per-partition digit counts, digit-major: part_hist[d * parts + p].  Each
@@ -85,7 +99,7 @@ __device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
 // otherwise serialise on one address).
 template <typename Key>
 __global__ __launch_bounds__(kNT) void k_rts_upsweep(const Key* __restrict__ keys, int64_t count, int shift,
-                                                     uint32_t* __restrict__ part_hist, int64_t parts) {
+                                                     int bits, uint32_t* __restrict__ part_hist, int64_t parts) {
     __shared__ uint32_t s_h[256];
     const int t = threadIdx.x;
     s_h[t] = 0;
@@ -95,8 +109,8 @@ __global__ __launch_bounds__(kNT) void k_rts_upsweep(const Key* __restrict__ key
     for (int r = 0; r < kKPT; ++r) {
         const int64_t idx = base + (int64_t)r * kNT + t;
         const bool valid = idx < count;
-        const uint32_t d = valid ? (uint32_t)(keys[idx] >> shift) & 255u : 0u;
-        const uint64_t peers = digit_peers(d, valid);
+        const uint32_t d = valid ? (uint32_t)(keys[idx] >> shift) & ((1u << bits) - 1u) : 0u;
+        const uint64_t peers = digit_peers(d, valid, bits);
         if (valid && count_below(peers) == 0) atomicAdd(&s_h[d], (uint32_t)__popcll(peers));
     }
     __syncthreads();
@@ -111,6 +125,8 @@ struct PassArgs {
     uint32_t* vout;
     int64_t count;
     int shift;
+    int bits;               // digit bits of this pass (1..8): key bits [shift, shift + bits)
+    uint32_t dmask;         // (1 << bits) - 1
     const uint32_t* hist;   // onesweep: [256] digit counts of all keys
     uint32_t* status;       // onesweep: [partitions][256]
     uint32_t* counter;      // onesweep: partition-id counter
@@ -152,8 +168,8 @@ __global__ __launch_bounds__(kNT) void k_sort_pass(PassArgs<Key> a) {
 #pragma unroll
     for (int r = 0; r < kKPT; ++r) {
         const bool valid = (wbase + r * kWave + l) < a.count;
-        const uint32_t d = (uint32_t)(key[r] >> a.shift) & 255u;
-        const uint64_t peers = digit_peers(d, valid);
+        const uint32_t d = (uint32_t)(key[r] >> a.shift) & a.dmask;
+        const uint64_t peers = digit_peers(d, valid, a.bits);
         const uint32_t below = count_below(peers);
         const uint32_t cnt = (uint32_t)__popcll(peers);
         uint32_t pre = 0;
@@ -228,7 +244,7 @@ __global__ __launch_bounds__(kNT) void k_sort_pass(PassArgs<Key> a) {
     for (int r = 0; r < kKPT; ++r) {
         const bool valid = (wbase + r * kWave + l) < a.count;
         if (valid) {
-            const uint32_t d = (uint32_t)(key[r] >> a.shift) & 255u;
+            const uint32_t d = (uint32_t)(key[r] >> a.shift) & a.dmask;
             const uint32_t pos = s_whist[w][d] + rank[r];
             if (pos < (uint32_t)kP) s_keys[pos] = key[r];
         }
@@ -243,7 +259,7 @@ __global__ __launch_bounds__(kNT) void k_sort_pass(PassArgs<Key> a) {
         gpos[r] = 0;
         if (i < nvalid) {
             const Key k = s_keys[i];
-            const uint32_t d = (uint32_t)(k >> a.shift) & 255u;
+            const uint32_t d = (uint32_t)(k >> a.shift) & a.dmask;
             const uint32_t g = s_gbase[d] + i;
             // a position outside the output can only come from inconsistent digit
             // counts; record it instead of writing out of bounds
@@ -259,7 +275,7 @@ __global__ __launch_bounds__(kNT) void k_sort_pass(PassArgs<Key> a) {
     for (int r = 0; r < kKPT; ++r) {
         const bool valid = (wbase + r * kWave + l) < a.count;
         if (valid) {
-            const uint32_t d = (uint32_t)(key[r] >> a.shift) & 255u;
+            const uint32_t d = (uint32_t)(key[r] >> a.shift) & a.dmask;
             const uint32_t pos = s_whist[w][d] + rank[r];
             if (pos < (uint32_t)kP) s_vals[pos] = val[r];
         }
@@ -273,20 +289,20 @@ __global__ __launch_bounds__(kNT) void k_sort_pass(PassArgs<Key> a) {
 }
 
 template <typename Key>
-hipError_t sort_histogram_impl(const Key* keys, int64_t count, int passes, int shift0, uint32_t* hist,
+hipError_t sort_histogram_impl(const Key* keys, int64_t count, int passes, int shift0, int end_bit, uint32_t* hist,
                                hipStream_t stream) {
     if (count <= 0) return hipSuccess;
     int64_t blocks = (count + 255) / 256;
     if (blocks > 2048) blocks = 2048;
     hipLaunchKernelGGL(k_sort_histogram<Key>, dim3((unsigned)blocks), dim3(256), 0, stream, keys, count,
-                       passes, shift0, hist);
+                       passes, shift0, end_bit > 0 ? end_bit : shift0 + 8 * passes, hist);
     return hipGetLastError();
 }
 
 template <typename Key>
 hipError_t sort_passes_impl(const Key* kin, const uint32_t* vin, Key* ka, uint32_t* va, Key* kb,
-                            uint32_t* vb, int64_t count, int passes, int shift0, const SortWorkspace& ws,
-                            SortAlgo algo, hipStream_t stream) {
+                            uint32_t* vb, int64_t count, int passes, int shift0, int end_bit,
+                            const SortWorkspace& ws, SortAlgo algo, hipStream_t stream) {
     if (count <= 0 || passes <= 0) return hipSuccess;
     if (count > kSortMaxCount) return hipErrorInvalidValue;
     const int64_t parts = sort_partitions(count);
@@ -299,6 +315,8 @@ hipError_t sort_passes_impl(const Key* kin, const uint32_t* vin, Key* ka, uint32
         a.vout = (p & 1) ? vb : va;
         a.count = count;
         a.shift = shift0 + 8 * p;
+        a.bits = std::max(1, std::min(8, end_bit - a.shift));
+        a.dmask = (1u << a.bits) - 1u;
         a.hist = ws.hist + (size_t)p * 256;
         a.status = ws.status + (size_t)p * parts * 256;
         a.counter = ws.counters + p;
@@ -310,7 +328,7 @@ hipError_t sort_passes_impl(const Key* kin, const uint32_t* vin, Key* ka, uint32
             hipLaunchKernelGGL((k_sort_pass<Key, true>), dim3((unsigned)parts), dim3(kNT), 0, stream, a);
         } else {
             hipLaunchKernelGGL(k_rts_upsweep<Key>, dim3((unsigned)parts), dim3(kNT), 0, stream, a.kin, count,
-                               a.shift, ws.part_hist, parts);
+                               a.shift, a.bits, ws.part_hist, parts);
             if ((e = hipGetLastError()) != hipSuccess) return e;
             e = launch_exclusive_scan(ws.part_hist, nullptr, ws.bases, 256 * parts, ws.scan_sums, ws.scan_total,
                                       stream);
@@ -338,13 +356,13 @@ hipError_t launch_fill_u32(uint32_t* p, int64_t count, uint32_t value, hipStream
 }
 
 hipError_t launch_sort_histogram(const uint64_t* keys, int64_t count, int passes, int shift0, uint32_t* hist,
-                                 hipStream_t stream) {
-    return sort_histogram_impl<uint64_t>(keys, count, passes, shift0, hist, stream);
+                                 hipStream_t stream, int end_bit) {
+    return sort_histogram_impl<uint64_t>(keys, count, passes, shift0, end_bit, hist, stream);
 }
 
 hipError_t launch_sort_histogram(const uint32_t* keys, int64_t count, int passes, int shift0, uint32_t* hist,
-                                 hipStream_t stream) {
-    return sort_histogram_impl<uint32_t>(keys, count, passes, shift0, hist, stream);
+                                 hipStream_t stream, int end_bit) {
+    return sort_histogram_impl<uint32_t>(keys, count, passes, shift0, end_bit, hist, stream);
 }
 
 hipError_t launch_sort_prepare(const SortWorkspace& ws, int64_t count, int passes, bool clear_hist,
@@ -360,14 +378,16 @@ hipError_t launch_sort_prepare(const SortWorkspace& ws, int64_t count, int passe
 
 hipError_t launch_sort_passes(const uint64_t* kin, const uint32_t* vin, uint64_t* ka, uint32_t* va,
                               uint64_t* kb, uint32_t* vb, int64_t count, int passes, int shift0,
-                              const SortWorkspace& ws, SortAlgo algo, hipStream_t stream) {
-    return sort_passes_impl<uint64_t>(kin, vin, ka, va, kb, vb, count, passes, shift0, ws, algo, stream);
+                              const SortWorkspace& ws, SortAlgo algo, hipStream_t stream, int end_bit) {
+    return sort_passes_impl<uint64_t>(kin, vin, ka, va, kb, vb, count, passes, shift0,
+                                      end_bit > 0 ? end_bit : shift0 + 8 * passes, ws, algo, stream);
 }
 
 hipError_t launch_sort_passes(const uint32_t* kin, const uint32_t* vin, uint32_t* ka, uint32_t* va,
                               uint32_t* kb, uint32_t* vb, int64_t count, int passes, int shift0,
-                              const SortWorkspace& ws, SortAlgo algo, hipStream_t stream) {
-    return sort_passes_impl<uint32_t>(kin, vin, ka, va, kb, vb, count, passes, shift0, ws, algo, stream);
+                              const SortWorkspace& ws, SortAlgo algo, hipStream_t stream, int end_bit) {
+    return sort_passes_impl<uint32_t>(kin, vin, ka, va, kb, vb, count, passes, shift0,
+                                      end_bit > 0 ? end_bit : shift0 + 8 * passes, ws, algo, stream);
 }
 
 }  // namespace cds
