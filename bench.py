@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "room"])
     ap.add_argument("--blend-variant", type=int, default=0)
+    ap.add_argument("--sort-variant", type=int, default=0, choices=[0, 1, 2, 3])
+    ap.add_argument("--sort-algo", default="auto", choices=["auto", "onesweep", "reduce_scan"])
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
@@ -153,7 +155,8 @@ def main():
            torch.empty((H, W), dtype=torch.int32, device=dev))
 
     def fwd(timing=False):
-        return R.forward(scene, cam, frame=frame, blend_variant=args.blend_variant, out=out, timing=timing)
+        return R.forward(scene, cam, frame=frame, blend_variant=args.blend_variant, out=out, timing=timing,
+                         sort_variant=args.sort_variant, sort_algo=args.sort_algo)
 
     for _ in range(args.warmup):
         fwd()

@@ -47,7 +47,8 @@ typedef enum cds_status {
     CDS_OK = 0,
     CDS_ERR_INVALID_ARG = 1, /* bad pointer, size or option; nothing was enqueued */
     CDS_ERR_OOM = 2,         /* the allocator returned NULL; outputs unspecified, no leak */
-    CDS_ERR_CAPACITY = 3,    /* a size limit of the library was exceeded (e.g. > 2^32-1 keys) */
+    CDS_ERR_CAPACITY = 3,    /* a size limit of the library was exceeded (more than 2^31-1
+                                Gaussians or 2^30-1 tile keys) */
     CDS_ERR_DEVICE = 4,      /* a HIP call or a device-side check failed (message has details) */
     CDS_ERR_BUSY = 5         /* the server has no free slot / budget for the request right now */
 } cds_status;
@@ -62,8 +63,8 @@ typedef struct cds_allocator {
     void* user;
 } cds_allocator;
 
-/* A scene: n Gaussians as structure-of-arrays float32 planes in DEVICE memory,
- * owned by the caller and only read by the library.
+/* A scene: n Gaussians (0 <= n <= 2^31-1) as structure-of-arrays float32
+ * planes in DEVICE memory, owned by the caller and only read by the library.
  *   means          [3][n]              world-space centres
  *   log_scales     [3][n]              log of the per-axis standard deviation
  *   quats          [4][n]              rotation (w, x, y, z); need not be normalised
@@ -119,7 +120,7 @@ typedef struct cds_render_opts {
                                    32-bit tile ids radix-sorted per key;
                                3 = depth digits per Gaussian, then a counting sort on the whole tile id
                                    fused with duplication (needs at most 4096 tiles per row);
-                               0 = default: 3 when possible, else 2. */
+                               0 = default: 2. */
     int32_t reserved;
 } cds_render_opts;
 
@@ -183,7 +184,9 @@ cds_status cds_render_backward(cds_ctx* ctx, cds_frame* frame, const cds_scene* 
 
 /* L1 image loss helper: dL_drgb[i] = sign(rgb[i] - target[i]) / count and,
  * if loss_out is not NULL, loss_out[0] = mean |rgb - target| (DEVICE float,
- * overwritten).  All pointers DEVICE, count elements. */
+ * overwritten; summed in a fixed order, so repeated calls agree bit for bit).
+ * All pointers DEVICE, count elements.  Calls on one context share a small
+ * reduction workspace: do not overlap them on different streams. */
 cds_status cds_l1_loss_grad(cds_ctx* ctx, const float* rgb, const float* target, int64_t count,
                             float* dL_drgb, float* loss_out, void* stream);
 

@@ -202,7 +202,7 @@ __global__ __launch_bounds__(256 / PPT) void k_blend_batch(const BatchItem* __re
 //   dL/dalpha_i = T_i (rgb_i - S_i) . dL/dC,   S_{i-1} = alpha_i rgb_i + (1 - alpha_i) S_i
 // alpha = min(0.99, o G): when unclamped dalpha/do = G and dalpha/dpower = alpha.
 // Per-splat sums over the wave are reduced with cross-lane shuffles and
-// added to the per-Gaussian 2D gradients with one atomic per value.
+// added to the per-Gaussian 2D gradients ([n][9]) with atomics.
 template <int PPT>
 __global__ __launch_bounds__(256 / PPT) void k_blend_bwd(BlendBwdArgs a, uint32_t per_xcd) {
     constexpr int NT = 256 / PPT;
@@ -287,7 +287,7 @@ __global__ __launch_bounds__(256 / PPT) void k_blend_bwd(BlendBwdArgs a, uint32_
                 any = true;
                 const float dyf = (float)dy;
                 const float one_m = 1.0f - alpha;
-                T[p] = T[p] / one_m;
+                T[p] = T[p] * __builtin_amdgcn_rcpf(one_m);  // 1 ulp; alpha <= 0.99
                 const float Tp = T[p];
                 const float dLda = Tp * ((f.y - S0[p]) * D0[p] + (f.z - S1[p]) * D1[p] +
                                          (f.w - S2[p]) * D2[p]);
@@ -310,31 +310,28 @@ __global__ __launch_bounds__(256 / PPT) void k_blend_bwd(BlendBwdArgs a, uint32_
                 }
             }
             if (__any(any)) {
-                gmx = wave_sum(gmx); gmy = wave_sum(gmy);
-                gA = wave_sum(gA); gB = wave_sum(gB); gC = wave_sum(gC);
-                go = wave_sum(go);
-                gr = wave_sum(gr); gg = wave_sum(gg); gb = wave_sum(gb);
-                if (lane_id() == 0) {
-                    const uint32_t id = s_id[k];
-                    float* g = a.grad2d;
-                    atomicAdd(g + id, gmx * kLn2);
-                    atomicAdd(g + n + id, gmy * kLn2);
-                    atomicAdd(g + 2 * n + id, gA);
-                    atomicAdd(g + 3 * n + id, gB);
-                    atomicAdd(g + 4 * n + id, gC);
-                    atomicAdd(g + 5 * n + id, go);
-                    atomicAdd(g + 6 * n + id, gr);
-                    atomicAdd(g + 7 * n + id, gg);
-                    atomicAdd(g + 8 * n + id, gb);
-                }
+                // nine wave sums: eight scattered over lane groups, one full;
+                // each Gaussian's nine gradients are contiguous, so one atomic
+                // instruction covers them
+                const float v8[8] = {gmx * kLn2, gmy * kLn2, gA, gB, gC, go, gr, gg};
+                const float s8 = wave_reduce_scatter8(v8);
+                const float sb = wave_sum(gb);
+                const uint32_t l = lane_id();
+                float* g = a.grad2d + (size_t)s_id[k] * 9;
+                if ((l & 7u) == 0) atomicAdd(g + (l >> 3), s8);
+                if (l == 0) atomicAdd(g + 8, sb);
             }
         }
     }
 }
 
+constexpr int kLossBlocks = 1024;
+
+// dL/drgb of the mean absolute error, and per-block partial sums of |rgb - target|.
 __global__ __launch_bounds__(256) void k_l1_loss_grad(const float* __restrict__ rgb,
                                                       const float* __restrict__ target, int64_t count,
-                                                      float* __restrict__ grad, float* loss) {
+                                                      float* __restrict__ grad, float* __restrict__ partial) {
+    __shared__ float s_w[256 / kWave];
     float acc = 0.0f;
     const float inv = 1.0f / (float)count;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
@@ -343,9 +340,26 @@ __global__ __launch_bounds__(256) void k_l1_loss_grad(const float* __restrict__ 
         grad[i] = d > 0.0f ? inv : (d < 0.0f ? -inv : 0.0f);
         acc += fabsf(d);
     }
-    if (loss) {
+    if (partial) {
         acc = wave_sum(acc);
-        if (lane_id() == 0) atomicAdd(loss, acc * inv);
+        if (lane_id() == 0) s_w[threadIdx.x / kWave] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) partial[blockIdx.x] = (s_w[0] + s_w[1]) + (s_w[2] + s_w[3]);
+    }
+}
+
+// loss = (sum of the partials, in a fixed order) / count: deterministic.
+__global__ __launch_bounds__(kLossBlocks) void k_l1_loss_finish(const float* __restrict__ partial, int nparts,
+                                                                int64_t count, float* __restrict__ loss) {
+    __shared__ float s_w[kLossBlocks / kWave];
+    float v = (int)threadIdx.x < nparts ? partial[threadIdx.x] : 0.0f;
+    v = wave_sum(v);
+    if (lane_id() == 0) s_w[threadIdx.x / kWave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float t = 0.0f;
+        for (int k = 0; k < kLossBlocks / kWave; ++k) t += s_w[k];
+        *loss = t / (float)count;
     }
 }
 
@@ -386,16 +400,15 @@ hipError_t launch_blend_backward(const BlendBwdArgs& a, hipStream_t stream) {
 }
 
 hipError_t launch_l1_loss_grad(const float* rgb, const float* target, int64_t count, float* grad,
-                               float* loss, hipStream_t stream) {
+                               float* loss, float* partial, hipStream_t stream) {
     if (count <= 0) return hipSuccess;
-    if (loss) {
-        hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(loss), 1, 0u, stream);
-        if (e != hipSuccess) return e;
-    }
     int64_t blocks = (count + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_l1_loss_grad, dim3((unsigned)blocks), dim3(256), 0, stream, rgb, target,
-                       count, grad, loss);
+    if (blocks > kLossBlocks) blocks = kLossBlocks;
+    hipLaunchKernelGGL(k_l1_loss_grad, dim3((unsigned)blocks), dim3(256), 0, stream, rgb, target, count, grad,
+                       loss ? partial : nullptr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !loss) return e;
+    hipLaunchKernelGGL(k_l1_loss_finish, dim3(1), dim3(kLossBlocks), 0, stream, partial, (int)blocks, count, loss);
     return hipGetLastError();
 }
 

@@ -38,6 +38,29 @@ __device__ __forceinline__ float wave_sum(float v) {
     return v;
 }
 
+// Wave sums of eight per-lane values, scattered over the lanes: afterwards
+// every lane holds the total of value index (lane >> 3) & 7.  Each butterfly
+// step sends half of the values still held and keeps the other half, so the
+// eight sums cost 4 + 2 + 1 + 3 = 10 cross-lane exchanges instead of 8 * 6.
+__device__ __forceinline__ float wave_reduce_scatter8(const float (&v)[8]) {
+    const uint32_t l = lane_id();
+    float a[4], b[2];
+    const bool h5 = (l & 32u) != 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        a[i] = (h5 ? v[4 + i] : v[i]) + __shfl_xor(h5 ? v[i] : v[4 + i], 32, kWave);
+    const bool h4 = (l & 16u) != 0;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+        b[i] = (h4 ? a[2 + i] : a[i]) + __shfl_xor(h4 ? a[i] : a[2 + i], 16, kWave);
+    const bool h3 = (l & 8u) != 0;
+    float c = (h3 ? b[1] : b[0]) + __shfl_xor(h3 ? b[0] : b[1], 8, kWave);
+    c += __shfl_xor(c, 4, kWave);
+    c += __shfl_xor(c, 2, kWave);
+    c += __shfl_xor(c, 1, kWave);
+    return c;
+}
+
 __device__ __forceinline__ uint32_t wave_max(uint32_t v) {
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) {

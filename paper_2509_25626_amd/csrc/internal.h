@@ -92,14 +92,44 @@ hipError_t launch_exclusive_scan(const uint32_t* in, const uint32_t* gather, uin
                                  uint64_t* block_sums, uint64_t* total, hipStream_t stream);
 
 // Key duplication over the visit order `order` (identity when null): writes
-// 64-bit keys and/or 32-bit tile ids plus values, and (if hist is not null)
-// the digit histograms: `depth_passes` depth-digit passes then `tile_passes`
-// tile-digit passes ([passes][256], zero on entry).
+// Digit layout of an LSD sort of key bits [shift0, end_bit) in `passes`
+// passes: the bits are split as evenly as possible (at most 8 per pass, the
+// lower passes taking the remainder), so that e.g. 12-bit tile ids sort in
+// two 6-bit passes whose digit runs are four times longer than 8 + 4.
+struct DigitPlan {
+    int passes = 0;
+    int shift[8] = {};
+    int bits[8] = {};
+};
+inline DigitPlan digit_plan(int passes, int shift0, int end_bit) {
+    DigitPlan d;
+    d.passes = passes;
+    const int total = end_bit - shift0;
+    int sh = shift0;
+    for (int p = 0; p < passes && p < 8; ++p) {
+        int b = total / passes + (p < total % passes ? 1 : 0);
+        if (b < 1) b = 1;
+        if (b > 8) b = 8;
+        d.shift[p] = sh;
+        d.bits[p] = b;
+        sh += b;
+    }
+    return d;
+}
+
+// 64-bit keys and/or 32-bit tile ids plus values.
 hipError_t launch_duplicate(int64_t n, const uint32_t* order, const uint32_t* offsets, const uint32_t* touched,
                             const uint2* rect, const uint32_t* depth_bits, int tiles_x, uint64_t* keys64,
-                            uint32_t* tiles32, uint32_t* values, uint32_t* hist, int depth_passes,
-                            int tile_passes, hipStream_t stream, const BatchItem* items = nullptr,
+                            uint32_t* tiles32, uint32_t* values, hipStream_t stream, const BatchItem* items = nullptr,
                             int nitems = 0);
+// Per-tile key counts from the rectangles: ranges [ntiles] of the sorted
+// list, the tile-digit histograms hist [plan.passes][256] (written, not
+// accumulated; may be null) and *total = K (may be null).  diff: ntiles + 1
+// ints of workspace.  Batched renders pass their items (global tile ids).
+constexpr int kTileCountBlocks = 512;
+hipError_t launch_tile_counts(int64_t n, const uint32_t* touched, const uint2* rect, int tiles_x, int64_t ntiles,
+                              int* diff, uint2* ranges, uint32_t* hist, const DigitPlan& plan, uint64_t* total,
+                              int max_blocks, hipStream_t stream, const BatchItem* items = nullptr, int nitems = 0);
 hipError_t launch_make_keys(const uint32_t* tiles, const uint32_t* values, const uint32_t* depth_bits,
                             int64_t count, uint64_t* keys, hipStream_t stream);
 
@@ -154,10 +184,13 @@ struct BinPlan {
     int64_t groups = 0;   // chunk groups of the column scan
     int64_t ntiles = 0;
 };
-constexpr int kBinChunk = 2048;
-constexpr int kBinGroup = 32;
-constexpr int kBinMaxBandRows = 16;
-constexpr int kBinMaxRowTiles = 4096;  // band_rows * tiles_x <= this (16 KiB of LDS per wave)
+constexpr int kBinChunk = 8192;      // Gaussians per chunk
+constexpr int kBinStage = 8192;      // keys staged per placement pass (>= kBinChunk)
+constexpr int kBinGroup = 32;        // chunks per group of the column scan
+constexpr int kBinMaxBandRows = 16;  // tile rows per counting band
+constexpr int kBinMaxRowTiles = 4096;  // band_rows * tiles_x <= this
+constexpr int kBinMaxTilesX = 512;   // tiles per row (8192 px)
+static_assert(kBinStage >= kBinChunk, "one tile's keys of a chunk must fit one placement pass");
 bool bin_supported(int tiles_x, int tiles_y);
 BinPlan bin_plan(int64_t n, int tiles_x, int tiles_y);
 // rectangles in visit order, culled splats as empty rectangles: vrect [n]
@@ -165,13 +198,14 @@ hipError_t launch_bin_gather(int64_t n, const uint32_t* order, const uint32_t* t
                              uint2* vrect, hipStream_t stream);
 // M [chunks][ntiles]: keys of each chunk in each tile
 hipError_t launch_bin_count(const BinPlan& p, int64_t n, const uint2* vrect, uint32_t* M, hipStream_t stream);
-// M -> E (first list position of each chunk's keys in each tile, in place);
+// E (first list position of each chunk's keys in each tile), from M;
 // P [groups][ntiles] and tsum [ntiles] are workspace; ranges [ntiles]; *total = K
-hipError_t launch_bin_scan(const BinPlan& p, uint32_t* M, uint32_t* P, uint32_t* tsum, uint2* ranges,
-                           uint64_t* total, hipStream_t stream);
-// values [count]: Gaussian indices in (tile, visit order); err |= 4 on an inconsistent count
+hipError_t launch_bin_scan(const BinPlan& p, const uint32_t* M, uint32_t* E, uint32_t* P, uint32_t* tsum,
+                           uint2* ranges, uint64_t* total, hipStream_t stream);
+// values [count]: Gaussian indices in (tile, visit order); M is the count
+// matrix, E the positions; err |= 4 / 8 on inconsistent counts
 hipError_t launch_bin_place(const BinPlan& p, int64_t n, const uint32_t* order, const uint2* vrect,
-                            const uint32_t* E, uint64_t count, uint32_t* values, uint32_t* err,
+                            const uint32_t* M, const uint32_t* E, uint64_t count, uint32_t* values, uint32_t* err,
                             hipStream_t stream);
 hipError_t launch_keys_from_ranges(const uint2* ranges, int64_t ntiles, const uint32_t* values,
                                    const uint32_t* depth_bits, uint64_t* keys, hipStream_t stream);
@@ -211,14 +245,14 @@ struct BlendBwdArgs {
     const uint32_t* ncontrib;
     const float* dL_drgb;
     int64_t n;
-    float* grad2d;  // [9][n], zero on entry
+    float* grad2d;  // [n][9] (mean x, mean y, conic A, B, C, opacity, r, g, b), zero on entry
 };
 hipError_t launch_blend_backward(const BlendBwdArgs& a, hipStream_t stream);
 
 struct PreBwdArgs {
     const int32_t* radius;
     const uint8_t* clamp_flags;
-    const float* grad2d;  // [9][n]
+    const float* grad2d;  // [n][9]
     float* g_means;
     float* g_log_scales;
     float* g_quats;
@@ -228,7 +262,8 @@ struct PreBwdArgs {
 hipError_t launch_preprocess_backward(const ProjParams& p, const SceneParams& s, const PreBwdArgs& a,
                                       hipStream_t stream);
 
+// partial: 1024 floats of device workspace
 hipError_t launch_l1_loss_grad(const float* rgb, const float* target, int64_t count, float* grad,
-                               float* loss, hipStream_t stream);
+                               float* loss, float* partial, hipStream_t stream);
 
 }  // namespace cds

@@ -64,11 +64,11 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(ProjParams P, SceneParam
         return;
     }
     const uint8_t flags = A.clamp_flags[i];
-    const float* G2 = A.grad2d;
-    const double gmx = G2[i], gmy = G2[n + i];
-    const double gA = G2[2 * n + i], gB = G2[3 * n + i], gC = G2[4 * n + i];
-    const double go = G2[5 * n + i];
-    double grgb[3] = {G2[6 * n + i], G2[7 * n + i], G2[8 * n + i]};
+    const float* G2 = A.grad2d + (size_t)i * 9;
+    const double gmx = G2[0], gmy = G2[1];
+    const double gA = G2[2], gB = G2[3], gC = G2[4];
+    const double go = G2[5];
+    double grgb[3] = {G2[6], G2[7], G2[8]};
 
     // ---- recompute the forward projection (float64)
     const double m0 = S.means[i], m1 = S.means[n + i], m2 = S.means[2 * n + i];

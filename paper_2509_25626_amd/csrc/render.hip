@@ -22,7 +22,7 @@ void release_frame_buffers(cds_frame* f) {
                       &f->offsets, &f->clampf, &f->blocksums, &f->total, &f->order0, &f->order1,
                       &f->dkey0, &f->dkey1, &f->sort_d.hist, &f->sort_d.status, &f->sort_d.counters,
                       &f->sort_d.part_hist, &f->sort_d.bases, &f->sort_d.scan_sums, &f->sort_d.scan_total,
-                      &f->vrect, &f->binM, &f->binP, &f->tsum,
+                      &f->vrect, &f->binM, &f->binE, &f->binP, &f->tsum, &f->tdiff, &f->thist,
                       &f->keys0, &f->keys1, &f->tk0, &f->tk1, &f->vals0, &f->vals1, &f->sort.hist,
                       &f->sort.status, &f->sort.counters, &f->sort.part_hist, &f->sort.bases,
                       &f->sort.scan_sums, &f->sort.scan_total, &f->ranges, &f->grad2d};
@@ -59,7 +59,7 @@ int tile_bits_for(int64_t ntiles) {
  *     tile-digit passes run over the keys, as 32-bit tile ids.
  *  3: as 2, but the tile-order pass is a counting sort on the whole tile id
  *     fused with duplication (tile binning): no per-key sort pass at all.
- *  0: 3 when the tile grid allows it, else 2.
+ *  0: 2 (the faster at every size measured so far).
  */
 cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scene, const cds_camera* cam,
                                int blend_variant, int sort_variant, SortAlgo algo, float* out_rgb, float* out_T,
@@ -72,7 +72,7 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
     const size_t nn = (size_t)(n > 0 ? n : 1);
     const int tile_passes = (tile_bits_for(ntiles) + 7) / 8;
     const bool can_bin = bin_supported(P.tiles_x, P.tiles_y);
-    if (sort_variant == 0) sort_variant = can_bin ? 3 : 2;
+    if (sort_variant == 0) sort_variant = 2;
     if (sort_variant == 3 && !can_bin)
         return fail(CDS_ERR_INVALID_ARG, "tile binning needs at most 4096 tiles per row");
     const bool presort = sort_variant == 2 || sort_variant == 3;
@@ -92,6 +92,10 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
         CDS_TRY(ensure(ctx, f->offsets, sizeof(uint32_t) * nn, 1.1));
         CDS_TRY(ensure(ctx, f->blocksums, sizeof(uint64_t) * scan_block_sums_size(n), 1.1));
     }
+    if (sort_variant == 2) {
+        CDS_TRY(ensure(ctx, f->tdiff, sizeof(int) * (size_t)(ntiles + 1), 1.1));
+        CDS_TRY(ensure(ctx, f->thist, sizeof(uint32_t) * 4 * 256));
+    }
     if (presort) {
         CDS_TRY(ensure(ctx, f->order0, sizeof(uint32_t) * nn, 1.1));
         CDS_TRY(ensure(ctx, f->order1, sizeof(uint32_t) * nn, 1.1));
@@ -104,6 +108,7 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
         bp = bin_plan(n, P.tiles_x, P.tiles_y);
         CDS_TRY(ensure(ctx, f->vrect, sizeof(uint2) * nn, 1.1));
         CDS_TRY(ensure(ctx, f->binM, sizeof(uint32_t) * (size_t)(bp.chunks * bp.ntiles), 1.1));
+        CDS_TRY(ensure(ctx, f->binE, sizeof(uint32_t) * (size_t)(bp.chunks * bp.ntiles), 1.1));
         CDS_TRY(ensure(ctx, f->binP, sizeof(uint32_t) * (size_t)(bp.groups * bp.ntiles), 1.1));
         CDS_TRY(ensure(ctx, f->tsum, sizeof(uint32_t) * (size_t)ntiles, 1.1));
     }
@@ -138,13 +143,19 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
         // per (chunk, band) tile counts, their column scan, tile ranges and K
         CDS_HIP(launch_bin_gather(n, order, sb.touched, sb.rect, (uint2*)f->vrect.p, stream), "bin gather");
         CDS_HIP(launch_bin_count(bp, n, (const uint2*)f->vrect.p, (uint32_t*)f->binM.p, stream), "bin count");
-        CDS_HIP(launch_bin_scan(bp, (uint32_t*)f->binM.p, (uint32_t*)f->binP.p, (uint32_t*)f->tsum.p,
-                                (uint2*)f->ranges.p, d_total, stream),
+        CDS_HIP(launch_bin_scan(bp, (const uint32_t*)f->binM.p, (uint32_t*)f->binE.p, (uint32_t*)f->binP.p,
+                                (uint32_t*)f->tsum.p, (uint2*)f->ranges.p, d_total, stream),
                 "bin scan");
     } else {
         CDS_HIP(launch_exclusive_scan(sb.touched, order, (uint32_t*)f->offsets.p, n, (uint64_t*)f->blocksums.p,
                                       d_total, stream),
                 "scan kernels");
+        if (presort)  // ranges and tile-digit histograms from the rectangles
+            CDS_HIP(launch_tile_counts(n, sb.touched, sb.rect, P.tiles_x, ntiles, (int*)f->tdiff.p,
+                                       (uint2*)f->ranges.p, (uint32_t*)f->thist.p,
+                                       digit_plan(tile_passes, 0, tile_bits_for(ntiles)), nullptr, kTileCountBlocks,
+                                       stream),
+                    "tile counts");
     }
     CDS_HIP(hipMemcpyAsync(ctx->host_pinned, d_total, sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
             "hipMemcpyAsync(key count)");
@@ -165,8 +176,8 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
     f->sort_variant = sort_variant;
 
     if (binned) {
-        CDS_HIP(launch_bin_place(bp, n, order, (const uint2*)f->vrect.p, (const uint32_t*)f->binM.p, K,
-                                 (uint32_t*)f->vals0.p, ctx->d_err, stream),
+        CDS_HIP(launch_bin_place(bp, n, order, (const uint2*)f->vrect.p, (const uint32_t*)f->binM.p,
+                                 (const uint32_t*)f->binE.p, K, (uint32_t*)f->vals0.p, ctx->d_err, stream),
                 "bin place");
         CDS_TRY(f->record(3, stream));
         CDS_TRY(f->record(4, stream));
@@ -188,22 +199,28 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
         }
         CDS_TRY(ensure_sort_workspace(ctx, f->sort, (int64_t)K, passes > 0 ? passes : 1));
         SortWorkspace ws = sort_ws(ctx, f->sort);
+        const bool onesweep = sort_uses_onesweep((int64_t)K, algo) && passes > 0;
         if (K > 0) {
-            // onesweep passes need the digit histograms of all keys; the duplicate
-            // pass builds them per Gaussian and per rectangle row
-            const bool need_hist = sort_uses_onesweep((int64_t)K, algo) && passes > 0;
-            if (need_hist) CDS_HIP(launch_sort_prepare(ws, (int64_t)K, passes, true, stream), "sort prepare");
-            uint32_t* hist = need_hist ? ws.hist : nullptr;
-            if (presort)
+            if (presort) {
+                // the onesweep passes take the tile-digit histograms made from the rectangles
+                if (onesweep) CDS_HIP(launch_sort_prepare(ws, (int64_t)K, passes, false, stream), "sort prepare");
+                ws.hist = (uint32_t*)f->thist.p;
                 CDS_HIP(launch_duplicate(n, order, (const uint32_t*)f->offsets.p, sb.touched, sb.rect,
                                          sb.depth_bits, P.tiles_x, nullptr, (uint32_t*)f->tk0.p,
-                                         (uint32_t*)f->vals0.p, hist, 0, tile_passes, stream),
+                                         (uint32_t*)f->vals0.p, stream),
                         "duplicate kernel");
-            else
+            } else {
                 CDS_HIP(launch_duplicate(n, nullptr, (const uint32_t*)f->offsets.p, sb.touched, sb.rect,
                                          sb.depth_bits, P.tiles_x, (uint64_t*)f->keys0.p, nullptr,
-                                         (uint32_t*)f->vals0.p, hist, 4, tile_passes, stream),
+                                         (uint32_t*)f->vals0.p, stream),
                         "duplicate kernel");
+                if (onesweep) {
+                    CDS_HIP(launch_sort_prepare(ws, (int64_t)K, passes, true, stream), "sort prepare");
+                    CDS_HIP(launch_sort_histogram((const uint64_t*)f->keys0.p, (int64_t)K, passes, 0, ws.hist,
+                                                  stream, 32 + tile_bits_for(ntiles)),
+                            "key histogram");
+                }
+            }
         }
         CDS_TRY(f->record(3, stream));
         const bool odd = (passes & 1) != 0;
@@ -231,8 +248,10 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
         f->res_values = (const uint32_t*)(odd ? f->vals1.p : f->vals0.p);
         CDS_TRY(f->record(4, stream));
         f->passes = presort ? 4 + tile_passes : passes;
-        CDS_HIP(launch_ranges(f->res_tiles, f->res_tile_stride, (int64_t)K, (uint2*)f->ranges.p, ntiles, stream),
-                "ranges kernel");
+        if (!presort)  // variant 2 has its ranges from the tile counts
+            CDS_HIP(launch_ranges(f->res_tiles, f->res_tile_stride, (int64_t)K, (uint2*)f->ranges.p, ntiles,
+                                  stream),
+                    "ranges kernel");
         CDS_TRY(f->record(5, stream));
     }
 

@@ -69,7 +69,7 @@ void release(cds_ctx* c, DevBuf& b) {
 cds_status validate_scene(const cds_scene* s) {
     if (!s) return fail(CDS_ERR_INVALID_ARG, "scene is NULL");
     if (s->n < 0) return fail(CDS_ERR_INVALID_ARG, "scene n < 0");
-    if (s->n > (int64_t)0xFFFFFFFF) return fail(CDS_ERR_CAPACITY, "more than 2^32-1 Gaussians");
+    if (s->n > (int64_t)0x7FFFFFFF) return fail(CDS_ERR_CAPACITY, "more than 2^31-1 Gaussians");
     if (s->sh_degree < 0 || s->sh_degree > CDS_MAX_SH_DEGREE)
         return fail(CDS_ERR_INVALID_ARG, "sh_degree must be in [0, 3]");
     if (s->n > 0 && (!s->means || !s->log_scales || !s->quats || !s->opacity_logits || !s->sh))
@@ -190,7 +190,8 @@ cds_status cds_create(cds_ctx** out, int device, const cds_allocator* alloc) {
         delete c;
         return hip_fail(e, "hipHostMalloc");
     }
-    c->d_err = (uint32_t*)ctx_alloc(c, 256);
+    // one allocation: the error word (256 B) and the loss partial sums (4 KiB)
+    c->d_err = (uint32_t*)ctx_alloc(c, 256 + 4096);
     if (!c->d_err) {
         (void)hipHostFree(c->host_pinned);
         delete c;
@@ -202,6 +203,7 @@ cds_status cds_create(cds_ctx** out, int device, const cds_allocator* alloc) {
         delete c;
         return hip_fail(e, "hipMemset");
     }
+    c->d_partial = reinterpret_cast<float*>(reinterpret_cast<char*>(c->d_err) + 256);
     c->scratch = new cds_frame();
     c->scratch->ctx = c;
     *out = c;
@@ -295,7 +297,7 @@ cds_status cds_l1_loss_grad(cds_ctx* ctx, const float* rgb, const float* target,
     if (!ctx || !rgb || !target || !dL_drgb || count < 0) return fail(CDS_ERR_INVALID_ARG, "bad argument");
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-    e = launch_l1_loss_grad(rgb, target, count, dL_drgb, loss_out, (hipStream_t)stream);
+    e = launch_l1_loss_grad(rgb, target, count, dL_drgb, loss_out, ctx->d_partial, (hipStream_t)stream);
     return e == hipSuccess ? CDS_OK : hip_fail(e, "l1 loss kernel");
 }
 
@@ -399,7 +401,8 @@ cds_status cds_check_device(cds_ctx* ctx, void* stream) {
         (void)hipMemset(ctx->d_err, 0, 4);
         return fail(CDS_ERR_DEVICE, "device-side check failed (code " + std::to_string(err) +
                                         "): 1 = a bounded wait in the radix sort gave up, "
-                                        "2 = a radix-sort scatter position was out of range");
+                                        "2 = a radix-sort scatter position was out of range, "
+                                        "4 or 8 = tile binning counts were inconsistent");
     }
     return CDS_OK;
 }

@@ -24,6 +24,7 @@ struct cds_ctx {
     bool has_alloc = false;
     uint64_t* host_pinned = nullptr;  // pinned host words for the per-render key count
     uint32_t* d_err = nullptr;        // device-side error word
+    float* d_partial = nullptr;       // 1024 floats: per-block partial sums of the loss
     cds_frame* scratch = nullptr;     // buffers of the stand-alone sort / scan calls
 };
 
@@ -33,7 +34,8 @@ struct cds_frame {
     cds::DevBuf mean2d, conic, rgb, depth, radius, rect, touched, offsets, clampf;
     cds::DevBuf blocksums, total;
     cds::DevBuf order0, order1, dkey0, dkey1;  // per-Gaussian depth sort (sort variants 2, 3)
-    cds::DevBuf vrect, binM, binP, tsum;       // tile binning (sort variant 3)
+    cds::DevBuf vrect, binM, binE, binP, tsum;  // tile binning (sort variant 3)
+    cds::DevBuf tdiff, thist;                  // per-tile counts and tile-digit histograms (variant 2)
     cds::SortState sort_d;
     // per key
     cds::DevBuf keys0, keys1;                  // 64-bit keys (variant 1; others: rebuilt on request)

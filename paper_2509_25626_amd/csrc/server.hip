@@ -133,7 +133,8 @@ cds_status run_batch(cds_server* s, Workspace& w) {
         N += sc.n;
         T += (int64_t)it.P.tiles_x * it.P.tiles_y;
     }
-    if (N > (int64_t)0xFFFFFFFF || T > (int64_t)0xFFFFFFFF) return fail(CDS_ERR_CAPACITY, "batch too large");
+    if (N > (int64_t)0x7FFFFFFF || T > (int64_t)0x7FFFFFFF) return fail(CDS_ERR_CAPACITY, "batch too large");
+    const int tile_passes = (tile_bits_for(T) + 7) / 8;
     SRV_HIP(hipMemcpyAsync(w.items_dev, w.items_host, sizeof(BatchItem) * nitems, hipMemcpyHostToDevice, stream),
             "hipMemcpyAsync(batch items)");
     const size_t nn = (size_t)std::max<int64_t>(N, 1);
@@ -153,6 +154,8 @@ cds_status run_batch(cds_server* s, Workspace& w) {
     SRV_TRY(ensure(ctx, f->dkey0, sizeof(uint32_t) * nn, 1.25));
     SRV_TRY(ensure(ctx, f->dkey1, sizeof(uint32_t) * nn, 1.25));
     SRV_TRY(ensure(ctx, f->ranges, sizeof(uint2) * (size_t)std::max<int64_t>(T, 1), 1.25));
+    SRV_TRY(ensure(ctx, f->tdiff, sizeof(int) * (size_t)(T + 1), 1.25));
+    SRV_TRY(ensure(ctx, f->thist, sizeof(uint32_t) * 4 * 256));
     SRV_TRY(ensure_sort_workspace(ctx, f->sort_d, N, 4));
 
     SplatBuffers sb;
@@ -178,6 +181,11 @@ cds_status run_batch(cds_server* s, Workspace& w) {
     SRV_HIP(launch_exclusive_scan(sb.touched, order, (uint32_t*)f->offsets.p, N, (uint64_t*)f->blocksums.p,
                                   (uint64_t*)f->total.p, stream),
             "scan");
+    // ranges and tile-digit histograms from the rectangles (global tile ids)
+    SRV_HIP(launch_tile_counts(N, sb.touched, sb.rect, 0, T, (int*)f->tdiff.p, (uint2*)f->ranges.p,
+                               (uint32_t*)f->thist.p, digit_plan(tile_passes, 0, tile_bits_for(T)), nullptr,
+                               kTileCountBlocks, stream, w.items_dev, nitems),
+            "batched tile counts");
     SRV_HIP(hipMemcpyAsync(w.pinned, f->total.p, sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
             "hipMemcpyAsync(key count)");
     SRV_HIP(hipStreamSynchronize(stream), "hipStreamSynchronize(key count)");
@@ -192,7 +200,6 @@ cds_status run_batch(cds_server* s, Workspace& w) {
         std::lock_guard<std::mutex> lk(s->mu);
         s->key_scale = std::max(0.05, 0.7 * s->key_scale + 0.3 * s->key_scale * (double)K / (double)est);
     }
-    const int tile_passes = (tile_bits_for(T) + 7) / 8;
     const size_t kk = (size_t)std::max<uint64_t>(K, 1);
     SRV_TRY(ensure(ctx, f->tk0, sizeof(uint32_t) * kk, 1.25));
     SRV_TRY(ensure(ctx, f->tk1, sizeof(uint32_t) * kk, 1.25));
@@ -201,11 +208,11 @@ cds_status run_batch(cds_server* s, Workspace& w) {
     SRV_TRY(ensure_sort_workspace(ctx, f->sort, (int64_t)K, std::max(tile_passes, 1)));
     SortWorkspace ws = sort_ws(ctx, f->sort);
     if (K > 0) {
-        const bool need_hist = sort_uses_onesweep((int64_t)K, algo) && tile_passes > 0;
-        if (need_hist) SRV_HIP(launch_sort_prepare(ws, (int64_t)K, tile_passes, true, stream), "sort prepare");
+        if (sort_uses_onesweep((int64_t)K, algo) && tile_passes > 0)
+            SRV_HIP(launch_sort_prepare(ws, (int64_t)K, tile_passes, false, stream), "sort prepare");
+        ws.hist = (uint32_t*)f->thist.p;
         SRV_HIP(launch_duplicate(N, order, (const uint32_t*)f->offsets.p, sb.touched, sb.rect, sb.depth_bits, 0,
-                                 nullptr, (uint32_t*)f->tk0.p, (uint32_t*)f->vals0.p, need_hist ? ws.hist : nullptr,
-                                 0, tile_passes, stream, w.items_dev, nitems),
+                                 nullptr, (uint32_t*)f->tk0.p, (uint32_t*)f->vals0.p, stream, w.items_dev, nitems),
                 "batched duplicate");
         SRV_HIP(launch_sort_passes((const uint32_t*)f->tk0.p, (const uint32_t*)f->vals0.p, (uint32_t*)f->tk1.p,
                                    (uint32_t*)f->vals1.p, (uint32_t*)f->tk0.p, (uint32_t*)f->vals0.p, (int64_t)K,
@@ -213,9 +220,7 @@ cds_status run_batch(cds_server* s, Workspace& w) {
                 "tile sort");
     }
     const bool odd = (tile_passes & 1) != 0;
-    const uint32_t* tiles = (const uint32_t*)(odd ? f->tk1.p : f->tk0.p);
     const uint32_t* values = (const uint32_t*)(odd ? f->vals1.p : f->vals0.p);
-    SRV_HIP(launch_ranges(tiles, 1, (int64_t)K, (uint2*)f->ranges.p, T, stream), "ranges");
     const int64_t grid = std::min<int64_t>(T, (int64_t)s->cus * 8);
     SRV_HIP(launch_blend_batch(w.items_dev, nitems, T, (const uint2*)f->ranges.p, values, sb.mean2d,
                                sb.conic_opacity, sb.rgb, w.counter, (int)grid, stream),

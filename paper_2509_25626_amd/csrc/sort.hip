@@ -49,11 +49,11 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, int6
         p[i] = value;
 }
 
-// Digit histograms of `passes` 8-bit digits (starting at bit `shift0`) over all keys.
+// Digit histograms of the plan's digits over all keys.
 template <typename Key>
-__global__ __launch_bounds__(256) void k_sort_histogram(const Key* __restrict__ keys, int64_t count,
-                                                        int passes, int shift0, int end_bit,
+__global__ __launch_bounds__(256) void k_sort_histogram(const Key* __restrict__ keys, int64_t count, DigitPlan plan,
                                                         uint32_t* __restrict__ hist) {
+    const int passes = plan.passes;
     __shared__ uint32_t s_hist[8 * 256];
     for (int k = threadIdx.x; k < passes * 256; k += blockDim.x) s_hist[k] = 0;
     __syncthreads();
@@ -61,11 +61,7 @@ __global__ __launch_bounds__(256) void k_sort_histogram(const Key* __restrict__ 
          i += (int64_t)gridDim.x * blockDim.x) {
         const Key key = keys[i];
         for (int p = 0; p < passes; ++p)
-        {
-            const int sh = shift0 + 8 * p;
-            const int bits = min(8, end_bit - sh);
-            atomicAdd(&s_hist[p * 256 + ((uint32_t)(key >> sh) & ((1u << bits) - 1u))], 1u);
-        }
+            atomicAdd(&s_hist[p * 256 + ((uint32_t)(key >> plan.shift[p]) & ((1u << plan.bits[p]) - 1u))], 1u);
     }
     __syncthreads();
     for (int k = threadIdx.x; k < passes * 256; k += blockDim.x) {
@@ -137,7 +133,8 @@ struct PassArgs {
 
 template <typename Key, bool kOnesweep>
 __global__ __launch_bounds__(kNT) void k_sort_pass(PassArgs<Key> a) {
-    __shared__ Key s_keys[kP];                  // reorder buffer (keys, then values)
+    __shared__ Key s_keys[kP];                  // reorder buffer
+    __shared__ uint32_t s_vals[kP];
     __shared__ uint32_t s_whist[kWaves][256];   // per-wave digit counters, then offsets
     __shared__ uint32_t s_gbase[256];
     __shared__ uint32_t s_scan[kWaves];
@@ -152,31 +149,39 @@ __global__ __launch_bounds__(kNT) void k_sort_pass(PassArgs<Key> a) {
     const uint32_t pid = s_pid;
     const int64_t base = (int64_t)pid * kP;
     const int64_t wbase = base + (int64_t)w * (kWave * kKPT);
+    const bool full = base + kP <= a.count;  // uniform: no tail in this partition
 
     Key key[kKPT];
     uint32_t val[kKPT];
 #pragma unroll
     for (int r = 0; r < kKPT; ++r) {
         const int64_t idx = wbase + r * kWave + l;
-        const bool valid = idx < a.count;
+        const bool valid = full || idx < a.count;
         key[r] = valid ? a.kin[idx] : (Key)0;
         val[r] = valid ? (a.vin ? a.vin[idx] : (uint32_t)idx) : 0u;
     }
 
-    // stable wave-level ranking
-    uint32_t rank[kKPT];
+    // Stable wave-level ranking.  Per round, the first lane of every digit
+    // group adds the group's size to the wave's counter with an LDS atomic;
+    // the rounds' atomics do not wait on each other's results (LDS executes a
+    // wave's operations in order), and the members then fetch the old count
+    // from their group's first lane.
+    uint32_t pre[kKPT], info[kKPT];  // info: below | first lane << 8
 #pragma unroll
     for (int r = 0; r < kKPT; ++r) {
-        const bool valid = (wbase + r * kWave + l) < a.count;
+        const bool valid = full || (wbase + r * kWave + l) < a.count;
         const uint32_t d = (uint32_t)(key[r] >> a.shift) & a.dmask;
         const uint64_t peers = digit_peers(d, valid, a.bits);
         const uint32_t below = count_below(peers);
-        const uint32_t cnt = (uint32_t)__popcll(peers);
-        uint32_t pre = 0;
-        if (valid) pre = s_whist[w][d];
-        if (valid && below == 0) s_whist[w][d] = pre + cnt;
-        rank[r] = pre + below;
+        const uint32_t first = valid ? (uint32_t)__builtin_ctzll(peers) : l;
+        pre[r] = 0;
+        if (valid && below == 0) pre[r] = atomicAdd(&s_whist[w][d], (uint32_t)__popcll(peers));
+        info[r] = below | (first << 8);
     }
+    uint32_t rank[kKPT];
+#pragma unroll
+    for (int r = 0; r < kKPT; ++r)
+        rank[r] = (uint32_t)__shfl((int)pre[r], (int)(info[r] >> 8), kWave) + (info[r] & 255u);
     __syncthreads();
 
     // thread t owns digit t
@@ -197,21 +202,21 @@ __global__ __launch_bounds__(kNT) void k_sort_pass(PassArgs<Key> a) {
             int64_t p = (int64_t)pid - 1;
             uint32_t spins = 0;
             while (p >= 0) {
-                uint32_t s[kLookBack];
+                uint32_t sw[kLookBack];
 #pragma unroll
                 for (int k = 0; k < kLookBack; ++k)
-                    s[k] = (p - k >= 0) ? atomic_load_agent(a.status + (size_t)(p - k) * 256 + t) : kFlagIncl;
+                    sw[k] = (p - k >= 0) ? atomic_load_agent(a.status + (size_t)(p - k) * 256 + t) : kFlagIncl;
                 int consumed = 0;
                 bool found = false, stalled = false;
 #pragma unroll
                 for (int k = 0; k < kLookBack; ++k) {
                     if (found || stalled) continue;
-                    const uint32_t f = s[k] & ~kValueMask;
+                    const uint32_t f = sw[k] & ~kValueMask;
                     if (f == 0u) {
                         stalled = true;
                         continue;
                     }
-                    excl += s[k] & kValueMask;
+                    excl += sw[k] & kValueMask;
                     ++consumed;
                     if (f == kFlagIncl) found = true;
                 }
@@ -239,52 +244,39 @@ __global__ __launch_bounds__(kNT) void k_sort_pass(PassArgs<Key> a) {
     s_gbase[t] = gb - bstart;
     __syncthreads();
 
-    // reorder keys by digit in LDS
+    // reorder (key, value) pairs by digit in LDS
 #pragma unroll
     for (int r = 0; r < kKPT; ++r) {
-        const bool valid = (wbase + r * kWave + l) < a.count;
+        const bool valid = full || (wbase + r * kWave + l) < a.count;
         if (valid) {
             const uint32_t d = (uint32_t)(key[r] >> a.shift) & a.dmask;
             const uint32_t pos = s_whist[w][d] + rank[r];
-            if (pos < (uint32_t)kP) s_keys[pos] = key[r];
+            if (pos < (uint32_t)kP) {
+                s_keys[pos] = key[r];
+                s_vals[pos] = val[r];
+            }
         }
     }
     __syncthreads();
+    // each digit run goes out as a contiguous stretch
     const int64_t rem = a.count - base;
     const uint32_t nvalid = rem < kP ? (uint32_t)rem : (uint32_t)kP;
-    uint32_t gpos[kKPT];
 #pragma unroll
     for (int r = 0; r < kKPT; ++r) {
         const uint32_t i = (uint32_t)(r * kNT + t);
-        gpos[r] = 0;
         if (i < nvalid) {
             const Key k = s_keys[i];
             const uint32_t d = (uint32_t)(k >> a.shift) & a.dmask;
             const uint32_t g = s_gbase[d] + i;
             // a position outside the output can only come from inconsistent digit
             // counts; record it instead of writing out of bounds
-            if ((int64_t)g < a.count) a.kout[g] = k;
-            else atomicOr(a.err, 2u);
-            gpos[r] = g;
+            if ((int64_t)g < a.count) {
+                a.kout[g] = k;
+                a.vout[g] = s_vals[i];
+            } else {
+                atomicOr(a.err, 2u);
+            }
         }
-    }
-    __syncthreads();
-    // the values follow the same permutation
-    uint32_t* s_vals = reinterpret_cast<uint32_t*>(s_keys);
-#pragma unroll
-    for (int r = 0; r < kKPT; ++r) {
-        const bool valid = (wbase + r * kWave + l) < a.count;
-        if (valid) {
-            const uint32_t d = (uint32_t)(key[r] >> a.shift) & a.dmask;
-            const uint32_t pos = s_whist[w][d] + rank[r];
-            if (pos < (uint32_t)kP) s_vals[pos] = val[r];
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < kKPT; ++r) {
-        const uint32_t i = (uint32_t)(r * kNT + t);
-        if (i < nvalid && (int64_t)gpos[r] < a.count) a.vout[gpos[r]] = s_vals[i];
     }
 }
 
@@ -294,8 +286,8 @@ hipError_t sort_histogram_impl(const Key* keys, int64_t count, int passes, int s
     if (count <= 0) return hipSuccess;
     int64_t blocks = (count + 255) / 256;
     if (blocks > 2048) blocks = 2048;
-    hipLaunchKernelGGL(k_sort_histogram<Key>, dim3((unsigned)blocks), dim3(256), 0, stream, keys, count,
-                       passes, shift0, end_bit > 0 ? end_bit : shift0 + 8 * passes, hist);
+    const DigitPlan plan = digit_plan(passes, shift0, end_bit > 0 ? end_bit : shift0 + 8 * passes);
+    hipLaunchKernelGGL(k_sort_histogram<Key>, dim3((unsigned)blocks), dim3(256), 0, stream, keys, count, plan, hist);
     return hipGetLastError();
 }
 
@@ -307,6 +299,8 @@ hipError_t sort_passes_impl(const Key* kin, const uint32_t* vin, Key* ka, uint32
     if (count > kSortMaxCount) return hipErrorInvalidValue;
     const int64_t parts = sort_partitions(count);
     const bool onesweep = sort_uses_onesweep(count, algo);
+    if (passes > 8) return hipErrorInvalidValue;
+    const DigitPlan plan = digit_plan(passes, shift0, end_bit);
     for (int p = 0; p < passes; ++p) {
         PassArgs<Key> a;
         a.kin = p == 0 ? kin : ((p & 1) ? ka : kb);
@@ -314,8 +308,8 @@ hipError_t sort_passes_impl(const Key* kin, const uint32_t* vin, Key* ka, uint32
         a.kout = (p & 1) ? kb : ka;
         a.vout = (p & 1) ? vb : va;
         a.count = count;
-        a.shift = shift0 + 8 * p;
-        a.bits = std::max(1, std::min(8, end_bit - a.shift));
+        a.shift = plan.shift[p];
+        a.bits = plan.bits[p];
         a.dmask = (1u << a.bits) - 1u;
         a.hist = ws.hist + (size_t)p * 256;
         a.status = ws.status + (size_t)p * parts * 256;

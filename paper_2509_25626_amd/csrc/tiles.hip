@@ -1,0 +1,172 @@
+// Per-tile key counts straight from the splat rectangles, without touching
+// the keys: every visible splat covers whole runs of consecutive tile ids
+// (one run per rectangle row), so a difference array over the tile ids
+// (+1 at a run's first tile, -1 past its last) integrates to the number of
+// keys of every tile.  From those counts follow, before any key exists,
+//  - the tile ranges of the sorted list (paper Section II-B(1): the start and
+//    end of every tile's splats; empty tiles (0, 0)),
+//  - the digit histograms of the tile-id radix passes (any digit layout), and
+//  - the key count K.
+// The runs of a batch of renders use the requests' global tile ids.
+#include "device_utils.h"
+#include "internal.h"
+
+namespace cds {
+namespace {
+
+constexpr int kDiffThreads = 256;
+constexpr int64_t kDiffLdsMaxTiles = 16383;  // ntiles + 1 ints fit 64 KiB of LDS
+
+struct DiffArgs {
+    int64_t n;
+    const uint32_t* touched;
+    const uint2* rect;
+    int tiles_x;
+    int64_t ntiles;
+    int* diff;  // [ntiles + 1], zero on entry
+    const BatchItem* items;
+    int nitems;
+};
+
+template <bool kLds>
+__global__ __launch_bounds__(kDiffThreads) void k_tile_diff(DiffArgs a) {
+    extern __shared__ int s_d[];
+    int* d = kLds ? s_d : a.diff;
+    if (kLds) {
+        for (int64_t k = threadIdx.x; k <= a.ntiles; k += kDiffThreads) s_d[k] = 0;
+        __syncthreads();
+    }
+    for (int64_t i = (int64_t)blockIdx.x * kDiffThreads + threadIdx.x; i < a.n;
+         i += (int64_t)gridDim.x * kDiffThreads) {
+        if (!a.touched[i]) continue;
+        const uint2 r = a.rect[i];
+        const uint32_t x0 = r.x & 0xFFFFu, y0 = r.x >> 16, x1 = r.y & 0xFFFFu, y1 = r.y >> 16;
+        uint32_t tx = (uint32_t)a.tiles_x, tb = 0;
+        if (a.items) {
+            const int it = find_item_by_gaussian(a.items, a.nitems, i);
+            tx = (uint32_t)a.items[it].P.tiles_x;
+            tb = (uint32_t)a.items[it].tile_base;
+        }
+        const uint32_t w = x1 - x0 + 1;
+        for (uint32_t y = y0; y <= y1; ++y) {
+            const uint32_t t0 = tb + y * tx + x0;
+            atomicAdd(&d[t0], 1);
+            atomicAdd(&d[t0 + w], -1);
+        }
+    }
+    if (kLds) {
+        __syncthreads();
+        for (int64_t k = threadIdx.x; k <= a.ntiles; k += kDiffThreads) {
+            const int v = s_d[k];
+            if (v) atomicAdd(&a.diff[k], v);
+        }
+    }
+}
+
+// One block: integrate the difference array to per-tile counts, scan them to
+// tile starts, and build the tile-digit histograms and K.
+constexpr int kRangeThreads = 1024;
+__global__ __launch_bounds__(kRangeThreads) void k_tile_ranges(int64_t ntiles, const int* __restrict__ diff,
+                                                               uint2* __restrict__ ranges, uint32_t* __restrict__ hist,
+                                                               DigitPlan plan, uint64_t* __restrict__ total) {
+    const int tile_passes = plan.passes;
+    __shared__ uint32_t s_hist[4 * 256];
+    __shared__ unsigned long long s_wave[kRangeThreads / kWave];
+    __shared__ int s_wcnt[kRangeThreads / kWave];
+    __shared__ unsigned long long s_start;
+    __shared__ int s_run;
+    const int t = threadIdx.x;
+    const int w = t / kWave;
+    const uint32_t lane = lane_id();
+    for (int k = t; k < 4 * 256; k += kRangeThreads) s_hist[k] = 0;
+    if (t == 0) {
+        s_start = 0;
+        s_run = 0;
+    }
+    __syncthreads();
+    for (int64_t base = 0; base < ntiles; base += kRangeThreads) {
+        const int64_t i = base + t;
+        // count = running sum of the difference array (int: entries may be negative)
+        int v = i < ntiles ? diff[i] : 0;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const int u = __shfl_up(v, (unsigned)o, kWave);
+            if (lane >= (uint32_t)o) v += u;
+        }
+        if (lane == kWave - 1) s_wcnt[w] = v;
+        __syncthreads();
+        int before = s_run, all = 0;
+#pragma unroll
+        for (int k = 0; k < kRangeThreads / kWave; ++k) {
+            before += k < w ? s_wcnt[k] : 0;
+            all += s_wcnt[k];
+        }
+        const uint32_t cnt = i < ntiles ? (uint32_t)(before + v) : 0u;
+        // start = exclusive running sum of the counts (64-bit)
+        unsigned long long inc = cnt;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const unsigned long long u = __shfl_up(inc, (unsigned)o, kWave);
+            if (lane >= (uint32_t)o) inc += u;
+        }
+        if (lane == kWave - 1) s_wave[w] = inc;
+        __syncthreads();
+        unsigned long long sb = s_start, sall = 0;
+#pragma unroll
+        for (int k = 0; k < kRangeThreads / kWave; ++k) {
+            sb += k < w ? s_wave[k] : 0ull;
+            sall += s_wave[k];
+        }
+        if (i < ntiles) {
+            const unsigned long long start = sb + inc - cnt;
+            ranges[i] = cnt ? make_uint2((uint32_t)start, (uint32_t)(start + cnt)) : make_uint2(0u, 0u);
+            if (cnt)
+                for (int q = 0; q < tile_passes; ++q)
+                    atomicAdd(&s_hist[q * 256 + (uint32_t)((i >> plan.shift[q]) & ((1 << plan.bits[q]) - 1))], cnt);
+        }
+        __syncthreads();
+        if (t == 0) {
+            s_run += all;
+            s_start += sall;
+        }
+        __syncthreads();
+    }
+    if (hist)
+        for (int k = t; k < tile_passes * 256; k += kRangeThreads) hist[k] = s_hist[k];
+    if (t == 0 && total) *total = s_start;
+}
+
+}  // namespace
+
+hipError_t launch_tile_counts(int64_t n, const uint32_t* touched, const uint2* rect, int tiles_x, int64_t ntiles,
+                              int* diff, uint2* ranges, uint32_t* hist, const DigitPlan& plan, uint64_t* total,
+                              int max_blocks, hipStream_t stream, const BatchItem* items, int nitems) {
+    if (ntiles <= 0) return hipSuccess;
+    if (plan.passes > 4) return hipErrorInvalidValue;
+    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(diff), ntiles + 1, 0u, stream);
+    if (e != hipSuccess) return e;
+    if (n > 0) {
+        DiffArgs a;
+        a.n = n;
+        a.touched = touched;
+        a.rect = rect;
+        a.tiles_x = tiles_x;
+        a.ntiles = ntiles;
+        a.diff = diff;
+        a.items = items;
+        a.nitems = nitems;
+        int64_t blocks = (n + kDiffThreads - 1) / kDiffThreads;
+        if (blocks > max_blocks) blocks = max_blocks;
+        if (ntiles <= kDiffLdsMaxTiles)
+            hipLaunchKernelGGL(k_tile_diff<true>, dim3((unsigned)blocks), dim3(kDiffThreads),
+                               sizeof(int) * (size_t)(ntiles + 1), stream, a);
+        else
+            hipLaunchKernelGGL(k_tile_diff<false>, dim3((unsigned)blocks), dim3(kDiffThreads), 0, stream, a);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_tile_ranges, dim3(1), dim3(kRangeThreads), 0, stream, ntiles, diff, ranges, hist, plan,
+                       total);
+    return hipGetLastError();
+}
+
+}  // namespace cds

@@ -73,7 +73,7 @@ def compare_projection(g, o):
 
 
 def effective_sort_variant(sort_variant):
-    return 3 if sort_variant == 0 else sort_variant  # every image here allows tile binning
+    return 2 if sort_variant == 0 else sort_variant
 
 
 def expected_offsets(o, sort_variant):
@@ -151,6 +151,18 @@ def test_sort_variants_bit_identical(R, wh, n):
             # offsets: the visit order differs by design (index order vs depth order)
             assert np.array_equal(a[k], b[k]), (sv, k)
         assert a["K"] == b["K"]
+
+
+def test_binning_many_keys_per_row(R):
+    # large splats: a (chunk, tile row) holds far more keys than one placement
+    # pass stages, so rows are placed in several passes over tile ranges
+    scene = S.scene_outdoor(16, 12_000, log_scale_mu=-1.2, log_scale_sigma=0.3)
+    cam = S.orbit_camera(1237, 822, 4.0, 30.0, 0.0)
+    a = gpu_render(R, scene, cam, sort_variant=1)
+    b = gpu_render(R, scene, cam, sort_variant=3)
+    assert a["K"] > 12_000 * 100
+    for k in ("keys", "values", "ranges", "image", "final_T", "n_contrib"):
+        assert np.array_equal(a[k], b[k]), k
 
 
 @pytest.mark.parametrize("variant", [1, 2, 4])
