@@ -395,7 +395,7 @@ hipError_t launch_blend_backward(const BlendBwdArgs& a, hipStream_t stream) {
     const int64_t tiles = (int64_t)a.tiles_x * a.tiles_y;
     if (tiles == 0) return hipSuccess;
     const uint32_t per = xcd_per(tiles);
-    hipLaunchKernelGGL(k_blend_bwd<1>, dim3(8 * per), dim3(256), 0, stream, a, per);
+    hipLaunchKernelGGL(k_blend_bwd<2>, dim3(8 * per), dim3(128), 0, stream, a, per);
     return hipGetLastError();
 }
 

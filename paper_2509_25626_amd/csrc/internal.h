@@ -127,6 +127,7 @@ hipError_t launch_duplicate(int64_t n, const uint32_t* order, const uint32_t* of
 // accumulated; may be null) and *total = K (may be null).  diff: ntiles + 1
 // ints of workspace.  Batched renders pass their items (global tile ids).
 constexpr int kTileCountBlocks = 512;
+constexpr int64_t kTileDiffLdsMaxTiles = 16383;  // ntiles + 1 ints fit 64 KiB of LDS
 hipError_t launch_tile_counts(int64_t n, const uint32_t* touched, const uint2* rect, int tiles_x, int64_t ntiles,
                               int* diff, uint2* ranges, uint32_t* hist, const DigitPlan& plan, uint64_t* total,
                               int max_blocks, hipStream_t stream, const BatchItem* items = nullptr, int nitems = 0);

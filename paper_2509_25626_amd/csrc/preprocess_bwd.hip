@@ -52,7 +52,13 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(ProjParams P, SceneParam
     const int64_t n = P.n;
     const int nb = (P.sh_degree + 1) * (P.sh_degree + 1);
 
-    if (A.radius[i] == 0) {
+    // Culled splats get zero gradients.  In a wave with live splats they run
+    // the same code and their results are replaced by zero at the store, so
+    // every output plane is written by one full-wave store (a culled lane's
+    // early store and a live lane's late store to the same line would each
+    // write back a partial line).
+    const bool live = A.radius[i] != 0;
+    if (!__any(live)) {  // the whole wave is culled: zeros, still one full-wave store per plane
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             A.g_means[k * n + i] = 0.f;
@@ -63,6 +69,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(ProjParams P, SceneParam
         for (int k = 0; k < nb * 3; ++k) A.g_sh[(int64_t)k * n + i] = 0.f;
         return;
     }
+    auto put = [live](float* dst, double v) { *dst = live ? (float)v : 0.0f; };
     const uint8_t flags = A.clamp_flags[i];
     const float* G2 = A.grad2d + (size_t)i * 9;
     const double gmx = G2[0], gmy = G2[1];
@@ -81,7 +88,8 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(ProjParams P, SceneParam
     double q[4];
     for (int k = 0; k < 4; ++k) q[k] = S.quats[k * n + i];
     const double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-    for (int k = 0; k < 4; ++k) q[k] /= qn;
+    const double iqn = 1.0 / qn;
+    for (int k = 0; k < 4; ++k) q[k] *= iqn;
     const double w = q[0], x = q[1], y = q[2], z = q[3];
     const double Rq[9] = {1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w * z), 2.0 * (x * z + w * y),
                           2.0 * (x * y + w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w * x),
@@ -92,10 +100,11 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(ProjParams P, SceneParam
             Sig[3 * r + c] = Rq[3 * r] * Rq[3 * c] * s2[0] + Rq[3 * r + 1] * Rq[3 * c + 1] * s2[1] +
                              Rq[3 * r + 2] * Rq[3 * c + 2] * s2[2];
     const bool clx = flags & 8, cly = flags & 16;
-    double ux = tx / tz, uy = ty / tz;
+    const double itz = 1.0 / tz;  // one division; the gradients below multiply by it
+    double ux = tx * itz, uy = ty * itz;
     if (clx) ux = ux > 0 ? P.limx : -P.limx;
     if (cly) uy = uy > 0 ? P.limy : -P.limy;
-    const double J[6] = {P.fx / tz, 0.0, -P.fx * ux / tz, 0.0, P.fy / tz, -P.fy * uy / tz};
+    const double J[6] = {P.fx * itz, 0.0, -P.fx * ux * itz, 0.0, P.fy * itz, -P.fy * uy * itz};
     double M[6];
     for (int r = 0; r < 2; ++r)
         for (int c = 0; c < 3; ++c)
@@ -108,12 +117,12 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(ProjParams P, SceneParam
     const double b = MS[0] * M[3] + MS[1] * M[4] + MS[2] * M[5];
     const double c = MS[3] * M[3] + MS[4] * M[4] + MS[5] * M[5] + 0.3;
     const double det = a * c - b * b;
-    const double d2 = det * det;
+    const double id2 = 1.0 / (det * det);
 
     // ---- conic (c, -b, a)/det -> (a, b, c)
-    const double ga = gA * (-c * c / d2) + gB * (b * c / d2) + gC * (-b * b / d2);
-    const double gb = gA * (2.0 * b * c / d2) + gB * (-(a * c + b * b) / d2) + gC * (2.0 * a * b / d2);
-    const double gc = gA * (-b * b / d2) + gB * (a * b / d2) + gC * (-a * a / d2);
+    const double ga = (gA * (-c * c) + gB * (b * c) + gC * (-b * b)) * id2;
+    const double gb = (gA * (2.0 * b * c) + gB * (-(a * c + b * b)) + gC * (2.0 * a * b)) * id2;
+    const double gc = (gA * (-b * b) + gB * (a * b) + gC * (-a * a)) * id2;
     const double Gs[4] = {ga, 0.5 * gb, 0.5 * gb, gc};
     // dL/dM = 2 G M Sigma ; dL/dSigma = M^T G M
     double gM[6];
@@ -131,16 +140,16 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(ProjParams P, SceneParam
         for (int k = 0; k < 3; ++k)
             gJ[3 * r + k] = gM[3 * r] * R[3 * k] + gM[3 * r + 1] * R[3 * k + 1] + gM[3 * r + 2] * R[3 * k + 2];
     double gt0 = 0.0, gt1 = 0.0, gt2 = 0.0;
-    const double tz2 = tz * tz, tz3 = tz2 * tz;
-    gt2 += gJ[0] * (-P.fx / tz2) + gJ[4] * (-P.fy / tz2);
-    if (!clx) { gt0 += gJ[2] * (-P.fx / tz2); gt2 += gJ[2] * (2.0 * P.fx * tx / tz3); }
-    else      { gt2 += gJ[2] * (P.fx * ux / tz2); }
-    if (!cly) { gt1 += gJ[5] * (-P.fy / tz2); gt2 += gJ[5] * (2.0 * P.fy * ty / tz3); }
-    else      { gt2 += gJ[5] * (P.fy * uy / tz2); }
+    const double itz2 = itz * itz, itz3 = itz2 * itz;
+    gt2 += gJ[0] * (-P.fx * itz2) + gJ[4] * (-P.fy * itz2);
+    if (!clx) { gt0 += gJ[2] * (-P.fx * itz2); gt2 += gJ[2] * (2.0 * P.fx * tx * itz3); }
+    else      { gt2 += gJ[2] * (P.fx * ux * itz2); }
+    if (!cly) { gt1 += gJ[5] * (-P.fy * itz2); gt2 += gJ[5] * (2.0 * P.fy * ty * itz3); }
+    else      { gt2 += gJ[5] * (P.fy * uy * itz2); }
     // 2D mean
-    gt0 += gmx * P.fx / tz;
-    gt1 += gmy * P.fy / tz;
-    gt2 += -gmx * P.fx * tx / tz2 - gmy * P.fy * ty / tz2;
+    gt0 += gmx * P.fx * itz;
+    gt1 += gmy * P.fy * itz;
+    gt2 += -gmx * P.fx * tx * itz2 - gmy * P.fy * ty * itz2;
 
     // ---- Sigma = Rq diag(s2) Rq^T
     double GR[9];  // gSig Rq
@@ -153,7 +162,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(ProjParams P, SceneParam
     for (int k = 0; k < 3; ++k) {
         // (Rq^T gSig Rq)_kk
         const double d = Rq[k] * GR[k] + Rq[3 + k] * GR[3 + k] + Rq[6 + k] * GR[6 + k];
-        A.g_log_scales[k * n + i] = (float)(2.0 * s2[k] * d);
+        put(&A.g_log_scales[k * n + i], 2.0 * s2[k] * d);
     }
     double gq[4];
     gq[0] = 2.0 * (-z * gR[1] + y * gR[2] + z * gR[3] - x * gR[5] - y * gR[6] + x * gR[7]);
@@ -164,11 +173,11 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(ProjParams P, SceneParam
     gq[3] = 2.0 * (-2.0 * z * gR[0] - w * gR[1] + x * gR[2] + w * gR[3] - 2.0 * z * gR[4] + y * gR[5] +
                    x * gR[6] + y * gR[7]);
     const double dot = q[0] * gq[0] + q[1] * gq[1] + q[2] * gq[2] + q[3] * gq[3];
-    for (int k = 0; k < 4; ++k) A.g_quats[k * n + i] = (float)((gq[k] - q[k] * dot) / qn);
+    for (int k = 0; k < 4; ++k) put(&A.g_quats[k * n + i], (gq[k] - q[k] * dot) * iqn);
 
     // ---- opacity
     const double o = 1.0 / (1.0 + exp(-(double)S.opacity_logits[i]));
-    A.g_opacity_logits[i] = (float)(go * o * (1.0 - o));
+    put(&A.g_opacity_logits[i], go * o * (1.0 - o));
 
     // ---- colour
     double gm[3] = {0.0, 0.0, 0.0};
@@ -177,7 +186,8 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(ProjParams P, SceneParam
             if (flags & (1u << ch)) grgb[ch] = 0.0;
         double v[3] = {m0 - P.campos[0], m1 - P.campos[1], m2 - P.campos[2]};
         const double vl = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-        const double dx = v[0] / vl, dy = v[1] / vl, dz = v[2] / vl;
+        const double ivl = 1.0 / vl;
+        const double dx = v[0] * ivl, dy = v[1] * ivl, dz = v[2] * ivl;
         double Y[16], wsum[16];
         sh_basis64(dx, dy, dz, Y);
 #pragma unroll
@@ -187,7 +197,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(ProjParams P, SceneParam
                 const float* cf = S.sh + (int64_t)k * 3 * n + i;
 #pragma unroll
                 for (int ch = 0; ch < 3; ++ch) {
-                    A.g_sh[((int64_t)k * 3 + ch) * n + i] = (float)(Y[k] * grgb[ch]);
+                    put(&A.g_sh[((int64_t)k * 3 + ch) * n + i], Y[k] * grgb[ch]);
                     wsum[k] += (double)cf[(int64_t)ch * n] * grgb[ch];
                 }
             }
@@ -195,13 +205,13 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(ProjParams P, SceneParam
         double gdir[3];
         sh_weighted_grad64(dx, dy, dz, wsum, gdir);
         const double dd = dx * gdir[0] + dy * gdir[1] + dz * gdir[2];
-        gm[0] = (gdir[0] - dx * dd) / vl;
-        gm[1] = (gdir[1] - dy * dd) / vl;
-        gm[2] = (gdir[2] - dz * dd) / vl;
+        gm[0] = (gdir[0] - dx * dd) * ivl;
+        gm[1] = (gdir[1] - dy * dd) * ivl;
+        gm[2] = (gdir[2] - dz * dd) * ivl;
     }
     // t_cam = Rcam m + t
     for (int k = 0; k < 3; ++k) gm[k] += R[k] * gt0 + R[3 + k] * gt1 + R[6 + k] * gt2;
-    for (int k = 0; k < 3; ++k) A.g_means[k * n + i] = (float)gm[k];
+    for (int k = 0; k < 3; ++k) put(&A.g_means[k * n + i], gm[k]);
 }
 
 }  // namespace

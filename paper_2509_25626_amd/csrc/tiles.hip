@@ -15,7 +15,6 @@ namespace cds {
 namespace {
 
 constexpr int kDiffThreads = 256;
-constexpr int64_t kDiffLdsMaxTiles = 16383;  // ntiles + 1 ints fit 64 KiB of LDS
 
 struct DiffArgs {
     int64_t n;
@@ -28,30 +27,43 @@ struct DiffArgs {
     int nitems;
 };
 
+// +1 / -1 at the ends of every rectangle row's run of tile ids.  Each thread
+// loads four splats before adding any, so their loads overlap.
 template <bool kLds>
 __global__ __launch_bounds__(kDiffThreads) void k_tile_diff(DiffArgs a) {
+    constexpr int kUnroll = 4;
     extern __shared__ int s_d[];
     int* d = kLds ? s_d : a.diff;
     if (kLds) {
         for (int64_t k = threadIdx.x; k <= a.ntiles; k += kDiffThreads) s_d[k] = 0;
         __syncthreads();
     }
-    for (int64_t i = (int64_t)blockIdx.x * kDiffThreads + threadIdx.x; i < a.n;
-         i += (int64_t)gridDim.x * kDiffThreads) {
-        if (!a.touched[i]) continue;
-        const uint2 r = a.rect[i];
-        const uint32_t x0 = r.x & 0xFFFFu, y0 = r.x >> 16, x1 = r.y & 0xFFFFu, y1 = r.y >> 16;
-        uint32_t tx = (uint32_t)a.tiles_x, tb = 0;
-        if (a.items) {
-            const int it = find_item_by_gaussian(a.items, a.nitems, i);
-            tx = (uint32_t)a.items[it].P.tiles_x;
-            tb = (uint32_t)a.items[it].tile_base;
+    const int64_t stride = (int64_t)gridDim.x * kDiffThreads;
+    for (int64_t i0 = (int64_t)blockIdx.x * kDiffThreads + threadIdx.x; i0 < a.n; i0 += kUnroll * stride) {
+        uint32_t cnt[kUnroll];
+        uint2 r[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int64_t i = i0 + u * stride;
+            cnt[u] = i < a.n ? a.touched[i] : 0u;
+            r[u] = cnt[u] ? a.rect[i] : make_uint2(0u, 0u);
         }
-        const uint32_t w = x1 - x0 + 1;
-        for (uint32_t y = y0; y <= y1; ++y) {
-            const uint32_t t0 = tb + y * tx + x0;
-            atomicAdd(&d[t0], 1);
-            atomicAdd(&d[t0 + w], -1);
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            if (!cnt[u]) continue;
+            const uint32_t x0 = r[u].x & 0xFFFFu, y0 = r[u].x >> 16, x1 = r[u].y & 0xFFFFu, y1 = r[u].y >> 16;
+            uint32_t tx = (uint32_t)a.tiles_x, tb = 0;
+            if (a.items) {
+                const int it = find_item_by_gaussian(a.items, a.nitems, i0 + u * stride);
+                tx = (uint32_t)a.items[it].P.tiles_x;
+                tb = (uint32_t)a.items[it].tile_base;
+            }
+            const uint32_t w = x1 - x0 + 1;
+            for (uint32_t y = y0; y <= y1; ++y) {
+                const uint32_t t0 = tb + y * tx + x0;
+                atomicAdd(&d[t0], 1);
+                atomicAdd(&d[t0 + w], -1);
+            }
         }
     }
     if (kLds) {
@@ -157,7 +169,7 @@ hipError_t launch_tile_counts(int64_t n, const uint32_t* touched, const uint2* r
         a.nitems = nitems;
         int64_t blocks = (n + kDiffThreads - 1) / kDiffThreads;
         if (blocks > max_blocks) blocks = max_blocks;
-        if (ntiles <= kDiffLdsMaxTiles)
+        if (ntiles <= kTileDiffLdsMaxTiles)
             hipLaunchKernelGGL(k_tile_diff<true>, dim3((unsigned)blocks), dim3(kDiffThreads),
                                sizeof(int) * (size_t)(ntiles + 1), stream, a);
         else
