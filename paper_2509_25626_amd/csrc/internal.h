@@ -162,14 +162,17 @@ hipError_t launch_sort_histogram(const uint32_t* keys, int64_t count, int passes
                                  hipStream_t stream, int end_bit = 0);
 hipError_t launch_sort_prepare(const SortWorkspace& ws, int64_t count, int passes, bool clear_hist,
                                hipStream_t stream);
-// Key bits at and above end_bit (0: shift0 + 8 * passes) must be zero; a
-// pass whose digit has fewer significant bits ranks on those bits only.
+// The sort covers key bits [shift0, end_bit) (end_bit 0: shift0 + 8 * passes)
+// split over the passes by digit_plan.  keep_keys false: the last pass
+// writes only the values (its keys are left unwritten).
 hipError_t launch_sort_passes(const uint64_t* kin, const uint32_t* vin, uint64_t* ka, uint32_t* va,
                               uint64_t* kb, uint32_t* vb, int64_t count, int passes, int shift0,
-                              const SortWorkspace& ws, SortAlgo algo, hipStream_t stream, int end_bit = 0);
+                              const SortWorkspace& ws, SortAlgo algo, hipStream_t stream, int end_bit = 0,
+                              bool keep_keys = true);
 hipError_t launch_sort_passes(const uint32_t* kin, const uint32_t* vin, uint32_t* ka, uint32_t* va,
                               uint32_t* kb, uint32_t* vb, int64_t count, int passes, int shift0,
-                              const SortWorkspace& ws, SortAlgo algo, hipStream_t stream, int end_bit = 0);
+                              const SortWorkspace& ws, SortAlgo algo, hipStream_t stream, int end_bit = 0,
+                              bool keep_keys = true);
 
 hipError_t launch_fill_u32(uint32_t* p, int64_t count, uint32_t value, hipStream_t stream);
 

@@ -226,12 +226,14 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
         const bool odd = (passes & 1) != 0;
         if (presort) {
             if (K > 0)
+                // the ranges come from the tile counts and the blend needs only the
+                // values, so the last pass does not write the tile ids
                 CDS_HIP(launch_sort_passes((const uint32_t*)f->tk0.p, (const uint32_t*)f->vals0.p,
                                            (uint32_t*)f->tk1.p, (uint32_t*)f->vals1.p, (uint32_t*)f->tk0.p,
                                            (uint32_t*)f->vals0.p, (int64_t)K, passes, 0, ws, algo, stream,
-                                           tile_bits_for(ntiles)),
+                                           tile_bits_for(ntiles), false),
                         "tile sort");
-            f->res_tiles = (const uint32_t*)(odd ? f->tk1.p : f->tk0.p);
+            f->res_tiles = passes > 0 ? nullptr : (const uint32_t*)f->tk0.p;
             f->res_tile_stride = 1;
             f->res_keys = nullptr;
         } else {

@@ -216,7 +216,7 @@ cds_status run_batch(cds_server* s, Workspace& w) {
                 "batched duplicate");
         SRV_HIP(launch_sort_passes((const uint32_t*)f->tk0.p, (const uint32_t*)f->vals0.p, (uint32_t*)f->tk1.p,
                                    (uint32_t*)f->vals1.p, (uint32_t*)f->tk0.p, (uint32_t*)f->vals0.p, (int64_t)K,
-                                   tile_passes, 0, ws, algo, stream, tile_bits_for(T)),
+                                   tile_passes, 0, ws, algo, stream, tile_bits_for(T), false),
                 "tile sort");
     }
     const bool odd = (tile_passes & 1) != 0;

@@ -91,28 +91,33 @@ __global__ __launch_bounds__(256) void k_sort_histogram(const Key* __restrict__ 
 }
 
 // Lanes of the wave holding the same digit (restricted to `valid` lanes),
-// from one ballot per significant digit bit (`bits` <= 8, uniform).  x is
-// all ones where the bit is set, so the lanes agreeing with this lane on the
-// bit are ~(m ^ x): five VALU operations per bit.
-__device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid, int bits) {
+// from one ballot per digit bit.  x is all ones where the bit is set, so the
+// lanes agreeing with this lane on the bit are ~(m ^ x).  The bit count is a
+// compile-time constant: no branches, and the ballots of different bits are
+// independent, so their SGPR hazards overlap.
+template <int kBits>
+__device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
+    uint32_t x[kBits];
+    uint64_t m[kBits];
+#pragma unroll
+    for (int b = 0; b < kBits; ++b) {
+        x[b] = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);
+        asm("" : "+v"(x[b]));  // compare x itself rather than a re-derived shift of d
+    }
+#pragma unroll
+    for (int b = 0; b < kBits; ++b) m[b] = ballot(x[b] != 0u);
     const uint64_t v = ballot(valid);
     uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
-        if (b < bits) {
-            uint32_t x = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);
-            asm("" : "+v"(x));  // compare x itself rather than a re-derived shift of d
-            const uint64_t m = ballot(x != 0u);
-            lo &= ~((uint32_t)m ^ x);
-            hi &= ~((uint32_t)(m >> 32) ^ x);
-        }
+    for (int b = 0; b < kBits; ++b) {
+        lo &= ~((uint32_t)m[b] ^ x[b]);
+        hi &= ~((uint32_t)(m[b] >> 32) ^ x[b]);
     }
     return ((uint64_t)hi << 32) | lo;
 }
 
-// Per-partition digit counts, digit-major: part_hist[d * parts + p].  Each
-// distinct digit of a wave round costs one LDS atomic (equal digits would
-// otherwise serialise on one address).
+// Per-partition digit counts, digit-major: part_hist[d * parts + p].  Counts
+// do not depend on order, so plain (skew-aware) LDS atomics suffice.
 template <typename Key>
 __global__ __launch_bounds__(kNT) void k_rts_upsweep(const Key* __restrict__ keys, int64_t count, int shift,
                                                      int bits, uint32_t* __restrict__ part_hist, int64_t parts) {
@@ -121,13 +126,16 @@ __global__ __launch_bounds__(kNT) void k_rts_upsweep(const Key* __restrict__ key
     s_h[t] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kP;
-#pragma unroll 4
+    Key k[kKPT];
+#pragma unroll
     for (int r = 0; r < kKPT; ++r) {
         const int64_t idx = base + (int64_t)r * kNT + t;
-        const bool valid = idx < count;
-        const uint32_t d = valid ? (uint32_t)(keys[idx] >> shift) & ((1u << bits) - 1u) : 0u;
-        const uint64_t peers = digit_peers(d, valid, bits);
-        if (valid && count_below(peers) == 0) atomicAdd(&s_h[d], (uint32_t)__popcll(peers));
+        k[r] = idx < count ? keys[idx] : (Key)0;
+    }
+#pragma unroll
+    for (int r = 0; r < kKPT; ++r) {
+        const int64_t idx = base + (int64_t)r * kNT + t;
+        if (idx < count) hist_add(s_h, (uint32_t)(k[r] >> shift) & ((1u << bits) - 1u));
     }
     __syncthreads();
     part_hist[(int64_t)t * parts + blockIdx.x] = s_h[t];
@@ -137,7 +145,7 @@ template <typename Key>
 struct PassArgs {
     const Key* kin;
     const uint32_t* vin;  // null: the value of input position i is i
-    Key* kout;
+    Key* kout;            // null: only the values are written (a last pass whose keys are not needed)
     uint32_t* vout;
     int64_t count;
     int shift;
@@ -151,34 +159,34 @@ struct PassArgs {
     uint32_t* err;
 };
 
-template <typename Key, bool kOnesweep>
-__global__ __launch_bounds__(kNT) void k_sort_pass(PassArgs<Key> a) {
-    __shared__ Key s_keys[kP];                  // reorder buffer
-    __shared__ uint32_t s_vals[kP];
-    __shared__ uint32_t s_whist[kWaves][256];   // per-wave digit counters, then offsets
-    __shared__ uint32_t s_gbase[256];
-    __shared__ uint32_t s_scan[kWaves];
-    __shared__ uint32_t s_pid;
-
+// One partition of one pass.  kFull: the partition has no tail (every key
+// valid), compiled separately so the common case carries no bounds checks.
+template <typename Key, bool kOnesweep, int kBits, bool kFull>
+__device__ __forceinline__ void sort_pass_body(const PassArgs<Key>& a, uint32_t pid, Key* s_keys, uint32_t* s_vals,
+                                               uint32_t (*s_whist)[256], uint32_t* s_gbase, uint32_t* s_scan) {
+    constexpr uint32_t kMask = (1u << kBits) - 1u;
     const int t = threadIdx.x;
     const int w = t / kWave;
     const uint32_t l = lane_id();
-    if (t == 0) s_pid = kOnesweep ? atomicAdd(a.counter, 1u) : blockIdx.x;
-    for (int k = t; k < kWaves * 256; k += kNT) (&s_whist[0][0])[k] = 0;
-    __syncthreads();
-    const uint32_t pid = s_pid;
     const int64_t base = (int64_t)pid * kP;
     const int64_t wbase = base + (int64_t)w * (kWave * kKPT);
-    const bool full = base + kP <= a.count;  // uniform: no tail in this partition
 
     Key key[kKPT];
     uint32_t val[kKPT];
 #pragma unroll
     for (int r = 0; r < kKPT; ++r) {
         const int64_t idx = wbase + r * kWave + l;
-        const bool valid = full || idx < a.count;
-        key[r] = valid ? a.kin[idx] : (Key)0;
-        val[r] = valid ? (a.vin ? a.vin[idx] : (uint32_t)idx) : 0u;
+        key[r] = (kFull || idx < a.count) ? a.kin[idx] : (Key)0;
+    }
+    if (a.vin) {  // uniform: one clean load loop either way
+#pragma unroll
+        for (int r = 0; r < kKPT; ++r) {
+            const int64_t idx = wbase + r * kWave + l;
+            val[r] = (kFull || idx < a.count) ? a.vin[idx] : 0u;
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < kKPT; ++r) val[r] = (uint32_t)(wbase + r * kWave + l);
     }
 
     // Stable wave-level ranking.  Per round, the first lane of every digit
@@ -189,9 +197,9 @@ __global__ __launch_bounds__(kNT) void k_sort_pass(PassArgs<Key> a) {
     uint32_t pre[kKPT], info[kKPT];  // info: below | first lane << 8
 #pragma unroll
     for (int r = 0; r < kKPT; ++r) {
-        const bool valid = full || (wbase + r * kWave + l) < a.count;
-        const uint32_t d = (uint32_t)(key[r] >> a.shift) & a.dmask;
-        const uint64_t peers = digit_peers(d, valid, a.bits);
+        const bool valid = kFull || (wbase + r * kWave + l) < a.count;
+        const uint32_t d = (uint32_t)(key[r] >> a.shift) & kMask;
+        const uint64_t peers = digit_peers<kBits>(d, valid);
         const uint32_t below = count_below(peers);
         const uint32_t first = valid ? (uint32_t)__builtin_ctzll(peers) : l;
         pre[r] = 0;
@@ -264,40 +272,95 @@ __global__ __launch_bounds__(kNT) void k_sort_pass(PassArgs<Key> a) {
     s_gbase[t] = gb - bstart;
     __syncthreads();
 
-    // reorder (key, value) pairs by digit in LDS
+    // reorder (key, value) pairs by digit in LDS; a slot can only fall outside
+    // the partition with inconsistent counts, and is then clamped
 #pragma unroll
     for (int r = 0; r < kKPT; ++r) {
-        const bool valid = full || (wbase + r * kWave + l) < a.count;
+        const bool valid = kFull || (wbase + r * kWave + l) < a.count;
         if (valid) {
-            const uint32_t d = (uint32_t)(key[r] >> a.shift) & a.dmask;
-            const uint32_t pos = s_whist[w][d] + rank[r];
-            if (pos < (uint32_t)kP) {
-                s_keys[pos] = key[r];
-                s_vals[pos] = val[r];
-            }
+            const uint32_t d = (uint32_t)(key[r] >> a.shift) & kMask;
+            const uint32_t pos = min(s_whist[w][d] + rank[r], (uint32_t)(kP - 1));
+            s_keys[pos] = key[r];
+            s_vals[pos] = val[r];
         }
     }
     __syncthreads();
     // each digit run goes out as a contiguous stretch
-    const int64_t rem = a.count - base;
-    const uint32_t nvalid = rem < kP ? (uint32_t)rem : (uint32_t)kP;
+    const uint32_t nvalid = kFull ? (uint32_t)kP : (uint32_t)(a.count - base);
 #pragma unroll
     for (int r = 0; r < kKPT; ++r) {
         const uint32_t i = (uint32_t)(r * kNT + t);
-        if (i < nvalid) {
+        if (kFull || i < nvalid) {
             const Key k = s_keys[i];
-            const uint32_t d = (uint32_t)(k >> a.shift) & a.dmask;
+            const uint32_t d = (uint32_t)(k >> a.shift) & kMask;
             const uint32_t g = s_gbase[d] + i;
             // a position outside the output can only come from inconsistent digit
             // counts; record it instead of writing out of bounds
             if ((int64_t)g < a.count) {
-                a.kout[g] = k;
+                if (a.kout) a.kout[g] = k;
                 a.vout[g] = s_vals[i];
             } else {
                 atomicOr(a.err, 2u);
             }
         }
     }
+}
+
+template <typename Key, bool kOnesweep, int kBits>
+__device__ __forceinline__ void sort_pass_kernel(const PassArgs<Key>& a) {
+    __shared__ Key s_keys[kP];                  // reorder buffer
+    __shared__ uint32_t s_vals[kP];
+    __shared__ uint32_t s_whist[kWaves][256];   // per-wave digit counters, then offsets
+    __shared__ uint32_t s_gbase[256];
+    __shared__ uint32_t s_scan[kWaves];
+    __shared__ uint32_t s_pid;
+
+    const int t = threadIdx.x;
+    if (t == 0) s_pid = kOnesweep ? atomicAdd(a.counter, 1u) : blockIdx.x;
+    for (int k = t; k < kWaves * 256; k += kNT) (&s_whist[0][0])[k] = 0;
+    __syncthreads();
+    const uint32_t pid = s_pid;
+    if ((int64_t)(pid + 1) * kP <= a.count)
+        sort_pass_body<Key, kOnesweep, kBits, true>(a, pid, s_keys, s_vals, s_whist, s_gbase, s_scan);
+    else
+        sort_pass_body<Key, kOnesweep, kBits, false>(a, pid, s_keys, s_vals, s_whist, s_gbase, s_scan);
+}
+
+// Onesweep passes: four workgroups per CU (VGPRs <= 128, 37 KB of LDS each),
+// so that partitions waiting in their look-back overlap with others' work.
+template <typename Key, int kBits>
+__global__ __launch_bounds__(kNT, 4) void k_sort_pass_onesweep(PassArgs<Key> a) {
+    sort_pass_kernel<Key, true, kBits>(a);
+}
+
+template <typename Key, int kBits>
+__global__ __launch_bounds__(kNT, 4) void k_sort_pass_rts(PassArgs<Key> a) {
+    sort_pass_kernel<Key, false, kBits>(a);
+}
+
+template <typename Key, bool kOnesweep, int kBits>
+void launch_pass_bits(const PassArgs<Key>& a, dim3 grid, hipStream_t stream) {
+    if constexpr (kOnesweep)
+        hipLaunchKernelGGL((k_sort_pass_onesweep<Key, kBits>), grid, dim3(kNT), 0, stream, a);
+    else
+        hipLaunchKernelGGL((k_sort_pass_rts<Key, kBits>), grid, dim3(kNT), 0, stream, a);
+}
+
+template <typename Key, bool kOnesweep>
+hipError_t launch_pass(const PassArgs<Key>& a, int64_t parts, hipStream_t stream) {
+    const dim3 grid((unsigned)parts);
+    switch (a.bits) {
+        case 1: launch_pass_bits<Key, kOnesweep, 1>(a, grid, stream); break;
+        case 2: launch_pass_bits<Key, kOnesweep, 2>(a, grid, stream); break;
+        case 3: launch_pass_bits<Key, kOnesweep, 3>(a, grid, stream); break;
+        case 4: launch_pass_bits<Key, kOnesweep, 4>(a, grid, stream); break;
+        case 5: launch_pass_bits<Key, kOnesweep, 5>(a, grid, stream); break;
+        case 6: launch_pass_bits<Key, kOnesweep, 6>(a, grid, stream); break;
+        case 7: launch_pass_bits<Key, kOnesweep, 7>(a, grid, stream); break;
+        case 8: launch_pass_bits<Key, kOnesweep, 8>(a, grid, stream); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 template <typename Key>
@@ -314,7 +377,7 @@ hipError_t sort_histogram_impl(const Key* keys, int64_t count, int passes, int s
 template <typename Key>
 hipError_t sort_passes_impl(const Key* kin, const uint32_t* vin, Key* ka, uint32_t* va, Key* kb,
                             uint32_t* vb, int64_t count, int passes, int shift0, int end_bit,
-                            const SortWorkspace& ws, SortAlgo algo, hipStream_t stream) {
+                            const SortWorkspace& ws, SortAlgo algo, hipStream_t stream, bool keep_keys) {
     if (count <= 0 || passes <= 0) return hipSuccess;
     if (count > kSortMaxCount) return hipErrorInvalidValue;
     const int64_t parts = sort_partitions(count);
@@ -327,6 +390,7 @@ hipError_t sort_passes_impl(const Key* kin, const uint32_t* vin, Key* ka, uint32
         a.vin = p == 0 ? vin : ((p & 1) ? va : vb);
         a.kout = (p & 1) ? kb : ka;
         a.vout = (p & 1) ? vb : va;
+        if (p == passes - 1 && !keep_keys) a.kout = nullptr;
         a.count = count;
         a.shift = plan.shift[p];
         a.bits = plan.bits[p];
@@ -339,7 +403,7 @@ hipError_t sort_passes_impl(const Key* kin, const uint32_t* vin, Key* ka, uint32
         a.err = ws.err;
         hipError_t e;
         if (onesweep) {
-            hipLaunchKernelGGL((k_sort_pass<Key, true>), dim3((unsigned)parts), dim3(kNT), 0, stream, a);
+            if ((e = launch_pass<Key, true>(a, parts, stream)) != hipSuccess) return e;
         } else {
             hipLaunchKernelGGL(k_rts_upsweep<Key>, dim3((unsigned)parts), dim3(kNT), 0, stream, a.kin, count,
                                a.shift, a.bits, ws.part_hist, parts);
@@ -347,7 +411,7 @@ hipError_t sort_passes_impl(const Key* kin, const uint32_t* vin, Key* ka, uint32
             e = launch_exclusive_scan(ws.part_hist, nullptr, ws.bases, 256 * parts, ws.scan_sums, ws.scan_total,
                                       stream);
             if (e != hipSuccess) return e;
-            hipLaunchKernelGGL((k_sort_pass<Key, false>), dim3((unsigned)parts), dim3(kNT), 0, stream, a);
+            if ((e = launch_pass<Key, false>(a, parts, stream)) != hipSuccess) return e;
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
@@ -392,16 +456,18 @@ hipError_t launch_sort_prepare(const SortWorkspace& ws, int64_t count, int passe
 
 hipError_t launch_sort_passes(const uint64_t* kin, const uint32_t* vin, uint64_t* ka, uint32_t* va,
                               uint64_t* kb, uint32_t* vb, int64_t count, int passes, int shift0,
-                              const SortWorkspace& ws, SortAlgo algo, hipStream_t stream, int end_bit) {
+                              const SortWorkspace& ws, SortAlgo algo, hipStream_t stream, int end_bit,
+                              bool keep_keys) {
     return sort_passes_impl<uint64_t>(kin, vin, ka, va, kb, vb, count, passes, shift0,
-                                      end_bit > 0 ? end_bit : shift0 + 8 * passes, ws, algo, stream);
+                                      end_bit > 0 ? end_bit : shift0 + 8 * passes, ws, algo, stream, keep_keys);
 }
 
 hipError_t launch_sort_passes(const uint32_t* kin, const uint32_t* vin, uint32_t* ka, uint32_t* va,
                               uint32_t* kb, uint32_t* vb, int64_t count, int passes, int shift0,
-                              const SortWorkspace& ws, SortAlgo algo, hipStream_t stream, int end_bit) {
+                              const SortWorkspace& ws, SortAlgo algo, hipStream_t stream, int end_bit,
+                              bool keep_keys) {
     return sort_passes_impl<uint32_t>(kin, vin, ka, va, kb, vb, count, passes, shift0,
-                                      end_bit > 0 ? end_bit : shift0 + 8 * passes, ws, algo, stream);
+                                      end_bit > 0 ? end_bit : shift0 + 8 * passes, ws, algo, stream, keep_keys);
 }
 
 }  // namespace cds
