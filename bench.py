@@ -54,17 +54,21 @@ def roofline(stages, scene, K, passes, info):
     sh_bytes = 4 * 3 * (scene.sh_degree + 1) ** 2
     tiles = int(info.tiles_x) * int(info.tiles_y)
     tile_passes = max(int(passes) - 4, 1)
+    tile_bits = max(1, (tiles - 1).bit_length())
+    tile_digit_bits = -(-tile_bits // tile_passes)  # widest digit of the balanced split
     table = {
         # kernel, launches per frame, algorithmic bytes per launch
         # preprocess: 40 B of geometry + SH in, 61 B of splat state out per Gaussian
         "preprocess_ms": ("k_preprocess", 1, (40 + sh_bytes + 61) * n),
-        # depth sort: 4 onesweep passes over (u32 depth, u32 index), 16 B per Gaussian each
-        "scan_ms": ("k_sort_pass<u32> (depth digits)", 4, 16 * n),
+        # depth presort: 4 onesweep passes over (u32 depth, u32 index), 16 B per Gaussian each
+        "scan_ms": ("k_sort_pass_onesweep<u32,8> (depth digits)", 4, 16 * n),
         # duplicate: 8 B per key (tile id, value) + 24 B per Gaussian read
         "duplicate_ms": ("k_duplicate", 1, 8 * K + 24 * n),
-        # tile sort: read and write (u32 tile id, u32 value), 16 B per key per pass
-        "sort_ms": ("k_sort_pass<u32> (tile digits)", tile_passes, 16 * K),
-        # ranges: read 4 B per key, write 8 B per tile
+        # tile sort: read and write (u32 tile id, u32 value), 16 B per key per pass; the
+        # last pass writes only the values (12 B per key); averaged over the launches
+        "sort_ms": (f"k_sort_pass_onesweep<u32,{tile_digit_bits}> (tile digits)", tile_passes,
+                    (16 * (tile_passes - 1) + 12) * K // tile_passes),
+        # ranges from sorted keys (sort variant 1): read 4 B per key, write 8 B per tile
         "ranges_ms": ("k_ranges4", 1, 4 * K + 8 * tiles),
     }
     dom = max(stages, key=stages.get)

@@ -51,14 +51,14 @@ __device__ __forceinline__ void stage_splat(const float2* __restrict__ mean2d,
 // cancel and float32 would lose the digits that decide alpha.  Float64 FMA
 // runs at the float32 (non-packed) rate on CDNA4, so this costs one
 // conversion per pair.  Returns false when the splat is skipped
-// (power > 0 or alpha < 1/255).
+// (power > 0 or alpha < 1/255); alpha and G are computed either way (the
+// callers select), and are only meaningful when it returns true.
 __device__ __forceinline__ bool splat_alpha(double adx2, double bdx, double c2, double dy, float opacity,
                                             float& alpha, float& G) {
     const double power = fma(dy, fma(c2, dy, bdx), adx2);  // log2(e) * power
-    if (power > 0.0) return false;
     G = __builtin_amdgcn_exp2f((float)power);
     alpha = fminf(kAlphaMax, opacity * G);
-    return !(alpha < kAlphaMin);
+    return !(power > 0.0) && !(alpha < kAlphaMin);
 }
 
 // One 16x16 tile: stage its sorted splats through LDS in batches and blend
@@ -117,22 +117,25 @@ __device__ __forceinline__ void blend_tile(int tx, int ty, int width, int height
             const double dx = q.x - fpx;
             const double adx2 = (q.z * dx) * dx;
             const double bdx = q.w * dx;
+            // alpha and the skip test without branches; one branch around the
+            // (mostly skipped) accumulation
 #pragma unroll
             for (int p = 0; p < PPT; ++p) {
-                if (done[p]) continue;
                 float alpha, G;
-                if (!splat_alpha(adx2, bdx, c2, q.y - fpy[p], f.x, alpha, G)) continue;
-                const float test_T = T[p] * (1.0f - alpha);
-                if (test_T < kTMin) {
-                    done[p] = true;
-                    continue;
+                const bool hit = splat_alpha(adx2, bdx, c2, q.y - fpy[p], f.x, alpha, G) && !done[p];
+                if (hit) {
+                    const float test_T = T[p] * (1.0f - alpha);
+                    if (test_T < kTMin) {
+                        done[p] = true;
+                    } else {
+                        const float wgt = alpha * T[p];
+                        C0[p] = fmaf(f.y, wgt, C0[p]);
+                        C1[p] = fmaf(f.z, wgt, C1[p]);
+                        C2[p] = fmaf(f.w, wgt, C2[p]);
+                        T[p] = test_T;
+                        last[p] = (uint32_t)(base + j + 1);
+                    }
                 }
-                const float wgt = alpha * T[p];
-                C0[p] = fmaf(f.y, wgt, C0[p]);
-                C1[p] = fmaf(f.z, wgt, C1[p]);
-                C2[p] = fmaf(f.w, wgt, C2[p]);
-                T[p] = test_T;
-                last[p] = (uint32_t)(base + j + 1);
             }
         }
     }

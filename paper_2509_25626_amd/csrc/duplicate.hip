@@ -61,7 +61,7 @@ __global__ __launch_bounds__(kNT) void k_duplicate(DupArgs A) {
             cnt = A.touched[gid];
             if (cnt) {
                 r = A.rect[gid];
-                depth = A.depth_bits[gid];
+                if (A.keys64) depth = A.depth_bits[gid];  // tile-id mode needs no depth
                 if (A.items) {
                     const int it = find_item_by_gaussian(A.items, A.nitems, gid);
                     tx_n = (uint32_t)A.items[it].P.tiles_x;
