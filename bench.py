@@ -53,6 +53,7 @@ def roofline(stages, scene, K, passes, info):
     n = scene.n
     sh_bytes = 4 * 3 * (scene.sh_degree + 1) ** 2
     tiles = int(info.tiles_x) * int(info.tiles_y)
+    nvis = int(info.num_visible)
     tile_passes = max(int(passes) - 4, 1)
     tile_bits = max(1, (tiles - 1).bit_length())
     tile_digit_bits = -(-tile_bits // tile_passes)  # widest digit of the balanced split
@@ -60,8 +61,10 @@ def roofline(stages, scene, K, passes, info):
         # kernel, launches per frame, algorithmic bytes per launch
         # preprocess: 40 B of geometry + SH in, 61 B of splat state out per Gaussian
         "preprocess_ms": ("k_preprocess", 1, (40 + sh_bytes + 61) * n),
-        # depth presort: 4 onesweep passes over (u32 depth, u32 index), 16 B per Gaussian each
-        "scan_ms": ("k_sort_pass_onesweep<u32,8> (depth digits)", 4, 16 * n),
+        # compaction of the visible splats: 16 B read per Gaussian, 20 B written per visible one
+        "scan_ms": ("k_vis_count + k_vis_scatter", 1, 16 * n + 20 * nvis),
+        # depth order: 4 onesweep passes over (u32 depth, u32 position) of the visible splats
+        "depth_order_ms": ("k_sort_pass_onesweep<u32,8> (depth digits)", 4, 16 * nvis),
         # duplicate: 8 B per key (tile id, value) + 24 B per Gaussian read
         "duplicate_ms": ("k_duplicate", 1, 8 * K + 24 * n),
         # tile sort: read and write (u32 tile id, u32 value), 16 B per key per pass; the

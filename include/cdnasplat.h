@@ -198,8 +198,8 @@ typedef struct cds_frame_info {
     int64_t n;                     /* Gaussians of the last render */
     int64_t num_keys;              /* K: duplicated (tile | depth) keys */
     int32_t width, height, tiles_x, tiles_y;
-    int32_t sort_passes;           /* 8-bit radix passes over the 64-bit key (depth + tile digits) */
-    int32_t reserved;
+    int32_t sort_passes;           /* radix passes over the key's digits (depth + tile) */
+    int32_t num_visible;           /* splats with at least one tile (visit positions of offsets, variant 2) */
     const float* mean2d;           /* [n] float2 (x, y), pixels */
     const float* conic_opacity;    /* [n] float4 (A, B, C, opacity): power = -A dx^2/2 - B dx dy - C dy^2/2 */
     const float* rgb;              /* [n] float4 (r, g, b, 0) after the clamp at 0 */
@@ -207,9 +207,10 @@ typedef struct cds_frame_info {
     const int32_t* radius;         /* [n] screen radius in pixels, 0 if culled */
     const uint32_t* tile_rect;     /* [n] uint2: (tx0 | ty0 << 16, tx1 | ty1 << 16), inclusive */
     const uint32_t* tiles_touched; /* [n] number of covered tiles */
-    const uint32_t* offsets;       /* [n] exclusive prefix sum of tiles_touched in visit order
-                                      (index order for sort variant 1, depth order for 2);
-                                      NULL for variant 3, which does not form it */
+    const uint32_t* offsets;       /* exclusive prefix sum of tiles_touched in visit order: [n] in
+                                      index order (sort variant 1); [num_visible] over the visible
+                                      splats in (depth, index) order (variant 2); NULL for variant 3,
+                                      which does not form it */
     const uint64_t* keys;          /* [K] sorted (tile << 32 | depth bits) */
     const uint32_t* values;        /* [K] Gaussian index of each sorted key */
     const uint32_t* ranges;        /* [tiles_x * tiles_y] uint2 [start, end), (0, 0) if empty */
@@ -220,15 +221,21 @@ cds_status cds_frame_get_info(cds_frame* frame, cds_frame_info* out);
 
 /* Per-stage device time of the frame's last forward (and backward) render,
  * in milliseconds, from HIP events recorded on the render's stream when the
- * forward ran with CDS_OPT_STAGE_TIMING.  Waits for those events.  `scan_ms`
- * covers everything between preprocessing and the host read-back of the key
- * count, read-back included: the per-Gaussian depth sort (sort variants 2,
- * 3), the prefix sum of tiles_touched (variants 1, 2) or the tile counts and
- * their scans (variant 3).  With sort variant 3 `duplicate_ms` is the fused
- * placement and `sort_ms`, `ranges_ms` are 0.  Backward fields are 0 until a
- * backward pass has run. */
+ * forward ran with CDS_OPT_STAGE_TIMING.  Waits for those events.
+ *   preprocess_ms   projection and colour (a1, a2)
+ *   scan_ms         up to the host read-back of the key count, included:
+ *                   the visible-splat compaction (sort variant 2), the prefix
+ *                   sum of tiles_touched (variant 1), or the depth sort and
+ *                   tile counts of binning (variant 3)
+ *   depth_order_ms  variant 2: depth sort of the visible splats, their key
+ *                   offsets, the per-tile counts and ranges; 0 otherwise
+ *   duplicate_ms    key generation (variant 3: the fused placement)
+ *   sort_ms         the per-key radix passes (0 for variant 3)
+ *   ranges_ms       ranges from the sorted keys (variant 1 only)
+ *   blend_ms        the per-pixel blend
+ * Backward fields are 0 until a backward pass has run. */
 typedef struct cds_stage_times {
-    float preprocess_ms, scan_ms, duplicate_ms, sort_ms, ranges_ms, blend_ms;
+    float preprocess_ms, scan_ms, depth_order_ms, duplicate_ms, sort_ms, ranges_ms, blend_ms;
     float blend_backward_ms, preprocess_backward_ms;
 } cds_stage_times;
 

@@ -1,0 +1,148 @@
+// Compaction of the visible splats (paper Section II-B(1): only splats that
+// overlap some tile are replicated and sorted).  In one pass over the N
+// Gaussians in index order:
+//   - per 4096-Gaussian tile: the number of visible splats and their keys
+//     (tiles touched), scanned to tile bases and to the totals n_vis and K,
+//   - a stable compaction (index order kept) of the visible splats' depth
+//     bits and of a 16-byte record (tile rectangle, Gaussian index), and
+//   - the digit histograms of the depth sort over the compacted keys.
+// K here is the sum of tiles touched, which does not depend on the order,
+// so one host read-back of (n_vis, K) sizes everything that follows.
+#include "device_utils.h"
+#include "internal.h"
+
+namespace cds {
+namespace {
+
+constexpr int kCT = 256;
+constexpr int kCIPT = 16;
+constexpr int64_t kCTile = (int64_t)kCT * kCIPT;
+constexpr int kCWaves = kCT / kWave;
+
+__global__ __launch_bounds__(kCT) void k_vis_count(int64_t n, const uint32_t* __restrict__ touched,
+                                                   uint64_t* __restrict__ vis_sums, uint64_t* __restrict__ key_sums) {
+    __shared__ unsigned long long s_v[kCWaves], s_k[kCWaves];
+    const int64_t base = (int64_t)blockIdx.x * kCTile;
+    uint32_t v = 0;
+    unsigned long long k = 0;
+#pragma unroll
+    for (int r = 0; r < kCIPT; ++r) {
+        const int64_t i = base + (int64_t)r * kCT + threadIdx.x;
+        const uint32_t c = i < n ? touched[i] : 0u;
+        v += c ? 1u : 0u;
+        k += c;
+    }
+    unsigned long long vv = v;
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        vv += __shfl_xor(vv, o, kWave);
+        k += __shfl_xor(k, o, kWave);
+    }
+    const int w = threadIdx.x / kWave;
+    if (lane_id() == 0) {
+        s_v[w] = vv;
+        s_k[w] = k;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long a = 0, b = 0;
+#pragma unroll
+        for (int q = 0; q < kCWaves; ++q) {
+            a += s_v[q];
+            b += s_k[q];
+        }
+        vis_sums[blockIdx.x] = a;
+        key_sums[blockIdx.x] = b;
+    }
+}
+
+// Wave w of block b takes items [b*4096 + w*1024, +1024) in 16 rounds of 64
+// consecutive items; a visible item's slot is the block base (scanned), the
+// wave's base within the block, the round's base within the wave and its
+// rank among the round's visible lanes (one ballot).
+__global__ __launch_bounds__(kCT) void k_vis_scatter(int64_t n, const uint32_t* __restrict__ touched,
+                                                     const uint2* __restrict__ rect,
+                                                     const uint32_t* __restrict__ depth_bits,
+                                                     const uint64_t* __restrict__ vis_base,
+                                                     uint32_t* __restrict__ dkey, uint4* __restrict__ rec,
+                                                     uint32_t* __restrict__ hist) {
+    __shared__ uint32_t s_hist[4 * 256];
+    __shared__ uint32_t s_wtot[kCWaves];
+    const int t = threadIdx.x;
+    const int w = t / kWave;
+    const uint32_t lane = lane_id();
+    for (int k = t; k < 4 * 256; k += kCT) s_hist[k] = 0;
+    const int64_t wbase = (int64_t)blockIdx.x * kCTile + (int64_t)w * (kWave * kCIPT);
+    uint32_t c[kCIPT];
+    uint32_t wtot = 0;
+#pragma unroll
+    for (int r = 0; r < kCIPT; ++r) {
+        const int64_t i = wbase + r * kWave + lane;
+        c[r] = i < n ? touched[i] : 0u;
+        wtot += (uint32_t)__popcll(ballot(c[r] != 0u));
+    }
+    if (lane == 0) s_wtot[w] = wtot;
+    __syncthreads();
+    uint32_t slot = (uint32_t)vis_base[blockIdx.x];
+    for (int q = 0; q < w; ++q) slot += s_wtot[q];
+#pragma unroll
+    for (int r = 0; r < kCIPT; ++r) {
+        const int64_t i = wbase + r * kWave + lane;
+        const uint64_t m = ballot(c[r] != 0u);
+        if (c[r]) {
+            const uint32_t pos = slot + count_below(m);
+            const uint32_t d = depth_bits[i];
+            const uint2 rc = rect[i];
+            dkey[pos] = d;
+            rec[pos] = make_uint4(rc.x, rc.y, (uint32_t)i, 0u);
+#pragma unroll
+            for (int p = 0; p < 4; ++p) hist_add(s_hist + p * 256, (d >> (8 * p)) & 255u);
+        }
+        slot += (uint32_t)__popcll(m);
+    }
+    __syncthreads();
+    for (int k = t; k < 4 * 256; k += kCT) {
+        const uint32_t v = s_hist[k];
+        if (v) atomicAdd(&hist[k], v);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_rec_gather(int64_t count, const uint32_t* __restrict__ order,
+                                                    const uint4* __restrict__ src, uint4* __restrict__ dst) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < count) dst[j] = src[order[j]];
+}
+
+}  // namespace
+
+int64_t compact_sums_size(int64_t n) { return (n + kCTile - 1) / kCTile + 1; }
+
+hipError_t launch_compact_visible(int64_t n, const uint32_t* touched, const uint2* rect, const uint32_t* depth_bits,
+                                  uint64_t* vis_sums, uint64_t* key_sums, uint64_t* totals, uint32_t* dkey,
+                                  uint4* rec, uint32_t* depth_hist, hipStream_t stream) {
+    const int64_t tiles = (n + kCTile - 1) / kCTile;
+    hipError_t e = launch_fill_u32(depth_hist, 4 * 256, 0u, stream);
+    if (e != hipSuccess) return e;
+    if (tiles > 0) {
+        hipLaunchKernelGGL(k_vis_count, dim3((unsigned)tiles), dim3(kCT), 0, stream, n, touched, vis_sums,
+                           key_sums);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if ((e = launch_scan_u64(vis_sums, tiles, totals, stream)) != hipSuccess) return e;
+    if ((e = launch_scan_u64(key_sums, tiles, totals + 1, stream)) != hipSuccess) return e;
+    if (tiles > 0) {
+        hipLaunchKernelGGL(k_vis_scatter, dim3((unsigned)tiles), dim3(kCT), 0, stream, n, touched, rect, depth_bits,
+                           vis_sums, dkey, rec, depth_hist);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+hipError_t launch_rec_gather(int64_t count, const uint32_t* order, const uint4* src, uint4* dst, hipStream_t stream) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rec_gather, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, stream, count, order, src,
+                       dst);
+    return hipGetLastError();
+}
+
+}  // namespace cds

@@ -37,6 +37,7 @@ struct DupArgs {
     uint32_t* values;
     const BatchItem* items;    // batched render: per-scene tile layout (null: one scene)
     int nitems;
+    const uint4* rec;          // compacted visible records in visit order (rect, Gaussian index), or null
 };
 
 __device__ __forceinline__ void emit(const DupArgs& A, uint32_t pos, uint32_t tile, uint32_t depth, uint32_t gid) {
@@ -55,7 +56,14 @@ __global__ __launch_bounds__(kNT) void k_duplicate(DupArgs A) {
         const int64_t j = base + lane;
         uint32_t off = 0, cnt = 0, gid = 0, depth = 0, tx_n = tiles_x, tbase = 0;
         uint2 r = make_uint2(0u, 0u);
-        if (j < n) {
+        if (j < n && A.rec) {
+            const uint4 q = A.rec[j];
+            gid = q.z;
+            off = A.offsets[j];
+            r = make_uint2(q.x, q.y);
+            cnt = ((q.y & 0xFFFFu) - (q.x & 0xFFFFu) + 1u) * ((q.y >> 16) - (q.x >> 16) + 1u);
+            if (A.keys64) depth = A.depth_bits[gid];
+        } else if (j < n) {
             gid = A.order ? A.order[j] : (uint32_t)j;
             off = A.offsets[j];
             cnt = A.touched[gid];
@@ -123,7 +131,7 @@ __global__ __launch_bounds__(256) void k_make_keys(const uint32_t* __restrict__ 
 hipError_t launch_duplicate(int64_t n, const uint32_t* order, const uint32_t* offsets, const uint32_t* touched,
                             const uint2* rect, const uint32_t* depth_bits, int tiles_x, uint64_t* keys64,
                             uint32_t* tiles32, uint32_t* values, hipStream_t stream, const BatchItem* items,
-                            int nitems) {
+                            int nitems, const uint4* rec) {
     if (n == 0) return hipSuccess;
     DupArgs A;
     A.n = n;
@@ -138,6 +146,7 @@ hipError_t launch_duplicate(int64_t n, const uint32_t* order, const uint32_t* of
     A.values = values;
     A.items = items;
     A.nitems = nitems;
+    A.rec = rec;
     const int64_t groups = (n + kNT - 1) / kNT;
     const int64_t grid = groups < 4096 ? groups : 4096;
     hipLaunchKernelGGL(k_duplicate, dim3((unsigned)grid), dim3(kNT), 0, stream, A);

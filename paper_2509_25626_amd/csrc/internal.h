@@ -84,12 +84,27 @@ __device__ __forceinline__ int find_item_by_tile(const BatchItem* items, int nit
 hipError_t launch_preprocess_batch(const BatchItem* items, int nitems, int64_t total, const SplatBuffers& out,
                                    hipStream_t stream);
 
+// Exclusive scan of `count` uint64 values in place (one workgroup), total to *total.
+hipError_t launch_scan_u64(uint64_t* values, int64_t count, uint64_t* total, hipStream_t stream);
+
+// Compaction of the visible splats (tiles touched > 0) in index order:
+// dkey[n_vis] depth bits, rec[n_vis] = (rect.x, rect.y, Gaussian index, 0),
+// depth_hist [4][256] digit histograms of dkey, totals[0] = n_vis,
+// totals[1] = K.  vis_sums, key_sums: compact_sums_size(n) uint64 each.
+int64_t compact_sums_size(int64_t n);
+hipError_t launch_compact_visible(int64_t n, const uint32_t* touched, const uint2* rect, const uint32_t* depth_bits,
+                                  uint64_t* vis_sums, uint64_t* key_sums, uint64_t* totals, uint32_t* dkey,
+                                  uint4* rec, uint32_t* depth_hist, hipStream_t stream);
+// dst[j] = src[order[j]]
+hipError_t launch_rec_gather(int64_t count, const uint32_t* order, const uint4* src, uint4* dst, hipStream_t stream);
+
 // Exclusive scan of n uint32 values (read as in[gather[i]] when gather is
 // not null); the total (uint64, device) is written too.  `block_sums` needs
 // scan_block_sums_size(n) uint64 elements.
 int64_t scan_block_sums_size(int64_t n);
 hipError_t launch_exclusive_scan(const uint32_t* in, const uint32_t* gather, uint32_t* out, int64_t n,
-                                 uint64_t* block_sums, uint64_t* total, hipStream_t stream);
+                                 uint64_t* block_sums, uint64_t* total, hipStream_t stream,
+                                 const uint4* rec = nullptr);
 
 // Key duplication over the visit order `order` (identity when null): writes
 // Digit layout of an LSD sort of key bits [shift0, end_bit) in `passes`
@@ -121,7 +136,7 @@ inline DigitPlan digit_plan(int passes, int shift0, int end_bit) {
 hipError_t launch_duplicate(int64_t n, const uint32_t* order, const uint32_t* offsets, const uint32_t* touched,
                             const uint2* rect, const uint32_t* depth_bits, int tiles_x, uint64_t* keys64,
                             uint32_t* tiles32, uint32_t* values, hipStream_t stream, const BatchItem* items = nullptr,
-                            int nitems = 0);
+                            int nitems = 0, const uint4* rec = nullptr);
 // Per-tile key counts from the rectangles: ranges [ntiles] of the sorted
 // list, the tile-digit histograms hist [plan.passes][256] (written, not
 // accumulated; may be null) and *total = K (may be null).  diff: ntiles + 1
@@ -130,7 +145,8 @@ constexpr int kTileCountBlocks = 512;
 constexpr int64_t kTileDiffLdsMaxTiles = 16383;  // ntiles + 1 ints fit 64 KiB of LDS
 hipError_t launch_tile_counts(int64_t n, const uint32_t* touched, const uint2* rect, int tiles_x, int64_t ntiles,
                               int* diff, uint2* ranges, uint32_t* hist, const DigitPlan& plan, uint64_t* total,
-                              int max_blocks, hipStream_t stream, const BatchItem* items = nullptr, int nitems = 0);
+                              int max_blocks, hipStream_t stream, const BatchItem* items = nullptr, int nitems = 0,
+                              const uint4* rec = nullptr);
 hipError_t launch_make_keys(const uint32_t* tiles, const uint32_t* values, const uint32_t* depth_bits,
                             int64_t count, uint64_t* keys, hipStream_t stream);
 

@@ -23,6 +23,7 @@ void release_frame_buffers(cds_frame* f) {
                       &f->dkey0, &f->dkey1, &f->sort_d.hist, &f->sort_d.status, &f->sort_d.counters,
                       &f->sort_d.part_hist, &f->sort_d.bases, &f->sort_d.scan_sums, &f->sort_d.scan_total,
                       &f->vrect, &f->binM, &f->binE, &f->binP, &f->tsum, &f->tdiff, &f->thist,
+                      &f->dkeyc, &f->recc, &f->recv, &f->vsums, &f->ksums,
                       &f->keys0, &f->keys1, &f->tk0, &f->tk1, &f->vals0, &f->vals1, &f->sort.hist,
                       &f->sort.status, &f->sort.counters, &f->sort.part_hist, &f->sort.bases,
                       &f->sort.scan_sums, &f->sort.scan_total, &f->ranges, &f->grad2d};
@@ -50,32 +51,37 @@ int tile_bits_for(int64_t ntiles) {
 /*
  * Sort variants.  Every variant yields the same sorted (tile | depth, index)
  * list and tile ranges.
- *  1: the 64-bit keys are generated per (Gaussian, tile) and radix-sorted on
- *     all their digits.
- *  2: the 32 depth bits of every key of a Gaussian are that Gaussian's depth,
- *     so the four depth-digit LSD passes run once over the N Gaussians
- *     (stable, ties by index); keys are generated in that order -- exactly
- *     the sequence the depth passes would have produced -- and only the
- *     tile-digit passes run over the keys, as 32-bit tile ids.
- *  3: as 2, but the tile-order pass is a counting sort on the whole tile id
- *     fused with duplication (tile binning): no per-key sort pass at all.
- *  0: 2 (the faster at every size measured so far).
+ *  1: the 64-bit keys are generated per (Gaussian, tile) in index order and
+ *     radix-sorted on all their digits.
+ *  2: the visible splats are compacted (index order kept) and their 32 depth
+ *     bits -- shared by all keys of a splat -- are sorted once per splat
+ *     (four LSD passes over n_vis, stable, ties by index); keys are generated
+ *     in that order, exactly the sequence the depth passes would have
+ *     produced, and only the tile-digit passes run over the keys, as 32-bit
+ *     tile ids.  Ranges and the tile-digit histograms come from the
+ *     rectangles (per-tile counts), so the last pass writes only the values.
+ *  3: a per-splat depth sort as in 2 (over all N), then the tile-order pass as
+ *     a counting sort on the whole tile id fused with duplication (binning).
+ *  0: 2 (the fastest at every size measured so far).
+ * Stage events: start, preprocess, key count read back, depth order, keys
+ * generated, tile sort, ranges, blend (see cds_stage_times).
  */
 cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scene, const cds_camera* cam,
                                int blend_variant, int sort_variant, SortAlgo algo, float* out_rgb, float* out_T,
                                uint32_t* out_ncontrib, hipStream_t stream) {
     const int64_t n = scene->n;
     f->timed_backward = false;
-    CDS_TRY(f->record(0, stream));
+    CDS_TRY(f->record(kEvStart, stream));
     const ProjParams P = make_proj(scene, cam);
     const int64_t ntiles = (int64_t)P.tiles_x * P.tiles_y;
     const size_t nn = (size_t)(n > 0 ? n : 1);
-    const int tile_passes = (tile_bits_for(ntiles) + 7) / 8;
+    const int tile_bits = tile_bits_for(ntiles);
+    const int tile_passes = (tile_bits + 7) / 8;
     const bool can_bin = bin_supported(P.tiles_x, P.tiles_y);
     if (sort_variant == 0) sort_variant = 2;
     if (sort_variant == 3 && !can_bin)
-        return fail(CDS_ERR_INVALID_ARG, "tile binning needs at most 4096 tiles per row");
-    const bool presort = sort_variant == 2 || sort_variant == 3;
+        return fail(CDS_ERR_INVALID_ARG, "tile binning needs at most 512 tiles per row");
+    const bool compact = sort_variant == 2;
     const bool binned = sort_variant == 3;
 
     CDS_TRY(ensure(ctx, f->mean2d, sizeof(float2) * nn, 1.1));
@@ -92,11 +98,16 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
         CDS_TRY(ensure(ctx, f->offsets, sizeof(uint32_t) * nn, 1.1));
         CDS_TRY(ensure(ctx, f->blocksums, sizeof(uint64_t) * scan_block_sums_size(n), 1.1));
     }
-    if (sort_variant == 2) {
+    if (compact) {
         CDS_TRY(ensure(ctx, f->tdiff, sizeof(int) * (size_t)(ntiles + 1), 1.1));
         CDS_TRY(ensure(ctx, f->thist, sizeof(uint32_t) * 4 * 256));
+        CDS_TRY(ensure(ctx, f->dkeyc, sizeof(uint32_t) * nn, 1.1));
+        CDS_TRY(ensure(ctx, f->recc, sizeof(uint4) * nn, 1.1));
+        CDS_TRY(ensure(ctx, f->recv, sizeof(uint4) * nn, 1.1));
+        CDS_TRY(ensure(ctx, f->vsums, sizeof(uint64_t) * compact_sums_size(n), 1.1));
+        CDS_TRY(ensure(ctx, f->ksums, sizeof(uint64_t) * compact_sums_size(n), 1.1));
     }
-    if (presort) {
+    if (compact || binned) {
         CDS_TRY(ensure(ctx, f->order0, sizeof(uint32_t) * nn, 1.1));
         CDS_TRY(ensure(ctx, f->order1, sizeof(uint32_t) * nn, 1.1));
         CDS_TRY(ensure(ctx, f->dkey0, sizeof(uint32_t) * nn, 1.1));
@@ -123,51 +134,52 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
     sb.touched = (uint32_t*)f->touched.p;
     sb.clamp_flags = (uint8_t*)f->clampf.p;
     CDS_HIP(launch_preprocess(P, make_scene(scene), sb, stream), "preprocess kernel");
-    CDS_TRY(f->record(1, stream));
+    CDS_TRY(f->record(kEvPreprocess, stream));
 
-    // depth order of the Gaussians (variants 2, 3): 4 passes, result in (dkey1, order1)
+    uint64_t* d_total = (uint64_t*)f->total.p;  // [0] = n_vis (variant 2), [1] = K
+    SortWorkspace wd = (compact || binned) ? sort_ws(ctx, f->sort_d) : SortWorkspace{};
     const uint32_t* order = nullptr;
-    if (presort && n > 0) {
-        SortWorkspace wd = sort_ws(ctx, f->sort_d);
-        if (sort_uses_onesweep(n, algo)) {
-            CDS_HIP(launch_sort_prepare(wd, n, 4, true, stream), "depth sort prepare");
-            CDS_HIP(launch_sort_histogram(sb.depth_bits, n, 4, 0, wd.hist, stream), "depth sort histogram");
+    if (compact) {
+        // visible splats compacted in index order, with the depth histograms; n_vis and K
+        CDS_HIP(launch_compact_visible(n, sb.touched, sb.rect, sb.depth_bits, (uint64_t*)f->vsums.p,
+                                       (uint64_t*)f->ksums.p, d_total, (uint32_t*)f->dkeyc.p, (uint4*)f->recc.p,
+                                       wd.hist, stream),
+                "visible compaction");
+    } else if (binned) {
+        // depth order of all N Gaussians: 4 passes, result in (dkey1, order1)
+        if (n > 0) {
+            if (sort_uses_onesweep(n, algo)) {
+                CDS_HIP(launch_sort_prepare(wd, n, 4, true, stream), "depth sort prepare");
+                CDS_HIP(launch_sort_histogram(sb.depth_bits, n, 4, 0, wd.hist, stream), "depth sort histogram");
+            }
+            CDS_HIP(launch_sort_passes(sb.depth_bits, nullptr, (uint32_t*)f->dkey0.p, (uint32_t*)f->order0.p,
+                                       (uint32_t*)f->dkey1.p, (uint32_t*)f->order1.p, n, 4, 0, wd, algo, stream),
+                    "depth sort");
+            order = (const uint32_t*)f->order1.p;
         }
-        CDS_HIP(launch_sort_passes(sb.depth_bits, nullptr, (uint32_t*)f->dkey0.p, (uint32_t*)f->order0.p,
-                                   (uint32_t*)f->dkey1.p, (uint32_t*)f->order1.p, n, 4, 0, wd, algo, stream),
-                "depth sort");
-        order = (const uint32_t*)f->order1.p;
-    }
-    uint64_t* d_total = (uint64_t*)f->total.p;
-    if (binned) {
-        // per (chunk, band) tile counts, their column scan, tile ranges and K
         CDS_HIP(launch_bin_gather(n, order, sb.touched, sb.rect, (uint2*)f->vrect.p, stream), "bin gather");
         CDS_HIP(launch_bin_count(bp, n, (const uint2*)f->vrect.p, (uint32_t*)f->binM.p, stream), "bin count");
         CDS_HIP(launch_bin_scan(bp, (const uint32_t*)f->binM.p, (uint32_t*)f->binE.p, (uint32_t*)f->binP.p,
-                                (uint32_t*)f->tsum.p, (uint2*)f->ranges.p, d_total, stream),
+                                (uint32_t*)f->tsum.p, (uint2*)f->ranges.p, d_total + 1, stream),
                 "bin scan");
     } else {
-        CDS_HIP(launch_exclusive_scan(sb.touched, order, (uint32_t*)f->offsets.p, n, (uint64_t*)f->blocksums.p,
-                                      d_total, stream),
+        CDS_HIP(launch_exclusive_scan(sb.touched, nullptr, (uint32_t*)f->offsets.p, n, (uint64_t*)f->blocksums.p,
+                                      d_total + 1, stream),
                 "scan kernels");
-        if (presort)  // ranges and tile-digit histograms from the rectangles
-            CDS_HIP(launch_tile_counts(n, sb.touched, sb.rect, P.tiles_x, ntiles, (int*)f->tdiff.p,
-                                       (uint2*)f->ranges.p, (uint32_t*)f->thist.p,
-                                       digit_plan(tile_passes, 0, tile_bits_for(ntiles)), nullptr, kTileCountBlocks,
-                                       stream),
-                    "tile counts");
     }
-    CDS_HIP(hipMemcpyAsync(ctx->host_pinned, d_total, sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
+    CDS_HIP(hipMemcpyAsync(ctx->host_pinned, d_total, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
             "hipMemcpyAsync(key count)");
     CDS_HIP(hipStreamSynchronize(stream), "hipStreamSynchronize(key count)");
-    CDS_TRY(f->record(2, stream));
-    const uint64_t K = ctx->host_pinned[0];
+    CDS_TRY(f->record(kEvCount, stream));
+    const int64_t nvis = compact ? (int64_t)ctx->host_pinned[0] : n;
+    const uint64_t K = ctx->host_pinned[1];
     if (K > (uint64_t)kSortMaxCount)
         return fail(CDS_ERR_CAPACITY, "render needs " + std::to_string(K) +
                                           " tile keys; the sorted list supports at most 2^30-1");
     const size_t kk = (size_t)(K > 0 ? K : 1);
     CDS_TRY(ensure(ctx, f->vals0, sizeof(uint32_t) * kk, 1.25));
     f->n = n;
+    f->n_vis = nvis;
     f->K = (int64_t)K;
     f->width = cam->width;
     f->height = cam->height;
@@ -176,21 +188,46 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
     f->sort_variant = sort_variant;
 
     if (binned) {
+        CDS_TRY(f->record(kEvDepth, stream));
         CDS_HIP(launch_bin_place(bp, n, order, (const uint2*)f->vrect.p, (const uint32_t*)f->binM.p,
                                  (const uint32_t*)f->binE.p, K, (uint32_t*)f->vals0.p, ctx->d_err, stream),
                 "bin place");
-        CDS_TRY(f->record(3, stream));
-        CDS_TRY(f->record(4, stream));
-        CDS_TRY(f->record(5, stream));
+        CDS_TRY(f->record(kEvKeys, stream));
+        CDS_TRY(f->record(kEvSort, stream));
+        CDS_TRY(f->record(kEvRanges, stream));
         f->res_values = (const uint32_t*)f->vals0.p;
         f->res_tiles = nullptr;
         f->res_tile_stride = 1;
         f->res_keys = nullptr;
         f->passes = 4;
     } else {
-        const int passes = presort ? tile_passes : 4 + tile_passes;
+        const uint4* recv = (const uint4*)f->recv.p;
+        if (compact && nvis > 0) {
+            // depth sort of the compacted keys (values: compacted positions), then
+            // the records in depth order, their key offsets, and the tile counts
+            if (sort_uses_onesweep(nvis, algo))
+                CDS_HIP(launch_sort_prepare(wd, nvis, 4, false, stream), "depth sort prepare");
+            CDS_HIP(launch_sort_passes((const uint32_t*)f->dkeyc.p, nullptr, (uint32_t*)f->dkey0.p,
+                                       (uint32_t*)f->order0.p, (uint32_t*)f->dkey1.p, (uint32_t*)f->order1.p, nvis,
+                                       4, 0, wd, algo, stream, 32, false),
+                    "depth sort");
+            CDS_HIP(launch_rec_gather(nvis, (const uint32_t*)f->order1.p, (const uint4*)f->recc.p, (uint4*)f->recv.p,
+                                      stream),
+                    "record gather");
+            CDS_HIP(launch_exclusive_scan(nullptr, nullptr, (uint32_t*)f->offsets.p, nvis,
+                                          (uint64_t*)f->blocksums.p, d_total + 2, stream, recv),
+                    "offset scan");
+        }
+        if (compact)  // ranges and tile-digit histograms from the rectangles
+            CDS_HIP(launch_tile_counts(nvis, nullptr, nullptr, P.tiles_x, ntiles, (int*)f->tdiff.p,
+                                       (uint2*)f->ranges.p, (uint32_t*)f->thist.p,
+                                       digit_plan(tile_passes, 0, tile_bits), nullptr, kTileCountBlocks, stream,
+                                       nullptr, 0, recv),
+                    "tile counts");
+        CDS_TRY(f->record(kEvDepth, stream));
+        const int passes = compact ? tile_passes : 4 + tile_passes;
         CDS_TRY(ensure(ctx, f->vals1, sizeof(uint32_t) * kk, 1.25));
-        if (presort) {
+        if (compact) {
             CDS_TRY(ensure(ctx, f->tk0, sizeof(uint32_t) * kk, 1.25));
             CDS_TRY(ensure(ctx, f->tk1, sizeof(uint32_t) * kk, 1.25));
         } else {
@@ -201,13 +238,13 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
         SortWorkspace ws = sort_ws(ctx, f->sort);
         const bool onesweep = sort_uses_onesweep((int64_t)K, algo) && passes > 0;
         if (K > 0) {
-            if (presort) {
+            if (compact) {
                 // the onesweep passes take the tile-digit histograms made from the rectangles
                 if (onesweep) CDS_HIP(launch_sort_prepare(ws, (int64_t)K, passes, false, stream), "sort prepare");
                 ws.hist = (uint32_t*)f->thist.p;
-                CDS_HIP(launch_duplicate(n, order, (const uint32_t*)f->offsets.p, sb.touched, sb.rect,
+                CDS_HIP(launch_duplicate(nvis, nullptr, (const uint32_t*)f->offsets.p, nullptr, nullptr,
                                          sb.depth_bits, P.tiles_x, nullptr, (uint32_t*)f->tk0.p,
-                                         (uint32_t*)f->vals0.p, stream),
+                                         (uint32_t*)f->vals0.p, stream, nullptr, 0, recv),
                         "duplicate kernel");
             } else {
                 CDS_HIP(launch_duplicate(n, nullptr, (const uint32_t*)f->offsets.p, sb.touched, sb.rect,
@@ -217,21 +254,21 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
                 if (onesweep) {
                     CDS_HIP(launch_sort_prepare(ws, (int64_t)K, passes, true, stream), "sort prepare");
                     CDS_HIP(launch_sort_histogram((const uint64_t*)f->keys0.p, (int64_t)K, passes, 0, ws.hist,
-                                                  stream, 32 + tile_bits_for(ntiles)),
+                                                  stream, 32 + tile_bits),
                             "key histogram");
                 }
             }
         }
-        CDS_TRY(f->record(3, stream));
+        CDS_TRY(f->record(kEvKeys, stream));
         const bool odd = (passes & 1) != 0;
-        if (presort) {
+        if (compact) {
             if (K > 0)
                 // the ranges come from the tile counts and the blend needs only the
                 // values, so the last pass does not write the tile ids
                 CDS_HIP(launch_sort_passes((const uint32_t*)f->tk0.p, (const uint32_t*)f->vals0.p,
                                            (uint32_t*)f->tk1.p, (uint32_t*)f->vals1.p, (uint32_t*)f->tk0.p,
-                                           (uint32_t*)f->vals0.p, (int64_t)K, passes, 0, ws, algo, stream,
-                                           tile_bits_for(ntiles), false),
+                                           (uint32_t*)f->vals0.p, (int64_t)K, passes, 0, ws, algo, stream, tile_bits,
+                                           false),
                         "tile sort");
             f->res_tiles = passes > 0 ? nullptr : (const uint32_t*)f->tk0.p;
             f->res_tile_stride = 1;
@@ -241,20 +278,20 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
                 CDS_HIP(launch_sort_passes((const uint64_t*)f->keys0.p, (const uint32_t*)f->vals0.p,
                                            (uint64_t*)f->keys1.p, (uint32_t*)f->vals1.p, (uint64_t*)f->keys0.p,
                                            (uint32_t*)f->vals0.p, (int64_t)K, passes, 0, ws, algo, stream,
-                                           32 + tile_bits_for(ntiles)),
+                                           32 + tile_bits),
                         "key sort");
             f->res_keys = (const uint64_t*)(odd ? f->keys1.p : f->keys0.p);
             f->res_tiles = reinterpret_cast<const uint32_t*>(f->res_keys) + 1;  // high words
             f->res_tile_stride = 2;
         }
         f->res_values = (const uint32_t*)(odd ? f->vals1.p : f->vals0.p);
-        CDS_TRY(f->record(4, stream));
-        f->passes = presort ? 4 + tile_passes : passes;
-        if (!presort)  // variant 2 has its ranges from the tile counts
+        CDS_TRY(f->record(kEvSort, stream));
+        f->passes = compact ? 4 + tile_passes : passes;
+        if (!compact)  // variant 2 has its ranges from the tile counts
             CDS_HIP(launch_ranges(f->res_tiles, f->res_tile_stride, (int64_t)K, (uint2*)f->ranges.p, ntiles,
                                   stream),
                     "ranges kernel");
-        CDS_TRY(f->record(5, stream));
+        CDS_TRY(f->record(kEvRanges, stream));
     }
 
     BlendArgs ba;
@@ -272,7 +309,7 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
     ba.out_T = out_T;
     ba.out_ncontrib = out_ncontrib;
     CDS_HIP(launch_blend(ba, blend_variant, stream), "blend kernel");
-    CDS_TRY(f->record(6, stream));
+    CDS_TRY(f->record(kEvBlend, stream));
     f->valid = true;
     return CDS_OK;
 }
@@ -301,7 +338,7 @@ cds_status render_backward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* sce
     if (n == 0) return CDS_OK;
     const ProjParams P = make_proj(scene, cam);
     CDS_TRY(ensure(ctx, f->grad2d, sizeof(float) * 9 * (size_t)n, 1.1));
-    CDS_TRY(f->record(7, stream));
+    CDS_TRY(f->record(kEvBwdStart, stream));
     CDS_HIP(launch_fill_u32((uint32_t*)f->grad2d.p, 9 * n, 0u, stream), "fill");
     BlendBwdArgs b;
     b.ranges = (const uint2*)f->ranges.p;
@@ -320,7 +357,7 @@ cds_status render_backward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* sce
     b.n = n;
     b.grad2d = (float*)f->grad2d.p;
     CDS_HIP(launch_blend_backward(b, stream), "blend backward kernel");
-    CDS_TRY(f->record(8, stream));
+    CDS_TRY(f->record(kEvBwdBlend, stream));
     PreBwdArgs pa;
     pa.radius = (const int32_t*)f->radius.p;
     pa.clamp_flags = (const uint8_t*)f->clampf.p;
@@ -331,7 +368,7 @@ cds_status render_backward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* sce
     pa.g_opacity_logits = g->opacity_logits;
     pa.g_sh = g->sh;
     CDS_HIP(launch_preprocess_backward(P, make_scene(scene), pa, stream), "preprocess backward kernel");
-    CDS_TRY(f->record(9, stream));
+    CDS_TRY(f->record(kEvBwdPre, stream));
     f->timed_backward = f->timing;
     return CDS_OK;
 }
@@ -352,25 +389,26 @@ cds_status cds_frame::record(int i, hipStream_t s) {
 }
 
 extern "C" cds_status cds_frame_stage_times(cds_frame* f, cds_stage_times* out) {
+    using namespace cds;
     if (!f || !out) return cds::fail(CDS_ERR_INVALID_ARG, "NULL argument");
     if (!f->valid || !f->timing) return cds::fail(CDS_ERR_INVALID_ARG, "frame has no timed render");
     hipError_t e = hipSetDevice(f->ctx->device);
     if (e != hipSuccess) return cds::hip_fail(e, "hipSetDevice");
-    const int last = f->timed_backward ? 9 : 6;
+    const int last = f->timed_backward ? kEvBwdPre : kEvBlend;
     if ((e = hipEventSynchronize(f->ev[last])) != hipSuccess) return cds::hip_fail(e, "hipEventSynchronize");
-    float ms[9] = {};
-    for (int i = 0; i < last; ++i) {
-        if (i == 6) continue;  // gap between the forward and the backward
-        if ((e = hipEventElapsedTime(&ms[i], f->ev[i], f->ev[i + 1])) != hipSuccess)
-            return cds::hip_fail(e, "hipEventElapsedTime");
-    }
-    out->preprocess_ms = ms[0];
-    out->scan_ms = ms[1];
-    out->duplicate_ms = ms[2];
-    out->sort_ms = ms[3];
-    out->ranges_ms = ms[4];
-    out->blend_ms = ms[5];
-    out->blend_backward_ms = f->timed_backward ? ms[7] : 0.f;
-    out->preprocess_backward_ms = f->timed_backward ? ms[8] : 0.f;
+    auto span = [&](int a, int b, float* out) -> hipError_t { return hipEventElapsedTime(out, f->ev[a], f->ev[b]); };
+    std::memset(out, 0, sizeof(*out));
+    if ((e = span(kEvStart, kEvPreprocess, &out->preprocess_ms)) != hipSuccess ||
+        (e = span(kEvPreprocess, kEvCount, &out->scan_ms)) != hipSuccess ||
+        (e = span(kEvCount, kEvDepth, &out->depth_order_ms)) != hipSuccess ||
+        (e = span(kEvDepth, kEvKeys, &out->duplicate_ms)) != hipSuccess ||
+        (e = span(kEvKeys, kEvSort, &out->sort_ms)) != hipSuccess ||
+        (e = span(kEvSort, kEvRanges, &out->ranges_ms)) != hipSuccess ||
+        (e = span(kEvRanges, kEvBlend, &out->blend_ms)) != hipSuccess)
+        return cds::hip_fail(e, "hipEventElapsedTime");
+    if (f->timed_backward &&
+        ((e = span(kEvBwdStart, kEvBwdBlend, &out->blend_backward_ms)) != hipSuccess ||
+         (e = span(kEvBwdBlend, kEvBwdPre, &out->preprocess_backward_ms)) != hipSuccess))
+        return cds::hip_fail(e, "hipEventElapsedTime");
     return CDS_OK;
 }

@@ -316,6 +316,7 @@ cds_status cds_frame_get_info(cds_frame* f, cds_frame_info* o) {
     o->tiles_x = f->tiles_x;
     o->tiles_y = f->tiles_y;
     o->sort_passes = f->passes;
+    o->num_visible = (int32_t)f->n_vis;
     o->mean2d = (const float*)f->mean2d.p;
     o->conic_opacity = (const float*)f->conic.p;
     o->rgb = (const float*)f->rgb.p;

@@ -16,6 +16,22 @@ struct SortState {
     DevBuf hist, status, counters, part_hist, bases, scan_sums, scan_total;
 };
 
+// stage boundaries of a timed render
+enum StageEvent {
+    kEvStart = 0,
+    kEvPreprocess,  // preprocess done
+    kEvCount,       // key count read back (compaction / scans)
+    kEvDepth,       // depth order, key offsets and tile counts ready
+    kEvKeys,        // keys generated
+    kEvSort,        // tile sort done
+    kEvRanges,      // ranges done
+    kEvBlend,       // blend done
+    kEvBwdStart,
+    kEvBwdBlend,
+    kEvBwdPre,
+    kEvCount_
+};
+
 }  // namespace cds
 
 struct cds_ctx {
@@ -36,6 +52,7 @@ struct cds_frame {
     cds::DevBuf order0, order1, dkey0, dkey1;  // per-Gaussian depth sort (sort variants 2, 3)
     cds::DevBuf vrect, binM, binE, binP, tsum;  // tile binning (sort variant 3)
     cds::DevBuf tdiff, thist;                  // per-tile counts and tile-digit histograms (variant 2)
+    cds::DevBuf dkeyc, recc, recv, vsums, ksums;  // compacted visible splats (variant 2)
     cds::SortState sort_d;
     // per key
     cds::DevBuf keys0, keys1;                  // 64-bit keys (variant 1; others: rebuilt on request)
@@ -46,7 +63,7 @@ struct cds_frame {
     cds::DevBuf ranges;
     // backward
     cds::DevBuf grad2d;
-    int64_t n = 0, K = 0;
+    int64_t n = 0, n_vis = 0, K = 0;
     int32_t width = 0, height = 0, tiles_x = 0, tiles_y = 0, passes = 0, sort_variant = 0;
     bool valid = false;
     // where the last render left its sorted list
@@ -54,9 +71,9 @@ struct cds_frame {
     const uint32_t* res_tiles = nullptr;  // tile id words, stride res_tile_stride (null: binned)
     int res_tile_stride = 1;
     const uint64_t* res_keys = nullptr;   // 64-bit keys, null until built (variants 2, 3)
-    // stage timing: events 0..6 bracket the forward stages, 7..9 the backward
+    // stage timing: HIP events at the stage boundaries (kEv*)
     bool timing = false, timed_backward = false;
-    hipEvent_t ev[10] = {};
+    hipEvent_t ev[cds::kEvCount_] = {};
     cds_status record(int i, hipStream_t s);
     void release_all();
 };

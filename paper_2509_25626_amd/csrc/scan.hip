@@ -14,22 +14,30 @@ constexpr int kNT = 256;
 constexpr int kIPT = 16;
 constexpr int64_t kTileItems = (int64_t)kNT * kIPT;
 
-// in[gather[i]] when `gather` is given, else in[i]
-__device__ __forceinline__ uint32_t scan_in(const uint32_t* __restrict__ in, const uint32_t* __restrict__ gather,
-                                            int64_t i) {
-    return gather ? in[gather[i]] : in[i];
+// Scan input: the tile count of a compacted splat record (area of its tile
+// rectangle) when `rec` is given, else in[gather[i]] or in[i].
+struct ScanSrc {
+    const uint32_t* in;
+    const uint32_t* gather;
+    const uint4* rec;
+};
+
+__device__ __forceinline__ uint32_t scan_in(const ScanSrc& s, int64_t i) {
+    if (s.rec) {
+        const uint4 r = s.rec[i];
+        return ((r.y & 0xFFFFu) - (r.x & 0xFFFFu) + 1u) * ((r.y >> 16) - (r.x >> 16) + 1u);
+    }
+    return s.gather ? s.in[s.gather[i]] : s.in[i];
 }
 
-__global__ __launch_bounds__(kNT) void k_scan_reduce(const uint32_t* __restrict__ in,
-                                                     const uint32_t* __restrict__ gather, int64_t n,
-                                                     uint64_t* __restrict__ sums) {
+__global__ __launch_bounds__(kNT) void k_scan_reduce(ScanSrc src, int64_t n, uint64_t* __restrict__ sums) {
     __shared__ uint32_t scratch[kNT / kWave];
     const int64_t base = (int64_t)blockIdx.x * kTileItems;
     uint32_t s = 0;
 #pragma unroll
     for (int k = 0; k < kIPT; ++k) {
         const int64_t idx = base + (int64_t)k * kNT + threadIdx.x;
-        if (idx < n) s += scan_in(in, gather, idx);
+        if (idx < n) s += scan_in(src, idx);
     }
     uint32_t total;
     block_excl_sum<kNT>(s, scratch, &total);
@@ -71,9 +79,7 @@ __global__ __launch_bounds__(1024) void k_scan_sums(uint64_t* __restrict__ sums,
     if (threadIdx.x == 0) *total = carry;
 }
 
-__global__ __launch_bounds__(kNT) void k_scan_down(const uint32_t* __restrict__ in,
-                                                   const uint32_t* __restrict__ gather, int64_t n,
-                                                   const uint64_t* __restrict__ sums,
+__global__ __launch_bounds__(kNT) void k_scan_down(ScanSrc src, int64_t n, const uint64_t* __restrict__ sums,
                                                    uint32_t* __restrict__ out) {
     __shared__ uint32_t scratch[kNT / kWave];
     // blocked arrangement: thread t owns items [t*kIPT, (t+1)*kIPT) of the tile
@@ -82,7 +88,7 @@ __global__ __launch_bounds__(kNT) void k_scan_down(const uint32_t* __restrict__ 
     uint32_t s = 0;
 #pragma unroll
     for (int k = 0; k < kIPT; ++k) {
-        v[k] = (base + k < n) ? scan_in(in, gather, base + k) : 0u;
+        v[k] = (base + k < n) ? scan_in(src, base + k) : 0u;
         s += v[k];
     }
     uint32_t run = block_excl_sum<kNT>(s, scratch, nullptr) + (uint32_t)sums[blockIdx.x];
@@ -97,16 +103,24 @@ __global__ __launch_bounds__(kNT) void k_scan_down(const uint32_t* __restrict__ 
 
 int64_t scan_block_sums_size(int64_t n) { return (n + kTileItems - 1) / kTileItems + 1; }
 
+hipError_t launch_scan_u64(uint64_t* values, int64_t count, uint64_t* total, hipStream_t stream) {
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, stream, values, count, total);
+    return hipGetLastError();
+}
+
 hipError_t launch_exclusive_scan(const uint32_t* in, const uint32_t* gather, uint32_t* out, int64_t n,
-                                 uint64_t* block_sums, uint64_t* total, hipStream_t stream) {
+                                 uint64_t* block_sums, uint64_t* total, hipStream_t stream, const uint4* rec) {
     const int64_t tiles = (n + kTileItems - 1) / kTileItems;
+    ScanSrc src;
+    src.in = in;
+    src.gather = gather;
+    src.rec = rec;
     if (tiles > 0) {
-        hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)tiles), dim3(kNT), 0, stream, in, gather, n, block_sums);
+        hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)tiles), dim3(kNT), 0, stream, src, n, block_sums);
     }
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, stream, block_sums, tiles, total);
     if (tiles > 0) {
-        hipLaunchKernelGGL(k_scan_down, dim3((unsigned)tiles), dim3(kNT), 0, stream, in, gather, n, block_sums,
-                           out);
+        hipLaunchKernelGGL(k_scan_down, dim3((unsigned)tiles), dim3(kNT), 0, stream, src, n, block_sums, out);
     }
     return hipGetLastError();
 }

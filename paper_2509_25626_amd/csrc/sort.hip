@@ -49,26 +49,6 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, int6
         p[i] = value;
 }
 
-// h[d] += 1 for every active lane.  The first few distinct digits of the wave
-// are merged into one atomic each (take the first remaining lane's digit,
-// count the lanes sharing it), which removes the serialisation of skewed
-// digits such as the exponent byte of a depth; the remaining lanes add one
-// by one.
-__device__ __forceinline__ void hist_add(uint32_t* h, uint32_t d) {
-    uint64_t left = ballot(true);
-    const uint32_t lane = lane_id();
-#pragma unroll
-    for (int it = 0; it < 3; ++it) {
-        if (!left) break;
-        const int src = __builtin_ctzll(left);
-        const uint32_t v = __builtin_amdgcn_readlane(d, src);
-        const uint64_t m = ballot(d == v) & left;
-        if (lane == (uint32_t)src) atomicAdd(&h[v], (uint32_t)__popcll(m));
-        left &= ~m;
-    }
-    if ((left >> lane) & 1ull) atomicAdd(&h[d], 1u);
-}
-
 // Digit histograms of the plan's digits over all keys.
 template <typename Key>
 __global__ __launch_bounds__(256) void k_sort_histogram(const Key* __restrict__ keys, int64_t count, DigitPlan plan,

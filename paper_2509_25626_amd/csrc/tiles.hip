@@ -23,6 +23,7 @@ struct DiffArgs {
     int tiles_x;
     int64_t ntiles;
     int* diff;  // [ntiles + 1], zero on entry
+    const uint4* rec;  // compacted visible records (rect in .x, .y) instead of touched/rect, or null
     const BatchItem* items;
     int nitems;
 };
@@ -45,8 +46,14 @@ __global__ __launch_bounds__(kDiffThreads) void k_tile_diff(DiffArgs a) {
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             const int64_t i = i0 + u * stride;
-            cnt[u] = i < a.n ? a.touched[i] : 0u;
-            r[u] = cnt[u] ? a.rect[i] : make_uint2(0u, 0u);
+            if (a.rec) {
+                cnt[u] = i < a.n ? 1u : 0u;
+                const uint4 q = i < a.n ? a.rec[i] : make_uint4(0u, 0u, 0u, 0u);
+                r[u] = make_uint2(q.x, q.y);
+            } else {
+                cnt[u] = i < a.n ? a.touched[i] : 0u;
+                r[u] = cnt[u] ? a.rect[i] : make_uint2(0u, 0u);
+            }
         }
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
@@ -152,7 +159,8 @@ __global__ __launch_bounds__(kRangeThreads) void k_tile_ranges(int64_t ntiles, c
 
 hipError_t launch_tile_counts(int64_t n, const uint32_t* touched, const uint2* rect, int tiles_x, int64_t ntiles,
                               int* diff, uint2* ranges, uint32_t* hist, const DigitPlan& plan, uint64_t* total,
-                              int max_blocks, hipStream_t stream, const BatchItem* items, int nitems) {
+                              int max_blocks, hipStream_t stream, const BatchItem* items, int nitems,
+                              const uint4* rec) {
     if (ntiles <= 0) return hipSuccess;
     if (plan.passes > 4) return hipErrorInvalidValue;
     hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(diff), ntiles + 1, 0u, stream);
@@ -165,6 +173,7 @@ hipError_t launch_tile_counts(int64_t n, const uint32_t* touched, const uint2* r
         a.tiles_x = tiles_x;
         a.ntiles = ntiles;
         a.diff = diff;
+        a.rec = rec;
         a.items = items;
         a.nitems = nitems;
         int64_t blocks = (n + kDiffThreads - 1) / kDiffThreads;

@@ -58,7 +58,7 @@ class CdsFrameInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("num_keys", ctypes.c_int64),
                 ("width", ctypes.c_int32), ("height", ctypes.c_int32),
                 ("tiles_x", ctypes.c_int32), ("tiles_y", ctypes.c_int32),
-                ("sort_passes", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("sort_passes", ctypes.c_int32), ("num_visible", ctypes.c_int32),
                 ("mean2d", P), ("conic_opacity", P), ("rgb", P), ("depth_bits", P),
                 ("radius", P), ("tile_rect", P), ("tiles_touched", P), ("offsets", P),
                 ("keys", P), ("values", P), ("ranges", P), ("clamp_flags", P)]
@@ -66,8 +66,8 @@ class CdsFrameInfo(ctypes.Structure):
 
 class CdsStageTimes(ctypes.Structure):
     _fields_ = [(k, ctypes.c_float) for k in
-                ("preprocess_ms", "scan_ms", "duplicate_ms", "sort_ms", "ranges_ms", "blend_ms",
-                 "blend_backward_ms", "preprocess_backward_ms")]
+                ("preprocess_ms", "scan_ms", "depth_order_ms", "duplicate_ms", "sort_ms", "ranges_ms",
+                 "blend_ms", "blend_backward_ms", "preprocess_backward_ms")]
 
 
 CDS_OPT_STAGE_TIMING = 1

@@ -151,14 +151,15 @@ class Frame:
         n, K = fi.n, fi.num_keys
         ntiles = fi.tiles_x * fi.tiles_y
         g = lambda ptr, cnt, dt: device_to_numpy(ptr, cnt, dt) if ptr else np.zeros(0, dt)
+        noff = fi.num_visible if fi.offsets and fi.num_visible != n else n
         return dict(
-            n=n, K=K, tiles_x=fi.tiles_x, tiles_y=fi.tiles_y, passes=fi.sort_passes,
+            n=n, K=K, tiles_x=fi.tiles_x, tiles_y=fi.tiles_y, passes=fi.sort_passes, n_vis=fi.num_visible,
             mean2d=g(fi.mean2d, 2 * n, np.float32).reshape(n, 2),
             conic_opacity=g(fi.conic_opacity, 4 * n, np.float32).reshape(n, 4),
             rgb=g(fi.rgb, 4 * n, np.float32).reshape(n, 4),
             depth_bits=g(fi.depth_bits, n, np.uint32), radius=g(fi.radius, n, np.int32),
             tile_rect=g(fi.tile_rect, 2 * n, np.uint32).reshape(n, 2),
-            tiles_touched=g(fi.tiles_touched, n, np.uint32), offsets=g(fi.offsets, n, np.uint32),
+            tiles_touched=g(fi.tiles_touched, n, np.uint32), offsets=g(fi.offsets, noff, np.uint32),
             keys=g(fi.keys, K, np.uint64), values=g(fi.values, K, np.uint32),
             ranges=g(fi.ranges, 2 * ntiles, np.uint32).reshape(ntiles, 2),
             clamp_flags=g(fi.clamp_flags, n, np.uint8))

@@ -81,9 +81,10 @@ def expected_offsets(o, sort_variant):
     if sort_variant == 3:  # binning never forms the key offsets
         return np.zeros(0, np.uint32)
     t = o["proj"]["tiles_touched"].astype(np.uint64)
-    if sort_variant == 2:  # Gaussians visited in (depth bits, index) order
-        t = t[np.argsort(o["proj"]["depth_bits"], kind="stable")]
-    return np.concatenate([[0], np.cumsum(t)[:-1]]).astype(np.uint32)
+    if sort_variant == 2:  # visible splats visited in (depth bits, index) order
+        vis = np.nonzero(t > 0)[0]
+        t = t[vis[np.argsort(o["proj"]["depth_bits"][vis], kind="stable")]]
+    return np.concatenate([[0], np.cumsum(t)[:-1]]).astype(np.uint32) if t.size else np.zeros(0, np.uint32)
 
 
 def compare_keys(g, o, flagged, sort_variant=0):
