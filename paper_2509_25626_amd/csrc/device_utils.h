@@ -112,6 +112,16 @@ __device__ __forceinline__ void hist_add(uint32_t* h, uint32_t d) {
     if ((left >> lane) & 1ull) atomicAdd(&h[d], 1u);
 }
 
+// Lanes of one wave exchanging values through LDS: the hardware executes a
+// wave's LDS operations in issue order, so only the compiler must keep the
+// stores before the other lanes' loads (and earlier loads before later
+// stores to the same slots).  Emits no instruction.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ uint32_t atomic_load_agent(const uint32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }

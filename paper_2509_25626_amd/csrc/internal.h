@@ -102,9 +102,13 @@ hipError_t launch_rec_gather(int64_t count, const uint32_t* order, const uint4* 
 // not null); the total (uint64, device) is written too.  `block_sums` needs
 // scan_block_sums_size(n) uint64 elements.
 int64_t scan_block_sums_size(int64_t n);
+// Key offsets of splat records.  With `owner`, also the record owning every
+// kKeyGenChunk-th key (owner[q] = the record whose keys include key
+// q * kKeyGenChunk; K / kKeyGenChunk + 1 words).
+constexpr int64_t kKeyGenChunk = 1024;
 hipError_t launch_exclusive_scan(const uint32_t* in, const uint32_t* gather, uint32_t* out, int64_t n,
                                  uint64_t* block_sums, uint64_t* total, hipStream_t stream,
-                                 const uint4* rec = nullptr);
+                                 const uint4* rec = nullptr, uint32_t* owner = nullptr);
 
 // Key duplication over the visit order `order` (identity when null): writes
 // Digit layout of an LSD sort of key bits [shift0, end_bit) in `passes`
@@ -185,10 +189,27 @@ hipError_t launch_sort_passes(const uint64_t* kin, const uint32_t* vin, uint64_t
                               uint64_t* kb, uint32_t* vb, int64_t count, int passes, int shift0,
                               const SortWorkspace& ws, SortAlgo algo, hipStream_t stream, int end_bit = 0,
                               bool keep_keys = true);
+// Keys of the tile sort generated inside its first pass instead of read:
+// key p is the tile of the record owning it (row-major order within the
+// record's rectangle), its value the record's Gaussian index, which is what
+// launch_duplicate writes in record mode.
+struct KeyGen {
+    const uint32_t* off;    // [n] first key of each record
+    const uint4* rec;       // [n] (x0 | y0 << 16, x1 | y1 << 16, Gaussian index, -)
+    const uint32_t* owner;  // [count / kKeyGenChunk + 1] from launch_exclusive_scan
+    int64_t n;
+    uint32_t tiles_x;
+};
+// With `gen`, kin and vin are ignored and the first pass generates the keys;
+// it needs the onesweep passes (hipErrorInvalidValue otherwise).
+// value_bits > 0 promises every value is below 2^value_bits: without
+// keep_keys, the passes after the first one whose remaining key bits and
+// value fit 32 bits then move one packed word per key instead of two
+// (intermediate keys are not written; the result is the same).
 hipError_t launch_sort_passes(const uint32_t* kin, const uint32_t* vin, uint32_t* ka, uint32_t* va,
                               uint32_t* kb, uint32_t* vb, int64_t count, int passes, int shift0,
                               const SortWorkspace& ws, SortAlgo algo, hipStream_t stream, int end_bit = 0,
-                              bool keep_keys = true);
+                              bool keep_keys = true, const KeyGen* gen = nullptr, int value_bits = 0);
 
 hipError_t launch_fill_u32(uint32_t* p, int64_t count, uint32_t value, hipStream_t stream);
 

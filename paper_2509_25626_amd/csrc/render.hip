@@ -19,7 +19,7 @@ void release_frame_events(cds_frame* f) {
 void release_frame_buffers(cds_frame* f) {
     cds_ctx* c = f->ctx;
     DevBuf* bufs[] = {&f->mean2d, &f->conic, &f->rgb, &f->depth, &f->radius, &f->rect, &f->touched,
-                      &f->offsets, &f->clampf, &f->blocksums, &f->total, &f->order0, &f->order1,
+                      &f->offsets, &f->kowner, &f->clampf, &f->blocksums, &f->total, &f->order0, &f->order1,
                       &f->dkey0, &f->dkey1, &f->sort_d.hist, &f->sort_d.status, &f->sort_d.counters,
                       &f->sort_d.part_hist, &f->sort_d.bases, &f->sort_d.scan_sums, &f->sort_d.scan_total,
                       &f->vrect, &f->binM, &f->binE, &f->binP, &f->tsum, &f->tdiff, &f->thist,
@@ -66,6 +66,13 @@ int tile_bits_for(int64_t ntiles) {
  * Stage events: start, preprocess, key count read back, depth order, keys
  * generated, tile sort, ranges, blend (see cds_stage_times).
  */
+// Bits needed for the values 0 .. v (at least 1).
+static int bit_width(int64_t v) {
+    int b = 1;
+    while (b < 63 && (v >> b) > 0) ++b;
+    return b;
+}
+
 cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scene, const cds_camera* cam,
                                int blend_variant, int sort_variant, SortAlgo algo, float* out_rgb, float* out_T,
                                uint32_t* out_ncontrib, hipStream_t stream) {
@@ -209,13 +216,15 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
                 CDS_HIP(launch_sort_prepare(wd, nvis, 4, false, stream), "depth sort prepare");
             CDS_HIP(launch_sort_passes((const uint32_t*)f->dkeyc.p, nullptr, (uint32_t*)f->dkey0.p,
                                        (uint32_t*)f->order0.p, (uint32_t*)f->dkey1.p, (uint32_t*)f->order1.p, nvis,
-                                       4, 0, wd, algo, stream, 32, false),
+                                       4, 0, wd, algo, stream, 32, false, nullptr, bit_width(nvis - 1)),
                     "depth sort");
             CDS_HIP(launch_rec_gather(nvis, (const uint32_t*)f->order1.p, (const uint4*)f->recc.p, (uint4*)f->recv.p,
                                       stream),
                     "record gather");
+            CDS_TRY(ensure(ctx, f->kowner, sizeof(uint32_t) * (size_t)(K / kKeyGenChunk + 1), 1.25));
             CDS_HIP(launch_exclusive_scan(nullptr, nullptr, (uint32_t*)f->offsets.p, nvis,
-                                          (uint64_t*)f->blocksums.p, d_total + 2, stream, recv),
+                                          (uint64_t*)f->blocksums.p, d_total + 2, stream, recv,
+                                          (uint32_t*)f->kowner.p),
                     "offset scan");
         }
         if (compact)  // ranges and tile-digit histograms from the rectangles
@@ -237,15 +246,24 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
         CDS_TRY(ensure_sort_workspace(ctx, f->sort, (int64_t)K, passes > 0 ? passes : 1));
         SortWorkspace ws = sort_ws(ctx, f->sort);
         const bool onesweep = sort_uses_onesweep((int64_t)K, algo) && passes > 0;
+        // variant 2 with onesweep passes: the first tile pass generates the keys
+        const bool fused = compact && onesweep;
+        KeyGen gen;
+        gen.off = (const uint32_t*)f->offsets.p;
+        gen.rec = recv;
+        gen.owner = (const uint32_t*)f->kowner.p;
+        gen.n = nvis;
+        gen.tiles_x = (uint32_t)P.tiles_x;
         if (K > 0) {
             if (compact) {
                 // the onesweep passes take the tile-digit histograms made from the rectangles
                 if (onesweep) CDS_HIP(launch_sort_prepare(ws, (int64_t)K, passes, false, stream), "sort prepare");
                 ws.hist = (uint32_t*)f->thist.p;
-                CDS_HIP(launch_duplicate(nvis, nullptr, (const uint32_t*)f->offsets.p, nullptr, nullptr,
-                                         sb.depth_bits, P.tiles_x, nullptr, (uint32_t*)f->tk0.p,
-                                         (uint32_t*)f->vals0.p, stream, nullptr, 0, recv),
-                        "duplicate kernel");
+                if (!fused)
+                    CDS_HIP(launch_duplicate(nvis, nullptr, (const uint32_t*)f->offsets.p, nullptr, nullptr,
+                                             sb.depth_bits, P.tiles_x, nullptr, (uint32_t*)f->tk0.p,
+                                             (uint32_t*)f->vals0.p, stream, nullptr, 0, recv),
+                            "duplicate kernel");
             } else {
                 CDS_HIP(launch_duplicate(n, nullptr, (const uint32_t*)f->offsets.p, sb.touched, sb.rect,
                                          sb.depth_bits, P.tiles_x, (uint64_t*)f->keys0.p, nullptr,
@@ -268,7 +286,7 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
                 CDS_HIP(launch_sort_passes((const uint32_t*)f->tk0.p, (const uint32_t*)f->vals0.p,
                                            (uint32_t*)f->tk1.p, (uint32_t*)f->vals1.p, (uint32_t*)f->tk0.p,
                                            (uint32_t*)f->vals0.p, (int64_t)K, passes, 0, ws, algo, stream, tile_bits,
-                                           false),
+                                           false, fused ? &gen : nullptr, bit_width(n - 1)),
                         "tile sort");
             f->res_tiles = passes > 0 ? nullptr : (const uint32_t*)f->tk0.p;
             f->res_tile_stride = 1;

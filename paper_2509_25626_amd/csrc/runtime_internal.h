@@ -53,6 +53,7 @@ struct cds_frame {
     cds::DevBuf vrect, binM, binE, binP, tsum;  // tile binning (sort variant 3)
     cds::DevBuf tdiff, thist;                  // per-tile counts and tile-digit histograms (variant 2)
     cds::DevBuf dkeyc, recc, recv, vsums, ksums;  // compacted visible splats (variant 2)
+    cds::DevBuf kowner;                        // record owning every 1024th key (variant 2)
     cds::SortState sort_d;
     // per key
     cds::DevBuf keys0, keys1;                  // 64-bit keys (variant 1; others: rebuilt on request)

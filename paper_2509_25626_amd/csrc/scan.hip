@@ -80,7 +80,7 @@ __global__ __launch_bounds__(1024) void k_scan_sums(uint64_t* __restrict__ sums,
 }
 
 __global__ __launch_bounds__(kNT) void k_scan_down(ScanSrc src, int64_t n, const uint64_t* __restrict__ sums,
-                                                   uint32_t* __restrict__ out) {
+                                                   uint32_t* __restrict__ out, uint32_t* __restrict__ owner) {
     __shared__ uint32_t scratch[kNT / kWave];
     // blocked arrangement: thread t owns items [t*kIPT, (t+1)*kIPT) of the tile
     const int64_t base = (int64_t)blockIdx.x * kTileItems + (int64_t)threadIdx.x * kIPT;
@@ -94,7 +94,15 @@ __global__ __launch_bounds__(kNT) void k_scan_down(ScanSrc src, int64_t n, const
     uint32_t run = block_excl_sum<kNT>(s, scratch, nullptr) + (uint32_t)sums[blockIdx.x];
 #pragma unroll
     for (int k = 0; k < kIPT; ++k) {
-        if (base + k < n) out[base + k] = run;
+        if (base + k < n) {
+            out[base + k] = run;
+            if (owner && v[k] > 0u) {
+                // chunk starts inside [run, run + v[k])
+                const uint32_t last = (run + v[k] - 1u) / (uint32_t)kKeyGenChunk;
+                for (uint32_t q = (run + (uint32_t)kKeyGenChunk - 1u) / (uint32_t)kKeyGenChunk; q <= last; ++q)
+                    owner[q] = (uint32_t)(base + k);
+            }
+        }
         run += v[k];
     }
 }
@@ -109,7 +117,8 @@ hipError_t launch_scan_u64(uint64_t* values, int64_t count, uint64_t* total, hip
 }
 
 hipError_t launch_exclusive_scan(const uint32_t* in, const uint32_t* gather, uint32_t* out, int64_t n,
-                                 uint64_t* block_sums, uint64_t* total, hipStream_t stream, const uint4* rec) {
+                                 uint64_t* block_sums, uint64_t* total, hipStream_t stream, const uint4* rec,
+                                 uint32_t* owner) {
     const int64_t tiles = (n + kTileItems - 1) / kTileItems;
     ScanSrc src;
     src.in = in;
@@ -120,7 +129,7 @@ hipError_t launch_exclusive_scan(const uint32_t* in, const uint32_t* gather, uin
     }
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, stream, block_sums, tiles, total);
     if (tiles > 0) {
-        hipLaunchKernelGGL(k_scan_down, dim3((unsigned)tiles), dim3(kNT), 0, stream, src, n, block_sums, out);
+        hipLaunchKernelGGL(k_scan_down, dim3((unsigned)tiles), dim3(kNT), 0, stream, src, n, block_sums, out, owner);
     }
     return hipGetLastError();
 }

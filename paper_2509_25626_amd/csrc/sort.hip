@@ -137,11 +137,89 @@ struct PassArgs {
     const uint32_t* bases;  // reduce-then-scan: [256][partitions] exclusive bases
     int64_t parts;
     uint32_t* err;
+    KeyGen gen;  // generated first-pass keys (gen.off non-null): kin and vin unused
+    // Packed words (32-bit keys, values of at most vbits bits): once the key
+    // bits left for later passes and the value fit one word, a pass writes
+    // ((key >> pack_shift) << vbits) | value to vout (and no keys), and the
+    // passes after it read such words as their keys.
+    uint32_t vbits;         // nonzero: pack the output
+    uint32_t pack_shift;
+    uint32_t unpack_mask;   // nonzero: keys are packed words, value = key & unpack_mask
 };
+
+// Generated keys (duplication fused into the first tile pass).  Key p
+// belongs to the record j with off[j] <= p < off[j + 1]; its key is the
+// tile, in row-major order within the record's rectangle, of its rank
+// p - off[j] there, and its value the record's Gaussian index.  A wave
+// generates its 16 rounds of 64 consecutive keys in order, starting from
+// the owner of its first key (owner table of the offset scan).  Let jb own
+// the key just before the round (or its first key, in the first round):
+// the round's owners are jb and the at most 64 records after it that start
+// inside the round (every record has at least one key).  Lane l takes
+// candidate jb + 1 + l and marks its start position in a 64-slot array;
+// one ballot over the slots gives lane l the number of candidates starting
+// at or before it, which is its owner's distance from jb.  The offsets and
+// records are read through a per-wave LDS window, reloaded when a round's
+// candidates would leave it.
+constexpr int kGenWindow = 256;  // records per wave window
+
+template <int kRounds>
+__device__ __forceinline__ void generate_keys(const KeyGen& g, int64_t count, int64_t wbase, uint32_t* key,
+                                              uint32_t* val, uint32_t* s_off, uint4* s_rec, uint32_t* s_mark) {
+    const uint32_t l = lane_id();
+    s_mark[l] = 0u;
+    int64_t jb = wbase < count ? (int64_t)g.owner[wbase / kKeyGenChunk] : 0;
+    int64_t jw = -(int64_t)kGenWindow;  // window = records [jw, jw + kGenWindow)
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+        const int64_t R = wbase + r * kWave;
+        key[r] = 0u;
+        val[r] = 0u;
+        if (R >= count) continue;  // uniform: past the last key
+        if (jb < jw || jb + kWave + 1 > jw + kGenWindow) {  // candidates jb .. jb + 64
+            jw = jb;
+            wave_lds_sync();
+            for (int k = (int)l; k < kGenWindow; k += kWave) {
+                const int64_t j = jw + k;
+                if (j < g.n) {
+                    s_off[k] = g.off[j];
+                    s_rec[k] = g.rec[j];
+                }
+            }
+            wave_lds_sync();
+        }
+        const uint32_t stamp = (uint32_t)r + 1u;
+        const int64_t jc = jb + 1 + (int64_t)l;
+        if (jc < g.n) {
+            const int64_t sc = (int64_t)s_off[jc - jw] - R;  // >= 0
+            if (sc < kWave) s_mark[sc] = stamp;
+        }
+        wave_lds_sync();
+        const uint64_t starts = ballot(s_mark[l] == stamp);
+        wave_lds_sync();
+        const uint32_t m = count_below(starts) + (uint32_t)((starts >> l) & 1ull);
+        const int64_t p = R + l;
+        if (p < count) {
+            const int k = (int)(jb + m - jw);
+            const uint4 q = s_rec[k];
+            const uint32_t c = (uint32_t)(p - s_off[k]);
+            const uint32_t x0 = q.x & 0xFFFFu, y0 = q.x >> 16, x1 = q.y & 0xFFFFu;
+            const uint32_t w = x1 - x0 + 1;
+            // c / w via a float estimate and an exact integer fix-up
+            uint32_t qq = (uint32_t)((float)c * __frcp_rn((float)w));
+            int32_t rem = (int32_t)c - (int32_t)(qq * w);
+            while (rem < 0) { --qq; rem += (int32_t)w; }
+            while (rem >= (int32_t)w) { ++qq; rem -= (int32_t)w; }
+            key[r] = (y0 + qq) * g.tiles_x + x0 + (uint32_t)rem;
+            val[r] = q.z;
+        }
+        jb += __builtin_amdgcn_readlane(m, kWave - 1);
+    }
+}
 
 // One partition of one pass.  kFull: the partition has no tail (every key
 // valid), compiled separately so the common case carries no bounds checks.
-template <typename Key, bool kOnesweep, int kBits, bool kFull>
+template <typename Key, bool kOnesweep, int kBits, bool kFull, bool kGen>
 __device__ __forceinline__ void sort_pass_body(const PassArgs<Key>& a, uint32_t pid, Key* s_keys, uint32_t* s_vals,
                                                uint32_t (*s_whist)[256], uint32_t* s_gbase, uint32_t* s_scan) {
     constexpr uint32_t kMask = (1u << kBits) - 1u;
@@ -153,12 +231,28 @@ __device__ __forceinline__ void sort_pass_body(const PassArgs<Key>& a, uint32_t 
 
     Key key[kKPT];
     uint32_t val[kKPT];
+    if constexpr (kGen) {
+        static_assert(sizeof(Key) == 4, "generated keys are 32-bit tile ids");
+        static_assert(sizeof(Key) == 4, "generated keys are 32-bit tile ids");
+        static_assert(kWave * kKPT == kKeyGenChunk, "a wave generates one owner-table chunk");
+        // per-wave window in the reorder buffers, unused until after the ranking:
+        // records in the wave's quarter of s_keys, offsets and marks in s_vals'
+        static_assert(kGenWindow * sizeof(uint4) <= sizeof(Key) * kP / kWaves, "records fit");
+        static_assert((kGenWindow + kWave) * sizeof(uint32_t) <= sizeof(uint32_t) * kP / kWaves, "offsets fit");
+        uint4* s_rec = reinterpret_cast<uint4*>(s_keys + (size_t)w * (kP / kWaves));
+        uint32_t* s_off = s_vals + (size_t)w * (kP / kWaves);
+        generate_keys<kKPT>(a.gen, a.count, wbase, reinterpret_cast<uint32_t*>(key), val, s_off, s_rec,
+                            s_off + kGenWindow);
+    } else {
 #pragma unroll
     for (int r = 0; r < kKPT; ++r) {
         const int64_t idx = wbase + r * kWave + l;
         key[r] = (kFull || idx < a.count) ? a.kin[idx] : (Key)0;
     }
-    if (a.vin) {  // uniform: one clean load loop either way
+    if (a.unpack_mask) {  // uniform
+#pragma unroll
+        for (int r = 0; r < kKPT; ++r) val[r] = (uint32_t)key[r] & a.unpack_mask;
+    } else if (a.vin) {  // uniform: one clean load loop either way
 #pragma unroll
         for (int r = 0; r < kKPT; ++r) {
             const int64_t idx = wbase + r * kWave + l;
@@ -167,6 +261,7 @@ __device__ __forceinline__ void sort_pass_body(const PassArgs<Key>& a, uint32_t 
     } else {
 #pragma unroll
         for (int r = 0; r < kKPT; ++r) val[r] = (uint32_t)(wbase + r * kWave + l);
+    }
     }
 
     // Stable wave-level ranking.  Per round, the first lane of every digit
@@ -278,7 +373,8 @@ __device__ __forceinline__ void sort_pass_body(const PassArgs<Key>& a, uint32_t 
             // counts; record it instead of writing out of bounds
             if ((int64_t)g < a.count) {
                 if (a.kout) a.kout[g] = k;
-                a.vout[g] = s_vals[i];
+                const uint32_t v = s_vals[i];
+                a.vout[g] = a.vbits ? ((uint32_t)(k >> a.pack_shift) << a.vbits) | v : v;
             } else {
                 atomicOr(a.err, 2u);
             }
@@ -286,9 +382,9 @@ __device__ __forceinline__ void sort_pass_body(const PassArgs<Key>& a, uint32_t 
     }
 }
 
-template <typename Key, bool kOnesweep, int kBits>
+template <typename Key, bool kOnesweep, int kBits, bool kGen = false>
 __device__ __forceinline__ void sort_pass_kernel(const PassArgs<Key>& a) {
-    __shared__ Key s_keys[kP];                  // reorder buffer
+    __shared__ __align__(16) Key s_keys[kP];    // reorder buffer
     __shared__ uint32_t s_vals[kP];
     __shared__ uint32_t s_whist[kWaves][256];   // per-wave digit counters, then offsets
     __shared__ uint32_t s_gbase[256];
@@ -301,9 +397,9 @@ __device__ __forceinline__ void sort_pass_kernel(const PassArgs<Key>& a) {
     __syncthreads();
     const uint32_t pid = s_pid;
     if ((int64_t)(pid + 1) * kP <= a.count)
-        sort_pass_body<Key, kOnesweep, kBits, true>(a, pid, s_keys, s_vals, s_whist, s_gbase, s_scan);
+        sort_pass_body<Key, kOnesweep, kBits, true, kGen>(a, pid, s_keys, s_vals, s_whist, s_gbase, s_scan);
     else
-        sort_pass_body<Key, kOnesweep, kBits, false>(a, pid, s_keys, s_vals, s_whist, s_gbase, s_scan);
+        sort_pass_body<Key, kOnesweep, kBits, false, kGen>(a, pid, s_keys, s_vals, s_whist, s_gbase, s_scan);
 }
 
 // Onesweep passes: four workgroups per CU (VGPRs <= 128, 37 KB of LDS each),
@@ -311,6 +407,12 @@ __device__ __forceinline__ void sort_pass_kernel(const PassArgs<Key>& a) {
 template <typename Key, int kBits>
 __global__ __launch_bounds__(kNT, 4) void k_sort_pass_onesweep(PassArgs<Key> a) {
     sort_pass_kernel<Key, true, kBits>(a);
+}
+
+// The first tile pass with its keys generated from the splat records.
+template <int kBits>
+__global__ __launch_bounds__(kNT, 4) void k_sort_pass_gen(PassArgs<uint32_t> a) {
+    sort_pass_kernel<uint32_t, true, kBits, true>(a);
 }
 
 template <typename Key, int kBits>
@@ -324,6 +426,22 @@ void launch_pass_bits(const PassArgs<Key>& a, dim3 grid, hipStream_t stream) {
         hipLaunchKernelGGL((k_sort_pass_onesweep<Key, kBits>), grid, dim3(kNT), 0, stream, a);
     else
         hipLaunchKernelGGL((k_sort_pass_rts<Key, kBits>), grid, dim3(kNT), 0, stream, a);
+}
+
+hipError_t launch_gen_pass(const PassArgs<uint32_t>& a, int64_t parts, hipStream_t stream) {
+    const dim3 grid((unsigned)parts);
+    switch (a.bits) {
+        case 1: hipLaunchKernelGGL(k_sort_pass_gen<1>, grid, dim3(kNT), 0, stream, a); break;
+        case 2: hipLaunchKernelGGL(k_sort_pass_gen<2>, grid, dim3(kNT), 0, stream, a); break;
+        case 3: hipLaunchKernelGGL(k_sort_pass_gen<3>, grid, dim3(kNT), 0, stream, a); break;
+        case 4: hipLaunchKernelGGL(k_sort_pass_gen<4>, grid, dim3(kNT), 0, stream, a); break;
+        case 5: hipLaunchKernelGGL(k_sort_pass_gen<5>, grid, dim3(kNT), 0, stream, a); break;
+        case 6: hipLaunchKernelGGL(k_sort_pass_gen<6>, grid, dim3(kNT), 0, stream, a); break;
+        case 7: hipLaunchKernelGGL(k_sort_pass_gen<7>, grid, dim3(kNT), 0, stream, a); break;
+        case 8: hipLaunchKernelGGL(k_sort_pass_gen<8>, grid, dim3(kNT), 0, stream, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 template <typename Key, bool kOnesweep>
@@ -357,22 +475,46 @@ hipError_t sort_histogram_impl(const Key* keys, int64_t count, int passes, int s
 template <typename Key>
 hipError_t sort_passes_impl(const Key* kin, const uint32_t* vin, Key* ka, uint32_t* va, Key* kb,
                             uint32_t* vb, int64_t count, int passes, int shift0, int end_bit,
-                            const SortWorkspace& ws, SortAlgo algo, hipStream_t stream, bool keep_keys) {
+                            const SortWorkspace& ws, SortAlgo algo, hipStream_t stream, bool keep_keys,
+                            const KeyGen* gen, int value_bits) {
     if (count <= 0 || passes <= 0) return hipSuccess;
     if (count > kSortMaxCount) return hipErrorInvalidValue;
     const int64_t parts = sort_partitions(count);
     const bool onesweep = sort_uses_onesweep(count, algo);
     if (passes > 8) return hipErrorInvalidValue;
+    if (gen && (!onesweep || sizeof(Key) != 4 || !gen->off || !gen->rec || !gen->owner))
+        return hipErrorInvalidValue;
     const DigitPlan plan = digit_plan(passes, shift0, end_bit);
+    // first pass whose output can be packed (32-bit keys, keys not kept)
+    int pack_pass = passes;
+    if (sizeof(Key) == 4 && !keep_keys && value_bits > 0 && value_bits < 32)
+        for (int p = 0; p + 1 < passes; ++p)
+            if (end_bit - (plan.shift[p] + plan.bits[p]) + value_bits <= 32) {
+                pack_pass = p;
+                break;
+            }
+    const int packed_from = pack_pass < passes ? plan.shift[pack_pass] + plan.bits[pack_pass] : 0;
     for (int p = 0; p < passes; ++p) {
         PassArgs<Key> a;
-        a.kin = p == 0 ? kin : ((p & 1) ? ka : kb);
-        a.vin = p == 0 ? vin : ((p & 1) ? va : vb);
-        a.kout = (p & 1) ? kb : ka;
-        a.vout = (p & 1) ? vb : va;
-        if (p == passes - 1 && !keep_keys) a.kout = nullptr;
+        Key* kout = (p & 1) ? kb : ka;
+        uint32_t* vout = (p & 1) ? vb : va;
+        if (p == 0) {
+            a.kin = kin;
+            a.vin = vin;
+        } else if (p > pack_pass) {  // packed words, written to the value buffer
+            a.kin = reinterpret_cast<const Key*>((p & 1) ? va : vb);
+            a.vin = nullptr;
+        } else {
+            a.kin = (p & 1) ? ka : kb;
+            a.vin = (p & 1) ? va : vb;
+        }
+        a.kout = (p >= pack_pass || (p == passes - 1 && !keep_keys)) ? nullptr : kout;
+        a.vout = vout;
+        a.unpack_mask = p > pack_pass ? (uint32_t)((1ull << value_bits) - 1ull) : 0u;
+        a.shift = p > pack_pass ? plan.shift[p] - packed_from + value_bits : plan.shift[p];
+        a.vbits = (p >= pack_pass && p < passes - 1) ? (uint32_t)value_bits : 0u;
+        a.pack_shift = p == pack_pass ? (uint32_t)packed_from : (uint32_t)value_bits;
         a.count = count;
-        a.shift = plan.shift[p];
         a.bits = plan.bits[p];
         a.dmask = (1u << a.bits) - 1u;
         a.hist = ws.hist + (size_t)p * 256;
@@ -381,8 +523,14 @@ hipError_t sort_passes_impl(const Key* kin, const uint32_t* vin, Key* ka, uint32
         a.bases = ws.bases;
         a.parts = parts;
         a.err = ws.err;
+        a.gen = KeyGen{};
         hipError_t e;
-        if (onesweep) {
+        if (p == 0 && gen) {
+            if constexpr (sizeof(Key) == 4) {
+                a.gen = *gen;
+                if ((e = launch_gen_pass(a, parts, stream)) != hipSuccess) return e;
+            }
+        } else if (onesweep) {
             if ((e = launch_pass<Key, true>(a, parts, stream)) != hipSuccess) return e;
         } else {
             hipLaunchKernelGGL(k_rts_upsweep<Key>, dim3((unsigned)parts), dim3(kNT), 0, stream, a.kin, count,
@@ -439,15 +587,17 @@ hipError_t launch_sort_passes(const uint64_t* kin, const uint32_t* vin, uint64_t
                               const SortWorkspace& ws, SortAlgo algo, hipStream_t stream, int end_bit,
                               bool keep_keys) {
     return sort_passes_impl<uint64_t>(kin, vin, ka, va, kb, vb, count, passes, shift0,
-                                      end_bit > 0 ? end_bit : shift0 + 8 * passes, ws, algo, stream, keep_keys);
+                                      end_bit > 0 ? end_bit : shift0 + 8 * passes, ws, algo, stream, keep_keys,
+                                      nullptr, 0);
 }
 
 hipError_t launch_sort_passes(const uint32_t* kin, const uint32_t* vin, uint32_t* ka, uint32_t* va,
                               uint32_t* kb, uint32_t* vb, int64_t count, int passes, int shift0,
                               const SortWorkspace& ws, SortAlgo algo, hipStream_t stream, int end_bit,
-                              bool keep_keys) {
+                              bool keep_keys, const KeyGen* gen, int value_bits) {
     return sort_passes_impl<uint32_t>(kin, vin, ka, va, kb, vb, count, passes, shift0,
-                                      end_bit > 0 ? end_bit : shift0 + 8 * passes, ws, algo, stream, keep_keys);
+                                      end_bit > 0 ? end_bit : shift0 + 8 * passes, ws, algo, stream, keep_keys,
+                                      gen, value_bits);
 }
 
 }  // namespace cds
