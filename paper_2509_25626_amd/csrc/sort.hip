@@ -40,7 +40,7 @@ constexpr uint32_t kFlagAgg = 1u << 30;
 constexpr uint32_t kFlagIncl = 2u << 30;
 constexpr uint32_t kValueMask = (1u << 30) - 1;
 constexpr uint32_t kSpinLimit = 1u << 22;
-constexpr int kLookBack = 8;  // predecessors read per look-back step
+constexpr int kLookBack = 16;  // status words a thread reads per look-back poll
 
 __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, int64_t count,
                                                   uint32_t value) {
@@ -221,7 +221,8 @@ __device__ __forceinline__ void generate_keys(const KeyGen& g, int64_t count, in
 // valid), compiled separately so the common case carries no bounds checks.
 template <typename Key, bool kOnesweep, int kBits, bool kFull, bool kGen>
 __device__ __forceinline__ void sort_pass_body(const PassArgs<Key>& a, uint32_t pid, Key* s_keys, uint32_t* s_vals,
-                                               uint32_t (*s_whist)[256], uint32_t* s_gbase, uint32_t* s_scan) {
+                                               uint32_t (*s_whist)[256], uint32_t* s_gbase, uint32_t* s_scan,
+                                               uint32_t digit_info) {
     constexpr uint32_t kMask = (1u << kBits) - 1u;
     const int t = threadIdx.x;
     const int w = t / kWave;
@@ -291,60 +292,15 @@ __device__ __forceinline__ void sort_pass_body(const PassArgs<Key>& a, uint32_t 
     const uint32_t c0 = s_whist[0][t], c1 = s_whist[1][t], c2 = s_whist[2][t], c3 = s_whist[3][t];
     static_assert(kWaves == 4, "digit bookkeeping assumes 4 waves");
     const uint32_t tot = c0 + c1 + c2 + c3;
-    uint32_t gb;  // global position of this partition's first key with digit t
-    if constexpr (kOnesweep) {
-        uint32_t* st = a.status + (size_t)pid * 256;
-        atomic_store_agent(st + t, (pid == 0 ? kFlagIncl : kFlagAgg) | tot);
-        const uint32_t gstart = block_excl_sum<kNT>(a.hist[t], s_scan, nullptr);
-        // Look-back: read a window of predecessors' status words at once (they
-        // are device-coherent loads, a memory round trip each), consume them
-        // nearest first, stop at an inclusive prefix, re-poll from the first
-        // one not ready.
-        uint32_t excl = 0;
-        if (pid > 0) {
-            int64_t p = (int64_t)pid - 1;
-            uint32_t spins = 0;
-            while (p >= 0) {
-                uint32_t sw[kLookBack];
-#pragma unroll
-                for (int k = 0; k < kLookBack; ++k)
-                    sw[k] = (p - k >= 0) ? atomic_load_agent(a.status + (size_t)(p - k) * 256 + t) : kFlagIncl;
-                int consumed = 0;
-                bool found = false, stalled = false;
-#pragma unroll
-                for (int k = 0; k < kLookBack; ++k) {
-                    if (found || stalled) continue;
-                    const uint32_t f = sw[k] & ~kValueMask;
-                    if (f == 0u) {
-                        stalled = true;
-                        continue;
-                    }
-                    excl += sw[k] & kValueMask;
-                    ++consumed;
-                    if (f == kFlagIncl) found = true;
-                }
-                if (found) break;
-                p -= consumed;
-                if (stalled) {
-                    if (++spins > kSpinLimit) {
-                        atomicOr(a.err, 1u);
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
-                }
-            }
-            atomic_store_agent(st + t, kFlagIncl | ((excl + tot) & kValueMask));
-        }
-        gb = gstart + excl;
-    } else {
-        gb = a.bases[(int64_t)t * a.parts + pid];
-    }
+    constexpr uint32_t kDig = 1u << kBits;  // digits of this pass
+    uint32_t* st = a.status + (size_t)pid * 256;
+    if constexpr (kOnesweep)  // publish this partition's counts first
+        if (t < (int)kDig) atomic_store_agent(st + t, (pid == 0 ? kFlagIncl : kFlagAgg) | tot);
     const uint32_t bstart = block_excl_sum<kNT>(tot, s_scan, nullptr);
     s_whist[0][t] = bstart;
     s_whist[1][t] = bstart + c0;
     s_whist[2][t] = bstart + c0 + c1;
     s_whist[3][t] = bstart + c0 + c1 + c2;
-    s_gbase[t] = gb - bstart;
     __syncthreads();
 
     // reorder (key, value) pairs by digit in LDS; a slot can only fall outside
@@ -359,6 +315,129 @@ __device__ __forceinline__ void sort_pass_body(const PassArgs<Key>& a, uint32_t 
             s_vals[pos] = val[r];
         }
     }
+    __syncthreads();  // s_whist is free from here on
+
+    uint32_t gb;  // global position of this partition's first key with digit t
+    if constexpr (kOnesweep) {
+        constexpr int kSeg = 256 >> kBits;  // threads per digit in the look-back
+        const uint32_t gstart = block_excl_sum<kNT>(digit_info, s_scan, nullptr);
+        // Look-back.  With 8-bit digits every thread polls for its own digit.
+        // With smaller ones it is block-cooperative: every poll, thread t reads kLookBack
+        // status words of digit t % kDig, segment t / kDig of the window of
+        // kSeg * kLookBack predecessors (device-coherent loads, one memory round
+        // trip for the whole window).  Each thread sums its words nearest first
+        // up to an inclusive prefix or the first one not ready; the digit's
+        // owner then combines its segments in order, and the digit is done at
+        // an inclusive prefix, else the next poll starts after what was consumed.
+        // The inclusive prefix thus moves kSeg * kLookBack partitions per round
+        // trip, which with small digits keeps it ahead of the partitions.
+        uint32_t excl = 0;
+        if (kSeg == 1 && pid > 0) {
+            // one thread per digit: each polls on its own, without barriers
+            if (t < (int)kDig) {
+                int64_t p = (int64_t)pid - 1;
+                uint32_t polls = 0;
+                while (p >= 0) {
+                    uint32_t sw[kLookBack];
+#pragma unroll
+                    for (int k = 0; k < kLookBack; ++k)
+                        sw[k] = (p - k >= 0) ? atomic_load_agent(a.status + (size_t)(p - k) * 256 + t) : kFlagIncl;
+                    uint32_t state = 0;
+                    int consumed = 0;
+#pragma unroll
+                    for (int k = 0; k < kLookBack; ++k) {
+                        if (state) continue;
+                        const uint32_t f = sw[k] & ~kValueMask;
+                        if (f == 0u) {
+                            state = 2;
+                            continue;
+                        }
+                        excl += sw[k] & kValueMask;
+                        ++consumed;
+                        if (f == kFlagIncl) state = 1;
+                    }
+                    if (state == 1) break;
+                    p -= consumed;
+                    if (state == 2) {
+                        if (++polls > kSpinLimit) {
+                            atomicOr(a.err, 1u);
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                    }
+                }
+                atomic_store_agent(st + t, kFlagIncl | ((excl + tot) & kValueMask));
+            }
+        } else if (pid > 0) {
+            uint32_t* s_sum = &s_whist[0][0];  // [256] per-thread sums
+            uint32_t* s_cnt = s_sum + 256;      // [256] state << 16 | words consumed
+            uint32_t* s_dist = s_sum + 512;     // [kDig] next distance, 0 = done
+            uint32_t* s_acc = s_sum + 768;      // [kDig] sum so far
+            const uint32_t d = (uint32_t)t & (kDig - 1u);
+            const uint32_t seg = (uint32_t)t >> kBits;
+            if (t < (int)kDig) {
+                s_dist[t] = 1u;
+                s_acc[t] = 0u;
+            }
+            __syncthreads();
+            uint32_t polls = 0;
+            for (;;) {
+                const uint32_t dist0 = s_dist[d];
+                uint32_t sum = 0, state = 0, cnt = 0;  // state: 1 inclusive found, 2 not ready
+                if (dist0) {
+                    const int64_t q0 = (int64_t)pid - dist0 - (int64_t)seg * kLookBack;
+                    uint32_t sw[kLookBack];
+#pragma unroll
+                    for (int k = 0; k < kLookBack; ++k)
+                        sw[k] = (q0 - k >= 0) ? atomic_load_agent(a.status + (size_t)(q0 - k) * 256 + d) : kFlagIncl;
+#pragma unroll
+                    for (int k = 0; k < kLookBack; ++k) {
+                        if (state) continue;
+                        const uint32_t f = sw[k] & ~kValueMask;
+                        if (f == 0u) {
+                            state = 2;
+                            continue;
+                        }
+                        sum += sw[k] & kValueMask;
+                        ++cnt;
+                        if (f == kFlagIncl) state = 1;
+                    }
+                }
+                s_sum[t] = sum;
+                s_cnt[t] = (state << 16) | cnt;
+                __syncthreads();
+                int pending = 0;
+                if (t < (int)kDig && s_dist[t] != 0u) {
+                    uint32_t acc = s_acc[t], dist = s_dist[t], stop = 0;
+#pragma unroll
+                    for (int sg = 0; sg < kSeg; ++sg) {
+                        if (stop) continue;
+                        const uint32_t sc = s_cnt[t + sg * (int)kDig];
+                        acc += s_sum[t + sg * (int)kDig];
+                        dist += sc & 0xFFFFu;
+                        stop = sc >> 16;
+                    }
+                    s_acc[t] = acc;
+                    s_dist[t] = stop == 1u ? 0u : dist;
+                    pending = stop != 1u;
+                }
+                if (__syncthreads_count(pending) == 0) break;
+                if (++polls > kSpinLimit) {  // uniform
+                    if (t == 0) atomicOr(a.err, 1u);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            if (t < (int)kDig) {
+                excl = s_acc[t];
+                atomic_store_agent(st + t, kFlagIncl | ((excl + tot) & kValueMask));
+            }
+        }
+        gb = gstart + excl;
+    } else {
+        gb = digit_info;
+    }
+    s_gbase[t] = gb - bstart;
     __syncthreads();
     // each digit run goes out as a contiguous stretch
     const uint32_t nvalid = kFull ? (uint32_t)kP : (uint32_t)(a.count - base);
@@ -393,13 +472,19 @@ __device__ __forceinline__ void sort_pass_kernel(const PassArgs<Key>& a) {
 
     const int t = threadIdx.x;
     if (t == 0) s_pid = kOnesweep ? atomicAdd(a.counter, 1u) : blockIdx.x;
+    const uint32_t hist_t = kOnesweep ? a.hist[t] : 0u;
     for (int k = t; k < kWaves * 256; k += kNT) (&s_whist[0][0])[k] = 0;
     __syncthreads();
     const uint32_t pid = s_pid;
+    // digit t's count over all keys (onesweep) or this partition's base for it
+    // (reduce-then-scan), loaded before the ranking so its latency overlaps
+    const uint32_t digit_info = kOnesweep ? hist_t : a.bases[(int64_t)t * a.parts + pid];
     if ((int64_t)(pid + 1) * kP <= a.count)
-        sort_pass_body<Key, kOnesweep, kBits, true, kGen>(a, pid, s_keys, s_vals, s_whist, s_gbase, s_scan);
+        sort_pass_body<Key, kOnesweep, kBits, true, kGen>(a, pid, s_keys, s_vals, s_whist, s_gbase, s_scan,
+                                                          digit_info);
     else
-        sort_pass_body<Key, kOnesweep, kBits, false, kGen>(a, pid, s_keys, s_vals, s_whist, s_gbase, s_scan);
+        sort_pass_body<Key, kOnesweep, kBits, false, kGen>(a, pid, s_keys, s_vals, s_whist, s_gbase, s_scan,
+                                                           digit_info);
 }
 
 // Onesweep passes: four workgroups per CU (VGPRs <= 128, 37 KB of LDS each),
