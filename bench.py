@@ -46,7 +46,7 @@ def parse():
     return ap.parse_args()
 
 
-def roofline(stages, scene, K, passes, info):
+def roofline(stages, scene, K, passes, info, first_pass_ms, variant, algo):
     """Roofline position of the dominant forward stage: algorithmic bytes per
     launch of its main kernel over that kernel's average launch duration, from
     the HIP events the library records on the render stream."""
@@ -57,6 +57,11 @@ def roofline(stages, scene, K, passes, info):
     tile_passes = max(int(passes) - 4, 1)
     tile_bits = max(1, (tiles - 1).bit_length())
     tile_digit_bits = -(-tile_bits // tile_passes)  # widest digit of the balanced split
+    # between tile passes a key travels as one packed word (remaining tile bits
+    # and Gaussian index) when they fit 32 bits
+    value_bits = max(1, (n - 1).bit_length())
+    packed = tile_passes > 1 and (tile_bits - tile_digit_bits) + value_bits <= 32
+    word = 4 if packed else 8
     table = {
         # kernel, launches per frame, algorithmic bytes per launch
         # preprocess: 40 B of geometry + SH in, 61 B of splat state out per Gaussian
@@ -67,19 +72,27 @@ def roofline(stages, scene, K, passes, info):
         "depth_order_ms": ("k_sort_pass_onesweep<u32,8> (depth digits)", 4, 16 * nvis),
         # duplicate: 8 B per key (tile id, value) + 24 B per Gaussian read
         "duplicate_ms": ("k_duplicate", 1, 8 * K + 24 * n),
-        # tile sort: read and write (u32 tile id, u32 value), 16 B per key per pass; the
-        # last pass writes only the values (12 B per key); averaged over the launches
-        "sort_ms": (f"k_sort_pass_onesweep<u32,{tile_digit_bits}> (tile digits)", tile_passes,
-                    (16 * (tile_passes - 1) + 12) * K // tile_passes),
+        # tile sort, its first pass: keys generated from the splat records in
+        # depth order (4 B offset + 16 B record per visible splat, 4 B owner per
+        # 1024 keys read) and written once as packed words (else tile id + value)
+        "sort_ms": (f"k_sort_pass_gen<{tile_digit_bits}>", 1, 20 * nvis + 4 * (K // 1024 + 1) + word * K),
+    }
+    if variant == 1:  # first pass over (u64 key, u32 value) pairs written by k_duplicate
+        table["sort_ms"] = (f"k_sort_pass_onesweep<u64,{tile_digit_bits}> (first pass)", 1, 24 * K)
+    elif algo == "reduce_scan":  # first pass over (u32 tile, u32 value) pairs written by k_duplicate
+        table["sort_ms"] = (f"k_sort_pass_rts<u32,{tile_digit_bits}> (first pass)", 1, (8 + word) * K)
+    table.update({
         # ranges from sorted keys (sort variant 1): read 4 B per key, write 8 B per tile
         "ranges_ms": ("k_ranges4", 1, 4 * K + 8 * tiles),
-    }
+    })
     dom = max(stages, key=stages.get)
     if dom not in table:
         return {"kernel": dom.replace("_ms", ""), "bound": "alu", "achieved": None, "peak": None,
                 "unit": None, "frac": None, "traffic": None, "stage_ms": round(stages[dom], 4)}
     kernel, launches, nbytes = table[dom]
     per_launch_ms = stages[dom] / launches
+    if dom == "sort_ms":  # the first pass alone, from its own event
+        per_launch_ms = first_pass_ms
     achieved = nbytes / (per_launch_ms * 1e-3) / 1e9
     return {"kernel": kernel, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kernel),
@@ -176,7 +189,9 @@ def main():
             stage_acc[k] = stage_acc.get(k, 0.0) + v
     torch.cuda.synchronize()
     t_fwd = (time.perf_counter() - t0) / args.steps
-    stages = {k: v / args.steps for k, v in stage_acc.items() if not k.endswith("backward_ms")}
+    stages = {k: v / args.steps for k, v in stage_acc.items()
+              if not k.endswith("backward_ms") and k != "sort_first_pass_ms"}
+    first_pass_ms = stage_acc.get("sort_first_pass_ms", 0.0) / args.steps
     info = frame.info()
     K, passes = int(info.num_keys), int(info.sort_passes)
 
@@ -209,7 +224,7 @@ def main():
         result_extra["backward_stage_ms"] = {k: round(v / args.steps, 4) for k, v in bw_acc.items()
                                              if k.endswith("backward_ms")}
 
-    roof = roofline(stages, scene, K, passes, info)
+    roof = roofline(stages, scene, K, passes, info, first_pass_ms, args.sort_variant, args.sort_algo)
 
     serving = None
     if not args.no_serving:

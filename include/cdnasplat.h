@@ -229,14 +229,19 @@ cds_status cds_frame_get_info(cds_frame* frame, cds_frame_info* out);
  *                   tile counts of binning (variant 3)
  *   depth_order_ms  variant 2: depth sort of the visible splats, their key
  *                   offsets, the per-tile counts and ranges; 0 otherwise
- *   duplicate_ms    key generation (variant 3: the fused placement)
- *   sort_ms         the per-key radix passes (0 for variant 3)
+ *   duplicate_ms    key generation as its own kernel (variant 1, variant 2
+ *                   with reduce-then-scan passes; variant 3: the fused
+ *                   placement); about 0 when the first pass generates them
+ *   sort_ms         the per-key radix passes (0 for variant 3); with variant 2
+ *                   and onesweep passes the first of them generates the keys
+ *   sort_first_pass_ms  the part of sort_ms taken by the first pass
  *   ranges_ms       ranges from the sorted keys (variant 1 only)
  *   blend_ms        the per-pixel blend
  * Backward fields are 0 until a backward pass has run. */
 typedef struct cds_stage_times {
     float preprocess_ms, scan_ms, depth_order_ms, duplicate_ms, sort_ms, ranges_ms, blend_ms;
     float blend_backward_ms, preprocess_backward_ms;
+    float sort_first_pass_ms;
 } cds_stage_times;
 
 cds_status cds_frame_stage_times(cds_frame* frame, cds_stage_times* out);

@@ -185,10 +185,11 @@ hipError_t launch_sort_prepare(const SortWorkspace& ws, int64_t count, int passe
 // The sort covers key bits [shift0, end_bit) (end_bit 0: shift0 + 8 * passes)
 // split over the passes by digit_plan.  keep_keys false: the last pass
 // writes only the values (its keys are left unwritten).
+// `first_done`, when given, is recorded on `stream` after the first pass.
 hipError_t launch_sort_passes(const uint64_t* kin, const uint32_t* vin, uint64_t* ka, uint32_t* va,
                               uint64_t* kb, uint32_t* vb, int64_t count, int passes, int shift0,
                               const SortWorkspace& ws, SortAlgo algo, hipStream_t stream, int end_bit = 0,
-                              bool keep_keys = true);
+                              bool keep_keys = true, hipEvent_t first_done = nullptr);
 // Keys of the tile sort generated inside its first pass instead of read:
 // key p is the tile of the record owning it (row-major order within the
 // record's rectangle), its value the record's Gaussian index, which is what
@@ -209,7 +210,8 @@ struct KeyGen {
 hipError_t launch_sort_passes(const uint32_t* kin, const uint32_t* vin, uint32_t* ka, uint32_t* va,
                               uint32_t* kb, uint32_t* vb, int64_t count, int passes, int shift0,
                               const SortWorkspace& ws, SortAlgo algo, hipStream_t stream, int end_bit = 0,
-                              bool keep_keys = true, const KeyGen* gen = nullptr, int value_bits = 0);
+                              bool keep_keys = true, const KeyGen* gen = nullptr, int value_bits = 0,
+                              hipEvent_t first_done = nullptr);
 
 hipError_t launch_fill_u32(uint32_t* p, int64_t count, uint32_t value, hipStream_t stream);
 

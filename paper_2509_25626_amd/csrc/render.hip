@@ -200,6 +200,7 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
                                  (const uint32_t*)f->binE.p, K, (uint32_t*)f->vals0.p, ctx->d_err, stream),
                 "bin place");
         CDS_TRY(f->record(kEvKeys, stream));
+        CDS_TRY(f->record(kEvSortFirst, stream));
         CDS_TRY(f->record(kEvSort, stream));
         CDS_TRY(f->record(kEvRanges, stream));
         f->res_values = (const uint32_t*)f->vals0.p;
@@ -286,7 +287,8 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
                 CDS_HIP(launch_sort_passes((const uint32_t*)f->tk0.p, (const uint32_t*)f->vals0.p,
                                            (uint32_t*)f->tk1.p, (uint32_t*)f->vals1.p, (uint32_t*)f->tk0.p,
                                            (uint32_t*)f->vals0.p, (int64_t)K, passes, 0, ws, algo, stream, tile_bits,
-                                           false, fused ? &gen : nullptr, bit_width(n - 1)),
+                                           false, fused ? &gen : nullptr, bit_width(n - 1),
+                                           f->event(kEvSortFirst)),
                         "tile sort");
             f->res_tiles = passes > 0 ? nullptr : (const uint32_t*)f->tk0.p;
             f->res_tile_stride = 1;
@@ -296,13 +298,14 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
                 CDS_HIP(launch_sort_passes((const uint64_t*)f->keys0.p, (const uint32_t*)f->vals0.p,
                                            (uint64_t*)f->keys1.p, (uint32_t*)f->vals1.p, (uint64_t*)f->keys0.p,
                                            (uint32_t*)f->vals0.p, (int64_t)K, passes, 0, ws, algo, stream,
-                                           32 + tile_bits),
+                                           32 + tile_bits, true, f->event(kEvSortFirst)),
                         "key sort");
             f->res_keys = (const uint64_t*)(odd ? f->keys1.p : f->keys0.p);
             f->res_tiles = reinterpret_cast<const uint32_t*>(f->res_keys) + 1;  // high words
             f->res_tile_stride = 2;
         }
         f->res_values = (const uint32_t*)(odd ? f->vals1.p : f->vals0.p);
+        if (K == 0 || passes == 0) CDS_TRY(f->record(kEvSortFirst, stream));  // no pass ran
         CDS_TRY(f->record(kEvSort, stream));
         f->passes = compact ? 4 + tile_passes : passes;
         if (!compact)  // variant 2 has its ranges from the tile counts
@@ -398,6 +401,12 @@ void cds_frame::release_all() {
     cds::release_frame_events(this);
 }
 
+hipEvent_t cds_frame::event(int i) {
+    if (!timing) return nullptr;
+    if (!ev[i] && hipEventCreate(&ev[i]) != hipSuccess) return nullptr;
+    return ev[i];
+}
+
 cds_status cds_frame::record(int i, hipStream_t s) {
     if (!timing) return CDS_OK;
     hipError_t e;
@@ -421,6 +430,7 @@ extern "C" cds_status cds_frame_stage_times(cds_frame* f, cds_stage_times* out) 
         (e = span(kEvCount, kEvDepth, &out->depth_order_ms)) != hipSuccess ||
         (e = span(kEvDepth, kEvKeys, &out->duplicate_ms)) != hipSuccess ||
         (e = span(kEvKeys, kEvSort, &out->sort_ms)) != hipSuccess ||
+        (e = span(kEvKeys, kEvSortFirst, &out->sort_first_pass_ms)) != hipSuccess ||
         (e = span(kEvSort, kEvRanges, &out->ranges_ms)) != hipSuccess ||
         (e = span(kEvRanges, kEvBlend, &out->blend_ms)) != hipSuccess)
         return cds::hip_fail(e, "hipEventElapsedTime");

@@ -23,6 +23,7 @@ enum StageEvent {
     kEvCount,       // key count read back (compaction / scans)
     kEvDepth,       // depth order, key offsets and tile counts ready
     kEvKeys,        // keys generated
+    kEvSortFirst,   // first radix pass over the keys done
     kEvSort,        // tile sort done
     kEvRanges,      // ranges done
     kEvBlend,       // blend done
@@ -76,6 +77,7 @@ struct cds_frame {
     bool timing = false, timed_backward = false;
     hipEvent_t ev[cds::kEvCount_] = {};
     cds_status record(int i, hipStream_t s);
+    hipEvent_t event(int i);  // the stage event, created on demand; null without timing
     void release_all();
 };
 

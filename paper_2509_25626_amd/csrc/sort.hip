@@ -151,32 +151,104 @@ struct PassArgs {
 // belongs to the record j with off[j] <= p < off[j + 1]; its key is the
 // tile, in row-major order within the record's rectangle, of its rank
 // p - off[j] there, and its value the record's Gaussian index.  A wave
-// generates its 16 rounds of 64 consecutive keys in order, starting from
-// the owner of its first key (owner table of the offset scan).  Let jb own
-// the key just before the round (or its first key, in the first round):
-// the round's owners are jb and the at most 64 records after it that start
-// inside the round (every record has at least one key).  Lane l takes
-// candidate jb + 1 + l and marks its start position in a 64-slot array;
-// one ballot over the slots gives lane l the number of candidates starting
-// at or before it, which is its owner's distance from jb.  The offsets and
-// records are read through a per-wave LDS window, reloaded when a round's
-// candidates would leave it.
+// generates its 16 rounds of 64 consecutive keys from the owner jb of its
+// first key (owner table of the offset scan) and a window of the records
+// from jb on (offsets and records in LDS).
+//  - When the window holds every record starting among the wave's keys (the
+//    usual case), each record after jb marks its start in a byte per key,
+//    stored transposed (key 64 r + l at byte 16 l + r) so that a lane reads
+//    the marks of its 16 rounds with one 16-byte load; the round's ballot
+//    then gives every lane the number of records starting at or before it,
+//    and the owner of its key is jb plus the marks before the round plus
+//    that number.
+//  - Otherwise the rounds run one after another: with jb the owner of the
+//    key before the round, the at most 64 records after it that start
+//    inside the round mark their start in a 64-slot array, one ballot gives
+//    the owners, and the window moves when a round's candidates leave it.
 constexpr int kGenWindow = 256;  // records per wave window
+
+// key of rank c in the record's rectangle; `q` = (x0 | y0 << 16, x1 | y1 << 16, ...)
+__device__ __forceinline__ uint32_t rect_key(uint4 q, uint32_t c, uint32_t tiles_x) {
+    const uint32_t x0 = q.x & 0xFFFFu, y0 = q.x >> 16, x1 = q.y & 0xFFFFu;
+    const uint32_t w = x1 - x0 + 1;
+    // c / w via a float estimate and an exact integer fix-up
+    uint32_t qq = (uint32_t)((float)c * __frcp_rn((float)w));
+    int32_t rem = (int32_t)c - (int32_t)(qq * w);
+    while (rem < 0) { --qq; rem += (int32_t)w; }
+    while (rem >= (int32_t)w) { ++qq; rem -= (int32_t)w; }
+    return (y0 + qq) * tiles_x + x0 + (uint32_t)rem;
+}
 
 template <int kRounds>
 __device__ __forceinline__ void generate_keys(const KeyGen& g, int64_t count, int64_t wbase, uint32_t* key,
-                                              uint32_t* val, uint32_t* s_off, uint4* s_rec, uint32_t* s_mark) {
+                                              uint32_t* val, uint32_t* s_off, uint4* s_rec, uint32_t* s_mark,
+                                              uint4* s_flag) {
+    static_assert(kRounds == 16, "one 16-byte mark load per lane");
     const uint32_t l = lane_id();
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+        key[r] = 0u;
+        val[r] = 0u;
+    }
+    if (wbase >= count) return;  // uniform: past the last key
+    int64_t jb = (int64_t)g.owner[wbase / kKeyGenChunk];
+    int64_t jw = jb;  // window = records [jw, jw + kGenWindow)
+    for (int k = (int)l; k < kGenWindow; k += kWave) {
+        const int64_t j = jw + k;
+        if (j < g.n) {
+            s_off[k] = g.off[j];
+            s_rec[k] = g.rec[j];
+        }
+    }
+    s_flag[l] = make_uint4(0u, 0u, 0u, 0u);
+    wave_lds_sync();
+    const int64_t wend = wbase + kWave * kRounds;
+    const bool covered = jw + kGenWindow >= g.n || (int64_t)s_off[kGenWindow - 1] >= wend;  // uniform
+    if (covered) {
+        uint8_t* flag = reinterpret_cast<uint8_t*>(s_flag);
+        for (int k = 1 + (int)l; k < kGenWindow; k += kWave) {
+            const int64_t j = jw + k;
+            if (j < g.n) {
+                const int64_t sp = (int64_t)s_off[k] - wbase;  // >= 1: j starts after the owner of wbase
+                if (sp < wend - wbase) flag[(sp & (kWave - 1)) * 16 + (sp >> 6)] = 1u;
+            }
+        }
+        wave_lds_sync();
+        const uint4 mk = s_flag[l];
+        const uint32_t mw[4] = {mk.x, mk.y, mk.z, mk.w};
+        const uint64_t le_mask = (2ull << l) - 1ull;  // lanes 0..l
+        int64_t jr = jb;                                // owner of the key before the round
+        constexpr int kGroup = 4;                       // rounds whose owner data are read together
+#pragma unroll
+        for (int g0 = 0; g0 < kRounds; g0 += kGroup) {
+            uint4 q[kGroup];
+            uint32_t c[kGroup];
+#pragma unroll
+            for (int i = 0; i < kGroup; ++i) {
+                const int r = g0 + i;
+                const uint64_t b = ballot(((mw[r >> 2] >> (8 * (r & 3))) & 0xFFu) != 0u);
+                const int k = (int)(jr - jw) + __popcll(b & le_mask);
+                q[i] = s_rec[k];
+                c[i] = (uint32_t)(wbase + r * kWave + l - s_off[k]);
+                jr += __popcll(b);
+            }
+#pragma unroll
+            for (int i = 0; i < kGroup; ++i) {
+                if (wbase + (g0 + i) * kWave + l < count) {
+                    key[g0 + i] = rect_key(q[i], c[i], g.tiles_x);
+                    val[g0 + i] = q[i].z;
+                }
+            }
+        }
+        return;
+    }
     s_mark[l] = 0u;
-    int64_t jb = wbase < count ? (int64_t)g.owner[wbase / kKeyGenChunk] : 0;
-    int64_t jw = -(int64_t)kGenWindow;  // window = records [jw, jw + kGenWindow)
+    wave_lds_sync();
 #pragma unroll
     for (int r = 0; r < kRounds; ++r) {
         const int64_t R = wbase + r * kWave;
-        key[r] = 0u;
-        val[r] = 0u;
         if (R >= count) continue;  // uniform: past the last key
-        if (jb < jw || jb + kWave + 1 > jw + kGenWindow) {  // candidates jb .. jb + 64
+        if (jb + kWave + 1 > jw + kGenWindow) {  // candidates jb .. jb + 64
             jw = jb;
             wave_lds_sync();
             for (int k = (int)l; k < kGenWindow; k += kWave) {
@@ -202,15 +274,7 @@ __device__ __forceinline__ void generate_keys(const KeyGen& g, int64_t count, in
         if (p < count) {
             const int k = (int)(jb + m - jw);
             const uint4 q = s_rec[k];
-            const uint32_t c = (uint32_t)(p - s_off[k]);
-            const uint32_t x0 = q.x & 0xFFFFu, y0 = q.x >> 16, x1 = q.y & 0xFFFFu;
-            const uint32_t w = x1 - x0 + 1;
-            // c / w via a float estimate and an exact integer fix-up
-            uint32_t qq = (uint32_t)((float)c * __frcp_rn((float)w));
-            int32_t rem = (int32_t)c - (int32_t)(qq * w);
-            while (rem < 0) { --qq; rem += (int32_t)w; }
-            while (rem >= (int32_t)w) { ++qq; rem -= (int32_t)w; }
-            key[r] = (y0 + qq) * g.tiles_x + x0 + (uint32_t)rem;
+            key[r] = rect_key(q, (uint32_t)(p - s_off[k]), g.tiles_x);
             val[r] = q.z;
         }
         jb += __builtin_amdgcn_readlane(m, kWave - 1);
@@ -239,11 +303,12 @@ __device__ __forceinline__ void sort_pass_body(const PassArgs<Key>& a, uint32_t 
         // per-wave window in the reorder buffers, unused until after the ranking:
         // records in the wave's quarter of s_keys, offsets and marks in s_vals'
         static_assert(kGenWindow * sizeof(uint4) <= sizeof(Key) * kP / kWaves, "records fit");
-        static_assert((kGenWindow + kWave) * sizeof(uint32_t) <= sizeof(uint32_t) * kP / kWaves, "offsets fit");
+        static_assert((kGenWindow + kWave + 256) * sizeof(uint32_t) <= sizeof(uint32_t) * kP / kWaves,
+                      "offsets, slots and marks fit");
         uint4* s_rec = reinterpret_cast<uint4*>(s_keys + (size_t)w * (kP / kWaves));
         uint32_t* s_off = s_vals + (size_t)w * (kP / kWaves);
         generate_keys<kKPT>(a.gen, a.count, wbase, reinterpret_cast<uint32_t*>(key), val, s_off, s_rec,
-                            s_off + kGenWindow);
+                            s_off + kGenWindow, reinterpret_cast<uint4*>(s_off + kGenWindow + kWave));
     } else {
 #pragma unroll
     for (int r = 0; r < kKPT; ++r) {
@@ -464,7 +529,7 @@ __device__ __forceinline__ void sort_pass_body(const PassArgs<Key>& a, uint32_t 
 template <typename Key, bool kOnesweep, int kBits, bool kGen = false>
 __device__ __forceinline__ void sort_pass_kernel(const PassArgs<Key>& a) {
     __shared__ __align__(16) Key s_keys[kP];    // reorder buffer
-    __shared__ uint32_t s_vals[kP];
+    __shared__ __align__(16) uint32_t s_vals[kP];
     __shared__ uint32_t s_whist[kWaves][256];   // per-wave digit counters, then offsets
     __shared__ uint32_t s_gbase[256];
     __shared__ uint32_t s_scan[kWaves];
@@ -561,7 +626,7 @@ template <typename Key>
 hipError_t sort_passes_impl(const Key* kin, const uint32_t* vin, Key* ka, uint32_t* va, Key* kb,
                             uint32_t* vb, int64_t count, int passes, int shift0, int end_bit,
                             const SortWorkspace& ws, SortAlgo algo, hipStream_t stream, bool keep_keys,
-                            const KeyGen* gen, int value_bits) {
+                            const KeyGen* gen, int value_bits, hipEvent_t first_done) {
     if (count <= 0 || passes <= 0) return hipSuccess;
     if (count > kSortMaxCount) return hipErrorInvalidValue;
     const int64_t parts = sort_partitions(count);
@@ -627,6 +692,7 @@ hipError_t sort_passes_impl(const Key* kin, const uint32_t* vin, Key* ka, uint32
             if ((e = launch_pass<Key, false>(a, parts, stream)) != hipSuccess) return e;
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (p == 0 && first_done && (e = hipEventRecord(first_done, stream)) != hipSuccess) return e;
     }
     return hipSuccess;
 }
@@ -670,19 +736,19 @@ hipError_t launch_sort_prepare(const SortWorkspace& ws, int64_t count, int passe
 hipError_t launch_sort_passes(const uint64_t* kin, const uint32_t* vin, uint64_t* ka, uint32_t* va,
                               uint64_t* kb, uint32_t* vb, int64_t count, int passes, int shift0,
                               const SortWorkspace& ws, SortAlgo algo, hipStream_t stream, int end_bit,
-                              bool keep_keys) {
+                              bool keep_keys, hipEvent_t first_done) {
     return sort_passes_impl<uint64_t>(kin, vin, ka, va, kb, vb, count, passes, shift0,
                                       end_bit > 0 ? end_bit : shift0 + 8 * passes, ws, algo, stream, keep_keys,
-                                      nullptr, 0);
+                                      nullptr, 0, first_done);
 }
 
 hipError_t launch_sort_passes(const uint32_t* kin, const uint32_t* vin, uint32_t* ka, uint32_t* va,
                               uint32_t* kb, uint32_t* vb, int64_t count, int passes, int shift0,
                               const SortWorkspace& ws, SortAlgo algo, hipStream_t stream, int end_bit,
-                              bool keep_keys, const KeyGen* gen, int value_bits) {
+                              bool keep_keys, const KeyGen* gen, int value_bits, hipEvent_t first_done) {
     return sort_passes_impl<uint32_t>(kin, vin, ka, va, kb, vb, count, passes, shift0,
                                       end_bit > 0 ? end_bit : shift0 + 8 * passes, ws, algo, stream, keep_keys,
-                                      gen, value_bits);
+                                      gen, value_bits, first_done);
 }
 
 }  // namespace cds

@@ -67,7 +67,7 @@ class CdsFrameInfo(ctypes.Structure):
 class CdsStageTimes(ctypes.Structure):
     _fields_ = [(k, ctypes.c_float) for k in
                 ("preprocess_ms", "scan_ms", "depth_order_ms", "duplicate_ms", "sort_ms", "ranges_ms",
-                 "blend_ms", "blend_backward_ms", "preprocess_backward_ms")]
+                 "blend_ms", "blend_backward_ms", "preprocess_backward_ms", "sort_first_pass_ms")]
 
 
 CDS_OPT_STAGE_TIMING = 1
