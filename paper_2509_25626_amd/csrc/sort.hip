@@ -1,29 +1,33 @@
-// Stable LSD radix sort of (32- or 64-bit key, 32-bit value) pairs with
-// 8-bit digits: the per-tile depth order of paper Section II-B(1), done as a
-// global sort of (tile | depth) keys.
+// Stable LSD radix sort of (32- or 64-bit key, 32-bit value) pairs: the
+// per-tile depth order of paper Section II-B(1), done as a depth sort of the
+// visible splats followed by a sort of their keys' tile ids.
 //
-// Every pass is a partitioned counting sort.  A workgroup (256 threads,
+// Every pass is a partitioned counting sort on a digit of up to 8 bits (the
+// key bits are split evenly over the passes).  A workgroup (256 threads,
 // 4096 keys) ranks its keys stably in LDS, reorders them by digit and writes
 // each digit run as one contiguous, coalesced store.  Ranking is wave64
 // native: keys are held "wave-striped" (round r of a wave covers 64
-// consecutive input keys), lanes with the same digit are found with eight
-// ballots, and a per-wave per-digit counter in LDS gives each key its rank;
-// processing rounds in order keeps the sort stable.
+// consecutive input keys), lanes with the same digit are found with one
+// ballot per digit bit, and a per-wave per-digit counter in LDS gives each key
+// its rank; processing rounds in order keeps the sort stable.
 //
 // Two ways give a partition the global position of its digit runs:
-//  - reduce-then-scan (default for large inputs): an upsweep kernel counts
-//    the digits of every partition into a digit-major [256][partitions]
-//    matrix, one exclusive scan of that matrix yields every (digit,
-//    partition) base, and the pass kernel reads its bases.  20 B/key for
-//    32-bit keys, and no workgroup ever waits for another.
-//  - onesweep: each partition publishes its digit counts and sums its
-//    predecessors' by decoupled look-back over a status word per (partition,
-//    digit) (bits 31..30 = 0 not ready, 1 partition count, 2 inclusive
-//    prefix).  16 B/key, but every inclusive prefix waits for a
-//    device-coherent round trip; on a chip of 8 XCDs that chain, not HBM,
-//    bounds large sorts, so it is used for small ones.  Its wait is bounded:
-//    after ~2^22 polls a workgroup records an error and proceeds, so a logic
-//    error can corrupt the output but never hang the device.
+//  - onesweep (default): each partition publishes its digit counts and sums
+//    its predecessors' by decoupled look-back over a status word per
+//    (partition, digit) (bits 31..30 = 0 not ready, 1 partition count, 2
+//    inclusive prefix).  The status words are device-coherent, so every poll
+//    is a memory round trip; with small digits the whole workgroup polls, a
+//    window of predecessors per digit at once.  The wait is bounded: after
+//    ~2^22 polls a workgroup records an error and proceeds, so a logic error
+//    can corrupt the output but never hang the device.
+//  - reduce-then-scan: an upsweep kernel counts the digits of every partition
+//    into a digit-major [256][partitions] matrix, one exclusive scan of that
+//    matrix yields every (digit, partition) base, and the pass kernel reads
+//    its bases.  No workgroup ever waits for another.
+//
+// The first tile pass of a render can generate its keys from the splat
+// records instead of reading them (generate_keys), and passes can carry key
+// and value as one packed word once they fit (PassArgs::vbits).
 #include <algorithm>
 
 #include "device_utils.h"
