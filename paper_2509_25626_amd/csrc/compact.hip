@@ -4,7 +4,7 @@
 //   - per 4096-Gaussian tile: the number of visible splats and their keys
 //     (tiles touched), scanned to tile bases and to the totals n_vis and K,
 //   - a stable compaction (index order kept) of the visible splats' depth
-//     bits and of a 16-byte record (tile rectangle, Gaussian index), and
+//     bits and of a 16-byte tile record (make_tile_rec), and
 //   - the digit histograms of the depth sort over the compacted keys.
 // K here is the sum of tiles touched, which does not depend on the order,
 // so one host read-back of (n_vis, K) sizes everything that follows.
@@ -65,7 +65,8 @@ __global__ __launch_bounds__(kCT) void k_vis_scatter(int64_t n, const uint32_t* 
                                                      const uint32_t* __restrict__ depth_bits,
                                                      const uint64_t* __restrict__ vis_base,
                                                      uint32_t* __restrict__ dkey, uint4* __restrict__ rec,
-                                                     uint32_t* __restrict__ hist) {
+                                                     uint32_t* __restrict__ hist, uint32_t tiles_x,
+                                                     const BatchItem* __restrict__ items, int nitems) {
     __shared__ uint32_t s_hist[4 * 256];
     __shared__ uint32_t s_wtot[kCWaves];
     const int t = threadIdx.x;
@@ -93,8 +94,14 @@ __global__ __launch_bounds__(kCT) void k_vis_scatter(int64_t n, const uint32_t* 
             const uint32_t pos = slot + count_below(m);
             const uint32_t d = depth_bits[i];
             const uint2 rc = rect[i];
+            uint32_t tx = tiles_x, tb = 0;
+            if (items) {
+                const int it = find_item_by_gaussian(items, nitems, i);
+                tx = (uint32_t)items[it].P.tiles_x;
+                tb = (uint32_t)items[it].tile_base;
+            }
             dkey[pos] = d;
-            rec[pos] = make_uint4(rc.x, rc.y, (uint32_t)i, 0u);
+            rec[pos] = make_tile_rec(rc, tx, tb, (uint32_t)i);
 #pragma unroll
             for (int p = 0; p < 4; ++p) hist_add(s_hist + p * 256, (d >> (8 * p)) & 255u);
         }
@@ -119,7 +126,8 @@ int64_t compact_sums_size(int64_t n) { return (n + kCTile - 1) / kCTile + 1; }
 
 hipError_t launch_compact_visible(int64_t n, const uint32_t* touched, const uint2* rect, const uint32_t* depth_bits,
                                   uint64_t* vis_sums, uint64_t* key_sums, uint64_t* totals, uint32_t* dkey,
-                                  uint4* rec, uint32_t* depth_hist, hipStream_t stream) {
+                                  uint4* rec, uint32_t* depth_hist, hipStream_t stream, int tiles_x,
+                                  const BatchItem* items, int nitems) {
     const int64_t tiles = (n + kCTile - 1) / kCTile;
     hipError_t e = launch_fill_u32(depth_hist, 4 * 256, 0u, stream);
     if (e != hipSuccess) return e;
@@ -132,7 +140,7 @@ hipError_t launch_compact_visible(int64_t n, const uint32_t* touched, const uint
     if ((e = launch_scan_u64(key_sums, tiles, totals + 1, stream)) != hipSuccess) return e;
     if (tiles > 0) {
         hipLaunchKernelGGL(k_vis_scatter, dim3((unsigned)tiles), dim3(kCT), 0, stream, n, touched, rect, depth_bits,
-                           vis_sums, dkey, rec, depth_hist);
+                           vis_sums, dkey, rec, depth_hist, (uint32_t)tiles_x, items, nitems);
         e = hipGetLastError();
     }
     return e;

@@ -57,11 +57,15 @@ __global__ __launch_bounds__(kNT) void k_duplicate(DupArgs A) {
         uint32_t off = 0, cnt = 0, gid = 0, depth = 0, tx_n = tiles_x, tbase = 0;
         uint2 r = make_uint2(0u, 0u);
         if (j < n && A.rec) {
+            // the record's rectangle as (0, 0)..(width - 1, height - 1) on rows of
+            // its stride, offset by its first tile
             const uint4 q = A.rec[j];
             gid = q.z;
             off = A.offsets[j];
-            r = make_uint2(q.x, q.y);
-            cnt = ((q.y & 0xFFFFu) - (q.x & 0xFFFFu) + 1u) * ((q.y >> 16) - (q.x >> 16) + 1u);
+            r = make_uint2(0u, ((q.x & 0xFFFFu) - 1u) | (((q.x >> 16) - 1u) << 16));
+            cnt = tile_rec_area(q);
+            tx_n = q.y;
+            tbase = q.w;
             if (A.keys64) depth = A.depth_bits[gid];
         } else if (j < n) {
             gid = A.order ? A.order[j] : (uint32_t)j;

@@ -87,14 +87,29 @@ hipError_t launch_preprocess_batch(const BatchItem* items, int nitems, int64_t t
 // Exclusive scan of `count` uint64 values in place (one workgroup), total to *total.
 hipError_t launch_scan_u64(uint64_t* values, int64_t count, uint64_t* total, hipStream_t stream);
 
+// Tile record of a visible splat (16 B): its rectangle of tiles as runs of
+// tile ids, (width | height << 16, row stride, Gaussian index, id of the first
+// tile).  Key c of the splat, in row-major order over the rectangle, is tile
+// first + (c / width) * stride + c % width.  Batched renders store global
+// tile ids (the request's tile base added), single renders their own.
+__host__ __device__ inline uint4 make_tile_rec(uint2 rect, uint32_t tiles_x, uint32_t tile_base, uint32_t gid) {
+    const uint32_t x0 = rect.x & 0xFFFFu, y0 = rect.x >> 16, x1 = rect.y & 0xFFFFu, y1 = rect.y >> 16;
+    return make_uint4((x1 - x0 + 1u) | ((y1 - y0 + 1u) << 16), tiles_x, gid, tile_base + y0 * tiles_x + x0);
+}
+__host__ __device__ inline uint32_t tile_rec_area(uint4 q) { return (q.x & 0xFFFFu) * (q.x >> 16); }
+
+struct BatchItem;
+
 // Compaction of the visible splats (tiles touched > 0) in index order:
-// dkey[n_vis] depth bits, rec[n_vis] = (rect.x, rect.y, Gaussian index, 0),
-// depth_hist [4][256] digit histograms of dkey, totals[0] = n_vis,
+// dkey[n_vis] depth bits, rec[n_vis] tile records (make_tile_rec; `items`
+// give the per-request grids of a batched render, else tiles_x and tile base
+// 0), depth_hist [4][256] digit histograms of dkey, totals[0] = n_vis,
 // totals[1] = K.  vis_sums, key_sums: compact_sums_size(n) uint64 each.
 int64_t compact_sums_size(int64_t n);
 hipError_t launch_compact_visible(int64_t n, const uint32_t* touched, const uint2* rect, const uint32_t* depth_bits,
                                   uint64_t* vis_sums, uint64_t* key_sums, uint64_t* totals, uint32_t* dkey,
-                                  uint4* rec, uint32_t* depth_hist, hipStream_t stream);
+                                  uint4* rec, uint32_t* depth_hist, hipStream_t stream, int tiles_x,
+                                  const BatchItem* items = nullptr, int nitems = 0);
 // dst[j] = src[order[j]]
 hipError_t launch_rec_gather(int64_t count, const uint32_t* order, const uint4* src, uint4* dst, hipStream_t stream);
 
@@ -190,16 +205,30 @@ hipError_t launch_sort_passes(const uint64_t* kin, const uint32_t* vin, uint64_t
                               uint64_t* kb, uint32_t* vb, int64_t count, int passes, int shift0,
                               const SortWorkspace& ws, SortAlgo algo, hipStream_t stream, int end_bit = 0,
                               bool keep_keys = true, hipEvent_t first_done = nullptr);
+// Bits needed for the values 0 .. v (at least 1).
+inline int value_bits_for(int64_t v) {
+    int b = 1;
+    while (b < 63 && (v >> b) > 0) ++b;
+    return b;
+}
+// First pass of launch_sort_passes whose output is packed words (see there),
+// or `passes` when none is.
+int sort_pack_pass(int passes, int shift0, int end_bit, int value_bits, bool keep_keys, bool key64);
+// Whether launch_sort_passes with key generation in its first pass reads or
+// writes the key buffers (ka, kb) at all; when not, they may be null.
+inline bool sort_gen_needs_key_buffers(int passes, int end_bit, int value_bits) {
+    return passes > 1 && sort_pack_pass(passes, 0, end_bit, value_bits, false, false) > 0;
+}
+
 // Keys of the tile sort generated inside its first pass instead of read:
 // key p is the tile of the record owning it (row-major order within the
 // record's rectangle), its value the record's Gaussian index, which is what
 // launch_duplicate writes in record mode.
 struct KeyGen {
     const uint32_t* off;    // [n] first key of each record
-    const uint4* rec;       // [n] (x0 | y0 << 16, x1 | y1 << 16, Gaussian index, -)
+    const uint4* rec;       // [n] tile records (make_tile_rec)
     const uint32_t* owner;  // [count / kKeyGenChunk + 1] from launch_exclusive_scan
     int64_t n;
-    uint32_t tiles_x;
 };
 // With `gen`, kin and vin are ignored and the first pass generates the keys;
 // it needs the onesweep passes (hipErrorInvalidValue otherwise).

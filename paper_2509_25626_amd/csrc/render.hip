@@ -66,13 +66,6 @@ int tile_bits_for(int64_t ntiles) {
  * Stage events: start, preprocess, key count read back, depth order, keys
  * generated, tile sort, ranges, blend (see cds_stage_times).
  */
-// Bits needed for the values 0 .. v (at least 1).
-static int bit_width(int64_t v) {
-    int b = 1;
-    while (b < 63 && (v >> b) > 0) ++b;
-    return b;
-}
-
 cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scene, const cds_camera* cam,
                                int blend_variant, int sort_variant, SortAlgo algo, float* out_rgb, float* out_T,
                                uint32_t* out_ncontrib, hipStream_t stream) {
@@ -150,7 +143,7 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
         // visible splats compacted in index order, with the depth histograms; n_vis and K
         CDS_HIP(launch_compact_visible(n, sb.touched, sb.rect, sb.depth_bits, (uint64_t*)f->vsums.p,
                                        (uint64_t*)f->ksums.p, d_total, (uint32_t*)f->dkeyc.p, (uint4*)f->recc.p,
-                                       wd.hist, stream),
+                                       wd.hist, stream, P.tiles_x),
                 "visible compaction");
     } else if (binned) {
         // depth order of all N Gaussians: 4 passes, result in (dkey1, order1)
@@ -217,7 +210,7 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
                 CDS_HIP(launch_sort_prepare(wd, nvis, 4, false, stream), "depth sort prepare");
             CDS_HIP(launch_sort_passes((const uint32_t*)f->dkeyc.p, nullptr, (uint32_t*)f->dkey0.p,
                                        (uint32_t*)f->order0.p, (uint32_t*)f->dkey1.p, (uint32_t*)f->order1.p, nvis,
-                                       4, 0, wd, algo, stream, 32, false, nullptr, bit_width(nvis - 1)),
+                                       4, 0, wd, algo, stream, 32, false, nullptr, value_bits_for(nvis - 1)),
                     "depth sort");
             CDS_HIP(launch_rec_gather(nvis, (const uint32_t*)f->order1.p, (const uint4*)f->recc.p, (uint4*)f->recv.p,
                                       stream),
@@ -236,10 +229,15 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
                     "tile counts");
         CDS_TRY(f->record(kEvDepth, stream));
         const int passes = compact ? tile_passes : 4 + tile_passes;
+        // variant 2 with onesweep passes: the first tile pass generates the keys
+        const bool fused = compact && sort_uses_onesweep((int64_t)K, algo) && passes > 0;
         CDS_TRY(ensure(ctx, f->vals1, sizeof(uint32_t) * kk, 1.25));
         if (compact) {
-            CDS_TRY(ensure(ctx, f->tk0, sizeof(uint32_t) * kk, 1.25));
-            CDS_TRY(ensure(ctx, f->tk1, sizeof(uint32_t) * kk, 1.25));
+            // generated keys packed with their values need no tile-id buffers
+            if (!fused || sort_gen_needs_key_buffers(passes, tile_bits, value_bits_for(n - 1))) {
+                CDS_TRY(ensure(ctx, f->tk0, sizeof(uint32_t) * kk, 1.25));
+                CDS_TRY(ensure(ctx, f->tk1, sizeof(uint32_t) * kk, 1.25));
+            }
         } else {
             CDS_TRY(ensure(ctx, f->keys0, sizeof(uint64_t) * kk, 1.25));
             CDS_TRY(ensure(ctx, f->keys1, sizeof(uint64_t) * kk, 1.25));
@@ -247,14 +245,11 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
         CDS_TRY(ensure_sort_workspace(ctx, f->sort, (int64_t)K, passes > 0 ? passes : 1));
         SortWorkspace ws = sort_ws(ctx, f->sort);
         const bool onesweep = sort_uses_onesweep((int64_t)K, algo) && passes > 0;
-        // variant 2 with onesweep passes: the first tile pass generates the keys
-        const bool fused = compact && onesweep;
         KeyGen gen;
         gen.off = (const uint32_t*)f->offsets.p;
         gen.rec = recv;
         gen.owner = (const uint32_t*)f->kowner.p;
         gen.n = nvis;
-        gen.tiles_x = (uint32_t)P.tiles_x;
         if (K > 0) {
             if (compact) {
                 // the onesweep passes take the tile-digit histograms made from the rectangles
@@ -287,7 +282,7 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
                 CDS_HIP(launch_sort_passes((const uint32_t*)f->tk0.p, (const uint32_t*)f->vals0.p,
                                            (uint32_t*)f->tk1.p, (uint32_t*)f->vals1.p, (uint32_t*)f->tk0.p,
                                            (uint32_t*)f->vals0.p, (int64_t)K, passes, 0, ws, algo, stream, tile_bits,
-                                           false, fused ? &gen : nullptr, bit_width(n - 1),
+                                           false, fused ? &gen : nullptr, value_bits_for(n - 1),
                                            f->event(kEvSortFirst)),
                         "tile sort");
             f->res_tiles = passes > 0 ? nullptr : (const uint32_t*)f->tk0.p;

@@ -14,8 +14,8 @@ constexpr int kNT = 256;
 constexpr int kIPT = 16;
 constexpr int64_t kTileItems = (int64_t)kNT * kIPT;
 
-// Scan input: the tile count of a compacted splat record (area of its tile
-// rectangle) when `rec` is given, else in[gather[i]] or in[i].
+// Scan input: the tile count of a splat's tile record when `rec` is given,
+// else in[gather[i]] or in[i].
 struct ScanSrc {
     const uint32_t* in;
     const uint32_t* gather;
@@ -23,10 +23,7 @@ struct ScanSrc {
 };
 
 __device__ __forceinline__ uint32_t scan_in(const ScanSrc& s, int64_t i) {
-    if (s.rec) {
-        const uint4 r = s.rec[i];
-        return ((r.y & 0xFFFFu) - (r.x & 0xFFFFu) + 1u) * ((r.y >> 16) - (r.x >> 16) + 1u);
-    }
+    if (s.rec) return tile_rec_area(s.rec[i]);
     return s.gather ? s.in[s.gather[i]] : s.in[i];
 }
 

@@ -5,10 +5,12 @@
 // workspace is free, the number of requests in flight is below the slot
 // limit, and the estimated workspace of the admitted requests fits the HBM
 // budget.  Each admitted batch runs as one pass of batched kernels:
-// preprocess over the concatenated Gaussians of all its scenes, one depth
-// sort, one scan and key-count read-back, duplication into global tile ids
-// (request tile bases), one tile sort, ranges, and a persistent blend whose
-// workgroups pull tiles of every request from one work counter.  Two
+// preprocess over the concatenated Gaussians of all its scenes, compaction
+// of the visible splats into tile records in global tile ids (request tile
+// bases) and the key-count read-back, one depth sort, the key offsets, the
+// ranges from the records, one tile sort whose first pass generates the
+// keys, and a persistent blend whose workgroups pull tiles of every request
+// from one work counter.  Two
 // workspaces on two streams let the next batch's preprocessing overlap the
 // current batch's sort and blend; requests that arrive meanwhile join the
 // next batch.
@@ -102,15 +104,15 @@ namespace {
         if (_s != CDS_OK) return _s; \
     } while (0)
 
-// Workspace estimate of one request: ~100 B per Gaussian of frame state and
-// depth sort, ~17 B per key (tile ids and values double-buffered, sort
-// status), keys estimated at 64 per Gaussian per megapixel, scaled by what
-// earlier batches measured.
+// Workspace estimate of one request: ~120 B per Gaussian of frame state,
+// visible-splat records and depth sort, ~9 B per key (packed words and
+// values, sort status), keys estimated at 64 per Gaussian per megapixel,
+// scaled by what earlier batches measured.
 int64_t estimate_bytes(const cds_server* s, const cds_scene& sc, const cds_camera& cam) {
     const double mp = (double)cam.width * cam.height / 1.0e6;
     const double keys = s->key_scale * 64.0 * (double)sc.n * std::max(mp, 0.05);
     const int64_t tiles = (int64_t)((cam.width + CDS_TILE - 1) / CDS_TILE) * ((cam.height + CDS_TILE - 1) / CDS_TILE);
-    return (int64_t)(100.0 * (double)sc.n + 17.0 * keys) + 8 * tiles + 4096;
+    return (int64_t)(120.0 * (double)sc.n + 9.0 * keys) + 12 * tiles + 4096;
 }
 
 cds_status run_batch(cds_server* s, Workspace& w) {
@@ -153,6 +155,11 @@ cds_status run_batch(cds_server* s, Workspace& w) {
     SRV_TRY(ensure(ctx, f->order1, sizeof(uint32_t) * nn, 1.25));
     SRV_TRY(ensure(ctx, f->dkey0, sizeof(uint32_t) * nn, 1.25));
     SRV_TRY(ensure(ctx, f->dkey1, sizeof(uint32_t) * nn, 1.25));
+    SRV_TRY(ensure(ctx, f->dkeyc, sizeof(uint32_t) * nn, 1.25));
+    SRV_TRY(ensure(ctx, f->recc, sizeof(uint4) * nn, 1.25));
+    SRV_TRY(ensure(ctx, f->recv, sizeof(uint4) * nn, 1.25));
+    SRV_TRY(ensure(ctx, f->vsums, sizeof(uint64_t) * compact_sums_size(N), 1.25));
+    SRV_TRY(ensure(ctx, f->ksums, sizeof(uint64_t) * compact_sums_size(N), 1.25));
     SRV_TRY(ensure(ctx, f->ranges, sizeof(uint2) * (size_t)std::max<int64_t>(T, 1), 1.25));
     SRV_TRY(ensure(ctx, f->tdiff, sizeof(int) * (size_t)(T + 1), 1.25));
     SRV_TRY(ensure(ctx, f->thist, sizeof(uint32_t) * 4 * 256));
@@ -170,26 +177,18 @@ cds_status run_batch(cds_server* s, Workspace& w) {
     SRV_HIP(launch_preprocess_batch(w.items_dev, nitems, N, sb, stream), "batched preprocess");
     const SortAlgo algo = SortAlgo::kAuto;
     SortWorkspace wd = sort_ws(ctx, f->sort_d);
-    if (sort_uses_onesweep(N, algo)) {
-        SRV_HIP(launch_sort_prepare(wd, N, 4, true, stream), "depth sort prepare");
-        SRV_HIP(launch_sort_histogram(sb.depth_bits, N, 4, 0, wd.hist, stream), "depth sort histogram");
-    }
-    SRV_HIP(launch_sort_passes(sb.depth_bits, nullptr, (uint32_t*)f->dkey0.p, (uint32_t*)f->order0.p,
-                               (uint32_t*)f->dkey1.p, (uint32_t*)f->order1.p, N, 4, 0, wd, algo, stream),
-            "depth sort");
-    const uint32_t* order = (const uint32_t*)f->order1.p;
-    SRV_HIP(launch_exclusive_scan(sb.touched, order, (uint32_t*)f->offsets.p, N, (uint64_t*)f->blocksums.p,
-                                  (uint64_t*)f->total.p, stream),
-            "scan");
-    // ranges and tile-digit histograms from the rectangles (global tile ids)
-    SRV_HIP(launch_tile_counts(N, sb.touched, sb.rect, 0, T, (int*)f->tdiff.p, (uint2*)f->ranges.p,
-                               (uint32_t*)f->thist.p, digit_plan(tile_passes, 0, tile_bits_for(T)), nullptr,
-                               kTileCountBlocks, stream, w.items_dev, nitems),
-            "batched tile counts");
-    SRV_HIP(hipMemcpyAsync(w.pinned, f->total.p, sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
+    uint64_t* d_total = (uint64_t*)f->total.p;  // [0] = visible splats, [1] = K
+    // visible splats compacted with tile records in global tile ids, the
+    // depth histograms, n_vis and K
+    SRV_HIP(launch_compact_visible(N, sb.touched, sb.rect, sb.depth_bits, (uint64_t*)f->vsums.p,
+                                   (uint64_t*)f->ksums.p, d_total, (uint32_t*)f->dkeyc.p, (uint4*)f->recc.p,
+                                   wd.hist, stream, 0, w.items_dev, nitems),
+            "batched compaction");
+    SRV_HIP(hipMemcpyAsync(w.pinned, d_total, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
             "hipMemcpyAsync(key count)");
     SRV_HIP(hipStreamSynchronize(stream), "hipStreamSynchronize(key count)");
-    const uint64_t K = w.pinned[0];
+    const int64_t nvis = (int64_t)w.pinned[0];
+    const uint64_t K = w.pinned[1];
     if (K > (uint64_t)kSortMaxCount) return fail(CDS_ERR_CAPACITY, "batch needs more than 2^30-1 tile keys");
     int64_t est = 0;
     for (const SrvRequest* r : w.reqs) {
@@ -200,9 +199,36 @@ cds_status run_batch(cds_server* s, Workspace& w) {
         std::lock_guard<std::mutex> lk(s->mu);
         s->key_scale = std::max(0.05, 0.7 * s->key_scale + 0.3 * s->key_scale * (double)K / (double)est);
     }
+    const uint4* recv = (const uint4*)f->recv.p;
+    if (nvis > 0) {
+        // depth order of the visible splats, their records in that order, key
+        // offsets and the owner of every 1024th key
+        if (sort_uses_onesweep(nvis, algo)) SRV_HIP(launch_sort_prepare(wd, nvis, 4, false, stream), "depth prepare");
+        SRV_HIP(launch_sort_passes((const uint32_t*)f->dkeyc.p, nullptr, (uint32_t*)f->dkey0.p, (uint32_t*)f->order0.p,
+                                   (uint32_t*)f->dkey1.p, (uint32_t*)f->order1.p, nvis, 4, 0, wd, algo, stream, 32,
+                                   false, nullptr, value_bits_for(nvis - 1)),
+                "depth sort");
+        SRV_HIP(launch_rec_gather(nvis, (const uint32_t*)f->order1.p, (const uint4*)f->recc.p, (uint4*)f->recv.p,
+                                  stream),
+                "record gather");
+        SRV_TRY(ensure(ctx, f->kowner, sizeof(uint32_t) * (size_t)(K / kKeyGenChunk + 1), 1.25));
+        SRV_HIP(launch_exclusive_scan(nullptr, nullptr, (uint32_t*)f->offsets.p, nvis, (uint64_t*)f->blocksums.p,
+                                      d_total + 2, stream, recv, (uint32_t*)f->kowner.p),
+                "offset scan");
+    }
+    // ranges and tile-digit histograms from the records (global tile ids)
+    const int tile_bits = tile_bits_for(T);
+    SRV_HIP(launch_tile_counts(nvis, nullptr, nullptr, 0, T, (int*)f->tdiff.p, (uint2*)f->ranges.p,
+                               (uint32_t*)f->thist.p, digit_plan(tile_passes, 0, tile_bits), nullptr, kTileCountBlocks,
+                               stream, nullptr, 0, recv),
+            "batched tile counts");
     const size_t kk = (size_t)std::max<uint64_t>(K, 1);
-    SRV_TRY(ensure(ctx, f->tk0, sizeof(uint32_t) * kk, 1.25));
-    SRV_TRY(ensure(ctx, f->tk1, sizeof(uint32_t) * kk, 1.25));
+    const bool fused = sort_uses_onesweep((int64_t)K, algo) && tile_passes > 0;
+    const int vbits = value_bits_for(N - 1);
+    if (!fused || sort_gen_needs_key_buffers(tile_passes, tile_bits, vbits)) {
+        SRV_TRY(ensure(ctx, f->tk0, sizeof(uint32_t) * kk, 1.25));
+        SRV_TRY(ensure(ctx, f->tk1, sizeof(uint32_t) * kk, 1.25));
+    }
     SRV_TRY(ensure(ctx, f->vals0, sizeof(uint32_t) * kk, 1.25));
     SRV_TRY(ensure(ctx, f->vals1, sizeof(uint32_t) * kk, 1.25));
     SRV_TRY(ensure_sort_workspace(ctx, f->sort, (int64_t)K, std::max(tile_passes, 1)));
@@ -211,12 +237,18 @@ cds_status run_batch(cds_server* s, Workspace& w) {
         if (sort_uses_onesweep((int64_t)K, algo) && tile_passes > 0)
             SRV_HIP(launch_sort_prepare(ws, (int64_t)K, tile_passes, false, stream), "sort prepare");
         ws.hist = (uint32_t*)f->thist.p;
-        SRV_HIP(launch_duplicate(N, order, (const uint32_t*)f->offsets.p, sb.touched, sb.rect, sb.depth_bits, 0,
-                                 nullptr, (uint32_t*)f->tk0.p, (uint32_t*)f->vals0.p, stream, w.items_dev, nitems),
-                "batched duplicate");
+        KeyGen gen;
+        gen.off = (const uint32_t*)f->offsets.p;
+        gen.rec = recv;
+        gen.owner = (const uint32_t*)f->kowner.p;
+        gen.n = nvis;
+        if (!fused)
+            SRV_HIP(launch_duplicate(nvis, nullptr, (const uint32_t*)f->offsets.p, nullptr, nullptr, nullptr, 0,
+                                     nullptr, (uint32_t*)f->tk0.p, (uint32_t*)f->vals0.p, stream, nullptr, 0, recv),
+                    "batched duplicate");
         SRV_HIP(launch_sort_passes((const uint32_t*)f->tk0.p, (const uint32_t*)f->vals0.p, (uint32_t*)f->tk1.p,
                                    (uint32_t*)f->vals1.p, (uint32_t*)f->tk0.p, (uint32_t*)f->vals0.p, (int64_t)K,
-                                   tile_passes, 0, ws, algo, stream, tile_bits_for(T), false),
+                                   tile_passes, 0, ws, algo, stream, tile_bits, false, fused ? &gen : nullptr, vbits),
                 "tile sort");
     }
     const bool odd = (tile_passes & 1) != 0;

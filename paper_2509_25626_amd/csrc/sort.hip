@@ -171,16 +171,15 @@ struct PassArgs {
 //    the owners, and the window moves when a round's candidates leave it.
 constexpr int kGenWindow = 256;  // records per wave window
 
-// key of rank c in the record's rectangle; `q` = (x0 | y0 << 16, x1 | y1 << 16, ...)
-__device__ __forceinline__ uint32_t rect_key(uint4 q, uint32_t c, uint32_t tiles_x) {
-    const uint32_t x0 = q.x & 0xFFFFu, y0 = q.x >> 16, x1 = q.y & 0xFFFFu;
-    const uint32_t w = x1 - x0 + 1;
+// key of rank c in a tile record's rectangle (make_tile_rec)
+__device__ __forceinline__ uint32_t rect_key(uint4 q, uint32_t c) {
+    const uint32_t w = q.x & 0xFFFFu;
     // c / w via a float estimate and an exact integer fix-up
     uint32_t qq = (uint32_t)((float)c * __frcp_rn((float)w));
     int32_t rem = (int32_t)c - (int32_t)(qq * w);
     while (rem < 0) { --qq; rem += (int32_t)w; }
     while (rem >= (int32_t)w) { ++qq; rem -= (int32_t)w; }
-    return (y0 + qq) * tiles_x + x0 + (uint32_t)rem;
+    return q.w + qq * q.y + (uint32_t)rem;
 }
 
 template <int kRounds>
@@ -239,7 +238,7 @@ __device__ __forceinline__ void generate_keys(const KeyGen& g, int64_t count, in
 #pragma unroll
             for (int i = 0; i < kGroup; ++i) {
                 if (wbase + (g0 + i) * kWave + l < count) {
-                    key[g0 + i] = rect_key(q[i], c[i], g.tiles_x);
+                    key[g0 + i] = rect_key(q[i], c[i]);
                     val[g0 + i] = q[i].z;
                 }
             }
@@ -278,7 +277,7 @@ __device__ __forceinline__ void generate_keys(const KeyGen& g, int64_t count, in
         if (p < count) {
             const int k = (int)(jb + m - jw);
             const uint4 q = s_rec[k];
-            key[r] = rect_key(q, (uint32_t)(p - s_off[k]), g.tiles_x);
+            key[r] = rect_key(q, (uint32_t)(p - s_off[k]));
             val[r] = q.z;
         }
         jb += __builtin_amdgcn_readlane(m, kWave - 1);
@@ -639,14 +638,7 @@ hipError_t sort_passes_impl(const Key* kin, const uint32_t* vin, Key* ka, uint32
     if (gen && (!onesweep || sizeof(Key) != 4 || !gen->off || !gen->rec || !gen->owner))
         return hipErrorInvalidValue;
     const DigitPlan plan = digit_plan(passes, shift0, end_bit);
-    // first pass whose output can be packed (32-bit keys, keys not kept)
-    int pack_pass = passes;
-    if (sizeof(Key) == 4 && !keep_keys && value_bits > 0 && value_bits < 32)
-        for (int p = 0; p + 1 < passes; ++p)
-            if (end_bit - (plan.shift[p] + plan.bits[p]) + value_bits <= 32) {
-                pack_pass = p;
-                break;
-            }
+    const int pack_pass = sort_pack_pass(passes, shift0, end_bit, value_bits, keep_keys, sizeof(Key) == 8);
     const int packed_from = pack_pass < passes ? plan.shift[pack_pass] + plan.bits[pack_pass] : 0;
     for (int p = 0; p < passes; ++p) {
         PassArgs<Key> a;
@@ -702,6 +694,16 @@ hipError_t sort_passes_impl(const Key* kin, const uint32_t* vin, Key* ka, uint32
 }
 
 }  // namespace
+
+int sort_pack_pass(int passes, int shift0, int end_bit, int value_bits, bool keep_keys, bool key64) {
+    // 32-bit keys whose final keys are not kept, once the key bits left for
+    // later passes and the value fit one word
+    if (key64 || keep_keys || value_bits <= 0 || value_bits >= 32 || passes < 1 || passes > 8) return passes;
+    const DigitPlan plan = digit_plan(passes, shift0, end_bit);
+    for (int p = 0; p + 1 < passes; ++p)
+        if (end_bit - (plan.shift[p] + plan.bits[p]) + value_bits <= 32) return p;
+    return passes;
+}
 
 bool sort_uses_onesweep(int64_t count, SortAlgo algo) {
     return algo == SortAlgo::kOnesweep ||

@@ -23,7 +23,7 @@ struct DiffArgs {
     int tiles_x;
     int64_t ntiles;
     int* diff;  // [ntiles + 1], zero on entry
-    const uint4* rec;  // compacted visible records (rect in .x, .y) instead of touched/rect, or null
+    const uint4* rec;  // tile records of the visible splats instead of touched/rect, or null
     const BatchItem* items;
     int nitems;
 };
@@ -41,33 +41,28 @@ __global__ __launch_bounds__(kDiffThreads) void k_tile_diff(DiffArgs a) {
     }
     const int64_t stride = (int64_t)gridDim.x * kDiffThreads;
     for (int64_t i0 = (int64_t)blockIdx.x * kDiffThreads + threadIdx.x; i0 < a.n; i0 += kUnroll * stride) {
-        uint32_t cnt[kUnroll];
-        uint2 r[kUnroll];
+        uint4 q[kUnroll];  // tile records (width | height << 16, stride, -, first tile)
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             const int64_t i = i0 + u * stride;
+            q[u] = make_uint4(0u, 0u, 0u, 0u);
             if (a.rec) {
-                cnt[u] = i < a.n ? 1u : 0u;
-                const uint4 q = i < a.n ? a.rec[i] : make_uint4(0u, 0u, 0u, 0u);
-                r[u] = make_uint2(q.x, q.y);
-            } else {
-                cnt[u] = i < a.n ? a.touched[i] : 0u;
-                r[u] = cnt[u] ? a.rect[i] : make_uint2(0u, 0u);
+                if (i < a.n) q[u] = a.rec[i];
+            } else if (i < a.n && a.touched[i]) {
+                uint32_t tx = (uint32_t)a.tiles_x, tb = 0;
+                if (a.items) {
+                    const int it = find_item_by_gaussian(a.items, a.nitems, i);
+                    tx = (uint32_t)a.items[it].P.tiles_x;
+                    tb = (uint32_t)a.items[it].tile_base;
+                }
+                q[u] = make_tile_rec(a.rect[i], tx, tb, 0u);
             }
         }
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-            if (!cnt[u]) continue;
-            const uint32_t x0 = r[u].x & 0xFFFFu, y0 = r[u].x >> 16, x1 = r[u].y & 0xFFFFu, y1 = r[u].y >> 16;
-            uint32_t tx = (uint32_t)a.tiles_x, tb = 0;
-            if (a.items) {
-                const int it = find_item_by_gaussian(a.items, a.nitems, i0 + u * stride);
-                tx = (uint32_t)a.items[it].P.tiles_x;
-                tb = (uint32_t)a.items[it].tile_base;
-            }
-            const uint32_t w = x1 - x0 + 1;
-            for (uint32_t y = y0; y <= y1; ++y) {
-                const uint32_t t0 = tb + y * tx + x0;
+            const uint32_t w = q[u].x & 0xFFFFu, h = q[u].x >> 16;
+            uint32_t t0 = q[u].w;
+            for (uint32_t y = 0; y < h; ++y, t0 += q[u].y) {
                 atomicAdd(&d[t0], 1);
                 atomicAdd(&d[t0 + w], -1);
             }
