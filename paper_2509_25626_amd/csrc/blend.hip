@@ -13,6 +13,13 @@
 // an early exit is voted block-wide once per batch, and a wave whose pixels
 // are all done leaves the batch early.
 //
+// Each staged splat also carries a pixel box outside which its alpha is
+// below 1/255 for certain (the ellipse of power >= -ln(255 o), widened by a
+// margin that covers the rounding of the alpha test).  A wave evaluates only
+// the splats whose box meets its pixels, found with four ballots per batch;
+// every pair it skips is one the alpha test would skip, so the result is the
+// same as evaluating all of them.
+//
 // Tiles are assigned in XCD-contiguous bands so neighbouring tiles, which
 // share most of their splats, hit the same L2.
 #include "device_utils.h"
@@ -29,12 +36,22 @@ constexpr float kTMin = 0.0001f;
 
 // Staged splat, one LDS slot per splat:
 //   s_q  double4 (mean x, mean y, A', B')   s_c double C'   s_f float4 (opacity, r, g, b)
+//   s_b  the tile pixels its alpha can reach: bytes (x min, x max, y min, y max)
+//        + 1, relative to the tile origin and clamped to [-1, 16]
 // with A' = -log2(e)/2 A, B' = -log2(e) B, C' = -log2(e)/2 C, so that
 // A' dx^2 + B' dx dy + C' dy^2 = log2(e) * power.
+//
+// Box: alpha >= 1/255 needs o exp(power) >= 1/255, i.e. d^T M d <= 2 ln(255 o)
+// with d = mean - pixel and M = [[A, B], [B, C]]; that ellipse lies within
+// |dx| <= sqrt(2 t C / det), |dy| <= sqrt(2 t A / det).  t is ln(255 o) plus
+// 1e-3 (+1e-5 relative): the float32 rounding of power, of exp2, of the
+// product and of the log2 that gives t move the test by far less.  Splats with o < 1/255 reach no pixel
+// (alpha <= o); when M is not positive definite or anything is not finite,
+// the box is unbounded.
 __device__ __forceinline__ void stage_splat(const float2* __restrict__ mean2d,
                                             const float4* __restrict__ conic_opacity,
                                             const float4* __restrict__ rgb, uint32_t id, double4* s_q,
-                                            double* s_c, float4* s_f, int k) {
+                                            double* s_c, float4* s_f, uint32_t* s_b, int k, int tx0, int ty0) {
     const double L = 1.4426950408889634;  // log2(e)
     const float2 m = mean2d[id];
     const float4 co = conic_opacity[id];
@@ -42,6 +59,36 @@ __device__ __forceinline__ void stage_splat(const float2* __restrict__ mean2d,
     s_q[k] = make_double4((double)m.x, (double)m.y, -0.5 * L * (double)co.x, -L * (double)co.y);
     s_c[k] = -0.5 * L * (double)co.z;
     s_f[k] = make_float4(co.w, c.x, c.y, c.z);
+    // box relative to the tile origin, in whole pixels, clamped to [-1, 16]
+    int x0 = -1, x1 = kTile, y0 = -1, y1 = kTile;  // unbounded
+    if (co.w < kAlphaMin) {
+        x0 = kTile;  // empty
+        x1 = -1;
+    } else {
+        const double a = (double)co.x, b = (double)co.y, cc = (double)co.z;
+        const double det = a * cc - b * b;
+        // ln(255 o) from the hardware log2 (error ~1e-7 relative), widened
+        const double t = (double)(__builtin_amdgcn_logf(255.0f * co.w) * kLn2) * (1.0 + 1e-5) + 1e-3;
+        if (a > 0.0 && cc > 0.0 && det > 0.0 && t > 0.0 && t < 1e30) {
+            const double ex = sqrt(2.0 * t * cc / det) * (1.0 + 1e-6) + 0.01;
+            const double ey = sqrt(2.0 * t * a / det) * (1.0 + 1e-6) + 0.01;
+            const double mx = (double)m.x - tx0, my = (double)m.y - ty0;
+            // comparisons are false for NaN, which keeps the unbounded box
+            if (mx - ex > -1.0) x0 = mx - ex < (double)kTile ? (int)floor(mx - ex) : kTile;
+            if (mx + ex < (double)kTile) x1 = mx + ex > -1.0 ? (int)ceil(mx + ex) : -1;
+            if (my - ey > -1.0) y0 = my - ey < (double)kTile ? (int)floor(my - ey) : kTile;
+            if (my + ey < (double)kTile) y1 = my + ey > -1.0 ? (int)ceil(my + ey) : -1;
+        }
+    }
+    s_b[k] = (uint32_t)(x0 + 1) | ((uint32_t)(x1 + 1) << 8) | ((uint32_t)(y0 + 1) << 16) | ((uint32_t)(y1 + 1) << 24);
+}
+
+// Whether a staged box (see stage_splat) meets the tile pixel rows
+// [r0, r1] (all 16 columns).
+__device__ __forceinline__ bool box_meets_rows(uint32_t box, int r0, int r1) {
+    const int x0 = (int)(box & 0xFFu) - 1, x1 = (int)((box >> 8) & 0xFFu) - 1;
+    const int y0 = (int)((box >> 16) & 0xFFu) - 1, y1 = (int)(box >> 24) - 1;
+    return x1 >= 0 && x0 <= kTile - 1 && y1 >= r0 && y0 <= r1;
 }
 
 // The blending decision of one (pixel, splat) pair, shared by the forward
@@ -72,12 +119,16 @@ __device__ __forceinline__ void blend_tile(int tx, int ty, int width, int height
                                            const float4* __restrict__ conic_opacity,
                                            const float4* __restrict__ rgb, float bg0, float bg1, float bg2,
                                            float* out_rgb, float* out_T, uint32_t* out_ncontrib, double4* s_q,
-                                           double* s_c, float4* s_f) {
+                                           double* s_c, float4* s_f, uint32_t* s_b) {
     constexpr int NT = 256 / PPT;
+    constexpr int kRowsPerWave = kWave / kTile * PPT;
     const int t = threadIdx.x;
     const int px = tx * kTile + (t & 15);
     const int py0 = ty * kTile + (t >> 4) * PPT;
     const double fpx = (double)px;
+    const uint32_t lane = lane_id();
+    // this wave's pixels: 16 columns, tile rows [wr0, wr0 + kRowsPerWave)
+    const int wr0 = (t / kWave) * kRowsPerWave;
 
     float T[PPT], C0[PPT], C1[PPT], C2[PPT];
     double fpy[PPT];
@@ -100,16 +151,34 @@ __device__ __forceinline__ void blend_tile(int tx, int ty, int width, int height
         if (__syncthreads_count(alive) == 0) break;
         for (int k = t; k < kBatch; k += NT) {
             const int idx = base + k;
-            if (idx < todo) stage_splat(mean2d, conic_opacity, rgb, point_list[range.x + idx], s_q, s_c, s_f, k);
+            if (idx < todo)
+                stage_splat(mean2d, conic_opacity, rgb, point_list[range.x + idx], s_q, s_c, s_f, s_b, k,
+                            tx * kTile, ty * kTile);
         }
         __syncthreads();
         const int cnt = min(kBatch, todo - base);
-        for (int j = 0; j < cnt; ++j) {
-            if ((j & 31) == 0) {
+        // the batch's splats whose box meets this wave's pixels, in list order
+        uint64_t cand[kBatch / kWave];
+#pragma unroll
+        for (int q = 0; q < kBatch / kWave; ++q) {
+            const int k = q * kWave + (int)lane;
+            cand[q] = ballot(k < cnt && box_meets_rows(s_b[k], wr0, wr0 + kRowsPerWave - 1));
+        }
+        int visited = 0;
+        bool wave_done = false;
+        for (int q = 0; q < kBatch / kWave && !wave_done; ++q) {
+            uint64_t m = cand[q];
+            while (m) {
+            const int j = q * kWave + __builtin_ctzll(m);
+            m &= m - 1;
+            if ((visited++ & 31) == 0) {
                 int live = 0;
 #pragma unroll
                 for (int p = 0; p < PPT; ++p) live |= done[p] ? 0 : 1;
-                if (!__any(live)) break;  // wave-uniform: this wave's pixels are all done
+                if (!__any(live)) {  // wave-uniform: this wave's pixels are all done
+                    wave_done = true;
+                    break;
+                }
             }
             const double4 q = s_q[j];
             const double c2 = s_c[j];
@@ -137,6 +206,7 @@ __device__ __forceinline__ void blend_tile(int tx, int ty, int width, int height
                     }
                 }
             }
+            }
         }
     }
 
@@ -160,11 +230,12 @@ __global__ __launch_bounds__(256 / PPT) void k_blend(BlendArgs a, uint32_t per_x
     __shared__ double4 s_q[kBatch];
     __shared__ double s_c[kBatch];
     __shared__ float4 s_f[kBatch];
+    __shared__ uint32_t s_b[kBatch];
     const uint32_t tile = xcd_band(blockIdx.x, per_xcd);
     if (tile >= (uint32_t)(a.tiles_x * a.tiles_y)) return;  // whole block: padding
     const int tx = (int)(tile % (uint32_t)a.tiles_x), ty = (int)(tile / (uint32_t)a.tiles_x);
     blend_tile<PPT>(tx, ty, a.width, a.height, a.ranges[tile], a.point_list, a.mean2d, a.conic_opacity, a.rgb,
-                    a.bg[0], a.bg[1], a.bg[2], a.out_rgb, a.out_T, a.out_ncontrib, s_q, s_c, s_f);
+                    a.bg[0], a.bg[1], a.bg[2], a.out_rgb, a.out_T, a.out_ncontrib, s_q, s_c, s_f, s_b);
 }
 
 // Persistent blend over every tile of a batch of renders: each workgroup
@@ -181,6 +252,7 @@ __global__ __launch_bounds__(256 / PPT) void k_blend_batch(const BatchItem* __re
     __shared__ double4 s_q[kBatch];
     __shared__ double s_c[kBatch];
     __shared__ float4 s_f[kBatch];
+    __shared__ uint32_t s_b[kBatch];
     __shared__ uint32_t s_tile;
     for (;;) {
         if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1u);
@@ -193,7 +265,7 @@ __global__ __launch_bounds__(256 / PPT) void k_blend_batch(const BatchItem* __re
         const uint32_t local = g - (uint32_t)it.tile_base;
         const int tx = (int)(local % (uint32_t)it.P.tiles_x), ty = (int)(local / (uint32_t)it.P.tiles_x);
         blend_tile<PPT>(tx, ty, it.P.width, it.P.height, ranges[g], point_list, mean2d, conic_opacity, rgb,
-                        it.bg[0], it.bg[1], it.bg[2], it.out_rgb, it.out_T, it.out_ncontrib, s_q, s_c, s_f);
+                        it.bg[0], it.bg[1], it.bg[2], it.out_rgb, it.out_T, it.out_ncontrib, s_q, s_c, s_f, s_b);
     }
 }
 
@@ -205,13 +277,17 @@ __global__ __launch_bounds__(256 / PPT) void k_blend_batch(const BatchItem* __re
 //   dL/dalpha_i = T_i (rgb_i - S_i) . dL/dC,   S_{i-1} = alpha_i rgb_i + (1 - alpha_i) S_i
 // alpha = min(0.99, o G): when unclamped dalpha/do = G and dalpha/dpower = alpha.
 // Per-splat sums over the wave are reduced with cross-lane shuffles and
-// added to the per-Gaussian 2D gradients ([n][9]) with atomics.
+// added to the per-Gaussian 2D gradients ([n][9]) with atomics.  A wave
+// visits only the splats whose box meets its pixels (as in the forward
+// pass): the others contribute nothing.
 template <int PPT>
 __global__ __launch_bounds__(256 / PPT) void k_blend_bwd(BlendBwdArgs a, uint32_t per_xcd) {
     constexpr int NT = 256 / PPT;
+    constexpr int kRowsPerWave = kWave / kTile * PPT;
     __shared__ double4 s_q[kBatch];
     __shared__ double s_c[kBatch];
     __shared__ float4 s_f[kBatch];
+    __shared__ uint32_t s_b[kBatch];
     __shared__ uint32_t s_id[kBatch];
     __shared__ uint32_t s_max;
 
@@ -223,6 +299,7 @@ __global__ __launch_bounds__(256 / PPT) void k_blend_bwd(BlendBwdArgs a, uint32_
     const int py0 = ty * kTile + (t >> 4) * PPT;
     const double fpx = (double)px;
     const int64_t npix = (int64_t)a.width * a.height;
+    const int wr0 = (t / kWave) * kRowsPerWave;  // this wave's first tile row
 
     float T[PPT], S0[PPT], S1[PPT], S2[PPT], D0[PPT], D1[PPT], D2[PPT];
     double fpy[PPT];
@@ -266,11 +343,23 @@ __global__ __launch_bounds__(256 / PPT) void k_blend_bwd(BlendBwdArgs a, uint32_
         for (int k = t; k < end - begin; k += NT) {
             const uint32_t id = a.point_list[range.x + begin + k];
             s_id[k] = id;
-            stage_splat(a.mean2d, a.conic_opacity, a.rgb, id, s_q, s_c, s_f, k);
+            stage_splat(a.mean2d, a.conic_opacity, a.rgb, id, s_q, s_c, s_f, s_b, k, tx * kTile, ty * kTile);
         }
         __syncthreads();
-        for (int j = end - 1; j >= begin; --j) {
-            const int k = j - begin;
+        const int cnt = end - begin;
+        uint64_t cand[kBatch / kWave];
+#pragma unroll
+        for (int qd = 0; qd < kBatch / kWave; ++qd) {
+            const int k = qd * kWave + (int)lane_id();
+            cand[qd] = ballot(k < cnt && box_meets_rows(s_b[k], wr0, wr0 + kRowsPerWave - 1));
+        }
+        for (int qd = kBatch / kWave - 1; qd >= 0; --qd) {
+            uint64_t m = cand[qd];
+            while (m) {  // back to front
+            const int bit = 63 - __builtin_clzll(m);
+            m &= ~(1ull << bit);
+            const int k = qd * kWave + bit;
+            const int j = begin + k;
             const double4 q = s_q[k];
             const double c2 = s_c[k];
             const float4 f = s_f[k];
@@ -323,6 +412,7 @@ __global__ __launch_bounds__(256 / PPT) void k_blend_bwd(BlendBwdArgs a, uint32_
                 float* g = a.grad2d + (size_t)s_id[k] * 9;
                 if ((l & 7u) == 0) atomicAdd(g + (l >> 3), s8);
                 if (l == 0) atomicAdd(g + 8, sb);
+            }
             }
         }
     }
