@@ -286,10 +286,13 @@ __device__ __forceinline__ void generate_keys(const KeyGen& g, int64_t count, in
 
 // One partition of one pass.  kFull: the partition has no tail (every key
 // valid), compiled separately so the common case carries no bounds checks.
-template <typename Key, bool kOnesweep, int kBits, bool kFull, bool kGen>
+// kPacked: the keys are packed words that hold their values (value = key &
+// unpack_mask), so no value is loaded, held or staged.
+template <typename Key, bool kOnesweep, int kBits, bool kFull, bool kGen, bool kPacked = false>
 __device__ __forceinline__ void sort_pass_body(const PassArgs<Key>& a, uint32_t pid, Key* s_keys, uint32_t* s_vals,
                                                uint32_t (*s_whist)[256], uint32_t* s_gbase, uint32_t* s_scan,
                                                uint32_t digit_info) {
+    static_assert(!kPacked || (sizeof(Key) == 4 && !kGen), "packed words are 32-bit keys read from memory");
     constexpr uint32_t kMask = (1u << kBits) - 1u;
     const int t = threadIdx.x;
     const int w = t / kWave;
@@ -318,7 +321,9 @@ __device__ __forceinline__ void sort_pass_body(const PassArgs<Key>& a, uint32_t 
         const int64_t idx = wbase + r * kWave + l;
         key[r] = (kFull || idx < a.count) ? a.kin[idx] : (Key)0;
     }
-    if (a.unpack_mask) {  // uniform
+    if constexpr (kPacked) {
+        // values stay inside the keys
+    } else if (a.unpack_mask) {  // uniform
 #pragma unroll
         for (int r = 0; r < kKPT; ++r) val[r] = (uint32_t)key[r] & a.unpack_mask;
     } else if (a.vin) {  // uniform: one clean load loop either way
@@ -380,7 +385,7 @@ __device__ __forceinline__ void sort_pass_body(const PassArgs<Key>& a, uint32_t 
             const uint32_t d = (uint32_t)(key[r] >> a.shift) & kMask;
             const uint32_t pos = min(s_whist[w][d] + rank[r], (uint32_t)(kP - 1));
             s_keys[pos] = key[r];
-            s_vals[pos] = val[r];
+            if constexpr (!kPacked) s_vals[pos] = val[r];
         }
     }
     __syncthreads();  // s_whist is free from here on
@@ -520,7 +525,11 @@ __device__ __forceinline__ void sort_pass_body(const PassArgs<Key>& a, uint32_t 
             // counts; record it instead of writing out of bounds
             if ((int64_t)g < a.count) {
                 if (a.kout) a.kout[g] = k;
-                const uint32_t v = s_vals[i];
+                uint32_t v;
+                if constexpr (kPacked)
+                    v = (uint32_t)k & a.unpack_mask;
+                else
+                    v = s_vals[i];
                 a.vout[g] = a.vbits ? ((uint32_t)(k >> a.pack_shift) << a.vbits) | v : v;
             } else {
                 atomicOr(a.err, 2u);
@@ -562,6 +571,30 @@ __global__ __launch_bounds__(kNT, 4) void k_sort_pass_onesweep(PassArgs<Key> a) 
     sort_pass_kernel<Key, true, kBits>(a);
 }
 
+// Onesweep pass over packed words (value inside the key): one word per key
+// in registers and in LDS.
+template <int kBits>
+__global__ __launch_bounds__(kNT, 4) void k_sort_pass_packed(PassArgs<uint32_t> a) {
+    __shared__ __align__(16) uint32_t s_keys[kP];
+    __shared__ uint32_t s_whist[kWaves][256];
+    __shared__ uint32_t s_gbase[256];
+    __shared__ uint32_t s_scan[kWaves];
+    __shared__ uint32_t s_pid;
+
+    const int t = threadIdx.x;
+    if (t == 0) s_pid = atomicAdd(a.counter, 1u);
+    const uint32_t hist_t = a.hist[t];
+    for (int k = t; k < kWaves * 256; k += kNT) (&s_whist[0][0])[k] = 0;
+    __syncthreads();
+    const uint32_t pid = s_pid;
+    if ((int64_t)(pid + 1) * kP <= a.count)
+        sort_pass_body<uint32_t, true, kBits, true, false, true>(a, pid, s_keys, nullptr, s_whist, s_gbase, s_scan,
+                                                                 hist_t);
+    else
+        sort_pass_body<uint32_t, true, kBits, false, false, true>(a, pid, s_keys, nullptr, s_whist, s_gbase, s_scan,
+                                                                  hist_t);
+}
+
 // The first tile pass with its keys generated from the splat records.
 template <int kBits>
 __global__ __launch_bounds__(kNT, 4) void k_sort_pass_gen(PassArgs<uint32_t> a) {
@@ -579,6 +612,22 @@ void launch_pass_bits(const PassArgs<Key>& a, dim3 grid, hipStream_t stream) {
         hipLaunchKernelGGL((k_sort_pass_onesweep<Key, kBits>), grid, dim3(kNT), 0, stream, a);
     else
         hipLaunchKernelGGL((k_sort_pass_rts<Key, kBits>), grid, dim3(kNT), 0, stream, a);
+}
+
+hipError_t launch_packed_pass(const PassArgs<uint32_t>& a, int64_t parts, hipStream_t stream) {
+    const dim3 grid((unsigned)parts);
+    switch (a.bits) {
+        case 1: hipLaunchKernelGGL(k_sort_pass_packed<1>, grid, dim3(kNT), 0, stream, a); break;
+        case 2: hipLaunchKernelGGL(k_sort_pass_packed<2>, grid, dim3(kNT), 0, stream, a); break;
+        case 3: hipLaunchKernelGGL(k_sort_pass_packed<3>, grid, dim3(kNT), 0, stream, a); break;
+        case 4: hipLaunchKernelGGL(k_sort_pass_packed<4>, grid, dim3(kNT), 0, stream, a); break;
+        case 5: hipLaunchKernelGGL(k_sort_pass_packed<5>, grid, dim3(kNT), 0, stream, a); break;
+        case 6: hipLaunchKernelGGL(k_sort_pass_packed<6>, grid, dim3(kNT), 0, stream, a); break;
+        case 7: hipLaunchKernelGGL(k_sort_pass_packed<7>, grid, dim3(kNT), 0, stream, a); break;
+        case 8: hipLaunchKernelGGL(k_sort_pass_packed<8>, grid, dim3(kNT), 0, stream, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_gen_pass(const PassArgs<uint32_t>& a, int64_t parts, hipStream_t stream) {
@@ -675,6 +724,10 @@ hipError_t sort_passes_impl(const Key* kin, const uint32_t* vin, Key* ka, uint32
             if constexpr (sizeof(Key) == 4) {
                 a.gen = *gen;
                 if ((e = launch_gen_pass(a, parts, stream)) != hipSuccess) return e;
+            }
+        } else if (onesweep && a.unpack_mask) {
+            if constexpr (sizeof(Key) == 4) {
+                if ((e = launch_packed_pass(a, parts, stream)) != hipSuccess) return e;
             }
         } else if (onesweep) {
             if ((e = launch_pass<Key, true>(a, parts, stream)) != hipSuccess) return e;

@@ -166,6 +166,33 @@ def test_binning_many_keys_per_row(R):
         assert np.array_equal(a[k], b[k]), k
 
 
+@pytest.mark.parametrize("variant", [1, 2, 4])
+def test_blend_cull_edge_splats(R, variant):
+    # the blend visits a splat only where its alpha can reach 1/255: opacities
+    # straddling 1/255 and needle-thin, rotated splats sit right at the edge
+    # of that region; the image must still match the oracle, and the three
+    # pixel layouts (different per-wave regions) must agree bit for bit
+    rng = np.random.Generator(np.random.PCG64(23))
+    n = 6000
+    scene = S.scene_c1(24, n)
+    logit = np.log((1.0 / 255.0) / (1.0 - 1.0 / 255.0))
+    op = rng.normal(logit, 0.05, size=n)
+    op[: n // 3] = rng.normal(0.5, 1.5, size=n // 3)
+    scene["opacity_logits"] = op.astype(np.float32)
+    ls = rng.normal(-3.5, 0.5, size=(3, n))
+    thin = rng.random(n) < 0.5
+    ls[0, thin] = rng.normal(-1.5, 0.3, size=thin.sum())  # long axis
+    ls[1, thin] = rng.normal(-6.5, 0.3, size=thin.sum())  # needle-thin
+    scene["log_scales"] = ls.astype(np.float32)
+    cam = S.orbit_camera(203, 117, 3.0, 20.0, 15.0)
+    g = gpu_render(R, scene, cam, variant)
+    o = O.render(scene, cam, round_f32=True)
+    compare_images(g, o, max_flip_frac=5e-3)
+    base = gpu_render(R, scene, cam, 2)
+    for k in ("image", "final_T", "n_contrib"):
+        assert np.array_equal(g[k], base[k]), k
+
+
 @pytest.mark.parametrize("mu,sigma,n", [(-7.0, 0.3, 200_000), (-4.5, 2.0, 100_000), (-1.0, 0.2, 3_000)])
 def test_generated_keys_match_duplication(R, mu, sigma, n):
     # the first tile pass generates the keys from the depth-ordered splat
