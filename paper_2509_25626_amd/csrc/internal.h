@@ -119,11 +119,13 @@ hipError_t launch_rec_gather(int64_t count, const uint32_t* order, const uint4* 
 int64_t scan_block_sums_size(int64_t n);
 // Key offsets of splat records.  With `owner`, also the record owning every
 // kKeyGenChunk-th key (owner[q] = the record whose keys include key
-// q * kKeyGenChunk; K / kKeyGenChunk + 1 words).
+// q * kKeyGenChunk; K / kKeyGenChunk + 1 words).  With count_dev, the
+// number of items is read on the device (`n` is an upper bound).
 constexpr int64_t kKeyGenChunk = 1024;
 hipError_t launch_exclusive_scan(const uint32_t* in, const uint32_t* gather, uint32_t* out, int64_t n,
                                  uint64_t* block_sums, uint64_t* total, hipStream_t stream,
-                                 const uint4* rec = nullptr, uint32_t* owner = nullptr);
+                                 const uint4* rec = nullptr, uint32_t* owner = nullptr,
+                                 const uint64_t* count_dev = nullptr);
 
 // Key duplication over the visit order `order` (identity when null): writes
 // Digit layout of an LSD sort of key bits [shift0, end_bit) in `passes`
@@ -165,7 +167,7 @@ constexpr int64_t kTileDiffLdsMaxTiles = 16383;  // ntiles + 1 ints fit 64 KiB o
 hipError_t launch_tile_counts(int64_t n, const uint32_t* touched, const uint2* rect, int tiles_x, int64_t ntiles,
                               int* diff, uint2* ranges, uint32_t* hist, const DigitPlan& plan, uint64_t* total,
                               int max_blocks, hipStream_t stream, const BatchItem* items = nullptr, int nitems = 0,
-                              const uint4* rec = nullptr);
+                              const uint4* rec = nullptr, const uint64_t* count_dev = nullptr);
 hipError_t launch_make_keys(const uint32_t* tiles, const uint32_t* values, const uint32_t* depth_bits,
                             int64_t count, uint64_t* keys, hipStream_t stream);
 
@@ -232,6 +234,10 @@ struct KeyGen {
 };
 // With `gen`, kin and vin are ignored and the first pass generates the keys;
 // it needs the onesweep passes (hipErrorInvalidValue otherwise).
+// With gather_src/gather_dst (keep_keys false), the last pass writes
+// gather_src[value] to gather_dst instead of the value to its value buffer.
+// With count_dev (not with gen), the number of keys is read on the device
+// from *count_dev; `count` is then an upper bound that sizes the grids.
 // value_bits > 0 promises every value is below 2^value_bits: without
 // keep_keys, the passes after the first one whose remaining key bits and
 // value fit 32 bits then move one packed word per key instead of two
@@ -240,7 +246,8 @@ hipError_t launch_sort_passes(const uint32_t* kin, const uint32_t* vin, uint32_t
                               uint32_t* kb, uint32_t* vb, int64_t count, int passes, int shift0,
                               const SortWorkspace& ws, SortAlgo algo, hipStream_t stream, int end_bit = 0,
                               bool keep_keys = true, const KeyGen* gen = nullptr, int value_bits = 0,
-                              hipEvent_t first_done = nullptr);
+                              hipEvent_t first_done = nullptr, const uint4* gather_src = nullptr,
+                              uint4* gather_dst = nullptr, const uint64_t* count_dev = nullptr);
 
 hipError_t launch_fill_u32(uint32_t* p, int64_t count, uint32_t value, hipStream_t stream);
 

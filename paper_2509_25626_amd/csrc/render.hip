@@ -14,6 +14,15 @@ void release_frame_events(cds_frame* f) {
             (void)hipEventDestroy(e);
             e = nullptr;
         }
+    for (hipEvent_t* e : {&f->fork, &f->join, &f->copied})
+        if (*e) {
+            (void)hipEventDestroy(*e);
+            *e = nullptr;
+        }
+    if (f->side) {
+        (void)hipStreamDestroy(f->side);  // waits for its work
+        f->side = nullptr;
+    }
 }
 
 void release_frame_buffers(cds_frame* f) {
@@ -169,8 +178,36 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
     }
     CDS_HIP(hipMemcpyAsync(ctx->host_pinned, d_total, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
             "hipMemcpyAsync(key count)");
-    CDS_HIP(hipStreamSynchronize(stream), "hipStreamSynchronize(key count)");
     CDS_TRY(f->record(kEvCount, stream));
+    if (compact) {
+        // Enqueued before the host waits for the counts, so the device is not idle
+        // meanwhile: these kernels are sized for all n Gaussians and read the
+        // number of visible splats (d_total[0]) on the device.
+        CDS_TRY(f->side_stream());
+        CDS_HIP(hipEventRecord(f->copied, stream), "hipEventRecord(copied)");
+        // ranges and tile-digit histograms from the records (their order does not
+        // matter), on the side stream while the depth sort runs
+        CDS_HIP(hipEventRecord(f->fork, stream), "hipEventRecord(fork)");
+        CDS_HIP(hipStreamWaitEvent(f->side, f->fork, 0), "hipStreamWaitEvent(fork)");
+        CDS_HIP(launch_tile_counts(n, nullptr, nullptr, P.tiles_x, ntiles, (int*)f->tdiff.p, (uint2*)f->ranges.p,
+                                   (uint32_t*)f->thist.p, digit_plan(tile_passes, 0, tile_bits), nullptr,
+                                   kTileCountBlocks, f->side, nullptr, 0, (const uint4*)f->recc.p, d_total),
+                "tile counts");
+        CDS_HIP(hipEventRecord(f->join, f->side), "hipEventRecord(join)");
+        if (n > 0) {
+            // depth sort of the compacted keys (values: compacted positions); the
+            // last pass writes the records in depth order (recv) instead
+            if (sort_uses_onesweep(n, algo)) CDS_HIP(launch_sort_prepare(wd, n, 4, false, stream), "depth prepare");
+            CDS_HIP(launch_sort_passes((const uint32_t*)f->dkeyc.p, nullptr, (uint32_t*)f->dkey0.p,
+                                       (uint32_t*)f->order0.p, (uint32_t*)f->dkey1.p, (uint32_t*)f->order1.p, n, 4,
+                                       0, wd, algo, stream, 32, false, nullptr, value_bits_for(n - 1), nullptr,
+                                       (const uint4*)f->recc.p, (uint4*)f->recv.p, d_total),
+                    "depth sort");
+        }
+        CDS_HIP(hipEventSynchronize(f->copied), "hipEventSynchronize(key count)");
+    } else {
+        CDS_HIP(hipStreamSynchronize(stream), "hipStreamSynchronize(key count)");
+    }
     const int64_t nvis = compact ? (int64_t)ctx->host_pinned[0] : n;
     const uint64_t K = ctx->host_pinned[1];
     if (K > (uint64_t)kSortMaxCount)
@@ -204,29 +241,13 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
     } else {
         const uint4* recv = (const uint4*)f->recv.p;
         if (compact && nvis > 0) {
-            // depth sort of the compacted keys (values: compacted positions), then
-            // the records in depth order, their key offsets, and the tile counts
-            if (sort_uses_onesweep(nvis, algo))
-                CDS_HIP(launch_sort_prepare(wd, nvis, 4, false, stream), "depth sort prepare");
-            CDS_HIP(launch_sort_passes((const uint32_t*)f->dkeyc.p, nullptr, (uint32_t*)f->dkey0.p,
-                                       (uint32_t*)f->order0.p, (uint32_t*)f->dkey1.p, (uint32_t*)f->order1.p, nvis,
-                                       4, 0, wd, algo, stream, 32, false, nullptr, value_bits_for(nvis - 1)),
-                    "depth sort");
-            CDS_HIP(launch_rec_gather(nvis, (const uint32_t*)f->order1.p, (const uint4*)f->recc.p, (uint4*)f->recv.p,
-                                      stream),
-                    "record gather");
+            // key offsets of the records in depth order and the owner of every 1024th key
             CDS_TRY(ensure(ctx, f->kowner, sizeof(uint32_t) * (size_t)(K / kKeyGenChunk + 1), 1.25));
-            CDS_HIP(launch_exclusive_scan(nullptr, nullptr, (uint32_t*)f->offsets.p, nvis,
-                                          (uint64_t*)f->blocksums.p, d_total + 2, stream, recv,
-                                          (uint32_t*)f->kowner.p),
+            CDS_HIP(launch_exclusive_scan(nullptr, nullptr, (uint32_t*)f->offsets.p, n, (uint64_t*)f->blocksums.p,
+                                          d_total + 2, stream, recv, (uint32_t*)f->kowner.p, d_total),
                     "offset scan");
         }
-        if (compact)  // ranges and tile-digit histograms from the rectangles
-            CDS_HIP(launch_tile_counts(nvis, nullptr, nullptr, P.tiles_x, ntiles, (int*)f->tdiff.p,
-                                       (uint2*)f->ranges.p, (uint32_t*)f->thist.p,
-                                       digit_plan(tile_passes, 0, tile_bits), nullptr, kTileCountBlocks, stream,
-                                       nullptr, 0, recv),
-                    "tile counts");
+        if (compact) CDS_HIP(hipStreamWaitEvent(stream, f->join, 0), "hipStreamWaitEvent(join)");
         CDS_TRY(f->record(kEvDepth, stream));
         const int passes = compact ? tile_passes : 4 + tile_passes;
         // variant 2 with onesweep passes: the first tile pass generates the keys
@@ -394,6 +415,19 @@ cds_status render_backward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* sce
 void cds_frame::release_all() {
     cds::release_frame_buffers(this);
     cds::release_frame_events(this);
+}
+
+cds_status cds_frame::side_stream() {
+    hipError_t e;
+    if (!side && (e = hipStreamCreateWithFlags(&side, hipStreamNonBlocking)) != hipSuccess)
+        return cds::hip_fail(e, "hipStreamCreate(side)");
+    if (!fork && (e = hipEventCreateWithFlags(&fork, hipEventDisableTiming)) != hipSuccess)
+        return cds::hip_fail(e, "hipEventCreate(fork)");
+    if (!join && (e = hipEventCreateWithFlags(&join, hipEventDisableTiming)) != hipSuccess)
+        return cds::hip_fail(e, "hipEventCreate(join)");
+    if (!copied && (e = hipEventCreateWithFlags(&copied, hipEventDisableTiming)) != hipSuccess)
+        return cds::hip_fail(e, "hipEventCreate(copied)");
+    return CDS_OK;
 }
 
 hipEvent_t cds_frame::event(int i) {

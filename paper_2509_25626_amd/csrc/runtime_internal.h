@@ -76,6 +76,12 @@ struct cds_frame {
     // stage timing: HIP events at the stage boundaries (kEv*)
     bool timing = false, timed_backward = false;
     hipEvent_t ev[cds::kEvCount_] = {};
+    // a second stream (default priority) for work that overlaps the depth
+    // sort, forked from and joined back into the render stream
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    hipEvent_t copied = nullptr;  // the key-count read-back has landed
+    cds_status side_stream();
     cds_status record(int i, hipStream_t s);
     hipEvent_t event(int i);  // the stage event, created on demand; null without timing
     void release_all();

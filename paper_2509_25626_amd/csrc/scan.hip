@@ -27,7 +27,9 @@ __device__ __forceinline__ uint32_t scan_in(const ScanSrc& s, int64_t i) {
     return s.gather ? s.in[s.gather[i]] : s.in[i];
 }
 
-__global__ __launch_bounds__(kNT) void k_scan_reduce(ScanSrc src, int64_t n, uint64_t* __restrict__ sums) {
+__global__ __launch_bounds__(kNT) void k_scan_reduce(ScanSrc src, int64_t n, uint64_t* __restrict__ sums,
+                                                     const uint64_t* __restrict__ count_dev) {
+    if (count_dev) n = (int64_t)*count_dev;  // tiles past it sum to 0
     __shared__ uint32_t scratch[kNT / kWave];
     const int64_t base = (int64_t)blockIdx.x * kTileItems;
     uint32_t s = 0;
@@ -77,7 +79,9 @@ __global__ __launch_bounds__(1024) void k_scan_sums(uint64_t* __restrict__ sums,
 }
 
 __global__ __launch_bounds__(kNT) void k_scan_down(ScanSrc src, int64_t n, const uint64_t* __restrict__ sums,
-                                                   uint32_t* __restrict__ out, uint32_t* __restrict__ owner) {
+                                                   uint32_t* __restrict__ out, uint32_t* __restrict__ owner,
+                                                   const uint64_t* __restrict__ count_dev) {
+    if (count_dev) n = (int64_t)*count_dev;
     __shared__ uint32_t scratch[kNT / kWave];
     // blocked arrangement: thread t owns items [t*kIPT, (t+1)*kIPT) of the tile
     const int64_t base = (int64_t)blockIdx.x * kTileItems + (int64_t)threadIdx.x * kIPT;
@@ -115,18 +119,20 @@ hipError_t launch_scan_u64(uint64_t* values, int64_t count, uint64_t* total, hip
 
 hipError_t launch_exclusive_scan(const uint32_t* in, const uint32_t* gather, uint32_t* out, int64_t n,
                                  uint64_t* block_sums, uint64_t* total, hipStream_t stream, const uint4* rec,
-                                 uint32_t* owner) {
+                                 uint32_t* owner, const uint64_t* count_dev) {
     const int64_t tiles = (n + kTileItems - 1) / kTileItems;
     ScanSrc src;
     src.in = in;
     src.gather = gather;
     src.rec = rec;
     if (tiles > 0) {
-        hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)tiles), dim3(kNT), 0, stream, src, n, block_sums);
+        hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)tiles), dim3(kNT), 0, stream, src, n, block_sums,
+                           count_dev);
     }
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, stream, block_sums, tiles, total);
     if (tiles > 0) {
-        hipLaunchKernelGGL(k_scan_down, dim3((unsigned)tiles), dim3(kNT), 0, stream, src, n, block_sums, out, owner);
+        hipLaunchKernelGGL(k_scan_down, dim3((unsigned)tiles), dim3(kNT), 0, stream, src, n, block_sums, out, owner,
+                           count_dev);
     }
     return hipGetLastError();
 }

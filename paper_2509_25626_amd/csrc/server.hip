@@ -206,11 +206,9 @@ cds_status run_batch(cds_server* s, Workspace& w) {
         if (sort_uses_onesweep(nvis, algo)) SRV_HIP(launch_sort_prepare(wd, nvis, 4, false, stream), "depth prepare");
         SRV_HIP(launch_sort_passes((const uint32_t*)f->dkeyc.p, nullptr, (uint32_t*)f->dkey0.p, (uint32_t*)f->order0.p,
                                    (uint32_t*)f->dkey1.p, (uint32_t*)f->order1.p, nvis, 4, 0, wd, algo, stream, 32,
-                                   false, nullptr, value_bits_for(nvis - 1)),
-                "depth sort");
-        SRV_HIP(launch_rec_gather(nvis, (const uint32_t*)f->order1.p, (const uint4*)f->recc.p, (uint4*)f->recv.p,
-                                  stream),
-                "record gather");
+                                   false, nullptr, value_bits_for(nvis - 1), nullptr, (const uint4*)f->recc.p,
+                                   (uint4*)f->recv.p),
+                "depth sort (records in depth order)");
         SRV_TRY(ensure(ctx, f->kowner, sizeof(uint32_t) * (size_t)(K / kKeyGenChunk + 1), 1.25));
         SRV_HIP(launch_exclusive_scan(nullptr, nullptr, (uint32_t*)f->offsets.p, nvis, (uint64_t*)f->blocksums.p,
                                       d_total + 2, stream, recv, (uint32_t*)f->kowner.p),

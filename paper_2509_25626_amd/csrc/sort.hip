@@ -104,7 +104,9 @@ __device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
 // do not depend on order, so plain (skew-aware) LDS atomics suffice.
 template <typename Key>
 __global__ __launch_bounds__(kNT) void k_rts_upsweep(const Key* __restrict__ keys, int64_t count, int shift,
-                                                     int bits, uint32_t* __restrict__ part_hist, int64_t parts) {
+                                                     int bits, uint32_t* __restrict__ part_hist, int64_t parts,
+                                                     const uint64_t* __restrict__ count_dev) {
+    if (count_dev) count = (int64_t)*count_dev;  // partitions past it count nothing
     __shared__ uint32_t s_h[256];
     const int t = threadIdx.x;
     s_h[t] = 0;
@@ -149,6 +151,12 @@ struct PassArgs {
     uint32_t vbits;         // nonzero: pack the output
     uint32_t pack_shift;
     uint32_t unpack_mask;   // nonzero: keys are packed words, value = key & unpack_mask
+    // last pass only: instead of value v, write gather_src[v] (16 B) to gather_dst
+    const uint4* gather_src;
+    uint4* gather_dst;
+    // when given, the number of keys (at most `count`, which sized the grid
+    // and the workspace) is read here on the device
+    const uint64_t* count_dev;
 };
 
 // Generated keys (duplication fused into the first tile pass).  Key p
@@ -530,7 +538,10 @@ __device__ __forceinline__ void sort_pass_body(const PassArgs<Key>& a, uint32_t 
                     v = (uint32_t)k & a.unpack_mask;
                 else
                     v = s_vals[i];
-                a.vout[g] = a.vbits ? ((uint32_t)(k >> a.pack_shift) << a.vbits) | v : v;
+                if (a.gather_dst)  // uniform
+                    a.gather_dst[g] = a.gather_src[v];
+                else
+                    a.vout[g] = a.vbits ? ((uint32_t)(k >> a.pack_shift) << a.vbits) | v : v;
             } else {
                 atomicOr(a.err, 2u);
             }
@@ -539,7 +550,9 @@ __device__ __forceinline__ void sort_pass_body(const PassArgs<Key>& a, uint32_t 
 }
 
 template <typename Key, bool kOnesweep, int kBits, bool kGen = false>
-__device__ __forceinline__ void sort_pass_kernel(const PassArgs<Key>& a) {
+__device__ __forceinline__ void sort_pass_kernel(const PassArgs<Key>& a_in) {
+    PassArgs<Key> a = a_in;
+    if (a.count_dev) a.count = (int64_t)*a.count_dev;
     __shared__ __align__(16) Key s_keys[kP];    // reorder buffer
     __shared__ __align__(16) uint32_t s_vals[kP];
     __shared__ uint32_t s_whist[kWaves][256];   // per-wave digit counters, then offsets
@@ -553,6 +566,7 @@ __device__ __forceinline__ void sort_pass_kernel(const PassArgs<Key>& a) {
     for (int k = t; k < kWaves * 256; k += kNT) (&s_whist[0][0])[k] = 0;
     __syncthreads();
     const uint32_t pid = s_pid;
+    if ((int64_t)pid * kP >= a.count) return;  // uniform: past the keys (device-side count)
     // digit t's count over all keys (onesweep) or this partition's base for it
     // (reduce-then-scan), loaded before the ranking so its latency overlaps
     const uint32_t digit_info = kOnesweep ? hist_t : a.bases[(int64_t)t * a.parts + pid];
@@ -575,6 +589,7 @@ __global__ __launch_bounds__(kNT, 4) void k_sort_pass_onesweep(PassArgs<Key> a) 
 // in registers and in LDS.
 template <int kBits>
 __global__ __launch_bounds__(kNT, 4) void k_sort_pass_packed(PassArgs<uint32_t> a) {
+    if (a.count_dev) a.count = (int64_t)*a.count_dev;
     __shared__ __align__(16) uint32_t s_keys[kP];
     __shared__ uint32_t s_whist[kWaves][256];
     __shared__ uint32_t s_gbase[256];
@@ -587,6 +602,7 @@ __global__ __launch_bounds__(kNT, 4) void k_sort_pass_packed(PassArgs<uint32_t> 
     for (int k = t; k < kWaves * 256; k += kNT) (&s_whist[0][0])[k] = 0;
     __syncthreads();
     const uint32_t pid = s_pid;
+    if ((int64_t)pid * kP >= a.count) return;  // uniform: past the keys (device-side count)
     if ((int64_t)(pid + 1) * kP <= a.count)
         sort_pass_body<uint32_t, true, kBits, true, false, true>(a, pid, s_keys, nullptr, s_whist, s_gbase, s_scan,
                                                                  hist_t);
@@ -678,7 +694,8 @@ template <typename Key>
 hipError_t sort_passes_impl(const Key* kin, const uint32_t* vin, Key* ka, uint32_t* va, Key* kb,
                             uint32_t* vb, int64_t count, int passes, int shift0, int end_bit,
                             const SortWorkspace& ws, SortAlgo algo, hipStream_t stream, bool keep_keys,
-                            const KeyGen* gen, int value_bits, hipEvent_t first_done) {
+                            const KeyGen* gen, int value_bits, hipEvent_t first_done, const uint4* gather_src,
+                            uint4* gather_dst, const uint64_t* count_dev) {
     if (count <= 0 || passes <= 0) return hipSuccess;
     if (count > kSortMaxCount) return hipErrorInvalidValue;
     const int64_t parts = sort_partitions(count);
@@ -686,6 +703,8 @@ hipError_t sort_passes_impl(const Key* kin, const uint32_t* vin, Key* ka, uint32
     if (passes > 8) return hipErrorInvalidValue;
     if (gen && (!onesweep || sizeof(Key) != 4 || !gen->off || !gen->rec || !gen->owner))
         return hipErrorInvalidValue;
+    if ((gather_dst != nullptr) != (gather_src != nullptr) || (gather_dst && keep_keys)) return hipErrorInvalidValue;
+    if (count_dev && gen) return hipErrorInvalidValue;
     const DigitPlan plan = digit_plan(passes, shift0, end_bit);
     const int pack_pass = sort_pack_pass(passes, shift0, end_bit, value_bits, keep_keys, sizeof(Key) == 8);
     const int packed_from = pack_pass < passes ? plan.shift[pack_pass] + plan.bits[pack_pass] : 0;
@@ -719,6 +738,9 @@ hipError_t sort_passes_impl(const Key* kin, const uint32_t* vin, Key* ka, uint32
         a.parts = parts;
         a.err = ws.err;
         a.gen = KeyGen{};
+        a.count_dev = count_dev;
+        a.gather_src = p == passes - 1 ? gather_src : nullptr;
+        a.gather_dst = p == passes - 1 ? gather_dst : nullptr;
         hipError_t e;
         if (p == 0 && gen) {
             if constexpr (sizeof(Key) == 4) {
@@ -733,7 +755,7 @@ hipError_t sort_passes_impl(const Key* kin, const uint32_t* vin, Key* ka, uint32
             if ((e = launch_pass<Key, true>(a, parts, stream)) != hipSuccess) return e;
         } else {
             hipLaunchKernelGGL(k_rts_upsweep<Key>, dim3((unsigned)parts), dim3(kNT), 0, stream, a.kin, count,
-                               a.shift, a.bits, ws.part_hist, parts);
+                               a.shift, a.bits, ws.part_hist, parts, count_dev);
             if ((e = hipGetLastError()) != hipSuccess) return e;
             e = launch_exclusive_scan(ws.part_hist, nullptr, ws.bases, 256 * parts, ws.scan_sums, ws.scan_total,
                                       stream);
@@ -798,16 +820,17 @@ hipError_t launch_sort_passes(const uint64_t* kin, const uint32_t* vin, uint64_t
                               bool keep_keys, hipEvent_t first_done) {
     return sort_passes_impl<uint64_t>(kin, vin, ka, va, kb, vb, count, passes, shift0,
                                       end_bit > 0 ? end_bit : shift0 + 8 * passes, ws, algo, stream, keep_keys,
-                                      nullptr, 0, first_done);
+                                      nullptr, 0, first_done, nullptr, nullptr, nullptr);
 }
 
 hipError_t launch_sort_passes(const uint32_t* kin, const uint32_t* vin, uint32_t* ka, uint32_t* va,
                               uint32_t* kb, uint32_t* vb, int64_t count, int passes, int shift0,
                               const SortWorkspace& ws, SortAlgo algo, hipStream_t stream, int end_bit,
-                              bool keep_keys, const KeyGen* gen, int value_bits, hipEvent_t first_done) {
+                              bool keep_keys, const KeyGen* gen, int value_bits, hipEvent_t first_done,
+                              const uint4* gather_src, uint4* gather_dst, const uint64_t* count_dev) {
     return sort_passes_impl<uint32_t>(kin, vin, ka, va, kb, vb, count, passes, shift0,
                                       end_bit > 0 ? end_bit : shift0 + 8 * passes, ws, algo, stream, keep_keys,
-                                      gen, value_bits, first_done);
+                                      gen, value_bits, first_done, gather_src, gather_dst, count_dev);
 }
 
 }  // namespace cds

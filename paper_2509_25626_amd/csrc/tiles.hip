@@ -26,6 +26,7 @@ struct DiffArgs {
     const uint4* rec;  // tile records of the visible splats instead of touched/rect, or null
     const BatchItem* items;
     int nitems;
+    const uint64_t* count_dev;  // when given, the number of splats (n is an upper bound)
 };
 
 // +1 / -1 at the ends of every rectangle row's run of tile ids.  Each thread
@@ -39,16 +40,17 @@ __global__ __launch_bounds__(kDiffThreads) void k_tile_diff(DiffArgs a) {
         for (int64_t k = threadIdx.x; k <= a.ntiles; k += kDiffThreads) s_d[k] = 0;
         __syncthreads();
     }
+    const int64_t n = a.count_dev ? (int64_t)*a.count_dev : a.n;
     const int64_t stride = (int64_t)gridDim.x * kDiffThreads;
-    for (int64_t i0 = (int64_t)blockIdx.x * kDiffThreads + threadIdx.x; i0 < a.n; i0 += kUnroll * stride) {
+    for (int64_t i0 = (int64_t)blockIdx.x * kDiffThreads + threadIdx.x; i0 < n; i0 += kUnroll * stride) {
         uint4 q[kUnroll];  // tile records (width | height << 16, stride, -, first tile)
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             const int64_t i = i0 + u * stride;
             q[u] = make_uint4(0u, 0u, 0u, 0u);
             if (a.rec) {
-                if (i < a.n) q[u] = a.rec[i];
-            } else if (i < a.n && a.touched[i]) {
+                if (i < n) q[u] = a.rec[i];
+            } else if (i < n && a.touched[i]) {
                 uint32_t tx = (uint32_t)a.tiles_x, tb = 0;
                 if (a.items) {
                     const int it = find_item_by_gaussian(a.items, a.nitems, i);
@@ -155,7 +157,7 @@ __global__ __launch_bounds__(kRangeThreads) void k_tile_ranges(int64_t ntiles, c
 hipError_t launch_tile_counts(int64_t n, const uint32_t* touched, const uint2* rect, int tiles_x, int64_t ntiles,
                               int* diff, uint2* ranges, uint32_t* hist, const DigitPlan& plan, uint64_t* total,
                               int max_blocks, hipStream_t stream, const BatchItem* items, int nitems,
-                              const uint4* rec) {
+                              const uint4* rec, const uint64_t* count_dev) {
     if (ntiles <= 0) return hipSuccess;
     if (plan.passes > 4) return hipErrorInvalidValue;
     hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(diff), ntiles + 1, 0u, stream);
@@ -171,6 +173,7 @@ hipError_t launch_tile_counts(int64_t n, const uint32_t* touched, const uint2* r
         a.rec = rec;
         a.items = items;
         a.nitems = nitems;
+        a.count_dev = count_dev;
         int64_t blocks = (n + kDiffThreads - 1) / kDiffThreads;
         if (blocks > max_blocks) blocks = max_blocks;
         if (ntiles <= kTileDiffLdsMaxTiles)
