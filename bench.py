@@ -169,26 +169,34 @@ def main():
     dev = torch.device("cuda", 0)
     scene = GaussianScene.from_numpy(scene_np, device=dev)
     R = Renderer(0)
-    frame = R.acquire_frame()
+    # two frame objects used in turn: a frame's stage events are read after the
+    # next frame has been enqueued, so reading them never stalls the stream
+    frames = [R.acquire_frame(), R.acquire_frame()]
+    frame = frames[0]
     H, W = cam.height, cam.width
     out = (torch.empty((3, H, W), device=dev), torch.empty((H, W), device=dev),
            torch.empty((H, W), dtype=torch.int32, device=dev))
 
-    def fwd(timing=False):
-        return R.forward(scene, cam, frame=frame, blend_variant=args.blend_variant, out=out, timing=timing,
+    def fwd(fr, timing=False):
+        return R.forward(scene, cam, frame=fr, blend_variant=args.blend_variant, out=out, timing=timing,
                          sort_variant=args.sort_variant, sort_algo=args.sort_algo)
 
-    for _ in range(args.warmup):
-        fwd()
+    def accumulate(acc, fr):
+        for k, v in fr.stage_times().items():
+            acc[k] = acc.get(k, 0.0) + v
+
+    for i in range(max(2, args.warmup)):
+        fwd(frames[i % 2])
     torch.cuda.synchronize()
     stage_acc = {}
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        fwd(timing=True)
-        for k, v in frame.stage_times().items():
-            stage_acc[k] = stage_acc.get(k, 0.0) + v
+    for i in range(args.steps):
+        fwd(frames[i % 2], timing=True)
+        if i > 0:
+            accumulate(stage_acc, frames[(i - 1) % 2])
     torch.cuda.synchronize()
     t_fwd = (time.perf_counter() - t0) / args.steps
+    accumulate(stage_acc, frames[(args.steps - 1) % 2])
     stages = {k: v / args.steps for k, v in stage_acc.items()
               if not k.endswith("backward_ms") and k != "sort_first_pass_ms"}
     first_pass_ms = stage_acc.get("sort_first_pass_ms", 0.0) / args.steps
@@ -203,22 +211,23 @@ def main():
         dl = torch.empty((3, H, W), device=dev)
         loss = torch.empty(1, device=dev)
 
-        def fwdbwd(timing=False):
-            rgb, T, nc, _ = fwd(timing)
+        def fwdbwd(fr, timing=False):
+            rgb, T, nc, _ = fwd(fr, timing)
             R.l1_loss_grad(rgb, target, dl, loss)
-            R.backward(frame, scene, cam, T, nc, dl, grads)
+            R.backward(fr, scene, cam, T, nc, dl, grads)
 
-        for _ in range(max(1, args.warmup // 2)):
-            fwdbwd()
+        for i in range(max(2, args.warmup // 2)):
+            fwdbwd(frames[i % 2])
         torch.cuda.synchronize()
         bw_acc = {}
         t0 = time.perf_counter()
-        for _ in range(args.steps):
-            fwdbwd(timing=True)
-            for k, v in frame.stage_times().items():
-                bw_acc[k] = bw_acc.get(k, 0.0) + v
+        for i in range(args.steps):
+            fwdbwd(frames[i % 2], timing=True)
+            if i > 0:
+                accumulate(bw_acc, frames[(i - 1) % 2])
         torch.cuda.synchronize()
         t_fb = (time.perf_counter() - t0) / args.steps
+        accumulate(bw_acc, frames[(args.steps - 1) % 2])
         result_extra["fwd_bwd_fps"] = round(1.0 / t_fb, 3)
         result_extra["fwd_bwd_ms"] = round(t_fb * 1e3, 4)
         result_extra["backward_stage_ms"] = {k: round(v / args.steps, 4) for k, v in bw_acc.items()
