@@ -444,20 +444,24 @@ int ora_ranges(int64_t count, const uint64_t* sorted_keys, int ntiles, uint32_t*
 typedef struct {
     double Tfinal;
     double C[3];
+    double D;                     /* expected inverse depth: sum of a T / depth */
     uint32_t ncontrib;
     uint32_t nused;               /* Gaussians actually blended */
     double m_power, m_alpha, m_T; /* smallest relative decision margins */
 } pixres;
 
-/* Blend one pixel over an ordered list of Gaussian indices. */
+/* Blend one pixel over an ordered list of Gaussian indices.  `invd` (1 /
+ * depth per Gaussian, or NULL) is composited like a colour channel without
+ * a background term: the expected inverse depth of the optional output of
+ * the Appendix B kernels. */
 static void blend_pixel(int px, int py, const uint32_t* list, int64_t len, int64_t n,
                         const double* mean2d, const double* conic, const double* opacity,
-                        const double* rgb, pixres* out,
+                        const double* rgb, const double* invd, pixres* out,
                         /* optional per-contribution record for the backward pass */
                         int64_t* c_pos, double* c_T, double* c_alpha, double* c_G, int* c_clamped,
                         int64_t* c_count) {
     const double amax = alpha_max(), amin = alpha_min(), tmin = t_min();
-    double T = 1.0, C[3] = {0.0, 0.0, 0.0};
+    double T = 1.0, C[3] = {0.0, 0.0, 0.0}, D = 0.0;
     double m_power = INFINITY, m_alpha = INFINITY, m_T = INFINITY;
     uint32_t last = 0;
     int64_t j, nc = 0;
@@ -496,12 +500,14 @@ static void blend_pixel(int px, int py, const uint32_t* list, int64_t len, int64
         C[0] += rgb[g] * a * T;
         C[1] += rgb[n + g] * a * T;
         C[2] += rgb[2 * n + g] * a * T;
+        if (invd) D += invd[g] * a * T;
         T = Tn;
         last = (uint32_t)(j + 1);
     }
     if (c_count) *c_count = nc;
     out->Tfinal = T;
     out->C[0] = C[0]; out->C[1] = C[1]; out->C[2] = C[2];
+    out->D = D;
     out->ncontrib = last;
     out->nused = (uint32_t)nc;
     out->m_power = m_power; out->m_alpha = m_alpha; out->m_T = m_T;
@@ -509,9 +515,10 @@ static void blend_pixel(int px, int py, const uint32_t* list, int64_t len, int64
 
 static void store_pixel(const pixres* r, int64_t pix, int64_t npix, const double* bg,
                         double* out_rgb, double* out_T, uint32_t* n_contrib, double* margins,
-                        uint32_t* n_used) {
+                        uint32_t* n_used, double* out_invdepth) {
     int ch;
     if (n_used) n_used[pix] = r->nused;
+    if (out_invdepth) out_invdepth[pix] = r->D;
     for (ch = 0; ch < 3; ++ch) out_rgb[ch * npix + pix] = r->C[ch] + r->Tfinal * bg[ch];
     out_T[pix] = r->Tfinal;
     n_contrib[pix] = r->ncontrib;
@@ -529,7 +536,8 @@ int ora_blend_tiles(int W, int H, int64_t n, const uint32_t* ranges, const uint3
                     const double* rgb, const double* bg,
                     double* out_rgb /*[3][H][W]*/, double* out_T /*[H][W]*/,
                     uint32_t* n_contrib /*[H][W]*/, double* margins /*[3][H][W] or NULL*/,
-                    uint32_t* n_used /*[H][W] or NULL*/) {
+                    uint32_t* n_used /*[H][W] or NULL*/, const double* invd /*[n] or NULL*/,
+                    double* out_invdepth /*[H][W] or NULL*/) {
     const int tiles_x = (W + TILE - 1) / TILE;
     const int64_t npix = (int64_t)W * H;
     int64_t p;
@@ -539,9 +547,9 @@ int ora_blend_tiles(int W, int H, int64_t n, const uint32_t* ranges, const uint3
         const int t = (y / TILE) * tiles_x + x / TILE;
         const uint32_t s = ranges[2 * t], e = ranges[2 * t + 1];
         pixres r;
-        blend_pixel(x, y, point_list + s, (int64_t)e - s, n, mean2d, conic, opacity, rgb, &r,
+        blend_pixel(x, y, point_list + s, (int64_t)e - s, n, mean2d, conic, opacity, rgb, invd, &r,
                     NULL, NULL, NULL, NULL, NULL, NULL);
-        store_pixel(&r, p, npix, bg, out_rgb, out_T, n_contrib, margins, n_used);
+        store_pixel(&r, p, npix, bg, out_rgb, out_T, n_contrib, margins, n_used, out_invdepth);
     }
     return 0;
 }
@@ -566,7 +574,7 @@ int ora_blend_brute(int W, int H, int64_t n, const int32_t* radius, const int32_
                     const double* mean2d, const double* conic, const double* opacity,
                     const double* rgb, const double* bg,
                     double* out_rgb, double* out_T, uint32_t* n_contrib, double* margins,
-                    uint32_t* n_used) {
+                    uint32_t* n_used, const double* invd, double* out_invdepth) {
     const int64_t npix = (int64_t)W * H;
     int64_t i, nv = 0, p;
     di* order = (di*)malloc(sizeof(di) * (size_t)(n > 0 ? n : 1));
@@ -592,8 +600,9 @@ int ora_blend_brute(int W, int H, int64_t n, const int32_t* radius, const int32_
                 continue;
             list[len++] = g;
         }
-        blend_pixel(x, y, list, len, n, mean2d, conic, opacity, rgb, &r, NULL, NULL, NULL, NULL, NULL, NULL);
-        store_pixel(&r, p, npix, bg, out_rgb, out_T, n_contrib, margins, n_used);
+        blend_pixel(x, y, list, len, n, mean2d, conic, opacity, rgb, invd, &r, NULL, NULL, NULL, NULL, NULL,
+                    NULL);
+        store_pixel(&r, p, npix, bg, out_rgb, out_T, n_contrib, margins, n_used, out_invdepth);
         free(list);
     }
     free(sorted);
@@ -614,12 +623,18 @@ int ora_blend_brute(int W, int H, int64_t n, const int32_t* radius, const int32_
  *   d out / d rgb_i  = a_i T_i
  *   d out / d a_i    = T_i (rgb_i - S_i),  S_N = bg,  S_{i-1} = a_i rgb_i + (1 - a_i) S_i
  *   d a / d o        = G (0 if clamped),  d a / d power = a (0 if clamped)
+ * The expected inverse depth D = sum_i (1 / depth_i) a_i T_i is one more
+ * channel with background 0: given dL/dD (or NULL), d D / d a_i = T_i
+ * (1 / depth_i - S^D_i) and d D / d (1 / depth_i) = a_i T_i, into g_invd.
  */
 int ora_backward_2d(int W, int H, int64_t n, const uint32_t* ranges, const uint32_t* point_list,
                     const double* mean2d, const double* conic, const double* opacity,
                     const double* rgb, const double* bg, const double* dL_dout /*[3][H][W]*/,
                     double* g_mean2d /*[2][n]*/, double* g_conic /*[3][n]*/,
-                    double* g_opacity /*[n]*/, double* g_rgb /*[3][n]*/) {
+                    double* g_opacity /*[n]*/, double* g_rgb /*[3][n]*/,
+                    const double* invd /*[n] or NULL*/, const double* dL_dinvdepth /*[H][W] or NULL*/,
+                    double* g_invd /*[n] or NULL*/) {
+    const int depth_on = invd && dL_dinvdepth && g_invd;
     const int tiles_x = (W + TILE - 1) / TILE;
     const int64_t npix = (int64_t)W * H;
     int64_t p, maxlen = 0, t, ntiles = (int64_t)tiles_x * ((H + TILE - 1) / TILE);
@@ -630,6 +645,7 @@ int ora_backward_2d(int W, int H, int64_t n, const uint32_t* ranges, const uint3
     memset(g_conic, 0, sizeof(double) * 3 * (size_t)n);
     memset(g_opacity, 0, sizeof(double) * (size_t)n);
     memset(g_rgb, 0, sizeof(double) * 3 * (size_t)n);
+    if (g_invd) memset(g_invd, 0, sizeof(double) * (size_t)n);
     for (t = 0; t < ntiles; ++t) {
         int64_t len = (int64_t)ranges[2 * t + 1] - ranges[2 * t];
         if (len > maxlen) maxlen = len;
@@ -645,13 +661,14 @@ int ora_backward_2d(int W, int H, int64_t n, const uint32_t* ranges, const uint3
         const int tt = (y / TILE) * tiles_x + x / TILE;
         const uint32_t s = ranges[2 * tt], e = ranges[2 * tt + 1];
         const uint32_t* list = point_list + s;
-        double go[3], S[3];
+        double go[3], S[3], gd = 0.0, Sd = 0.0;
         int64_t nc = 0, k;
         int ch;
         pixres r;
-        blend_pixel(x, y, list, (int64_t)e - s, n, mean2d, conic, opacity, rgb, &r,
+        blend_pixel(x, y, list, (int64_t)e - s, n, mean2d, conic, opacity, rgb, NULL, &r,
                     c_pos, c_T, c_alpha, c_G, c_clamped, &nc);
         for (ch = 0; ch < 3; ++ch) { go[ch] = dL_dout[ch * npix + p]; S[ch] = bg[ch]; }
+        if (depth_on) gd = dL_dinvdepth[p];
         for (k = nc - 1; k >= 0; --k) {
             const uint32_t g = list[c_pos[k]];
             const double a = c_alpha[k], T = c_T[k], G = c_G[k];
@@ -663,6 +680,11 @@ int ora_backward_2d(int W, int H, int64_t n, const uint32_t* ranges, const uint3
                 g_rgb[ch * n + g] += a * T * go[ch];
                 dLda += T * (c - S[ch]) * go[ch];
                 S[ch] = a * c + (1.0 - a) * S[ch];
+            }
+            if (depth_on) {
+                g_invd[g] += a * T * gd;
+                dLda += T * (invd[g] - Sd) * gd;
+                Sd = a * invd[g] + (1.0 - a) * Sd;
             }
             if (!c_clamped[k]) {
                 const double dLdp = dLda * a;
@@ -692,7 +714,8 @@ int ora_backward_params(int64_t n, int degree,
                         const double* g_rgb,
                         double* g_means /*[3][n]*/, double* g_log_scales /*[3][n]*/,
                         double* g_quats /*[4][n]*/, double* g_opac_logits /*[n]*/,
-                        double* g_sh /*[(deg+1)^2][3][n]*/) {
+                        double* g_sh /*[(deg+1)^2][3][n]*/,
+                        const double* g_invd /*[n] or NULL: dL / d(1 / depth)*/) {
     const int nb = (degree + 1) * (degree + 1);
     const double* V = cam->view;
     const double Rc[9] = {V[0], V[1], V[2], V[4], V[5], V[6], V[8], V[9], V[10]};
@@ -806,6 +829,8 @@ int ora_backward_params(int64_t n, int degree,
             gt[1] += gmy * cam->fy / tz;
             gt[2] += -gmx * cam->fx * g.tcam[0] / (tz * tz) - gmy * cam->fy * g.tcam[1] / (tz * tz);
         }
+        /* 1 / depth with depth = t_cam z */
+        if (g_invd) gt[2] += -g_invd[i] / (g.tcam[2] * g.tcam[2]);
         /* t_cam = Rc m + t  ->  dL/dm += Rc^T dL/dt */
         for (c = 0; c < 3; ++c) gm[c] += Rc[c] * gt[0] + Rc[3 + c] * gt[1] + Rc[6 + c] * gt[2];
         for (c = 0; c < 3; ++c) g_means[c * n + i] = gm[c];

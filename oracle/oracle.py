@@ -66,10 +66,10 @@ def lib():
         L.ora_build_keys.argtypes = [i64, P, P, P, i32, P, P]
         L.ora_sort_keys.argtypes = [i64, P, P]
         L.ora_ranges.argtypes = [i64, P, i32, P]
-        L.ora_blend_tiles.argtypes = [i32, i32, i64, P, P, P, P, P, P, P, P, P, P, P, P]
-        L.ora_blend_brute.argtypes = [i32, i32, i64, P, P, P, i32, P, P, P, P, P, P, P, P, P, P]
-        L.ora_backward_2d.argtypes = [i32, i32, i64, P, P, P, P, P, P, P, P, P, P, P, P]
-        L.ora_backward_params.argtypes = [i64, i32, P, P, P, P, P, ctypes.POINTER(OraCamera)] + [P] * 9
+        L.ora_blend_tiles.argtypes = [i32, i32, i64, P, P, P, P, P, P, P, P, P, P, P, P, P, P]
+        L.ora_blend_brute.argtypes = [i32, i32, i64, P, P, P, i32, P, P, P, P, P, P, P, P, P, P, P, P]
+        L.ora_backward_2d.argtypes = [i32, i32, i64, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P]
+        L.ora_backward_params.argtypes = [i64, i32, P, P, P, P, P, ctypes.POINTER(OraCamera)] + [P] * 10
         L.ora_sh_basis.argtypes = [P, i64, i32, P]
         L.ora_sh_basis.restype = None
         for f in ("ora_build_keys", "ora_sort_keys", "ora_ranges", "ora_blend_tiles",
@@ -80,7 +80,7 @@ def lib():
 
 
 def _p(a):
-    return a.ctypes.data_as(ctypes.c_void_p)
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
 
 
 def _check(rc, what):
@@ -130,6 +130,7 @@ def project(scene, cam, round_f32=True):
                                                   "clamp_flags", "near_flags")])
     _check(rc, "project")
     out["n"] = n
+    out["round_f32"] = bool(round_f32)
     return out
 
 
@@ -163,7 +164,20 @@ def ranges(sorted_keys, width, height):
     return r
 
 
-def blend_tiles(proj, rng, point_list, cam):
+def inverse_depth(proj):
+    """1 / depth per Gaussian (0 where culled): the channel composited into
+    the expected inverse depth.  With the float32-rounded projection the depth
+    is rounded to float32 first, as the pipeline stores it."""
+    d = proj["depth"].astype(np.float32).astype(np.float64) if proj.get("round_f32") else proj["depth"]
+    vis = proj["radius"] > 0
+    out = np.zeros(proj["n"])
+    out[vis] = 1.0 / d[vis]
+    return out
+
+
+def blend_tiles(proj, rng, point_list, cam, invdepth=None):
+    """Tile-list blend; with `invdepth` (an [H, W] array) also the expected
+    inverse depth."""
     c = make_camera(cam)
     W, H, n = c.width, c.height, proj["n"]
     bg = np.array([c.bg[0], c.bg[1], c.bg[2]])
@@ -172,17 +186,19 @@ def blend_tiles(proj, rng, point_list, cam):
     nc = np.zeros((H, W), np.uint32)
     margins = np.zeros((3, H, W))
     used = np.zeros((H, W), np.uint32)
+    invd = inverse_depth(proj) if invdepth is not None else None
     _check(lib().ora_blend_tiles(W, H, n, _p(np.ascontiguousarray(rng, np.uint32)),
                                  _p(np.ascontiguousarray(point_list, np.uint32)),
                                  _p(proj["mean2d"]), _p(proj["conic"]), _p(proj["opacity"]),
                                  _p(proj["rgb"]), _p(bg), _p(img), _p(T), _p(nc), _p(margins),
-                                 _p(used)),
+                                 _p(used), _p(invd), _p(invdepth)),
            "blend_tiles")
     return img, T, nc, margins, used
 
 
-def blend_brute(proj, cam, tile_filter=True):
-    """Every pixel against every visible Gaussian in (depth, index) order."""
+def blend_brute(proj, cam, tile_filter=True, invdepth=None):
+    """Every pixel against every visible Gaussian in (depth, index) order;
+    with `invdepth` (an [H, W] array) also the expected inverse depth."""
     c = make_camera(cam)
     W, H, n = c.width, c.height, proj["n"]
     bg = np.array([c.bg[0], c.bg[1], c.bg[2]])
@@ -195,7 +211,8 @@ def blend_brute(proj, cam, tile_filter=True):
                                  _p(proj["depth_bits"]), int(bool(tile_filter)),
                                  _p(proj["mean2d"]), _p(proj["conic"]), _p(proj["opacity"]),
                                  _p(proj["rgb"]), _p(bg), _p(img), _p(T), _p(nc), _p(margins),
-                                 _p(used)),
+                                 _p(used), _p(inverse_depth(proj) if invdepth is not None else None),
+                                 _p(invdepth)),
            "blend_brute")
     return img, T, nc, margins, used
 
@@ -208,13 +225,16 @@ def render(scene, cam, round_f32=True):
     k0, v0 = keys_unsorted(proj, W)
     ks, vs = sort_keys(k0, v0)
     rg = ranges(ks, W, H)
-    img, T, nc, margins, used = blend_tiles(proj, rg, vs, cam)
+    invdepth = np.zeros((H, W))
+    img, T, nc, margins, used = blend_tiles(proj, rg, vs, cam, invdepth=invdepth)
     return dict(proj=proj, keys_unsorted=k0, vals_unsorted=v0, keys=ks, vals=vs, ranges=rg,
-                image=img, final_T=T, n_contrib=nc, margins=margins, n_used=used, K=int(ks.size))
+                image=img, final_T=T, n_contrib=nc, margins=margins, n_used=used, K=int(ks.size),
+                invdepth=invdepth)
 
 
-def backward(scene, cam, dL_dout, fwd=None, round_f32=True):
-    """Exact gradients of sum(dL_dout * image) w.r.t. every raw parameter."""
+def backward(scene, cam, dL_dout, fwd=None, round_f32=True, dL_dinvdepth=None):
+    """Exact gradients of sum(dL_dout * image) (+ sum(dL_dinvdepth *
+    invdepth)) w.r.t. every raw parameter."""
     n, deg, (means, ls, q, ol, sh) = _scene_arrays(scene)
     if fwd is None:
         fwd = render(scene, cam, round_f32)
@@ -225,10 +245,15 @@ def backward(scene, cam, dL_dout, fwd=None, round_f32=True):
     g2 = dict(mean2d=np.zeros((2, n)), conic=np.zeros((3, n)), opacity=np.zeros(n),
               rgb=np.zeros((3, n)))
     dl = np.ascontiguousarray(dL_dout, dtype=np.float64).reshape(3, H, W)
+    dld = invd = None
+    if dL_dinvdepth is not None:
+        dld = np.ascontiguousarray(dL_dinvdepth, dtype=np.float64).reshape(H, W)
+        invd = inverse_depth(proj)
+        g2["invdepth"] = np.zeros(n)
     _check(lib().ora_backward_2d(W, H, n, _p(fwd["ranges"]), _p(fwd["vals"]), _p(proj["mean2d"]),
                                  _p(proj["conic"]), _p(proj["opacity"]), _p(proj["rgb"]), _p(bg),
                                  _p(dl), _p(g2["mean2d"]), _p(g2["conic"]), _p(g2["opacity"]),
-                                 _p(g2["rgb"])), "backward_2d")
+                                 _p(g2["rgb"]), _p(invd), _p(dld), _p(g2.get("invdepth"))), "backward_2d")
     kb = (deg + 1) ** 2
     gp = dict(means=np.zeros((3, n)), log_scales=np.zeros((3, n)), quats=np.zeros((4, n)),
               opacity_logits=np.zeros(n), sh=np.zeros((kb, 3, n)))
@@ -236,7 +261,8 @@ def backward(scene, cam, dL_dout, fwd=None, round_f32=True):
                                      ctypes.byref(c), _p(g2["mean2d"]), _p(g2["conic"]),
                                      _p(g2["opacity"]), _p(g2["rgb"]), _p(gp["means"]),
                                      _p(gp["log_scales"]), _p(gp["quats"]),
-                                     _p(gp["opacity_logits"]), _p(gp["sh"])), "backward_params")
+                                     _p(gp["opacity_logits"]), _p(gp["sh"]), _p(g2.get("invdepth"))),
+           "backward_params")
     gp["grad2d"] = g2
     return gp
 
