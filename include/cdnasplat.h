@@ -167,6 +167,19 @@ cds_status cds_render_forward(cds_ctx* ctx, cds_frame* frame, const cds_scene* s
                               void* stream);
 
 /*
+ * cds_render_forward with the optional expected inverse depth of the
+ * Appendix B blend kernels (their `invdepth` output):
+ *   out_invdepth DEVICE float [H][W]  sum over the blended Gaussians of
+ *                                     alpha * T / depth (no background
+ *                                     term), or NULL for none
+ * Everything else as cds_render_forward.
+ */
+cds_status cds_render_forward_ex(cds_ctx* ctx, cds_frame* frame, const cds_scene* scene,
+                                 const cds_camera* cam, const cds_render_opts* opts,
+                                 float* out_rgb, float* out_T, uint32_t* out_ncontrib,
+                                 float* out_invdepth, void* stream);
+
+/*
  * Backward pass of the last forward render of `frame`: the exact derivative
  * of the forward with every discrete decision (culls, tile lists, skipped and
  * terminated blending steps, colour and alpha clamps, Jacobian guard band)
@@ -181,6 +194,21 @@ cds_status cds_render_backward(cds_ctx* ctx, cds_frame* frame, const cds_scene* 
                                const cds_camera* cam, const float* out_T,
                                const uint32_t* out_ncontrib, const float* dL_drgb,
                                const cds_scene_grad* grads, void* stream);
+
+/*
+ * cds_render_backward with a gradient for the expected inverse depth too:
+ *   dL_dinvdepth DEVICE float [H][W]  gradient of the loss w.r.t. the
+ *                                     out_invdepth of cds_render_forward_ex,
+ *                                     or NULL (then the same as
+ *                                     cds_render_backward)
+ * The inverse depth flows back through alpha (as a colour channel with no
+ * background) and through 1 / depth to the means.
+ */
+cds_status cds_render_backward_ex(cds_ctx* ctx, cds_frame* frame, const cds_scene* scene,
+                                  const cds_camera* cam, const float* out_T,
+                                  const uint32_t* out_ncontrib, const float* dL_drgb,
+                                  const float* dL_dinvdepth, const cds_scene_grad* grads,
+                                  void* stream);
 
 /* L1 image loss helper: dL_drgb[i] = sign(rgb[i] - target[i]) / count and,
  * if loss_out is not NULL, loss_out[0] = mean |rgb - target| (DEVICE float,

@@ -22,6 +22,10 @@
 //
 // Tiles are assigned in XCD-contiguous bands so neighbouring tiles, which
 // share most of their splats, hit the same L2.
+//
+// Optional expected inverse depth (the inverse-depth output of the paper's
+// Appendix B kernels): 1 / depth of every splat composited like one more
+// colour channel with no background (kDepth, staged per splat in s_d).
 #include "device_utils.h"
 #include "internal.h"
 
@@ -112,14 +116,16 @@ __device__ __forceinline__ bool splat_alpha(double adx2, double bdx, double c2, 
 // each pixel front to back.  Shared by the single-render kernel and the
 // persistent batched kernel so a request renders bit-identically in both.
 // Every thread of the workgroup must call it (it contains barriers).
-template <int PPT>
+template <int PPT, bool kDepth = false>
 __device__ __forceinline__ void blend_tile(int tx, int ty, int width, int height, uint2 range,
                                            const uint32_t* __restrict__ point_list,
                                            const float2* __restrict__ mean2d,
                                            const float4* __restrict__ conic_opacity,
                                            const float4* __restrict__ rgb, float bg0, float bg1, float bg2,
                                            float* out_rgb, float* out_T, uint32_t* out_ncontrib, double4* s_q,
-                                           double* s_c, float4* s_f, uint32_t* s_b) {
+                                           double* s_c, float4* s_f, uint32_t* s_b,
+                                           const uint32_t* __restrict__ depth_bits = nullptr,
+                                           float* out_invdepth = nullptr, float* s_d = nullptr) {
     constexpr int NT = 256 / PPT;
     constexpr int kRowsPerWave = kWave / kTile * PPT;
     const int t = threadIdx.x;
@@ -130,14 +136,14 @@ __device__ __forceinline__ void blend_tile(int tx, int ty, int width, int height
     // this wave's pixels: 16 columns, tile rows [wr0, wr0 + kRowsPerWave)
     const int wr0 = (t / kWave) * kRowsPerWave;
 
-    float T[PPT], C0[PPT], C1[PPT], C2[PPT];
+    float T[PPT], C0[PPT], C1[PPT], C2[PPT], D[PPT];
     double fpy[PPT];
     uint32_t last[PPT];
     bool done[PPT];
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
         T[p] = 1.0f;
-        C0[p] = C1[p] = C2[p] = 0.0f;
+        C0[p] = C1[p] = C2[p] = D[p] = 0.0f;
         last[p] = 0;
         fpy[p] = (double)(py0 + p);
         done[p] = !(px < width && py0 + p < height);
@@ -151,9 +157,11 @@ __device__ __forceinline__ void blend_tile(int tx, int ty, int width, int height
         if (__syncthreads_count(alive) == 0) break;
         for (int k = t; k < kBatch; k += NT) {
             const int idx = base + k;
-            if (idx < todo)
-                stage_splat(mean2d, conic_opacity, rgb, point_list[range.x + idx], s_q, s_c, s_f, s_b, k,
-                            tx * kTile, ty * kTile);
+            if (idx < todo) {
+                const uint32_t id = point_list[range.x + idx];
+                stage_splat(mean2d, conic_opacity, rgb, id, s_q, s_c, s_f, s_b, k, tx * kTile, ty * kTile);
+                if constexpr (kDepth) s_d[k] = 1.0f / __uint_as_float(depth_bits[id]);
+            }
         }
         __syncthreads();
         const int cnt = min(kBatch, todo - base);
@@ -201,6 +209,7 @@ __device__ __forceinline__ void blend_tile(int tx, int ty, int width, int height
                         C0[p] = fmaf(f.y, wgt, C0[p]);
                         C1[p] = fmaf(f.z, wgt, C1[p]);
                         C2[p] = fmaf(f.w, wgt, C2[p]);
+                        if constexpr (kDepth) D[p] = fmaf(s_d[j], wgt, D[p]);
                         T[p] = test_T;
                         last[p] = (uint32_t)(base + j + 1);
                     }
@@ -221,21 +230,24 @@ __device__ __forceinline__ void blend_tile(int tx, int ty, int width, int height
             out_rgb[pix] = fmaf(T[p], bg0, C0[p]);
             out_rgb[npix + pix] = fmaf(T[p], bg1, C1[p]);
             out_rgb[2 * npix + pix] = fmaf(T[p], bg2, C2[p]);
+            if constexpr (kDepth) out_invdepth[pix] = D[p];
         }
     }
 }
 
-template <int PPT>
+template <int PPT, bool kDepth>
 __global__ __launch_bounds__(256 / PPT) void k_blend(BlendArgs a, uint32_t per_xcd) {
     __shared__ double4 s_q[kBatch];
     __shared__ double s_c[kBatch];
     __shared__ float4 s_f[kBatch];
     __shared__ uint32_t s_b[kBatch];
+    __shared__ float s_d[kDepth ? kBatch : 1];
     const uint32_t tile = xcd_band(blockIdx.x, per_xcd);
     if (tile >= (uint32_t)(a.tiles_x * a.tiles_y)) return;  // whole block: padding
     const int tx = (int)(tile % (uint32_t)a.tiles_x), ty = (int)(tile / (uint32_t)a.tiles_x);
-    blend_tile<PPT>(tx, ty, a.width, a.height, a.ranges[tile], a.point_list, a.mean2d, a.conic_opacity, a.rgb,
-                    a.bg[0], a.bg[1], a.bg[2], a.out_rgb, a.out_T, a.out_ncontrib, s_q, s_c, s_f, s_b);
+    blend_tile<PPT, kDepth>(tx, ty, a.width, a.height, a.ranges[tile], a.point_list, a.mean2d, a.conic_opacity,
+                            a.rgb, a.bg[0], a.bg[1], a.bg[2], a.out_rgb, a.out_T, a.out_ncontrib, s_q, s_c, s_f,
+                            s_b, a.depth_bits, a.out_invdepth, s_d);
 }
 
 // Persistent blend over every tile of a batch of renders: each workgroup
@@ -280,7 +292,7 @@ __global__ __launch_bounds__(256 / PPT) void k_blend_batch(const BatchItem* __re
 // added to the per-Gaussian 2D gradients ([n][9]) with atomics.  A wave
 // visits only the splats whose box meets its pixels (as in the forward
 // pass): the others contribute nothing.
-template <int PPT>
+template <int PPT, bool kDepth>
 __global__ __launch_bounds__(256 / PPT) void k_blend_bwd(BlendBwdArgs a, uint32_t per_xcd) {
     constexpr int NT = 256 / PPT;
     constexpr int kRowsPerWave = kWave / kTile * PPT;
@@ -289,6 +301,7 @@ __global__ __launch_bounds__(256 / PPT) void k_blend_bwd(BlendBwdArgs a, uint32_
     __shared__ float4 s_f[kBatch];
     __shared__ uint32_t s_b[kBatch];
     __shared__ uint32_t s_id[kBatch];
+    __shared__ float s_d[kDepth ? kBatch : 1];
     __shared__ uint32_t s_max;
 
     const uint32_t tile = xcd_band(blockIdx.x, per_xcd);
@@ -301,7 +314,7 @@ __global__ __launch_bounds__(256 / PPT) void k_blend_bwd(BlendBwdArgs a, uint32_
     const int64_t npix = (int64_t)a.width * a.height;
     const int wr0 = (t / kWave) * kRowsPerWave;  // this wave's first tile row
 
-    float T[PPT], S0[PPT], S1[PPT], S2[PPT], D0[PPT], D1[PPT], D2[PPT];
+    float T[PPT], S0[PPT], S1[PPT], S2[PPT], D0[PPT], D1[PPT], D2[PPT], Sd[PPT], Dd[PPT];
     double fpy[PPT];
     uint32_t last[PPT];
     uint32_t mylast = 0;
@@ -312,6 +325,7 @@ __global__ __launch_bounds__(256 / PPT) void k_blend_bwd(BlendBwdArgs a, uint32_
         S0[p] = a.bg[0];
         S1[p] = a.bg[1];
         S2[p] = a.bg[2];
+        Sd[p] = 0.0f;  // inverse depth behind: no background term
         if (px < a.width && py < a.height) {
             const int64_t pix = (int64_t)py * a.width + px;
             T[p] = a.final_T[pix];
@@ -319,10 +333,11 @@ __global__ __launch_bounds__(256 / PPT) void k_blend_bwd(BlendBwdArgs a, uint32_
             D0[p] = a.dL_drgb[pix];
             D1[p] = a.dL_drgb[npix + pix];
             D2[p] = a.dL_drgb[2 * npix + pix];
+            Dd[p] = kDepth ? a.dL_dinvdepth[pix] : 0.0f;
         } else {
             T[p] = 1.0f;
             last[p] = 0;
-            D0[p] = D1[p] = D2[p] = 0.0f;
+            D0[p] = D1[p] = D2[p] = Dd[p] = 0.0f;
         }
         mylast = last[p] > mylast ? last[p] : mylast;
     }
@@ -344,6 +359,7 @@ __global__ __launch_bounds__(256 / PPT) void k_blend_bwd(BlendBwdArgs a, uint32_
             const uint32_t id = a.point_list[range.x + begin + k];
             s_id[k] = id;
             stage_splat(a.mean2d, a.conic_opacity, a.rgb, id, s_q, s_c, s_f, s_b, k, tx * kTile, ty * kTile);
+            if constexpr (kDepth) s_d[k] = 1.0f / __uint_as_float(a.depth_bits[id]);
         }
         __syncthreads();
         const int cnt = end - begin;
@@ -368,7 +384,8 @@ __global__ __launch_bounds__(256 / PPT) void k_blend_bwd(BlendBwdArgs a, uint32_
             const double bdx = q.w * dx;
             const float dxf = (float)dx;
             float gmx = 0.f, gmy = 0.f, gA = 0.f, gB = 0.f, gC = 0.f, go = 0.f, gr = 0.f, gg = 0.f,
-                  gb = 0.f;
+                  gb = 0.f, gd = 0.f;
+            const float invd = kDepth ? s_d[k] : 0.0f;
             bool any = false;
 #pragma unroll
             for (int p = 0; p < PPT; ++p) {
@@ -381,8 +398,8 @@ __global__ __launch_bounds__(256 / PPT) void k_blend_bwd(BlendBwdArgs a, uint32_
                 const float one_m = 1.0f - alpha;
                 T[p] = T[p] * __builtin_amdgcn_rcpf(one_m);  // 1 ulp; alpha <= 0.99
                 const float Tp = T[p];
-                const float dLda = Tp * ((f.y - S0[p]) * D0[p] + (f.z - S1[p]) * D1[p] +
-                                         (f.w - S2[p]) * D2[p]);
+                float dLda = Tp * ((f.y - S0[p]) * D0[p] + (f.z - S1[p]) * D1[p] +
+                                   (f.w - S2[p]) * D2[p]);
                 S0[p] = alpha * f.y + one_m * S0[p];
                 S1[p] = alpha * f.z + one_m * S1[p];
                 S2[p] = alpha * f.w + one_m * S2[p];
@@ -390,6 +407,11 @@ __global__ __launch_bounds__(256 / PPT) void k_blend_bwd(BlendBwdArgs a, uint32_
                 gr += wgt * D0[p];
                 gg += wgt * D1[p];
                 gb += wgt * D2[p];
+                if constexpr (kDepth) {
+                    dLda += Tp * (invd - Sd[p]) * Dd[p];
+                    Sd[p] = alpha * invd + one_m * Sd[p];
+                    gd += wgt * Dd[p];
+                }
                 if (!(f.x * G > kAlphaMax)) {
                     go += dLda * G;
                     const float dLdp = dLda * alpha;
@@ -409,9 +431,13 @@ __global__ __launch_bounds__(256 / PPT) void k_blend_bwd(BlendBwdArgs a, uint32_
                 const float s8 = wave_reduce_scatter8(v8);
                 const float sb = wave_sum(gb);
                 const uint32_t l = lane_id();
-                float* g = a.grad2d + (size_t)s_id[k] * 9;
+                float* g = a.grad2d + (size_t)s_id[k] * kGrad2d;
                 if ((l & 7u) == 0) atomicAdd(g + (l >> 3), s8);
                 if (l == 0) atomicAdd(g + 8, sb);
+                if constexpr (kDepth) {
+                    const float sd = wave_sum(gd);
+                    if (l == 0) atomicAdd(g + 9, sd);
+                }
             }
             }
         }
@@ -465,10 +491,21 @@ hipError_t launch_blend(const BlendArgs& a, int variant, hipStream_t stream) {
     if (tiles == 0) return hipSuccess;
     const uint32_t per = xcd_per(tiles);
     const dim3 grid(8 * per);
+    const bool depth = a.out_invdepth != nullptr;
+    if (depth && !a.depth_bits) return hipErrorInvalidValue;
     switch (variant) {
-        case 1: hipLaunchKernelGGL(k_blend<1>, grid, dim3(256), 0, stream, a, per); break;
-        case 4: hipLaunchKernelGGL(k_blend<4>, grid, dim3(64), 0, stream, a, per); break;
-        default: hipLaunchKernelGGL(k_blend<2>, grid, dim3(128), 0, stream, a, per); break;
+        case 1:
+            if (depth) hipLaunchKernelGGL((k_blend<1, true>), grid, dim3(256), 0, stream, a, per);
+            else hipLaunchKernelGGL((k_blend<1, false>), grid, dim3(256), 0, stream, a, per);
+            break;
+        case 4:
+            if (depth) hipLaunchKernelGGL((k_blend<4, true>), grid, dim3(64), 0, stream, a, per);
+            else hipLaunchKernelGGL((k_blend<4, false>), grid, dim3(64), 0, stream, a, per);
+            break;
+        default:
+            if (depth) hipLaunchKernelGGL((k_blend<2, true>), grid, dim3(128), 0, stream, a, per);
+            else hipLaunchKernelGGL((k_blend<2, false>), grid, dim3(128), 0, stream, a, per);
+            break;
     }
     return hipGetLastError();
 }
@@ -488,7 +525,12 @@ hipError_t launch_blend_backward(const BlendBwdArgs& a, hipStream_t stream) {
     const int64_t tiles = (int64_t)a.tiles_x * a.tiles_y;
     if (tiles == 0) return hipSuccess;
     const uint32_t per = xcd_per(tiles);
-    hipLaunchKernelGGL(k_blend_bwd<2>, dim3(8 * per), dim3(128), 0, stream, a, per);
+    if (a.dL_dinvdepth) {
+        if (!a.depth_bits) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_blend_bwd<2, true>), dim3(8 * per), dim3(128), 0, stream, a, per);
+    } else {
+        hipLaunchKernelGGL((k_blend_bwd<2, false>), dim3(8 * per), dim3(128), 0, stream, a, per);
+    }
     return hipGetLastError();
 }
 

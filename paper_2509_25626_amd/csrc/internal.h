@@ -303,6 +303,8 @@ struct BlendArgs {
     float* out_rgb;
     float* out_T;
     uint32_t* out_ncontrib;
+    const uint32_t* depth_bits;  // float32 bits of each Gaussian's depth (read with out_invdepth)
+    float* out_invdepth;         // [H][W] expected inverse depth, or null
 };
 hipError_t launch_blend(const BlendArgs& a, int variant, hipStream_t stream);
 
@@ -311,6 +313,10 @@ hipError_t launch_blend(const BlendArgs& a, int variant, hipStream_t stream);
 hipError_t launch_blend_batch(const BatchItem* items, int nitems, int64_t total_tiles, const uint2* ranges,
                               const uint32_t* point_list, const float2* mean2d, const float4* conic_opacity,
                               const float4* rgb, uint32_t* counter, int grid, hipStream_t stream);
+
+// Per-Gaussian 2D gradients of the backward pass, one row per Gaussian:
+// mean x, mean y, conic A, B, C, opacity, r, g, b, 1 / depth.
+constexpr int kGrad2d = 10;
 
 struct BlendBwdArgs {
     const uint2* ranges;
@@ -323,15 +329,17 @@ struct BlendBwdArgs {
     const float* final_T;
     const uint32_t* ncontrib;
     const float* dL_drgb;
+    const uint32_t* depth_bits;  // float32 bits of each Gaussian's depth (read with dL_dinvdepth)
+    const float* dL_dinvdepth;   // [H][W] gradient w.r.t. the expected inverse depth, or null
     int64_t n;
-    float* grad2d;  // [n][9] (mean x, mean y, conic A, B, C, opacity, r, g, b), zero on entry
+    float* grad2d;  // [n][kGrad2d], zero on entry
 };
 hipError_t launch_blend_backward(const BlendBwdArgs& a, hipStream_t stream);
 
 struct PreBwdArgs {
     const int32_t* radius;
     const uint8_t* clamp_flags;
-    const float* grad2d;  // [n][9]
+    const float* grad2d;  // [n][kGrad2d]
     float* g_means;
     float* g_log_scales;
     float* g_quats;

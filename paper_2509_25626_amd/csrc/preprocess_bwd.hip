@@ -71,11 +71,12 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(ProjParams P, SceneParam
     }
     auto put = [live](float* dst, double v) { *dst = live ? (float)v : 0.0f; };
     const uint8_t flags = A.clamp_flags[i];
-    const float* G2 = A.grad2d + (size_t)i * 9;
+    const float* G2 = A.grad2d + (size_t)i * kGrad2d;
     const double gmx = G2[0], gmy = G2[1];
     const double gA = G2[2], gB = G2[3], gC = G2[4];
     const double go = G2[5];
     double grgb[3] = {G2[6], G2[7], G2[8]};
+    const double ginvd = G2[9];  // dL / d(1 / depth), depth = t_cam z
 
     // ---- recompute the forward projection (float64)
     const double m0 = S.means[i], m1 = S.means[n + i], m2 = S.means[2 * n + i];
@@ -150,6 +151,8 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(ProjParams P, SceneParam
     gt0 += gmx * P.fx * itz;
     gt1 += gmy * P.fy * itz;
     gt2 += -gmx * P.fx * tx * itz2 - gmy * P.fy * ty * itz2;
+    // expected inverse depth
+    gt2 += -ginvd * itz2;
 
     // ---- Sigma = Rq diag(s2) Rq^T
     double GR[9];  // gSig Rq

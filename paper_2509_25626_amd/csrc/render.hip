@@ -77,7 +77,7 @@ int tile_bits_for(int64_t ntiles) {
  */
 cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scene, const cds_camera* cam,
                                int blend_variant, int sort_variant, SortAlgo algo, float* out_rgb, float* out_T,
-                               uint32_t* out_ncontrib, hipStream_t stream) {
+                               uint32_t* out_ncontrib, float* out_invdepth, hipStream_t stream) {
     const int64_t n = scene->n;
     f->timed_backward = false;
     CDS_TRY(f->record(kEvStart, stream));
@@ -345,6 +345,8 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
     ba.out_rgb = out_rgb;
     ba.out_T = out_T;
     ba.out_ncontrib = out_ncontrib;
+    ba.depth_bits = sb.depth_bits;
+    ba.out_invdepth = out_invdepth;
     CDS_HIP(launch_blend(ba, blend_variant, stream), "blend kernel");
     CDS_TRY(f->record(kEvBlend, stream));
     f->valid = true;
@@ -370,13 +372,13 @@ cds_status frame_build_keys(cds_frame* f) {
 
 cds_status render_backward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scene, const cds_camera* cam,
                                 const float* out_T, const uint32_t* out_ncontrib, const float* dL_drgb,
-                                const cds_scene_grad* g, hipStream_t stream) {
+                                const float* dL_dinvdepth, const cds_scene_grad* g, hipStream_t stream) {
     const int64_t n = scene->n;
     if (n == 0) return CDS_OK;
     const ProjParams P = make_proj(scene, cam);
-    CDS_TRY(ensure(ctx, f->grad2d, sizeof(float) * 9 * (size_t)n, 1.1));
+    CDS_TRY(ensure(ctx, f->grad2d, sizeof(float) * kGrad2d * (size_t)n, 1.1));
     CDS_TRY(f->record(kEvBwdStart, stream));
-    CDS_HIP(launch_fill_u32((uint32_t*)f->grad2d.p, 9 * n, 0u, stream), "fill");
+    CDS_HIP(launch_fill_u32((uint32_t*)f->grad2d.p, kGrad2d * n, 0u, stream), "fill");
     BlendBwdArgs b;
     b.ranges = (const uint2*)f->ranges.p;
     b.point_list = f->res_values;
@@ -391,6 +393,8 @@ cds_status render_backward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* sce
     b.final_T = out_T;
     b.ncontrib = out_ncontrib;
     b.dL_drgb = dL_drgb;
+    b.depth_bits = (const uint32_t*)f->depth.p;
+    b.dL_dinvdepth = dL_dinvdepth;
     b.n = n;
     b.grad2d = (float*)f->grad2d.p;
     CDS_HIP(launch_blend_backward(b, stream), "blend backward kernel");

@@ -238,9 +238,9 @@ void cds_frame_release(cds_frame* f) {
     delete f;
 }
 
-cds_status cds_render_forward(cds_ctx* ctx, cds_frame* f, const cds_scene* scene, const cds_camera* cam,
-                              const cds_render_opts* opts, float* out_rgb, float* out_T,
-                              uint32_t* out_ncontrib, void* stream_) {
+cds_status cds_render_forward_ex(cds_ctx* ctx, cds_frame* f, const cds_scene* scene, const cds_camera* cam,
+                                 const cds_render_opts* opts, float* out_rgb, float* out_T,
+                                 uint32_t* out_ncontrib, float* out_invdepth, void* stream_) {
     if (!ctx || !f) return fail(CDS_ERR_INVALID_ARG, "context or frame is NULL");
     if (f->ctx != ctx) return fail(CDS_ERR_INVALID_ARG, "frame belongs to another context");
     cds_status st;
@@ -270,12 +270,18 @@ cds_status cds_render_forward(cds_ctx* ctx, cds_frame* f, const cds_scene* scene
     f->valid = false;
     f->timing = timing;
     return render_forward_impl(ctx, f, scene, cam, variant, sort_variant, algo, out_rgb, out_T, out_ncontrib,
-                               stream);
+                               out_invdepth, stream);
 }
 
-cds_status cds_render_backward(cds_ctx* ctx, cds_frame* f, const cds_scene* scene, const cds_camera* cam,
-                               const float* out_T, const uint32_t* out_ncontrib, const float* dL_drgb,
-                               const cds_scene_grad* g, void* stream_) {
+cds_status cds_render_forward(cds_ctx* ctx, cds_frame* f, const cds_scene* scene, const cds_camera* cam,
+                              const cds_render_opts* opts, float* out_rgb, float* out_T,
+                              uint32_t* out_ncontrib, void* stream) {
+    return cds_render_forward_ex(ctx, f, scene, cam, opts, out_rgb, out_T, out_ncontrib, nullptr, stream);
+}
+
+cds_status cds_render_backward_ex(cds_ctx* ctx, cds_frame* f, const cds_scene* scene, const cds_camera* cam,
+                                  const float* out_T, const uint32_t* out_ncontrib, const float* dL_drgb,
+                                  const float* dL_dinvdepth, const cds_scene_grad* g, void* stream_) {
     if (!ctx || !f || f->ctx != ctx) return fail(CDS_ERR_INVALID_ARG, "bad context or frame");
     cds_status st;
     if ((st = validate_scene(scene)) != CDS_OK) return st;
@@ -289,7 +295,13 @@ cds_status cds_render_backward(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
     hipStream_t stream = (hipStream_t)stream_;
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-    return render_backward_impl(ctx, f, scene, cam, out_T, out_ncontrib, dL_drgb, g, stream);
+    return render_backward_impl(ctx, f, scene, cam, out_T, out_ncontrib, dL_drgb, dL_dinvdepth, g, stream);
+}
+
+cds_status cds_render_backward(cds_ctx* ctx, cds_frame* f, const cds_scene* scene, const cds_camera* cam,
+                               const float* out_T, const uint32_t* out_ncontrib, const float* dL_drgb,
+                               const cds_scene_grad* g, void* stream) {
+    return cds_render_backward_ex(ctx, f, scene, cam, out_T, out_ncontrib, dL_drgb, nullptr, g, stream);
 }
 
 cds_status cds_l1_loss_grad(cds_ctx* ctx, const float* rgb, const float* target, int64_t count,

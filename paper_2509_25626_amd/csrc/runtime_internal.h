@@ -105,12 +105,12 @@ SortWorkspace sort_ws(cds_ctx* ctx, SortState& s);
 
 cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scene, const cds_camera* cam,
                                int blend_variant, int sort_variant, SortAlgo algo, float* out_rgb, float* out_T,
-                               uint32_t* out_ncontrib, hipStream_t stream);
+                               uint32_t* out_ncontrib, float* out_invdepth, hipStream_t stream);
 SortAlgo sort_algo_from_flags(uint32_t flags);
 int tile_bits_for(int64_t ntiles);
 cds_status frame_build_keys(cds_frame* f);
 cds_status render_backward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scene, const cds_camera* cam,
                                 const float* out_T, const uint32_t* out_ncontrib, const float* dL_drgb,
-                                const cds_scene_grad* g, hipStream_t stream);
+                                const float* dL_dinvdepth, const cds_scene_grad* g, hipStream_t stream);
 
 }  // namespace cds

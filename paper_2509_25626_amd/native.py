@@ -98,6 +98,10 @@ SIGNATURES = {
                                           ctypes.POINTER(CdsRenderOpts), P, P, P, P]),
     "cds_render_backward": (ctypes.c_int, [P, P, ctypes.POINTER(CdsScene), ctypes.POINTER(CdsCamera),
                                            P, P, P, ctypes.POINTER(CdsSceneGrad), P]),
+    "cds_render_forward_ex": (ctypes.c_int, [P, P, ctypes.POINTER(CdsScene), ctypes.POINTER(CdsCamera),
+                                             ctypes.POINTER(CdsRenderOpts), P, P, P, P, P]),
+    "cds_render_backward_ex": (ctypes.c_int, [P, P, ctypes.POINTER(CdsScene), ctypes.POINTER(CdsCamera),
+                                              P, P, P, P, ctypes.POINTER(CdsSceneGrad), P]),
     "cds_l1_loss_grad": (ctypes.c_int, [P, P, P, ctypes.c_int64, P, P, P]),
     "cds_frame_get_info": (ctypes.c_int, [P, ctypes.POINTER(CdsFrameInfo)]),
     "cds_frame_stage_times": (ctypes.c_int, [P, ctypes.POINTER(CdsStageTimes)]),

@@ -207,8 +207,11 @@ class Renderer:
         self._pool.append(frame)
 
     def forward(self, scene: GaussianScene, cam, frame: Frame | None = None, blend_variant: int = 0,
-                out=None, timing: bool = False, sort_variant: int = 0, sort_algo: str = "auto"):
-        """Render; returns (rgb [3,H,W], final_T [H,W], n_contrib [H,W] int32 view of uint32, frame)."""
+                out=None, timing: bool = False, sort_variant: int = 0, sort_algo: str = "auto",
+                invdepth=None):
+        """Render; returns (rgb [3,H,W], final_T [H,W], n_contrib [H,W] int32 view of uint32, frame).
+        With `invdepth` (True, or an [H,W] float32 tensor to fill) the expected
+        inverse depth is rendered too and returned as a fifth element."""
         cs = native.camera_struct(cam)
         H, W = cs.height, cs.width
         if out is None:
@@ -221,13 +224,21 @@ class Renderer:
         flags = (native.CDS_OPT_STAGE_TIMING if timing else 0) | _sort_flag(sort_algo)
         opts = native.CdsRenderOpts(flags, int(blend_variant), int(sort_variant), 0)
         sst = scene.struct()
-        check(self.L.cds_render_forward(self.handle, frame.handle, ctypes.byref(sst), ctypes.byref(cs),
-                                        ctypes.byref(opts), rgb.data_ptr(), T.data_ptr(), nc.data_ptr(),
-                                        _stream_handle(self.device)))
-        return rgb, T, nc, frame
+        if invdepth is None:
+            check(self.L.cds_render_forward(self.handle, frame.handle, ctypes.byref(sst), ctypes.byref(cs),
+                                            ctypes.byref(opts), rgb.data_ptr(), T.data_ptr(), nc.data_ptr(),
+                                            _stream_handle(self.device)))
+            return rgb, T, nc, frame
+        if invdepth is True:
+            invdepth = torch.empty((H, W), dtype=torch.float32, device=self.device)
+        check(self.L.cds_render_forward_ex(self.handle, frame.handle, ctypes.byref(sst), ctypes.byref(cs),
+                                           ctypes.byref(opts), rgb.data_ptr(), T.data_ptr(), nc.data_ptr(),
+                                           invdepth.data_ptr(), _stream_handle(self.device)))
+        return rgb, T, nc, frame, invdepth
 
-    def backward(self, frame: Frame, scene: GaussianScene, cam, T, nc, dL_drgb, grads=None):
-        """Gradients of the last forward render of `frame`; returns a dict of tensors."""
+    def backward(self, frame: Frame, scene: GaussianScene, cam, T, nc, dL_drgb, grads=None, dL_dinvdepth=None):
+        """Gradients of the last forward render of `frame` (and of its inverse
+        depth, with `dL_dinvdepth` [H,W]); returns a dict of tensors."""
         cs = native.camera_struct(cam)
         if grads is None:
             grads = {k: torch.empty_like(getattr(scene, k))
@@ -236,9 +247,15 @@ class Renderer:
                                   ("means", "log_scales", "quats", "opacity_logits", "sh")))
         dl = dL_drgb.contiguous()
         sst = scene.struct()
-        check(self.L.cds_render_backward(self.handle, frame.handle, ctypes.byref(sst), ctypes.byref(cs),
-                                         T.data_ptr(), nc.data_ptr(), dl.data_ptr(), ctypes.byref(g),
-                                         _stream_handle(self.device)))
+        if dL_dinvdepth is None:
+            check(self.L.cds_render_backward(self.handle, frame.handle, ctypes.byref(sst), ctypes.byref(cs),
+                                             T.data_ptr(), nc.data_ptr(), dl.data_ptr(), ctypes.byref(g),
+                                             _stream_handle(self.device)))
+        else:
+            dd = dL_dinvdepth.contiguous()
+            check(self.L.cds_render_backward_ex(self.handle, frame.handle, ctypes.byref(sst), ctypes.byref(cs),
+                                                T.data_ptr(), nc.data_ptr(), dl.data_ptr(), dd.data_ptr(),
+                                                ctypes.byref(g), _stream_handle(self.device)))
         return grads
 
     def l1_loss_grad(self, rgb, target, grad=None, loss=None):
@@ -285,6 +302,32 @@ class RenderFn(torch.autograd.Function):
     def backward(ctx, grad_rgb):
         T, nc = ctx.saved_tensors
         g = ctx.renderer.backward(ctx.frame, ctx.scene, ctx.cam, T, nc, grad_rgb)
+        ctx.renderer.release_frame(ctx.frame)
+        ctx.frame = None
+        return (None, None, g["means"], g["log_scales"], g["quats"], g["opacity_logits"], g["sh"])
+
+
+class RenderDepthFn(torch.autograd.Function):
+    """Differentiable render with the expected inverse depth: (image, invdepth) =
+    RenderDepthFn.apply(renderer, cam, means, log_scales, quats, opacity_logits, sh)."""
+
+    @staticmethod
+    def forward(ctx, renderer, cam, means, log_scales, quats, opacity_logits, sh):
+        scene = GaussianScene(means.detach(), log_scales.detach(), quats.detach(),
+                              opacity_logits.detach(), sh.detach())
+        rgb, T, nc, frame, invd = renderer.forward(scene, cam, invdepth=True)
+        ctx.renderer, ctx.cam, ctx.scene, ctx.frame = renderer, cam, scene, frame
+        ctx.save_for_backward(T, nc)
+        return rgb, invd
+
+    @staticmethod
+    def backward(ctx, grad_rgb, grad_invdepth):
+        T, nc = ctx.saved_tensors
+        if grad_rgb is None:
+            grad_rgb = torch.zeros((3,) + tuple(T.shape), dtype=torch.float32, device=T.device)
+        if grad_invdepth is None:
+            grad_invdepth = torch.zeros_like(T)
+        g = ctx.renderer.backward(ctx.frame, ctx.scene, ctx.cam, T, nc, grad_rgb, dL_dinvdepth=grad_invdepth)
         ctx.renderer.release_frame(ctx.frame)
         ctx.frame = None
         return (None, None, g["means"], g["log_scales"], g["quats"], g["opacity_logits"], g["sh"])

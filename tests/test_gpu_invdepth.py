@@ -1,0 +1,84 @@
+"""Expected inverse depth (the optional output of the paper's Appendix B blend
+kernels) and its gradient: GPU against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2509_25626_amd import scenes as S
+from tests.test_gpu_parity import R, flip_mask, IMG_TOL  # noqa: F401  (fixture)
+
+pytestmark = pytest.mark.gpu
+
+
+def _forward(R, scene, cam, variant=0):
+    from paper_2509_25626_amd.render import GaussianScene
+    gs = GaussianScene.from_numpy(scene)
+    rgb, T, nc, frame, invd = R.forward(gs, cam, blend_variant=variant, invdepth=True)
+    rgb0, T0, nc0, frame0 = R.forward(gs, cam, blend_variant=variant)
+    torch.cuda.synchronize()
+    R.check_device()
+    out = dict(image=rgb.cpu().numpy(), final_T=T.cpu().numpy(), n_contrib=nc.cpu().numpy().view(np.uint32),
+               invdepth=invd.cpu().numpy(), image0=rgb0.cpu().numpy(), final_T0=T0.cpu().numpy(),
+               n_contrib0=nc0.cpu().numpy().view(np.uint32))
+    R.release_frame(frame)
+    R.release_frame(frame0)
+    return out
+
+
+@pytest.mark.parametrize("cfg,variant", [("c1", 0), ("c1", 1), ("c1", 4), ("outdoor", 0)])
+def test_inverse_depth_matches_oracle(R, cfg, variant):
+    if cfg == "c1":
+        scene, cam = S.config_scene("c1")
+    else:
+        scene = S.scene_outdoor(14, 6000)
+        cam = S.orbit_camera(203, 117, 4.0, 40.0, -5.0)
+    g = _forward(R, scene, cam, variant)
+    o = O.render(scene, cam, round_f32=True)
+    # asking for the inverse depth leaves the other outputs bit for bit
+    assert np.array_equal(g["image"], g["image0"])
+    assert np.array_equal(g["final_T"], g["final_T0"])
+    assert np.array_equal(g["n_contrib"], g["n_contrib0"])
+    good = ~flip_mask(o)
+    err = np.abs(g["invdepth"] - o["invdepth"])
+    assert err[good].max() <= IMG_TOL, err[good].max()
+    assert o["invdepth"][good].max() > 0.05
+
+
+def test_inverse_depth_gradient_matches_oracle(R):
+    from paper_2509_25626_amd.render import GaussianScene
+    scene = S.scene_fd_subcase(41, 500)
+    cam = S.orbit_camera(64, 64, 4.0, 20.0, 5.0, bg=(0.1, 0.2, 0.3))
+    H, W = cam.height, cam.width
+    rng = np.random.default_rng(7)
+    dl = rng.normal(size=(3, H, W)).astype(np.float32)
+    dd = (rng.normal(size=(H, W)) * 4.0).astype(np.float32)
+    gs = GaussianScene.from_numpy(scene)
+    rgb, T, nc, frame, invd = R.forward(gs, cam, invdepth=True)
+    grads = R.backward(frame, gs, cam, T, nc, torch.from_numpy(dl).cuda(), dL_dinvdepth=torch.from_numpy(dd).cuda())
+    torch.cuda.synchronize()
+    R.release_frame(frame)
+    o = O.render(scene, cam, round_f32=True)
+    og = O.backward(scene, cam, dl.astype(np.float64), fwd=o, round_f32=True, dL_dinvdepth=dd.astype(np.float64))
+    og0 = O.backward(scene, cam, dl.astype(np.float64), fwd=o, round_f32=True)
+    assert np.linalg.norm(og["means"] - og0["means"]) > 0.05 * np.linalg.norm(og["means"])
+    for k in ("means", "log_scales", "quats", "opacity_logits", "sh"):
+        gg = grads[k].cpu().numpy().astype(np.float64).reshape(-1)
+        oo = og[k].reshape(-1)
+        rel = np.linalg.norm(gg - oo) / max(np.linalg.norm(oo), 1e-30)
+        elem_ok = np.abs(gg - oo) <= 1e-3 * np.abs(oo) + 1e-6 * np.abs(oo).max()
+        assert rel <= 1e-4, (k, rel)
+        assert elem_ok.mean() >= 0.999, (k, elem_ok.mean())
+
+
+def test_depth_autograd_function(R):
+    from paper_2509_25626_amd.render import RenderDepthFn
+    scene = S.scene_fd_subcase(41, 300)
+    cam = S.orbit_camera(48, 40, 4.0, 0.0, 0.0)
+    ts = {k: torch.from_numpy(np.ascontiguousarray(scene[k])).cuda().requires_grad_(True)
+          for k in ("means", "log_scales", "quats", "opacity_logits", "sh")}
+    img, invd = RenderDepthFn.apply(R, cam, ts["means"], ts["log_scales"], ts["quats"], ts["opacity_logits"],
+                                    ts["sh"])
+    (invd * torch.rand_like(invd)).sum().backward()
+    assert ts["means"].grad is not None and ts["means"].grad.abs().sum() > 0
+    assert torch.isfinite(ts["means"].grad).all()
