@@ -2,7 +2,7 @@
 // the splat alpha, Algorithm 1) and its backward pass.
 //
 // One workgroup per 16x16 tile.  The tile's sorted splats are staged through
-// LDS in batches of 256 (the shared-memory staging the paper measures at
+// LDS in batches (the shared-memory staging the paper measures at
 // +11.3%), the colour included (the coalesced-RGB point).  Each lane blends
 // PPT vertically adjacent pixels (PPT = 1, 2, 4), so every LDS read of a splat
 // serves PPT pixel evaluations and the column-dependent terms of the
@@ -26,13 +26,19 @@
 // Optional expected inverse depth (the inverse-depth output of the paper's
 // Appendix B kernels): 1 / depth of every splat composited like one more
 // colour channel with no background (kDepth, staged per splat in s_d).
+#include <algorithm>
+
 #include "device_utils.h"
 #include "internal.h"
 
 namespace cds {
 namespace {
 
-constexpr int kBatch = 256;
+// splats staged per batch: the forward keeps its registers under 64 and its
+// LDS at 8 KB with 128 (eight waves per SIMD); the backward, heavier per
+// splat, is faster with fewer, larger batches
+constexpr int kBatch = 128;
+constexpr int kBwdBatch = 256;
 constexpr float kLn2 = 0.69314718055994531f;
 constexpr float kAlphaMax = 0.99f;
 constexpr float kAlphaMin = 1.0f / 255.0f;
@@ -250,6 +256,143 @@ __global__ __launch_bounds__(256 / PPT) void k_blend(BlendArgs a, uint32_t per_x
                             s_b, a.depth_bits, a.out_invdepth, s_d);
 }
 
+// Work-stealing blend (the load-balanced variant): one tile's time is
+// nearly the same everywhere, but 4096 tiles fill a chip of ~2300 resident
+// workgroups about 1.8 times, so a per-tile grid leaves much of the chip idle
+// in its last wave.  Here every wave takes half tiles (16 x 8 pixels, two
+// vertically adjacent pixels per lane, as a wave of the PPT = 2 tile kernel)
+// from one counter until none is left, with its own LDS staging area and no
+// workgroup barrier.  Each pixel sees the same splats in the same order
+// through the same arithmetic as in the tile kernels, so the output is the
+// same bit for bit.
+constexpr int kWaveBatch = 128;  // splats staged per wave and batch
+
+template <int PPT, bool kDepth>
+__device__ __forceinline__ void blend_half_tile(const BlendArgs& a, uint32_t tile, uint32_t half, double4* s_q,
+                                                double* s_c, float4* s_f, uint32_t* s_b, float* s_d) {
+    constexpr int kRows = kWave / kTile * PPT;  // rows of the tile this wave blends
+    const uint32_t lane = lane_id();
+    const int tx = (int)(tile % (uint32_t)a.tiles_x), ty = (int)(tile / (uint32_t)a.tiles_x);
+    const int wr0 = (int)half * kRows;  // first tile row of this half
+    const int px = tx * kTile + (int)(lane & 15u);
+    const int py0 = ty * kTile + wr0 + (int)(lane >> 4) * PPT;
+    const double fpx = (double)px;
+    const uint2 range = a.ranges[tile];
+
+    float T[PPT], C0[PPT], C1[PPT], C2[PPT], D[PPT];
+    double fpy[PPT];
+    uint32_t last[PPT];
+    bool done[PPT];
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        T[p] = 1.0f;
+        C0[p] = C1[p] = C2[p] = D[p] = 0.0f;
+        last[p] = 0;
+        fpy[p] = (double)(py0 + p);
+        done[p] = !(px < a.width && py0 + p < a.height);
+    }
+    const int todo = (int)(range.y - range.x);
+    for (int base = 0; base < todo; base += kWaveBatch) {
+        int alive = 0;
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) alive |= done[p] ? 0 : 1;
+        if (!__any(alive)) break;  // wave-uniform
+        wave_lds_sync();           // the previous batch has been read
+        for (int k = (int)lane; k < kWaveBatch; k += kWave) {
+            const int idx = base + k;
+            if (idx < todo) {
+                const uint32_t id = a.point_list[range.x + idx];
+                stage_splat(a.mean2d, a.conic_opacity, a.rgb, id, s_q, s_c, s_f, s_b, k, tx * kTile, ty * kTile);
+                if constexpr (kDepth) s_d[k] = 1.0f / __uint_as_float(a.depth_bits[id]);
+            }
+        }
+        wave_lds_sync();
+        const int cnt = min(kWaveBatch, todo - base);
+        uint64_t cand[kWaveBatch / kWave];
+#pragma unroll
+        for (int q = 0; q < kWaveBatch / kWave; ++q) {
+            const int k = q * kWave + (int)lane;
+            cand[q] = ballot(k < cnt && box_meets_rows(s_b[k], wr0, wr0 + kRows - 1));
+        }
+        int visited = 0;
+        bool wave_done = false;
+        for (int q = 0; q < kWaveBatch / kWave && !wave_done; ++q) {
+            uint64_t m = cand[q];
+            while (m) {
+                const int j = q * kWave + __builtin_ctzll(m);
+                m &= m - 1;
+                if ((visited++ & 31) == 0) {
+                    int live = 0;
+#pragma unroll
+                    for (int p = 0; p < PPT; ++p) live |= done[p] ? 0 : 1;
+                    if (!__any(live)) {
+                        wave_done = true;
+                        break;
+                    }
+                }
+                const double4 qq = s_q[j];
+                const double c2 = s_c[j];
+                const float4 f = s_f[j];
+                const double dx = qq.x - fpx;
+                const double adx2 = (qq.z * dx) * dx;
+                const double bdx = qq.w * dx;
+#pragma unroll
+                for (int p = 0; p < PPT; ++p) {
+                    float alpha, G;
+                    const bool hit = splat_alpha(adx2, bdx, c2, qq.y - fpy[p], f.x, alpha, G) && !done[p];
+                    if (hit) {
+                        const float test_T = T[p] * (1.0f - alpha);
+                        if (test_T < kTMin) {
+                            done[p] = true;
+                        } else {
+                            const float wgt = alpha * T[p];
+                            C0[p] = fmaf(f.y, wgt, C0[p]);
+                            C1[p] = fmaf(f.z, wgt, C1[p]);
+                            C2[p] = fmaf(f.w, wgt, C2[p]);
+                            if constexpr (kDepth) D[p] = fmaf(s_d[j], wgt, D[p]);
+                            T[p] = test_T;
+                            last[p] = (uint32_t)(base + j + 1);
+                        }
+                    }
+                }
+            }
+        }
+    }
+    const int64_t npix = (int64_t)a.width * a.height;
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        const int py = py0 + p;
+        if (px < a.width && py < a.height) {
+            const int64_t pix = (int64_t)py * a.width + px;
+            if (a.out_T) a.out_T[pix] = T[p];
+            if (a.out_ncontrib) a.out_ncontrib[pix] = last[p];
+            a.out_rgb[pix] = fmaf(T[p], a.bg[0], C0[p]);
+            a.out_rgb[npix + pix] = fmaf(T[p], a.bg[1], C1[p]);
+            a.out_rgb[2 * npix + pix] = fmaf(T[p], a.bg[2], C2[p]);
+            if constexpr (kDepth) a.out_invdepth[pix] = D[p];
+        }
+    }
+}
+
+template <int PPT, bool kDepth>
+__global__ __launch_bounds__(128) void k_blend_steal(BlendArgs a, uint32_t* counter, uint32_t units) {
+    constexpr uint32_t kParts = kTile / (kWave / kTile * PPT);  // wave units per tile
+    constexpr int kW = 128 / kWave;
+    __shared__ double4 s_q[kW][kWaveBatch];
+    __shared__ double s_c[kW][kWaveBatch];
+    __shared__ float4 s_f[kW][kWaveBatch];
+    __shared__ uint32_t s_b[kW][kWaveBatch];
+    __shared__ float s_d[kW][kDepth ? kWaveBatch : 1];
+    const int w = threadIdx.x / kWave;
+    for (;;) {  // every wave leaves once the counter passes the last half tile
+        uint32_t u = 0;
+        if (lane_id() == 0) u = atomicAdd(counter, 1u);
+        u = (uint32_t)__builtin_amdgcn_readfirstlane((int)u);
+        if (u >= units) break;
+        blend_half_tile<PPT, kDepth>(a, u / kParts, u % kParts, s_q[w], s_c[w], s_f[w], s_b[w], s_d[w]);
+    }
+}
+
 // Persistent blend over every tile of a batch of renders: each workgroup
 // takes the next global tile id from an atomic counter until none is left
 // (every wave reaches the exit), finds the owning request by binary search
@@ -296,12 +439,12 @@ template <int PPT, bool kDepth>
 __global__ __launch_bounds__(256 / PPT) void k_blend_bwd(BlendBwdArgs a, uint32_t per_xcd) {
     constexpr int NT = 256 / PPT;
     constexpr int kRowsPerWave = kWave / kTile * PPT;
-    __shared__ double4 s_q[kBatch];
-    __shared__ double s_c[kBatch];
-    __shared__ float4 s_f[kBatch];
-    __shared__ uint32_t s_b[kBatch];
-    __shared__ uint32_t s_id[kBatch];
-    __shared__ float s_d[kDepth ? kBatch : 1];
+    __shared__ double4 s_q[kBwdBatch];
+    __shared__ double s_c[kBwdBatch];
+    __shared__ float4 s_f[kBwdBatch];
+    __shared__ uint32_t s_b[kBwdBatch];
+    __shared__ uint32_t s_id[kBwdBatch];
+    __shared__ float s_d[kDepth ? kBwdBatch : 1];
     __shared__ uint32_t s_max;
 
     const uint32_t tile = xcd_band(blockIdx.x, per_xcd);
@@ -352,8 +495,8 @@ __global__ __launch_bounds__(256 / PPT) void k_blend_bwd(BlendBwdArgs a, uint32_
     const uint32_t len = range.y - range.x;
     const int maxlast = (int)(s_max < len ? s_max : len);
     const int64_t n = a.n;
-    for (int end = maxlast; end > 0; end -= kBatch) {
-        const int begin = end - kBatch > 0 ? end - kBatch : 0;
+    for (int end = maxlast; end > 0; end -= kBwdBatch) {
+        const int begin = end - kBwdBatch > 0 ? end - kBwdBatch : 0;
         __syncthreads();  // the previous batch is fully consumed
         for (int k = t; k < end - begin; k += NT) {
             const uint32_t id = a.point_list[range.x + begin + k];
@@ -363,13 +506,13 @@ __global__ __launch_bounds__(256 / PPT) void k_blend_bwd(BlendBwdArgs a, uint32_
         }
         __syncthreads();
         const int cnt = end - begin;
-        uint64_t cand[kBatch / kWave];
+        uint64_t cand[kBwdBatch / kWave];
 #pragma unroll
-        for (int qd = 0; qd < kBatch / kWave; ++qd) {
+        for (int qd = 0; qd < kBwdBatch / kWave; ++qd) {
             const int k = qd * kWave + (int)lane_id();
             cand[qd] = ballot(k < cnt && box_meets_rows(s_b[k], wr0, wr0 + kRowsPerWave - 1));
         }
-        for (int qd = kBatch / kWave - 1; qd >= 0; --qd) {
+        for (int qd = kBwdBatch / kWave - 1; qd >= 0; --qd) {
             uint64_t m = cand[qd];
             while (m) {  // back to front
             const int bit = 63 - __builtin_clzll(m);
@@ -493,6 +636,33 @@ hipError_t launch_blend(const BlendArgs& a, int variant, hipStream_t stream) {
     const dim3 grid(8 * per);
     const bool depth = a.out_invdepth != nullptr;
     if (depth && !a.depth_bits) return hipErrorInvalidValue;
+    if (variant == 3 || variant == 5) {
+        if (!a.counter) return hipErrorInvalidValue;
+        hipError_t e = launch_fill_u32(a.counter, 1, 0u, stream);
+        if (e != hipSuccess) return e;
+        const uint32_t units = (uint32_t)((variant == 3 ? 2 : 1) * tiles);
+        int dev = 0, cus = 256;
+        if (hipGetDevice(&dev) == hipSuccess)
+            (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        // at most as many workgroups (two waves each) as fit, all of them busy
+        const int64_t g = std::min<int64_t>((int64_t)(units + 1) / 2, (int64_t)cus * 12);
+        if (variant == 3) {
+            if (depth)
+                hipLaunchKernelGGL((k_blend_steal<2, true>), dim3((unsigned)g), dim3(128), 0, stream, a, a.counter,
+                                   units);
+            else
+                hipLaunchKernelGGL((k_blend_steal<2, false>), dim3((unsigned)g), dim3(128), 0, stream, a, a.counter,
+                                   units);
+        } else {
+            if (depth)
+                hipLaunchKernelGGL((k_blend_steal<4, true>), dim3((unsigned)g), dim3(128), 0, stream, a, a.counter,
+                                   units);
+            else
+                hipLaunchKernelGGL((k_blend_steal<4, false>), dim3((unsigned)g), dim3(128), 0, stream, a, a.counter,
+                                   units);
+        }
+        return hipGetLastError();
+    }
     switch (variant) {
         case 1:
             if (depth) hipLaunchKernelGGL((k_blend<1, true>), grid, dim3(256), 0, stream, a, per);

@@ -305,7 +305,9 @@ struct BlendArgs {
     uint32_t* out_ncontrib;
     const uint32_t* depth_bits;  // float32 bits of each Gaussian's depth (read with out_invdepth)
     float* out_invdepth;         // [H][W] expected inverse depth, or null
+    uint32_t* counter;           // work counter of the work-stealing variant (3)
 };
+// variant: 1, 2, 4 = pixels per thread of the per-tile kernel; 3 = work-stealing half tiles
 hipError_t launch_blend(const BlendArgs& a, int variant, hipStream_t stream);
 
 // Persistent blend over the tiles of a batch: workgroups pull global tile

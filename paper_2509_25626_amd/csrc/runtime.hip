@@ -258,8 +258,8 @@ cds_status cds_render_forward_ex(cds_ctx* ctx, cds_frame* f, const cds_scene* sc
         timing = (opts->flags & CDS_OPT_STAGE_TIMING) != 0;
         algo = sort_algo_from_flags(opts->flags);
         variant = opts->blend_variant;
-        if (variant != 0 && variant != 1 && variant != 2 && variant != 4)
-            return fail(CDS_ERR_INVALID_ARG, "blend_variant must be 0, 1, 2 or 4");
+        if (variant < 0 || variant > 5)
+            return fail(CDS_ERR_INVALID_ARG, "blend_variant must be 0 to 5");
         if (opts->sort_variant < 0 || opts->sort_variant > 3)
             return fail(CDS_ERR_INVALID_ARG, "sort_variant must be 0, 1, 2 or 3");
         sort_variant = opts->sort_variant;

@@ -26,7 +26,7 @@ def _forward(R, scene, cam, variant=0):
     return out
 
 
-@pytest.mark.parametrize("cfg,variant", [("c1", 0), ("c1", 1), ("c1", 4), ("outdoor", 0)])
+@pytest.mark.parametrize("cfg,variant", [("c1", 0), ("c1", 1), ("c1", 3), ("c1", 4), ("outdoor", 0), ("outdoor", 3)])
 def test_inverse_depth_matches_oracle(R, cfg, variant):
     if cfg == "c1":
         scene, cam = S.config_scene("c1")
