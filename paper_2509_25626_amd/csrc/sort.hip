@@ -44,7 +44,7 @@ constexpr uint32_t kFlagAgg = 1u << 30;
 constexpr uint32_t kFlagIncl = 2u << 30;
 constexpr uint32_t kValueMask = (1u << 30) - 1;
 constexpr uint32_t kSpinLimit = 1u << 22;
-constexpr int kLookBack = 16;  // status words a thread reads per look-back poll
+constexpr int kLookBack = 8;  // status words a thread reads per look-back poll (measured: 8 over 2, 4, 16, 32)
 
 __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, int64_t count,
                                                   uint32_t value) {
@@ -292,11 +292,126 @@ __device__ __forceinline__ void generate_keys(const KeyGen& g, int64_t count, in
     }
 }
 
+// Decoupled look-back of partition pid: the sum of the counts of digit t over
+// all earlier partitions (threads t < 2^kBits), after which this partition's
+// inclusive prefix is published.  s_tmp: 1024 words of LDS scratch, used
+// only when the look-back is block-cooperative (digits under 8 bits).
+template <typename Key, int kBits>
+__device__ __forceinline__ uint32_t look_back(const PassArgs<Key>& a, uint32_t pid, uint32_t tot, uint32_t* st,
+                                              uint32_t* s_tmp) {
+    constexpr uint32_t kDig = 1u << kBits;
+    constexpr int kSeg = 256 >> kBits;  // threads per digit in the look-back
+    const int t = threadIdx.x;
+    uint32_t excl = 0;
+    if (kSeg == 1 && pid > 0) {
+        // one thread per digit: each polls on its own, without barriers
+        if (t < (int)kDig) {
+            int64_t p = (int64_t)pid - 1;
+            uint32_t polls = 0;
+            while (p >= 0) {
+                uint32_t sw[kLookBack];
+#pragma unroll
+                for (int k = 0; k < kLookBack; ++k)
+                    sw[k] = (p - k >= 0) ? atomic_load_agent(a.status + (size_t)(p - k) * 256 + t) : kFlagIncl;
+                uint32_t state = 0;
+                int consumed = 0;
+#pragma unroll
+                for (int k = 0; k < kLookBack; ++k) {
+                    if (state) continue;
+                    const uint32_t f = sw[k] & ~kValueMask;
+                    if (f == 0u) {
+                        state = 2;
+                        continue;
+                    }
+                    excl += sw[k] & kValueMask;
+                    ++consumed;
+                    if (f == kFlagIncl) state = 1;
+                }
+                if (state == 1) break;
+                p -= consumed;
+                if (state == 2) {
+                    if (++polls > kSpinLimit) {
+                        atomicOr(a.err, 1u);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+            }
+            atomic_store_agent(st + t, kFlagIncl | ((excl + tot) & kValueMask));
+        }
+    } else if (pid > 0) {
+        uint32_t* s_sum = s_tmp;           // [256] per-thread sums
+        uint32_t* s_cnt = s_sum + 256;      // [256] state << 16 | words consumed
+        uint32_t* s_dist = s_sum + 512;     // [kDig] next distance, 0 = done
+        uint32_t* s_acc = s_sum + 768;      // [kDig] sum so far
+        const uint32_t d = (uint32_t)t & (kDig - 1u);
+        const uint32_t seg = (uint32_t)t >> kBits;
+        if (t < (int)kDig) {
+            s_dist[t] = 1u;
+            s_acc[t] = 0u;
+        }
+        __syncthreads();
+        uint32_t polls = 0;
+        for (;;) {
+            const uint32_t dist0 = s_dist[d];
+            uint32_t sum = 0, state = 0, cnt = 0;  // state: 1 inclusive found, 2 not ready
+            if (dist0) {
+                const int64_t q0 = (int64_t)pid - dist0 - (int64_t)seg * kLookBack;
+                uint32_t sw[kLookBack];
+#pragma unroll
+                for (int k = 0; k < kLookBack; ++k)
+                    sw[k] = (q0 - k >= 0) ? atomic_load_agent(a.status + (size_t)(q0 - k) * 256 + d) : kFlagIncl;
+#pragma unroll
+                for (int k = 0; k < kLookBack; ++k) {
+                    if (state) continue;
+                    const uint32_t f = sw[k] & ~kValueMask;
+                    if (f == 0u) {
+                        state = 2;
+                        continue;
+                    }
+                    sum += sw[k] & kValueMask;
+                    ++cnt;
+                    if (f == kFlagIncl) state = 1;
+                }
+            }
+            s_sum[t] = sum;
+            s_cnt[t] = (state << 16) | cnt;
+            __syncthreads();
+            int pending = 0;
+            if (t < (int)kDig && s_dist[t] != 0u) {
+                uint32_t acc = s_acc[t], dist = s_dist[t], stop = 0;
+#pragma unroll
+                for (int sg = 0; sg < kSeg; ++sg) {
+                    if (stop) continue;
+                    const uint32_t sc = s_cnt[t + sg * (int)kDig];
+                    acc += s_sum[t + sg * (int)kDig];
+                    dist += sc & 0xFFFFu;
+                    stop = sc >> 16;
+                }
+                s_acc[t] = acc;
+                s_dist[t] = stop == 1u ? 0u : dist;
+                pending = stop != 1u;
+            }
+            if (__syncthreads_count(pending) == 0) break;
+            if (++polls > kSpinLimit) {  // uniform
+                if (t == 0) atomicOr(a.err, 1u);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        if (t < (int)kDig) {
+            excl = s_acc[t];
+            atomic_store_agent(st + t, kFlagIncl | ((excl + tot) & kValueMask));
+        }
+    }
+    return excl;
+}
+
 // One partition of one pass.  kFull: the partition has no tail (every key
 // valid), compiled separately so the common case carries no bounds checks.
 // kPacked: the keys are packed words that hold their values (value = key &
 // unpack_mask), so no value is loaded, held or staged.
-template <typename Key, bool kOnesweep, int kBits, bool kFull, bool kGen, bool kPacked = false>
+template <typename Key, bool kOnesweep, int kBits, bool kFull, bool kGen, bool kPacked = false, bool kLeanRank = false>
 __device__ __forceinline__ void sort_pass_body(const PassArgs<Key>& a, uint32_t pid, Key* s_keys, uint32_t* s_vals,
                                                uint32_t (*s_whist)[256], uint32_t* s_gbase, uint32_t* s_scan,
                                                uint32_t digit_info) {
@@ -351,22 +466,39 @@ __device__ __forceinline__ void sort_pass_body(const PassArgs<Key>& a, uint32_t 
     // the rounds' atomics do not wait on each other's results (LDS executes a
     // wave's operations in order), and the members then fetch the old count
     // from their group's first lane.
-    uint32_t pre[kKPT], info[kKPT];  // info: below | first lane << 8
-#pragma unroll
-    for (int r = 0; r < kKPT; ++r) {
-        const bool valid = kFull || (wbase + r * kWave + l) < a.count;
-        const uint32_t d = (uint32_t)(key[r] >> a.shift) & kMask;
-        const uint64_t peers = digit_peers<kBits>(d, valid);
-        const uint32_t below = count_below(peers);
-        const uint32_t first = valid ? (uint32_t)__builtin_ctzll(peers) : l;
-        pre[r] = 0;
-        if (valid && below == 0) pre[r] = atomicAdd(&s_whist[w][d], (uint32_t)__popcll(peers));
-        info[r] = below | (first << 8);
-    }
     uint32_t rank[kKPT];
+    if constexpr (kLeanRank) {
+        // each round's old count is fetched as soon as its atomic returns:
+        // the LDS latency is exposed per round, but no per-round state is
+        // held, which leaves room for more resident workgroups
 #pragma unroll
-    for (int r = 0; r < kKPT; ++r)
-        rank[r] = (uint32_t)__shfl((int)pre[r], (int)(info[r] >> 8), kWave) + (info[r] & 255u);
+        for (int r = 0; r < kKPT; ++r) {
+            const bool valid = kFull || (wbase + r * kWave + l) < a.count;
+            const uint32_t d = (uint32_t)(key[r] >> a.shift) & kMask;
+            const uint64_t peers = digit_peers<kBits>(d, valid);
+            const uint32_t below = count_below(peers);
+            const uint32_t first = valid ? (uint32_t)__builtin_ctzll(peers) : l;
+            uint32_t pre = 0;
+            if (valid && below == 0) pre = atomicAdd(&s_whist[w][d], (uint32_t)__popcll(peers));
+            rank[r] = (uint32_t)__shfl((int)pre, (int)first, kWave) + below;
+        }
+    } else {
+        uint32_t pre[kKPT], info[kKPT];  // info: below | first lane << 8
+#pragma unroll
+        for (int r = 0; r < kKPT; ++r) {
+            const bool valid = kFull || (wbase + r * kWave + l) < a.count;
+            const uint32_t d = (uint32_t)(key[r] >> a.shift) & kMask;
+            const uint64_t peers = digit_peers<kBits>(d, valid);
+            const uint32_t below = count_below(peers);
+            const uint32_t first = valid ? (uint32_t)__builtin_ctzll(peers) : l;
+            pre[r] = 0;
+            if (valid && below == 0) pre[r] = atomicAdd(&s_whist[w][d], (uint32_t)__popcll(peers));
+            info[r] = below | (first << 8);
+        }
+#pragma unroll
+        for (int r = 0; r < kKPT; ++r)
+            rank[r] = (uint32_t)__shfl((int)pre[r], (int)(info[r] >> 8), kWave) + (info[r] & 255u);
+    }
     __syncthreads();
 
     // thread t owns digit t
@@ -400,7 +532,6 @@ __device__ __forceinline__ void sort_pass_body(const PassArgs<Key>& a, uint32_t 
 
     uint32_t gb;  // global position of this partition's first key with digit t
     if constexpr (kOnesweep) {
-        constexpr int kSeg = 256 >> kBits;  // threads per digit in the look-back
         const uint32_t gstart = block_excl_sum<kNT>(digit_info, s_scan, nullptr);
         // Look-back.  With 8-bit digits every thread polls for its own digit.
         // With smaller ones it is block-cooperative: every poll, thread t reads kLookBack
@@ -412,108 +543,7 @@ __device__ __forceinline__ void sort_pass_body(const PassArgs<Key>& a, uint32_t 
         // an inclusive prefix, else the next poll starts after what was consumed.
         // The inclusive prefix thus moves kSeg * kLookBack partitions per round
         // trip, which with small digits keeps it ahead of the partitions.
-        uint32_t excl = 0;
-        if (kSeg == 1 && pid > 0) {
-            // one thread per digit: each polls on its own, without barriers
-            if (t < (int)kDig) {
-                int64_t p = (int64_t)pid - 1;
-                uint32_t polls = 0;
-                while (p >= 0) {
-                    uint32_t sw[kLookBack];
-#pragma unroll
-                    for (int k = 0; k < kLookBack; ++k)
-                        sw[k] = (p - k >= 0) ? atomic_load_agent(a.status + (size_t)(p - k) * 256 + t) : kFlagIncl;
-                    uint32_t state = 0;
-                    int consumed = 0;
-#pragma unroll
-                    for (int k = 0; k < kLookBack; ++k) {
-                        if (state) continue;
-                        const uint32_t f = sw[k] & ~kValueMask;
-                        if (f == 0u) {
-                            state = 2;
-                            continue;
-                        }
-                        excl += sw[k] & kValueMask;
-                        ++consumed;
-                        if (f == kFlagIncl) state = 1;
-                    }
-                    if (state == 1) break;
-                    p -= consumed;
-                    if (state == 2) {
-                        if (++polls > kSpinLimit) {
-                            atomicOr(a.err, 1u);
-                            break;
-                        }
-                        __builtin_amdgcn_s_sleep(1);
-                    }
-                }
-                atomic_store_agent(st + t, kFlagIncl | ((excl + tot) & kValueMask));
-            }
-        } else if (pid > 0) {
-            uint32_t* s_sum = &s_whist[0][0];  // [256] per-thread sums
-            uint32_t* s_cnt = s_sum + 256;      // [256] state << 16 | words consumed
-            uint32_t* s_dist = s_sum + 512;     // [kDig] next distance, 0 = done
-            uint32_t* s_acc = s_sum + 768;      // [kDig] sum so far
-            const uint32_t d = (uint32_t)t & (kDig - 1u);
-            const uint32_t seg = (uint32_t)t >> kBits;
-            if (t < (int)kDig) {
-                s_dist[t] = 1u;
-                s_acc[t] = 0u;
-            }
-            __syncthreads();
-            uint32_t polls = 0;
-            for (;;) {
-                const uint32_t dist0 = s_dist[d];
-                uint32_t sum = 0, state = 0, cnt = 0;  // state: 1 inclusive found, 2 not ready
-                if (dist0) {
-                    const int64_t q0 = (int64_t)pid - dist0 - (int64_t)seg * kLookBack;
-                    uint32_t sw[kLookBack];
-#pragma unroll
-                    for (int k = 0; k < kLookBack; ++k)
-                        sw[k] = (q0 - k >= 0) ? atomic_load_agent(a.status + (size_t)(q0 - k) * 256 + d) : kFlagIncl;
-#pragma unroll
-                    for (int k = 0; k < kLookBack; ++k) {
-                        if (state) continue;
-                        const uint32_t f = sw[k] & ~kValueMask;
-                        if (f == 0u) {
-                            state = 2;
-                            continue;
-                        }
-                        sum += sw[k] & kValueMask;
-                        ++cnt;
-                        if (f == kFlagIncl) state = 1;
-                    }
-                }
-                s_sum[t] = sum;
-                s_cnt[t] = (state << 16) | cnt;
-                __syncthreads();
-                int pending = 0;
-                if (t < (int)kDig && s_dist[t] != 0u) {
-                    uint32_t acc = s_acc[t], dist = s_dist[t], stop = 0;
-#pragma unroll
-                    for (int sg = 0; sg < kSeg; ++sg) {
-                        if (stop) continue;
-                        const uint32_t sc = s_cnt[t + sg * (int)kDig];
-                        acc += s_sum[t + sg * (int)kDig];
-                        dist += sc & 0xFFFFu;
-                        stop = sc >> 16;
-                    }
-                    s_acc[t] = acc;
-                    s_dist[t] = stop == 1u ? 0u : dist;
-                    pending = stop != 1u;
-                }
-                if (__syncthreads_count(pending) == 0) break;
-                if (++polls > kSpinLimit) {  // uniform
-                    if (t == 0) atomicOr(a.err, 1u);
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-            }
-            if (t < (int)kDig) {
-                excl = s_acc[t];
-                atomic_store_agent(st + t, kFlagIncl | ((excl + tot) & kValueMask));
-            }
-        }
+        const uint32_t excl = look_back<Key, kBits>(a, pid, tot, st, &s_whist[0][0]);
         gb = gstart + excl;
     } else {
         gb = digit_info;
@@ -586,7 +616,8 @@ __global__ __launch_bounds__(kNT, 4) void k_sort_pass_onesweep(PassArgs<Key> a) 
 }
 
 // Onesweep pass over packed words (value inside the key): one word per key
-// in registers and in LDS.
+// in registers and in LDS, and the lean ranking (88 VGPRs: five workgroups
+// per CU against four).
 template <int kBits>
 __global__ __launch_bounds__(kNT, 4) void k_sort_pass_packed(PassArgs<uint32_t> a) {
     if (a.count_dev) a.count = (int64_t)*a.count_dev;
@@ -604,10 +635,10 @@ __global__ __launch_bounds__(kNT, 4) void k_sort_pass_packed(PassArgs<uint32_t> 
     const uint32_t pid = s_pid;
     if ((int64_t)pid * kP >= a.count) return;  // uniform: past the keys (device-side count)
     if ((int64_t)(pid + 1) * kP <= a.count)
-        sort_pass_body<uint32_t, true, kBits, true, false, true>(a, pid, s_keys, nullptr, s_whist, s_gbase, s_scan,
+        sort_pass_body<uint32_t, true, kBits, true, false, true, true>(a, pid, s_keys, nullptr, s_whist, s_gbase, s_scan,
                                                                  hist_t);
     else
-        sort_pass_body<uint32_t, true, kBits, false, false, true>(a, pid, s_keys, nullptr, s_whist, s_gbase, s_scan,
+        sort_pass_body<uint32_t, true, kBits, false, false, true, true>(a, pid, s_keys, nullptr, s_whist, s_gbase, s_scan,
                                                                   hist_t);
 }
 
