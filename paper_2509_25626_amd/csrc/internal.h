@@ -192,6 +192,16 @@ constexpr int64_t kSortPartition = (int64_t)kSortThreads * kSortKeysPerThread;
 constexpr int64_t kSortMaxCount = (int64_t(1) << 30) - 1;
 constexpr int64_t kSortRtsMinPartitions = int64_t(1) << 40;  // auto: onesweep (measured faster at 80M keys)
 inline int64_t sort_partitions(int64_t count) { return (count + kSortPartition - 1) / kSortPartition; }
+// Large onesweep sorts run 512-thread workgroups over 8192-key partitions:
+// half the partitions, hence half the partition-id atomics.  Workspaces are
+// sized with sort_partitions, the larger count.
+constexpr int kSortThreadsWide = 512;
+constexpr int64_t kSortWideMinCount = int64_t(1) << 23;
+inline bool sort_uses_wide(int64_t count) { return count >= kSortWideMinCount; }
+inline int64_t sort_partitions_wide(int64_t count) {
+    const int64_t part = (int64_t)kSortThreadsWide * kSortKeysPerThread;
+    return (count + part - 1) / part;
+}
 bool sort_uses_onesweep(int64_t count, SortAlgo algo);
 hipError_t launch_sort_histogram(const uint64_t* keys, int64_t count, int passes, int shift0, uint32_t* hist,
                                  hipStream_t stream, int end_bit = 0);

@@ -36,15 +36,16 @@
 namespace cds {
 namespace {
 
-constexpr int kNT = kSortThreads;
 constexpr int kKPT = kSortKeysPerThread;
-constexpr int kP = kNT * kKPT;
-constexpr int kWaves = kNT / kWave;
+constexpr int kNTR = kSortThreads;  // reduce-then-scan workgroups
+constexpr int kPR = kNTR * kKPT;
 constexpr uint32_t kFlagAgg = 1u << 30;
 constexpr uint32_t kFlagIncl = 2u << 30;
 constexpr uint32_t kValueMask = (1u << 30) - 1;
 constexpr uint32_t kSpinLimit = 1u << 22;
-constexpr int kLookBack = 8;  // status words a thread reads per look-back poll (measured: 8 over 2, 4, 16, 32)
+// status words a thread of a 256-thread workgroup reads per look-back poll
+// (measured: 8 over 2, 4, 16, 32)
+constexpr int kLookBack256 = 8;
 
 __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, int64_t count,
                                                   uint32_t value) {
@@ -103,7 +104,7 @@ __device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
 // Per-partition digit counts, digit-major: part_hist[d * parts + p].  Counts
 // do not depend on order, so plain (skew-aware) LDS atomics suffice.
 template <typename Key>
-__global__ __launch_bounds__(kNT) void k_rts_upsweep(const Key* __restrict__ keys, int64_t count, int shift,
+__global__ __launch_bounds__(kNTR) void k_rts_upsweep(const Key* __restrict__ keys, int64_t count, int shift,
                                                      int bits, uint32_t* __restrict__ part_hist, int64_t parts,
                                                      const uint64_t* __restrict__ count_dev) {
     if (count_dev) count = (int64_t)*count_dev;  // partitions past it count nothing
@@ -111,16 +112,16 @@ __global__ __launch_bounds__(kNT) void k_rts_upsweep(const Key* __restrict__ key
     const int t = threadIdx.x;
     s_h[t] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kP;
+    const int64_t base = (int64_t)blockIdx.x * kPR;
     Key k[kKPT];
 #pragma unroll
     for (int r = 0; r < kKPT; ++r) {
-        const int64_t idx = base + (int64_t)r * kNT + t;
+        const int64_t idx = base + (int64_t)r * kNTR + t;
         k[r] = idx < count ? keys[idx] : (Key)0;
     }
 #pragma unroll
     for (int r = 0; r < kKPT; ++r) {
-        const int64_t idx = base + (int64_t)r * kNT + t;
+        const int64_t idx = base + (int64_t)r * kNTR + t;
         if (idx < count) hist_add(s_h, (uint32_t)(k[r] >> shift) & ((1u << bits) - 1u));
     }
     __syncthreads();
@@ -294,13 +295,16 @@ __device__ __forceinline__ void generate_keys(const KeyGen& g, int64_t count, in
 
 // Decoupled look-back of partition pid: the sum of the counts of digit t over
 // all earlier partitions (threads t < 2^kBits), after which this partition's
-// inclusive prefix is published.  s_tmp: 1024 words of LDS scratch, used
-// only when the look-back is block-cooperative (digits under 8 bits).
-template <typename Key, int kBits>
+// inclusive prefix is published.  s_tmp: 2 kNT + 512 words of LDS scratch,
+// used when the look-back is block-cooperative (more threads than digits).
+template <typename Key, int kBits, int kNT>
 __device__ __forceinline__ uint32_t look_back(const PassArgs<Key>& a, uint32_t pid, uint32_t tot, uint32_t* st,
                                               uint32_t* s_tmp) {
     constexpr uint32_t kDig = 1u << kBits;
-    constexpr int kSeg = 256 >> kBits;  // threads per digit in the look-back
+    constexpr int kSeg = kNT >> kBits;  // threads per digit in the look-back
+    // status words per thread and poll: a window of kSeg * kLookBack * 256 / kNT
+    // predecessors per digit
+    constexpr int kLookBack = kLookBack256 * 256 / kNT > 0 ? kLookBack256 * 256 / kNT : 1;
     const int t = threadIdx.x;
     uint32_t excl = 0;
     if (kSeg == 1 && pid > 0) {
@@ -340,10 +344,10 @@ __device__ __forceinline__ uint32_t look_back(const PassArgs<Key>& a, uint32_t p
             atomic_store_agent(st + t, kFlagIncl | ((excl + tot) & kValueMask));
         }
     } else if (pid > 0) {
-        uint32_t* s_sum = s_tmp;           // [256] per-thread sums
-        uint32_t* s_cnt = s_sum + 256;      // [256] state << 16 | words consumed
-        uint32_t* s_dist = s_sum + 512;     // [kDig] next distance, 0 = done
-        uint32_t* s_acc = s_sum + 768;      // [kDig] sum so far
+        uint32_t* s_sum = s_tmp;             // [kNT] per-thread sums
+        uint32_t* s_cnt = s_sum + kNT;        // [kNT] state << 16 | words consumed
+        uint32_t* s_dist = s_sum + 2 * kNT;   // [kDig] next distance, 0 = done
+        uint32_t* s_acc = s_dist + 256;       // [kDig] sum so far
         const uint32_t d = (uint32_t)t & (kDig - 1u);
         const uint32_t seg = (uint32_t)t >> kBits;
         if (t < (int)kDig) {
@@ -411,12 +415,15 @@ __device__ __forceinline__ uint32_t look_back(const PassArgs<Key>& a, uint32_t p
 // valid), compiled separately so the common case carries no bounds checks.
 // kPacked: the keys are packed words that hold their values (value = key &
 // unpack_mask), so no value is loaded, held or staged.
-template <typename Key, bool kOnesweep, int kBits, bool kFull, bool kGen, bool kPacked = false, bool kLeanRank = false>
+template <int kNT, typename Key, bool kOnesweep, int kBits, bool kFull, bool kGen, bool kPacked = false,
+          bool kLeanRank = false>
 __device__ __forceinline__ void sort_pass_body(const PassArgs<Key>& a, uint32_t pid, Key* s_keys, uint32_t* s_vals,
                                                uint32_t (*s_whist)[256], uint32_t* s_gbase, uint32_t* s_scan,
                                                uint32_t digit_info) {
     static_assert(!kPacked || (sizeof(Key) == 4 && !kGen), "packed words are 32-bit keys read from memory");
     constexpr uint32_t kMask = (1u << kBits) - 1u;
+    constexpr int kP = kNT * kKPT;       // keys per partition
+    constexpr int kWaves = kNT / kWave;
     const int t = threadIdx.x;
     const int w = t / kWave;
     const uint32_t l = lane_id();
@@ -501,19 +508,25 @@ __device__ __forceinline__ void sort_pass_body(const PassArgs<Key>& a, uint32_t 
     }
     __syncthreads();
 
-    // thread t owns digit t
-    const uint32_t c0 = s_whist[0][t], c1 = s_whist[1][t], c2 = s_whist[2][t], c3 = s_whist[3][t];
-    static_assert(kWaves == 4, "digit bookkeeping assumes 4 waves");
-    const uint32_t tot = c0 + c1 + c2 + c3;
+    // thread t < 256 owns digit t
+    uint32_t tot = 0;
+    if (t < 256)
+#pragma unroll
+        for (int v = 0; v < kWaves; ++v) tot += s_whist[v][t];
     constexpr uint32_t kDig = 1u << kBits;  // digits of this pass
     uint32_t* st = a.status + (size_t)pid * 256;
     if constexpr (kOnesweep)  // publish this partition's counts first
         if (t < (int)kDig) atomic_store_agent(st + t, (pid == 0 ? kFlagIncl : kFlagAgg) | tot);
     const uint32_t bstart = block_excl_sum<kNT>(tot, s_scan, nullptr);
-    s_whist[0][t] = bstart;
-    s_whist[1][t] = bstart + c0;
-    s_whist[2][t] = bstart + c0 + c1;
-    s_whist[3][t] = bstart + c0 + c1 + c2;
+    if (t < 256) {
+        uint32_t run = bstart;
+#pragma unroll
+        for (int v = 0; v < kWaves; ++v) {
+            const uint32_t c = s_whist[v][t];
+            s_whist[v][t] = run;
+            run += c;
+        }
+    }
     __syncthreads();
 
     // reorder (key, value) pairs by digit in LDS; a slot can only fall outside
@@ -543,12 +556,12 @@ __device__ __forceinline__ void sort_pass_body(const PassArgs<Key>& a, uint32_t 
         // an inclusive prefix, else the next poll starts after what was consumed.
         // The inclusive prefix thus moves kSeg * kLookBack partitions per round
         // trip, which with small digits keeps it ahead of the partitions.
-        const uint32_t excl = look_back<Key, kBits>(a, pid, tot, st, &s_whist[0][0]);
+        const uint32_t excl = look_back<Key, kBits, kNT>(a, pid, tot, st, &s_whist[0][0]);
         gb = gstart + excl;
     } else {
         gb = digit_info;
     }
-    s_gbase[t] = gb - bstart;
+    if (t < 256) s_gbase[t] = gb - bstart;
     __syncthreads();
     // each digit run goes out as a contiguous stretch
     const uint32_t nvalid = kFull ? (uint32_t)kP : (uint32_t)(a.count - base);
@@ -579,8 +592,10 @@ __device__ __forceinline__ void sort_pass_body(const PassArgs<Key>& a, uint32_t 
     }
 }
 
-template <typename Key, bool kOnesweep, int kBits, bool kGen = false>
+template <int kNT, typename Key, bool kOnesweep, int kBits, bool kGen = false>
 __device__ __forceinline__ void sort_pass_kernel(const PassArgs<Key>& a_in) {
+    constexpr int kP = kNT * kKPT;
+    constexpr int kWaves = kNT / kWave;
     PassArgs<Key> a = a_in;
     if (a.count_dev) a.count = (int64_t)*a.count_dev;
     __shared__ __align__(16) Key s_keys[kP];    // reorder buffer
@@ -592,34 +607,47 @@ __device__ __forceinline__ void sort_pass_kernel(const PassArgs<Key>& a_in) {
 
     const int t = threadIdx.x;
     if (t == 0) s_pid = kOnesweep ? atomicAdd(a.counter, 1u) : blockIdx.x;
-    const uint32_t hist_t = kOnesweep ? a.hist[t] : 0u;
+    const uint32_t hist_t = (kOnesweep && t < 256) ? a.hist[t] : 0u;
     for (int k = t; k < kWaves * 256; k += kNT) (&s_whist[0][0])[k] = 0;
     __syncthreads();
     const uint32_t pid = s_pid;
     if ((int64_t)pid * kP >= a.count) return;  // uniform: past the keys (device-side count)
     // digit t's count over all keys (onesweep) or this partition's base for it
     // (reduce-then-scan), loaded before the ranking so its latency overlaps
-    const uint32_t digit_info = kOnesweep ? hist_t : a.bases[(int64_t)t * a.parts + pid];
+    const uint32_t digit_info = (kOnesweep || t >= 256) ? hist_t : a.bases[(int64_t)t * a.parts + pid];
     if ((int64_t)(pid + 1) * kP <= a.count)
-        sort_pass_body<Key, kOnesweep, kBits, true, kGen>(a, pid, s_keys, s_vals, s_whist, s_gbase, s_scan,
+        sort_pass_body<kNT, Key, kOnesweep, kBits, true, kGen>(a, pid, s_keys, s_vals, s_whist, s_gbase, s_scan,
                                                           digit_info);
     else
-        sort_pass_body<Key, kOnesweep, kBits, false, kGen>(a, pid, s_keys, s_vals, s_whist, s_gbase, s_scan,
+        sort_pass_body<kNT, Key, kOnesweep, kBits, false, kGen>(a, pid, s_keys, s_vals, s_whist, s_gbase, s_scan,
                                                            digit_info);
 }
 
-// Onesweep passes: four workgroups per CU (VGPRs <= 128, 37 KB of LDS each),
-// so that partitions waiting in their look-back overlap with others' work.
-template <typename Key, int kBits>
-__global__ __launch_bounds__(kNT, 4) void k_sort_pass_onesweep(PassArgs<Key> a) {
-    sort_pass_kernel<Key, true, kBits>(a);
+// Workgroup shape of the onesweep kernels: 256 threads (4096-key partitions)
+// or, for large sorts, 512 (8192-key partitions).  Every partition takes its
+// id from one device-scope atomic counter, so that a partition only ever waits
+// for partitions that are already running; those atomics are serialized
+// (about 12 ns each measured), which bounds a pass over 20k partitions to
+// ~0.23 ms.  Larger partitions halve that.  The second launch bound (waves
+// per SIMD) keeps VGPRs at most 128: four 256-thread or two 512-thread
+// workgroups per CU.
+template <int kNT>
+constexpr int kMinBlocks = 4;
+
+// Onesweep passes (37 KB of LDS per 256 threads), so that partitions waiting
+// in their look-back overlap with others' work.
+template <typename Key, int kBits, int kNT>
+__global__ __launch_bounds__(kNT, kMinBlocks<kNT>) void k_sort_pass_onesweep(PassArgs<Key> a) {
+    sort_pass_kernel<kNT, Key, true, kBits>(a);
 }
 
 // Onesweep pass over packed words (value inside the key): one word per key
-// in registers and in LDS, and the lean ranking (88 VGPRs: five workgroups
-// per CU against four).
-template <int kBits>
-__global__ __launch_bounds__(kNT, 4) void k_sort_pass_packed(PassArgs<uint32_t> a) {
+// in registers and in LDS, and the lean ranking (88 VGPRs: five 256-thread
+// workgroups per CU against four).
+template <int kBits, int kNT>
+__global__ __launch_bounds__(kNT, kMinBlocks<kNT>) void k_sort_pass_packed(PassArgs<uint32_t> a) {
+    constexpr int kP = kNT * kKPT;
+    constexpr int kWaves = kNT / kWave;
     if (a.count_dev) a.count = (int64_t)*a.count_dev;
     __shared__ __align__(16) uint32_t s_keys[kP];
     __shared__ uint32_t s_whist[kWaves][256];
@@ -629,85 +657,73 @@ __global__ __launch_bounds__(kNT, 4) void k_sort_pass_packed(PassArgs<uint32_t> 
 
     const int t = threadIdx.x;
     if (t == 0) s_pid = atomicAdd(a.counter, 1u);
-    const uint32_t hist_t = a.hist[t];
+    const uint32_t hist_t = t < 256 ? a.hist[t] : 0u;
     for (int k = t; k < kWaves * 256; k += kNT) (&s_whist[0][0])[k] = 0;
     __syncthreads();
     const uint32_t pid = s_pid;
     if ((int64_t)pid * kP >= a.count) return;  // uniform: past the keys (device-side count)
     if ((int64_t)(pid + 1) * kP <= a.count)
-        sort_pass_body<uint32_t, true, kBits, true, false, true, true>(a, pid, s_keys, nullptr, s_whist, s_gbase, s_scan,
-                                                                 hist_t);
+        sort_pass_body<kNT, uint32_t, true, kBits, true, false, true, true>(a, pid, s_keys, nullptr, s_whist, s_gbase,
+                                                                            s_scan, hist_t);
     else
-        sort_pass_body<uint32_t, true, kBits, false, false, true, true>(a, pid, s_keys, nullptr, s_whist, s_gbase, s_scan,
-                                                                  hist_t);
+        sort_pass_body<kNT, uint32_t, true, kBits, false, false, true, true>(a, pid, s_keys, nullptr, s_whist, s_gbase,
+                                                                             s_scan, hist_t);
 }
 
 // The first tile pass with its keys generated from the splat records.
-template <int kBits>
-__global__ __launch_bounds__(kNT, 4) void k_sort_pass_gen(PassArgs<uint32_t> a) {
-    sort_pass_kernel<uint32_t, true, kBits, true>(a);
+template <int kBits, int kNT>
+__global__ __launch_bounds__(kNT, kMinBlocks<kNT>) void k_sort_pass_gen(PassArgs<uint32_t> a) {
+    sort_pass_kernel<kNT, uint32_t, true, kBits, true>(a);
 }
 
 template <typename Key, int kBits>
-__global__ __launch_bounds__(kNT, 4) void k_sort_pass_rts(PassArgs<Key> a) {
-    sort_pass_kernel<Key, false, kBits>(a);
+__global__ __launch_bounds__(kNTR, 4) void k_sort_pass_rts(PassArgs<Key> a) {
+    sort_pass_kernel<kNTR, Key, false, kBits>(a);
 }
 
-template <typename Key, bool kOnesweep, int kBits>
-void launch_pass_bits(const PassArgs<Key>& a, dim3 grid, hipStream_t stream) {
-    if constexpr (kOnesweep)
-        hipLaunchKernelGGL((k_sort_pass_onesweep<Key, kBits>), grid, dim3(kNT), 0, stream, a);
+// kind: 0 plain onesweep, 1 packed words, 2 generated keys, 3 reduce-then-scan
+template <typename Key, int kNT, int kBits>
+void launch_kind(int kind, const PassArgs<Key>& a, dim3 grid, hipStream_t stream) {
+    if constexpr (sizeof(Key) == 4) {
+        if (kind == 1) {
+            hipLaunchKernelGGL((k_sort_pass_packed<kBits, kNT>), grid, dim3(kNT), 0, stream, a);
+            return;
+        }
+        if (kind == 2) {
+            hipLaunchKernelGGL((k_sort_pass_gen<kBits, kNT>), grid, dim3(kNT), 0, stream, a);
+            return;
+        }
+    }
+    if (kind == 3)
+        hipLaunchKernelGGL((k_sort_pass_rts<Key, kBits>), grid, dim3(kNTR), 0, stream, a);
     else
-        hipLaunchKernelGGL((k_sort_pass_rts<Key, kBits>), grid, dim3(kNT), 0, stream, a);
+        hipLaunchKernelGGL((k_sort_pass_onesweep<Key, kBits, kNT>), grid, dim3(kNT), 0, stream, a);
 }
 
-hipError_t launch_packed_pass(const PassArgs<uint32_t>& a, int64_t parts, hipStream_t stream) {
+template <typename Key, int kNT>
+hipError_t launch_pass_nt(int kind, const PassArgs<Key>& a, int64_t parts, hipStream_t stream) {
     const dim3 grid((unsigned)parts);
     switch (a.bits) {
-        case 1: hipLaunchKernelGGL(k_sort_pass_packed<1>, grid, dim3(kNT), 0, stream, a); break;
-        case 2: hipLaunchKernelGGL(k_sort_pass_packed<2>, grid, dim3(kNT), 0, stream, a); break;
-        case 3: hipLaunchKernelGGL(k_sort_pass_packed<3>, grid, dim3(kNT), 0, stream, a); break;
-        case 4: hipLaunchKernelGGL(k_sort_pass_packed<4>, grid, dim3(kNT), 0, stream, a); break;
-        case 5: hipLaunchKernelGGL(k_sort_pass_packed<5>, grid, dim3(kNT), 0, stream, a); break;
-        case 6: hipLaunchKernelGGL(k_sort_pass_packed<6>, grid, dim3(kNT), 0, stream, a); break;
-        case 7: hipLaunchKernelGGL(k_sort_pass_packed<7>, grid, dim3(kNT), 0, stream, a); break;
-        case 8: hipLaunchKernelGGL(k_sort_pass_packed<8>, grid, dim3(kNT), 0, stream, a); break;
+        case 1: launch_kind<Key, kNT, 1>(kind, a, grid, stream); break;
+        case 2: launch_kind<Key, kNT, 2>(kind, a, grid, stream); break;
+        case 3: launch_kind<Key, kNT, 3>(kind, a, grid, stream); break;
+        case 4: launch_kind<Key, kNT, 4>(kind, a, grid, stream); break;
+        case 5: launch_kind<Key, kNT, 5>(kind, a, grid, stream); break;
+        case 6: launch_kind<Key, kNT, 6>(kind, a, grid, stream); break;
+        case 7: launch_kind<Key, kNT, 7>(kind, a, grid, stream); break;
+        case 8: launch_kind<Key, kNT, 8>(kind, a, grid, stream); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_gen_pass(const PassArgs<uint32_t>& a, int64_t parts, hipStream_t stream) {
-    const dim3 grid((unsigned)parts);
-    switch (a.bits) {
-        case 1: hipLaunchKernelGGL(k_sort_pass_gen<1>, grid, dim3(kNT), 0, stream, a); break;
-        case 2: hipLaunchKernelGGL(k_sort_pass_gen<2>, grid, dim3(kNT), 0, stream, a); break;
-        case 3: hipLaunchKernelGGL(k_sort_pass_gen<3>, grid, dim3(kNT), 0, stream, a); break;
-        case 4: hipLaunchKernelGGL(k_sort_pass_gen<4>, grid, dim3(kNT), 0, stream, a); break;
-        case 5: hipLaunchKernelGGL(k_sort_pass_gen<5>, grid, dim3(kNT), 0, stream, a); break;
-        case 6: hipLaunchKernelGGL(k_sort_pass_gen<6>, grid, dim3(kNT), 0, stream, a); break;
-        case 7: hipLaunchKernelGGL(k_sort_pass_gen<7>, grid, dim3(kNT), 0, stream, a); break;
-        case 8: hipLaunchKernelGGL(k_sort_pass_gen<8>, grid, dim3(kNT), 0, stream, a); break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-template <typename Key, bool kOnesweep>
-hipError_t launch_pass(const PassArgs<Key>& a, int64_t parts, hipStream_t stream) {
-    const dim3 grid((unsigned)parts);
-    switch (a.bits) {
-        case 1: launch_pass_bits<Key, kOnesweep, 1>(a, grid, stream); break;
-        case 2: launch_pass_bits<Key, kOnesweep, 2>(a, grid, stream); break;
-        case 3: launch_pass_bits<Key, kOnesweep, 3>(a, grid, stream); break;
-        case 4: launch_pass_bits<Key, kOnesweep, 4>(a, grid, stream); break;
-        case 5: launch_pass_bits<Key, kOnesweep, 5>(a, grid, stream); break;
-        case 6: launch_pass_bits<Key, kOnesweep, 6>(a, grid, stream); break;
-        case 7: launch_pass_bits<Key, kOnesweep, 7>(a, grid, stream); break;
-        case 8: launch_pass_bits<Key, kOnesweep, 8>(a, grid, stream); break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+template <typename Key>
+hipError_t launch_pass(int kind, bool wide, const PassArgs<Key>& a, int64_t parts, hipStream_t stream) {
+    if ((kind == 1 || kind == 2) && sizeof(Key) != 4) return hipErrorInvalidValue;
+    if constexpr (sizeof(Key) == 4)  // 32-bit keys only: 64-bit ones would need 104 KB of LDS
+        if (wide && kind != 3) return launch_pass_nt<Key, kSortThreadsWide>(kind, a, parts, stream);
+    if (wide) return hipErrorInvalidValue;
+    return launch_pass_nt<Key, kSortThreads>(kind, a, parts, stream);
 }
 
 template <typename Key>
@@ -729,8 +745,9 @@ hipError_t sort_passes_impl(const Key* kin, const uint32_t* vin, Key* ka, uint32
                             uint4* gather_dst, const uint64_t* count_dev) {
     if (count <= 0 || passes <= 0) return hipSuccess;
     if (count > kSortMaxCount) return hipErrorInvalidValue;
-    const int64_t parts = sort_partitions(count);
     const bool onesweep = sort_uses_onesweep(count, algo);
+    const bool wide = onesweep && sizeof(Key) == 4 && sort_uses_wide(count);
+    const int64_t parts = wide ? sort_partitions_wide(count) : sort_partitions(count);
     if (passes > 8) return hipErrorInvalidValue;
     if (gen && (!onesweep || sizeof(Key) != 4 || !gen->off || !gen->rec || !gen->owner))
         return hipErrorInvalidValue;
@@ -774,24 +791,20 @@ hipError_t sort_passes_impl(const Key* kin, const uint32_t* vin, Key* ka, uint32
         a.gather_dst = p == passes - 1 ? gather_dst : nullptr;
         hipError_t e;
         if (p == 0 && gen) {
-            if constexpr (sizeof(Key) == 4) {
-                a.gen = *gen;
-                if ((e = launch_gen_pass(a, parts, stream)) != hipSuccess) return e;
-            }
+            a.gen = *gen;
+            if ((e = launch_pass<Key>(2, wide, a, parts, stream)) != hipSuccess) return e;
         } else if (onesweep && a.unpack_mask) {
-            if constexpr (sizeof(Key) == 4) {
-                if ((e = launch_packed_pass(a, parts, stream)) != hipSuccess) return e;
-            }
+            if ((e = launch_pass<Key>(1, wide, a, parts, stream)) != hipSuccess) return e;
         } else if (onesweep) {
-            if ((e = launch_pass<Key, true>(a, parts, stream)) != hipSuccess) return e;
+            if ((e = launch_pass<Key>(0, wide, a, parts, stream)) != hipSuccess) return e;
         } else {
-            hipLaunchKernelGGL(k_rts_upsweep<Key>, dim3((unsigned)parts), dim3(kNT), 0, stream, a.kin, count,
+            hipLaunchKernelGGL(k_rts_upsweep<Key>, dim3((unsigned)parts), dim3(kNTR), 0, stream, a.kin, count,
                                a.shift, a.bits, ws.part_hist, parts, count_dev);
             if ((e = hipGetLastError()) != hipSuccess) return e;
             e = launch_exclusive_scan(ws.part_hist, nullptr, ws.bases, 256 * parts, ws.scan_sums, ws.scan_total,
                                       stream);
             if (e != hipSuccess) return e;
-            if ((e = launch_pass<Key, false>(a, parts, stream)) != hipSuccess) return e;
+            if ((e = launch_pass<Key>(3, false, a, parts, stream)) != hipSuccess) return e;
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if (p == 0 && first_done && (e = hipEventRecord(first_done, stream)) != hipSuccess) return e;
