@@ -203,9 +203,15 @@ __device__ __forceinline__ void generate_keys(const KeyGen& g, int64_t count, in
         val[r] = 0u;
     }
     if (wbase >= count) return;  // uniform: past the last key
+    const int64_t wend = wbase + kWave * kRounds;
+    // owners of the wave's first key and of the first key after it: the
+    // records the wave needs are jb .. jn (the owner table has an entry per
+    // chunk start below count)
     int64_t jb = (int64_t)g.owner[wbase / kKeyGenChunk];
+    const int64_t jn = wend < count ? (int64_t)g.owner[wend / kKeyGenChunk] : g.n - 1;
     int64_t jw = jb;  // window = records [jw, jw + kGenWindow)
-    for (int k = (int)l; k < kGenWindow; k += kWave) {
+    const int nrec = (int)min<int64_t>((int64_t)kGenWindow, jn - jb + 1);  // records loaded
+    for (int k = (int)l; k < nrec; k += kWave) {
         const int64_t j = jw + k;
         if (j < g.n) {
             s_off[k] = g.off[j];
@@ -214,16 +220,12 @@ __device__ __forceinline__ void generate_keys(const KeyGen& g, int64_t count, in
     }
     s_flag[l] = make_uint4(0u, 0u, 0u, 0u);
     wave_lds_sync();
-    const int64_t wend = wbase + kWave * kRounds;
-    const bool covered = jw + kGenWindow >= g.n || (int64_t)s_off[kGenWindow - 1] >= wend;  // uniform
+    const bool covered = jn - jb < kGenWindow;  // uniform
     if (covered) {
         uint8_t* flag = reinterpret_cast<uint8_t*>(s_flag);
-        for (int k = 1 + (int)l; k < kGenWindow; k += kWave) {
-            const int64_t j = jw + k;
-            if (j < g.n) {
-                const int64_t sp = (int64_t)s_off[k] - wbase;  // >= 1: j starts after the owner of wbase
-                if (sp < wend - wbase) flag[(sp & (kWave - 1)) * 16 + (sp >> 6)] = 1u;
-            }
+        for (int k = 1 + (int)l; k < nrec; k += kWave) {
+            const int64_t sp = (int64_t)s_off[k] - wbase;  // >= 1: j starts after the owner of wbase
+            if (sp < wend - wbase) flag[(sp & (kWave - 1)) * 16 + (sp >> 6)] = 1u;
         }
         wave_lds_sync();
         const uint4 mk = s_flag[l];
@@ -416,7 +418,7 @@ __device__ __forceinline__ uint32_t look_back(const PassArgs<Key>& a, uint32_t p
 // kPacked: the keys are packed words that hold their values (value = key &
 // unpack_mask), so no value is loaded, held or staged.
 template <int kNT, typename Key, bool kOnesweep, int kBits, bool kFull, bool kGen, bool kPacked = false,
-          bool kLeanRank = false>
+          bool kLeanRank = false, bool kWaveLocal = false>
 __device__ __forceinline__ void sort_pass_body(const PassArgs<Key>& a, uint32_t pid, Key* s_keys, uint32_t* s_vals,
                                                uint32_t (*s_whist)[256], uint32_t* s_gbase, uint32_t* s_scan,
                                                uint32_t digit_info) {
@@ -474,7 +476,7 @@ __device__ __forceinline__ void sort_pass_body(const PassArgs<Key>& a, uint32_t 
     // wave's operations in order), and the members then fetch the old count
     // from their group's first lane.
     uint32_t rank[kKPT];
-    if constexpr (kLeanRank) {
+    if constexpr (kLeanRank || kWaveLocal) {
         // each round's old count is fetched as soon as its atomic returns:
         // the LDS latency is exposed per round, but no per-round state is
         // held, which leaves room for more resident workgroups
@@ -505,6 +507,82 @@ __device__ __forceinline__ void sort_pass_body(const PassArgs<Key>& a, uint32_t 
 #pragma unroll
         for (int r = 0; r < kKPT; ++r)
             rank[r] = (uint32_t)__shfl((int)pre[r], (int)(info[r] >> 8), kWave) + (info[r] & 255u);
+    }
+    if constexpr (kWaveLocal) {
+        // Wave-local reorder: each wave sorts its own keys by digit inside its
+        // slice of the buffers right after its ranking, so that no key or rank
+        // is held across the block scan and the look-back (fewer VGPRs, more
+        // resident workgroups), and the scatter writes each wave's digit runs
+        // at (wave, digit) offsets.
+        static_assert(kOnesweep && kBits <= 6 && sizeof(Key) == 4, "one digit per lane, 32-bit keys");
+        constexpr uint32_t kDigW = 1u << kBits;
+        constexpr int kWK = kWave * kKPT;                       // keys per wave
+        const uint32_t cnt = l < kDigW ? s_whist[w][l] : 0u;  // the wave's own atomics are complete
+        const uint32_t wst = wave_incl_sum(cnt) - cnt;         // digit l's start inside the slice
+        if (l < kDigW) s_whist[w][l] = (wst << 16) | cnt;
+        Key* s_wk = s_keys + (size_t)w * kWK;
+        uint32_t* s_wv = kPacked ? nullptr : s_vals + (size_t)w * kWK;
+        // the digits are recomputed below rather than held through the ranking
+#pragma unroll
+        for (int r = 0; r < kKPT; ++r) asm volatile("" : "+v"(key[r]));
+#pragma unroll
+        for (int r = 0; r < kKPT; ++r) {
+            const bool valid = kFull || (wbase + r * kWave + l) < a.count;
+            const uint32_t d = (uint32_t)(key[r] >> a.shift) & kMask;
+            const uint32_t pos = min((uint32_t)__shfl((int)wst, (int)d, kWave) + rank[r], (uint32_t)(kWK - 1));
+            if (valid) {
+                s_wk[pos] = key[r];
+                if constexpr (!kPacked) s_wv[pos] = val[r];
+            }
+        }
+        __syncthreads();
+        // thread t < 2^kBits owns digit t: per wave, count (low half) and start in the slice (high half)
+        uint32_t x[kWaves];
+        uint32_t tot = 0;
+#pragma unroll
+        for (int v = 0; v < kWaves; ++v) {
+            x[v] = t < (int)kDigW ? s_whist[v][t] : 0u;
+            tot += x[v] & 0xFFFFu;
+        }
+        uint32_t* st = a.status + (size_t)pid * 256;
+        if (t < (int)kDigW) atomic_store_agent(st + t, (pid == 0 ? kFlagIncl : kFlagAgg) | tot);
+        const uint32_t gstart = block_excl_sum<kNT>(digit_info, s_scan, nullptr);  // barriers: counts read
+        const uint32_t gb = gstart + look_back<Key, kBits, kNT>(a, pid, tot, st, &s_whist[0][0]);
+        __syncthreads();  // the look-back's scratch is free
+        if (t < (int)kDigW) {  // position of a slice's slot = its wave's offset for the digit + slot
+            uint32_t run = gb;
+#pragma unroll
+            for (int v = 0; v < kWaves; ++v) {
+                s_whist[v][t] = run - (x[v] >> 16);
+                run += x[v] & 0xFFFFu;
+            }
+        }
+        __syncthreads();
+        const int64_t nw = kFull ? (int64_t)kWK : min((int64_t)kWK, max((int64_t)0, a.count - wbase));
+#pragma unroll
+        for (int r = 0; r < kKPT; ++r) {
+            const uint32_t i = (uint32_t)(r * kWave) + l;
+            if (kFull || (int64_t)i < nw) {
+                const Key k = s_wk[i];
+                const uint32_t d = (uint32_t)(k >> a.shift) & kMask;
+                const uint32_t g = s_whist[w][d] + i;
+                if ((int64_t)g < a.count) {
+                    if (a.kout) a.kout[g] = k;
+                    uint32_t v;
+                    if constexpr (kPacked)
+                        v = (uint32_t)k & a.unpack_mask;
+                    else
+                        v = s_wv[i];
+                    if (a.gather_dst)  // uniform
+                        a.gather_dst[g] = a.gather_src[v];
+                    else
+                        a.vout[g] = a.vbits ? ((uint32_t)(k >> a.pack_shift) << a.vbits) | v : v;
+                } else {
+                    atomicOr(a.err, 2u);
+                }
+            }
+        }
+        return;
     }
     __syncthreads();
 
@@ -633,6 +711,10 @@ __device__ __forceinline__ void sort_pass_kernel(const PassArgs<Key>& a_in) {
 // workgroups per CU.
 template <int kNT>
 constexpr int kMinBlocks = 4;
+// the packed-word pass over 8192-key partitions with small digits reorders
+// wave by wave: few enough VGPRs for three workgroups per CU (LDS allows it)
+template <int kNT, int kBits>
+constexpr bool kPackedWaveLocal = kNT >= 512 && kBits <= 6;
 
 // Onesweep passes (37 KB of LDS per 256 threads), so that partitions waiting
 // in their look-back overlap with others' work.
@@ -663,10 +745,10 @@ __global__ __launch_bounds__(kNT, kMinBlocks<kNT>) void k_sort_pass_packed(PassA
     const uint32_t pid = s_pid;
     if ((int64_t)pid * kP >= a.count) return;  // uniform: past the keys (device-side count)
     if ((int64_t)(pid + 1) * kP <= a.count)
-        sort_pass_body<kNT, uint32_t, true, kBits, true, false, true, true>(a, pid, s_keys, nullptr, s_whist, s_gbase,
+        sort_pass_body<kNT, uint32_t, true, kBits, true, false, true, true, kPackedWaveLocal<kNT, kBits>>(a, pid, s_keys, nullptr, s_whist, s_gbase,
                                                                             s_scan, hist_t);
     else
-        sort_pass_body<kNT, uint32_t, true, kBits, false, false, true, true>(a, pid, s_keys, nullptr, s_whist, s_gbase,
+        sort_pass_body<kNT, uint32_t, true, kBits, false, false, true, true, kPackedWaveLocal<kNT, kBits>>(a, pid, s_keys, nullptr, s_whist, s_gbase,
                                                                              s_scan, hist_t);
 }
 
