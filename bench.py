@@ -75,7 +75,9 @@ def roofline(stages, scene, K, passes, info, first_pass_ms, variant, algo):
         # tile sort, its first pass: keys generated from the splat records in
         # depth order (4 B offset + 16 B record per visible splat, 4 B owner per
         # 1024 keys read) and written once as packed words (else tile id + value)
-        "sort_ms": (f"k_sort_pass_gen<{tile_digit_bits}>", 1, 20 * nvis + 4 * (K // 1024 + 1) + word * K),
+        # (512-thread workgroups from 2^23 keys on, as the library chooses)
+        "sort_ms": (f"k_sort_pass_gen<{tile_digit_bits}, {512 if K >= (1 << 23) else 256}>", 1,
+                    20 * nvis + 4 * (K // 1024 + 1) + word * K),
     }
     if variant == 1:  # first pass over (u64 key, u32 value) pairs written by k_duplicate
         table["sort_ms"] = (f"k_sort_pass_onesweep<u64,{tile_digit_bits}> (first pass)", 1, 24 * K)
