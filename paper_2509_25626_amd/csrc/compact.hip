@@ -74,14 +74,21 @@ __global__ __launch_bounds__(kCT) void k_vis_scatter(int64_t n, const uint32_t* 
     const uint32_t lane = lane_id();
     for (int k = t; k < 4 * 256; k += kCT) s_hist[k] = 0;
     const int64_t wbase = (int64_t)blockIdx.x * kCTile + (int64_t)w * (kWave * kCIPT);
-    uint32_t c[kCIPT];
-    uint32_t wtot = 0;
+    // every round's inputs are loaded up front (one memory latency per wave,
+    // not one per round; a line holds visible and culled items alike)
+    uint32_t c[kCIPT], dv[kCIPT];
+    uint2 rv[kCIPT];
 #pragma unroll
     for (int r = 0; r < kCIPT; ++r) {
         const int64_t i = wbase + r * kWave + lane;
-        c[r] = i < n ? touched[i] : 0u;
-        wtot += (uint32_t)__popcll(ballot(c[r] != 0u));
+        const bool in = i < n;
+        c[r] = in ? touched[i] : 0u;
+        dv[r] = in ? depth_bits[i] : 0u;
+        rv[r] = in ? rect[i] : make_uint2(0u, 0u);
     }
+    uint32_t wtot = 0;
+#pragma unroll
+    for (int r = 0; r < kCIPT; ++r) wtot += (uint32_t)__popcll(ballot(c[r] != 0u));
     if (lane == 0) s_wtot[w] = wtot;
     __syncthreads();
     uint32_t slot = (uint32_t)vis_base[blockIdx.x];
@@ -92,8 +99,8 @@ __global__ __launch_bounds__(kCT) void k_vis_scatter(int64_t n, const uint32_t* 
         const uint64_t m = ballot(c[r] != 0u);
         if (c[r]) {
             const uint32_t pos = slot + count_below(m);
-            const uint32_t d = depth_bits[i];
-            const uint2 rc = rect[i];
+            const uint32_t d = dv[r];
+            const uint2 rc = rv[r];
             uint32_t tx = tiles_x, tb = 0;
             if (items) {
                 const int it = find_item_by_gaussian(items, nitems, i);

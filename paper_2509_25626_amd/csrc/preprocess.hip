@@ -54,12 +54,34 @@ __device__ __forceinline__ void sh_basis_f32(float x, float y, float z, int degr
     b[15] = -kY3a * x * (xx - 3.0f * yy);
 }
 
+// colour = sum_k basis[k] sh[k] over the kNB coefficients, each channel
+// accumulated in coefficient order; all coefficient loads are issued before
+// the first product
+template <int kNB>
+__device__ __forceinline__ void sh_colour(const float* __restrict__ sh, int64_t n, int64_t i, const float* basis,
+                                          float col[3]) {
+    float v[kNB][3];
+#pragma unroll
+    for (int k = 0; k < kNB; ++k)
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) v[k][ch] = sh[((int64_t)k * 3 + ch) * n + i];
+#pragma unroll
+    for (int k = 0; k < kNB; ++k)
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) col[ch] += basis[k] * v[k][ch];
+}
+
 // Gaussian i of a scene with P.n Gaussians; outputs go to slot `o` of O.
 __device__ __forceinline__ void preprocess_one(const ProjParams& P, const SceneParams& S, int64_t i,
                                                const SplatBuffers& O, int64_t o) {
     const int64_t n = P.n;
 
     const double m0 = S.means[i], m1 = S.means[n + i], m2 = S.means[2 * n + i];
+    // the other per-Gaussian inputs load with the means (one memory latency);
+    // a line holds culled and visible Gaussians alike
+    const float ls0 = S.log_scales[i], ls1 = S.log_scales[n + i], ls2 = S.log_scales[2 * n + i];
+    const float q0 = S.quats[i], q1 = S.quats[n + i], q2 = S.quats[2 * n + i], q3 = S.quats[3 * n + i];
+    const float olog = S.opacity_logits[i];
     const double tx = P.R[0] * m0 + P.R[1] * m1 + P.R[2] * m2 + P.t[0];
     const double ty = P.R[3] * m0 + P.R[4] * m1 + P.R[5] * m2 + P.t[1];
     const double tz = P.R[6] * m0 + P.R[7] * m1 + P.R[8] * m2 + P.t[2];
@@ -73,10 +95,10 @@ __device__ __forceinline__ void preprocess_one(const ProjParams& P, const SceneP
 
     if (visible) {
         // 3D covariance Sigma = Rq diag(s^2) Rq^T, s = exp(log_scale)
-        const double s0 = exp(2.0 * (double)S.log_scales[i]);
-        const double s1 = exp(2.0 * (double)S.log_scales[n + i]);
-        const double s2 = exp(2.0 * (double)S.log_scales[2 * n + i]);
-        double qw = S.quats[i], qx = S.quats[n + i], qy = S.quats[2 * n + i], qz = S.quats[3 * n + i];
+        const double s0 = exp(2.0 * (double)ls0);
+        const double s1 = exp(2.0 * (double)ls1);
+        const double s2 = exp(2.0 * (double)ls2);
+        double qw = q0, qx = q1, qy = q2, qz = q3;
         const double qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
         qw /= qn; qx /= qn; qy /= qn; qz /= qn;
         const double r00 = 1.0 - 2.0 * (qy * qy + qz * qz), r01 = 2.0 * (qx * qy - qw * qz),
@@ -159,20 +181,19 @@ __device__ __forceinline__ void preprocess_one(const ProjParams& P, const SceneP
         return;
     }
 
-    const float opacity = (float)(1.0 / (1.0 + exp(-(double)S.opacity_logits[i])));
+    const float opacity = (float)(1.0 / (1.0 + exp(-(double)olog)));
 
     // colour: view direction from the camera centre, SH up to degree 3
     double dx = m0 - P.campos[0], dy = m1 - P.campos[1], dz = m2 - P.campos[2];
     const double dl = sqrt(dx * dx + dy * dy + dz * dz);
     float basis[16];
     sh_basis_f32((float)(dx / dl), (float)(dy / dl), (float)(dz / dl), P.sh_degree, basis);
-    const int nb = (P.sh_degree + 1) * (P.sh_degree + 1);
     float col[3] = {0.f, 0.f, 0.f};
-    for (int k = 0; k < nb; ++k) {
-        const float* c = S.sh + (int64_t)k * 3 * n + i;
-        col[0] += basis[k] * c[0];
-        col[1] += basis[k] * c[n];
-        col[2] += basis[k] * c[2 * n];
+    switch (P.sh_degree) {  // uniform
+        case 0: sh_colour<1>(S.sh, n, i, basis, col); break;
+        case 1: sh_colour<4>(S.sh, n, i, basis, col); break;
+        case 2: sh_colour<9>(S.sh, n, i, basis, col); break;
+        default: sh_colour<16>(S.sh, n, i, basis, col); break;
     }
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
