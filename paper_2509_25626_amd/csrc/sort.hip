@@ -3,9 +3,10 @@
 // visible splats followed by a sort of their keys' tile ids.
 //
 // Every pass is a partitioned counting sort on a digit of up to 8 bits (the
-// key bits are split evenly over the passes).  A workgroup (256 threads,
-// 4096 keys) ranks its keys stably in LDS, reorders them by digit and writes
-// each digit run as one contiguous, coalesced store.  Ranking is wave64
+// key bits are split evenly over the passes).  A workgroup (256 threads over
+// 4096 keys, or 512 over 8192 for onesweep sorts of 2^23+ 32-bit keys) ranks
+// its keys stably in LDS, reorders them by digit and writes each digit run as
+// one contiguous, coalesced store.  Ranking is wave64
 // native: keys are held "wave-striped" (round r of a wave covers 64
 // consecutive input keys), lanes with the same digit are found with one
 // ballot per digit bit, and a per-wave per-digit counter in LDS gives each key
@@ -77,26 +78,23 @@ __global__ __launch_bounds__(256) void k_sort_histogram(const Key* __restrict__ 
 
 // Lanes of the wave holding the same digit (restricted to `valid` lanes),
 // from one ballot per digit bit.  x is all ones where the bit is set, so the
-// lanes agreeing with this lane on the bit are ~(m ^ x).  The bit count is a
+// lanes agreeing with this lane on the bit are ~(m ^ x); one three-input
+// bitwise op per half keeps them: v_bitop3(m, p, x) = p & ~(m ^ x), whose
+// truth table (true at (m, p, x) = (0, 1, 0) and (1, 1, 1): 0x84) reads the
+// same whichever outer operand is the table's high bit.  The bit count is a
 // compile-time constant: no branches, and the ballots of different bits are
-// independent, so their SGPR hazards overlap.
+// independent.
 template <int kBits>
 __device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
-    uint32_t x[kBits];
-    uint64_t m[kBits];
-#pragma unroll
-    for (int b = 0; b < kBits; ++b) {
-        x[b] = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);
-        asm("" : "+v"(x[b]));  // compare x itself rather than a re-derived shift of d
-    }
-#pragma unroll
-    for (int b = 0; b < kBits; ++b) m[b] = ballot(x[b] != 0u);
     const uint64_t v = ballot(valid);
     uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
 #pragma unroll
     for (int b = 0; b < kBits; ++b) {
-        lo &= ~((uint32_t)m[b] ^ x[b]);
-        hi &= ~((uint32_t)(m[b] >> 32) ^ x[b]);
+        uint32_t x = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);
+        asm("" : "+v"(x));  // compare x itself rather than a re-derived shift of d
+        const uint64_t m = ballot(x != 0u);
+        lo = __builtin_amdgcn_bitop3_b32((uint32_t)m, lo, x, 0x84);
+        hi = __builtin_amdgcn_bitop3_b32((uint32_t)(m >> 32), hi, x, 0x84);
     }
     return ((uint64_t)hi << 32) | lo;
 }
@@ -489,7 +487,7 @@ __device__ __forceinline__ void sort_pass_body(const PassArgs<Key>& a, uint32_t 
             const uint32_t first = valid ? (uint32_t)__builtin_ctzll(peers) : l;
             uint32_t pre = 0;
             if (valid && below == 0) pre = atomicAdd(&s_whist[w][d], (uint32_t)__popcll(peers));
-            rank[r] = (uint32_t)__shfl((int)pre, (int)first, kWave) + below;
+            rank[r] = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(first << 2), (int)pre) + below;
         }
     } else {
         uint32_t pre[kKPT], info[kKPT];  // info: below | first lane << 8
@@ -506,7 +504,7 @@ __device__ __forceinline__ void sort_pass_body(const PassArgs<Key>& a, uint32_t 
         }
 #pragma unroll
         for (int r = 0; r < kKPT; ++r)
-            rank[r] = (uint32_t)__shfl((int)pre[r], (int)(info[r] >> 8), kWave) + (info[r] & 255u);
+            rank[r] = (uint32_t)__builtin_amdgcn_ds_bpermute((int)((info[r] >> 8) << 2), (int)pre[r]) + (info[r] & 255u);
     }
     if constexpr (kWaveLocal) {
         // Wave-local reorder: each wave sorts its own keys by digit inside its
@@ -559,6 +557,8 @@ __device__ __forceinline__ void sort_pass_body(const PassArgs<Key>& a, uint32_t 
         }
         __syncthreads();
         const int64_t nw = kFull ? (int64_t)kWK : min((int64_t)kWK, max((int64_t)0, a.count - wbase));
+        const uint32_t count32 = (uint32_t)a.count;  // counts are below 2^30
+        bool bad = false;  // as in the block-wide scatter below
 #pragma unroll
         for (int r = 0; r < kKPT; ++r) {
             const uint32_t i = (uint32_t)(r * kWave) + l;
@@ -566,7 +566,7 @@ __device__ __forceinline__ void sort_pass_body(const PassArgs<Key>& a, uint32_t 
                 const Key k = s_wk[i];
                 const uint32_t d = (uint32_t)(k >> a.shift) & kMask;
                 const uint32_t g = s_whist[w][d] + i;
-                if ((int64_t)g < a.count) {
+                if (g < count32) {
                     if (a.kout) a.kout[g] = k;
                     uint32_t v;
                     if constexpr (kPacked)
@@ -578,10 +578,11 @@ __device__ __forceinline__ void sort_pass_body(const PassArgs<Key>& a, uint32_t 
                     else
                         a.vout[g] = a.vbits ? ((uint32_t)(k >> a.pack_shift) << a.vbits) | v : v;
                 } else {
-                    atomicOr(a.err, 2u);
+                    bad = true;
                 }
             }
         }
+        if (bad) atomicOr(a.err, 2u);
         return;
     }
     __syncthreads();
@@ -643,6 +644,10 @@ __device__ __forceinline__ void sort_pass_body(const PassArgs<Key>& a, uint32_t 
     __syncthreads();
     // each digit run goes out as a contiguous stretch
     const uint32_t nvalid = kFull ? (uint32_t)kP : (uint32_t)(a.count - base);
+    const uint32_t count32 = (uint32_t)a.count;  // counts are below 2^30
+    // a position outside the output can only come from inconsistent digit
+    // counts: it is recorded, never written
+    bool bad = false;
 #pragma unroll
     for (int r = 0; r < kKPT; ++r) {
         const uint32_t i = (uint32_t)(r * kNT + t);
@@ -650,9 +655,7 @@ __device__ __forceinline__ void sort_pass_body(const PassArgs<Key>& a, uint32_t 
             const Key k = s_keys[i];
             const uint32_t d = (uint32_t)(k >> a.shift) & kMask;
             const uint32_t g = s_gbase[d] + i;
-            // a position outside the output can only come from inconsistent digit
-            // counts; record it instead of writing out of bounds
-            if ((int64_t)g < a.count) {
+            if (g < count32) {
                 if (a.kout) a.kout[g] = k;
                 uint32_t v;
                 if constexpr (kPacked)
@@ -664,10 +667,11 @@ __device__ __forceinline__ void sort_pass_body(const PassArgs<Key>& a, uint32_t 
                 else
                     a.vout[g] = a.vbits ? ((uint32_t)(k >> a.pack_shift) << a.vbits) | v : v;
             } else {
-                atomicOr(a.err, 2u);
+                bad = true;
             }
         }
     }
+    if (bad) atomicOr(a.err, 2u);
 }
 
 template <int kNT, typename Key, bool kOnesweep, int kBits, bool kGen = false>
