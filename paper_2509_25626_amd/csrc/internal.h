@@ -316,6 +316,7 @@ struct BlendArgs {
     const uint32_t* depth_bits;  // float32 bits of each Gaussian's depth (read with out_invdepth)
     float* out_invdepth;         // [H][W] expected inverse depth, or null
     uint32_t* counter;           // work counter of the work-stealing variant (3)
+    int64_t n;                   // number of splats: a list entry at or past it is never read
 };
 // variant: 1, 2, 4 = pixels per thread of the per-tile kernel; 3 = work-stealing half tiles
 hipError_t launch_blend(const BlendArgs& a, int variant, hipStream_t stream);
@@ -323,8 +324,9 @@ hipError_t launch_blend(const BlendArgs& a, int variant, hipStream_t stream);
 // Persistent blend over the tiles of a batch: workgroups pull global tile
 // ids from `counter` (zero on entry) until all `total_tiles` are done.
 hipError_t launch_blend_batch(const BatchItem* items, int nitems, int64_t total_tiles, const uint2* ranges,
-                              const uint32_t* point_list, const float2* mean2d, const float4* conic_opacity,
-                              const float4* rgb, uint32_t* counter, int grid, hipStream_t stream);
+                              const uint32_t* point_list, int64_t n, const float2* mean2d,
+                              const float4* conic_opacity, const float4* rgb, uint32_t* counter, int grid,
+                              hipStream_t stream);
 
 // Per-Gaussian 2D gradients of the backward pass, one row per Gaussian:
 // mean x, mean y, conic A, B, C, opacity, r, g, b, 1 / depth.

@@ -348,6 +348,7 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
     ba.depth_bits = sb.depth_bits;
     ba.out_invdepth = out_invdepth;
     ba.counter = reinterpret_cast<uint32_t*>(d_total + 8);  // a free word of the frame's totals
+    ba.n = n;
     CDS_HIP(launch_blend(ba, blend_variant, stream), "blend kernel");
     CDS_TRY(f->record(kEvBlend, stream));
     f->valid = true;

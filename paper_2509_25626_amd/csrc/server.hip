@@ -252,7 +252,7 @@ cds_status run_batch(cds_server* s, Workspace& w) {
     const bool odd = (tile_passes & 1) != 0;
     const uint32_t* values = (const uint32_t*)(odd ? f->vals1.p : f->vals0.p);
     const int64_t grid = std::min<int64_t>(T, (int64_t)s->cus * 8);
-    SRV_HIP(launch_blend_batch(w.items_dev, nitems, T, (const uint2*)f->ranges.p, values, sb.mean2d,
+    SRV_HIP(launch_blend_batch(w.items_dev, nitems, T, (const uint2*)f->ranges.p, values, N, sb.mean2d,
                                sb.conic_opacity, sb.rgb, w.counter, (int)grid, stream),
             "batched blend");
     SRV_HIP(hipEventRecord(w.done, stream), "hipEventRecord");

@@ -181,11 +181,18 @@ constexpr int kGenWindow = 256;  // records per wave window
 // key of rank c in a tile record's rectangle (make_tile_rec)
 __device__ __forceinline__ uint32_t rect_key(uint4 q, uint32_t c) {
     const uint32_t w = q.x & 0xFFFFu;
-    // c / w via a float estimate and an exact integer fix-up
-    uint32_t qq = (uint32_t)((float)c * __frcp_rn((float)w));
+    // c / w is a row of the rectangle, below 2^16; the estimate from the
+    // hardware reciprocal (1 ulp) is within 2^16 * 2^-21 of it, so its
+    // truncation is off by at most one, which one step each way corrects
+    uint32_t qq = (uint32_t)((float)c * __builtin_amdgcn_rcpf((float)w));
     int32_t rem = (int32_t)c - (int32_t)(qq * w);
-    while (rem < 0) { --qq; rem += (int32_t)w; }
-    while (rem >= (int32_t)w) { ++qq; rem -= (int32_t)w; }
+    if (rem < 0) {
+        --qq;
+        rem += (int32_t)w;
+    } else if (rem >= (int32_t)w) {
+        ++qq;
+        rem -= (int32_t)w;
+    }
     return q.w + qq * q.y + (uint32_t)rem;
 }
 
@@ -477,7 +484,10 @@ __device__ __forceinline__ void sort_pass_body(const PassArgs<Key>& a, uint32_t 
     if constexpr (kLeanRank || kWaveLocal) {
         // each round's old count is fetched as soon as its atomic returns:
         // the LDS latency is exposed per round, but no per-round state is
-        // held, which leaves room for more resident workgroups
+        // held, which leaves room for more resident workgroups.  The count
+        // travels from the group's first lane by ds_bpermute: a store by that
+        // lane and loads by the others would be ordered only in the source
+        // (the compiler may run the other lanes' loads first).
 #pragma unroll
         for (int r = 0; r < kKPT; ++r) {
             const bool valid = kFull || (wbase + r * kWave + l) < a.count;
@@ -515,7 +525,8 @@ __device__ __forceinline__ void sort_pass_body(const PassArgs<Key>& a, uint32_t 
         static_assert(kOnesweep && kBits <= 6 && sizeof(Key) == 4, "one digit per lane, 32-bit keys");
         constexpr uint32_t kDigW = 1u << kBits;
         constexpr int kWK = kWave * kKPT;                       // keys per wave
-        const uint32_t cnt = l < kDigW ? s_whist[w][l] : 0u;  // the wave's own atomics are complete
+        wave_lds_sync();  // the wave's ranking atomics (other lanes) before the reads
+        const uint32_t cnt = l < kDigW ? s_whist[w][l] : 0u;
         const uint32_t wst = wave_incl_sum(cnt) - cnt;         // digit l's start inside the slice
         if (l < kDigW) s_whist[w][l] = (wst << 16) | cnt;
         Key* s_wk = s_keys + (size_t)w * kWK;
@@ -573,10 +584,14 @@ __device__ __forceinline__ void sort_pass_body(const PassArgs<Key>& a, uint32_t 
                         v = (uint32_t)k & a.unpack_mask;
                     else
                         v = s_wv[i];
-                    if (a.gather_dst)  // uniform
-                        a.gather_dst[g] = a.gather_src[v];
-                    else
+                    if (a.gather_dst) {  // uniform; values are positions below count
+                        if (v < count32)
+                            a.gather_dst[g] = a.gather_src[v];
+                        else
+                            bad = true;
+                    } else {
                         a.vout[g] = a.vbits ? ((uint32_t)(k >> a.pack_shift) << a.vbits) | v : v;
+                    }
                 } else {
                     bad = true;
                 }
@@ -662,10 +677,14 @@ __device__ __forceinline__ void sort_pass_body(const PassArgs<Key>& a, uint32_t 
                     v = (uint32_t)k & a.unpack_mask;
                 else
                     v = s_vals[i];
-                if (a.gather_dst)  // uniform
-                    a.gather_dst[g] = a.gather_src[v];
-                else
+                if (a.gather_dst) {  // uniform; values are positions below count
+                    if (v < count32)
+                        a.gather_dst[g] = a.gather_src[v];
+                    else
+                        bad = true;
+                } else {
                     a.vout[g] = a.vbits ? ((uint32_t)(k >> a.pack_shift) << a.vbits) | v : v;
+                }
             } else {
                 bad = true;
             }
