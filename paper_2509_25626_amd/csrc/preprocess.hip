@@ -225,10 +225,19 @@ __global__ __launch_bounds__(256) void k_preprocess(ProjParams P, SceneParams S,
 // batch; each lane finds its scene by binary search over the item bases.
 __global__ __launch_bounds__(256) void k_preprocess_batch(const BatchItem* __restrict__ items, int nitems,
                                                           int64_t total, SplatBuffers O) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= total) return;
-    const int r = find_item_by_gaussian(items, nitems, g);
-    preprocess_one(items[r].P, items[r].S, g - items[r].gauss_base, O, g);
+    const int64_t g0 = (int64_t)blockIdx.x * blockDim.x;
+    const int64_t g = g0 + threadIdx.x;
+    const int64_t glast = (g0 + blockDim.x < total ? g0 + blockDim.x : total) - 1;
+    // a block almost always lies inside one item: then the item is looked up
+    // once and, uniform, its parameters load as scalars
+    const int r0 = find_item_by_gaussian(items, nitems, g0);
+    if (r0 == find_item_by_gaussian(items, nitems, glast)) {  // uniform
+        const int r = __builtin_amdgcn_readfirstlane(r0);
+        if (g < total) preprocess_one(items[r].P, items[r].S, g - items[r].gauss_base, O, g);
+    } else if (g < total) {
+        const int r = find_item_by_gaussian(items, nitems, g);
+        preprocess_one(items[r].P, items[r].S, g - items[r].gauss_base, O, g);
+    }
 }
 
 }  // namespace

@@ -108,6 +108,9 @@ namespace {
 // visible-splat records and depth sort, ~9 B per key (packed words and
 // values, sort status), keys estimated at 64 per Gaussian per megapixel,
 // scaled by what earlier batches measured.
+constexpr int64_t kBatchMaxTiles = kTileDiffLdsMaxTiles;     // 14-bit global tile ids
+constexpr int64_t kBatchMaxGaussians = int64_t(1) << 25;      // 25-bit Gaussian indices
+
 int64_t estimate_bytes(const cds_server* s, const cds_scene& sc, const cds_camera& cam) {
     const double mp = (double)cam.width * cam.height / 1.0e6;
     const double keys = s->key_scale * 64.0 * (double)sc.n * std::max(mp, 0.05);
@@ -218,7 +221,7 @@ cds_status run_batch(cds_server* s, Workspace& w) {
     const int tile_bits = tile_bits_for(T);
     SRV_HIP(launch_tile_counts(nvis, nullptr, nullptr, 0, T, (int*)f->tdiff.p, (uint2*)f->ranges.p,
                                (uint32_t*)f->thist.p, digit_plan(tile_passes, 0, tile_bits), nullptr, kTileCountBlocks,
-                               stream, nullptr, 0, recv),
+                               stream, nullptr, 0, (const uint4*)f->recc.p),  // index order: chunks stay in one request
             "batched tile counts");
     const size_t kk = (size_t)std::max<uint64_t>(K, 1);
     const bool fused = sort_uses_onesweep((int64_t)K, algo) && tile_passes > 0;
@@ -301,14 +304,23 @@ void worker_main(cds_server* s) {
         // admit: arrival order, slot limit, batch limit, HBM budget
         if (free_ws && !s->pending.empty()) {
             std::vector<SrvRequest*> batch;
-            int64_t bytes = 0;
+            int64_t bytes = 0, tiles = 0, gaussians = 0;
             while (!s->pending.empty() && (int)batch.size() < s->opts.max_batch &&
                    s->inflight + (int)batch.size() < s->opts.max_slots) {
                 SrvRequest* r = s->pending.front();
                 const bool alone = batch.empty() && s->reserved == 0;
                 if (!alone && s->reserved + bytes + r->est_bytes > s->budget) break;
+                // a batch's global tile ids and Gaussian indices stay small enough
+                // for the single render's sort shape: tile counts in one LDS array,
+                // two tile passes of at most 7-bit digits, and the second pass's
+                // key bits with the index in one packed word
+                const int64_t rt = (int64_t)((r->cam.width + CDS_TILE - 1) / CDS_TILE) * ((r->cam.height + CDS_TILE - 1) / CDS_TILE);
+                const int64_t rg = s->scenes[r->scene].n;
+                if (!batch.empty() && (tiles + rt > kBatchMaxTiles || gaussians + rg > kBatchMaxGaussians)) break;
                 batch.push_back(r);
                 bytes += r->est_bytes;
+                tiles += rt;
+                gaussians += rg;
                 s->pending.pop_front();
             }
             if (!batch.empty()) {

@@ -310,7 +310,8 @@ __device__ __forceinline__ uint32_t look_back(const PassArgs<Key>& a, uint32_t p
     constexpr uint32_t kDig = 1u << kBits;
     constexpr int kSeg = kNT >> kBits;  // threads per digit in the look-back
     // status words per thread and poll: a window of kSeg * kLookBack * 256 / kNT
-    // predecessors per digit
+    // predecessors per digit (for 512 threads over 8-bit digits a 32-word window
+    // measured slower than this 8)
     constexpr int kLookBack = kLookBack256 * 256 / kNT > 0 ? kLookBack256 * 256 / kNT : 1;
     const int t = threadIdx.x;
     uint32_t excl = 0;

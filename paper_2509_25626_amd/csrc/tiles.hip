@@ -79,6 +79,69 @@ __global__ __launch_bounds__(kDiffThreads) void k_tile_diff(DiffArgs a) {
     }
 }
 
+// Tile grids too large for one LDS array (batched renders, whose tile ids are
+// global): a workgroup takes a contiguous chunk of records.  The chunk's
+// records mostly belong to one or two requests, whose tile ids span a window
+// that fits LDS: the rows are counted there and the window is added to the
+// global array once.  A chunk whose window does not fit adds its rows with
+// global atomics.  Chunks are large enough that the window flushes (one
+// atomic per touched window entry) stay few: at most ~512 workgroups.
+constexpr int64_t kDiffChunkMin = (int64_t)kDiffThreads * 32;  // records per workgroup, at least
+constexpr int64_t kDiffChunkBlocks = 512;
+__global__ __launch_bounds__(kDiffThreads) void k_tile_diff_chunk(DiffArgs a, int64_t chunk) {
+    extern __shared__ int s_d[];  // kTileDiffLdsMaxTiles + 1 ints
+    __shared__ uint32_t s_lo, s_hi;
+    const int64_t n = a.count_dev ? (int64_t)*a.count_dev : a.n;
+    const int64_t c0 = (int64_t)blockIdx.x * chunk;
+    if (c0 >= n) return;  // uniform
+    const int64_t c1 = c0 + chunk < n ? c0 + chunk : n;
+    const int t = threadIdx.x;
+    if (t == 0) {
+        s_lo = 0xFFFFFFFFu;
+        s_hi = 0u;
+    }
+    __syncthreads();
+    // window [lo, hi]: every index a row of the chunk adds at
+    uint32_t lo = 0xFFFFFFFFu, hi = 0u;
+    for (int64_t i = c0 + t; i < c1; i += kDiffThreads) {
+        const uint4 q = a.rec[i];  // (width | height << 16, row stride, -, first tile)
+        const uint32_t w = q.x & 0xFFFFu, h = q.x >> 16;
+        const uint32_t last = h > 0 ? q.w + (h - 1) * q.y + w : q.w;
+        lo = q.w < lo ? q.w : lo;
+        hi = last > hi ? last : hi;
+    }
+    atomicMin(&s_lo, lo);
+    atomicMax(&s_hi, hi);
+    __syncthreads();
+    const uint32_t blo = s_lo, bhi = s_hi;
+    const bool fits = bhi >= blo && bhi - blo <= (uint32_t)kTileDiffLdsMaxTiles;  // uniform
+    if (fits) {
+        for (uint32_t k = (uint32_t)t; k <= bhi - blo; k += kDiffThreads) s_d[k] = 0;
+        __syncthreads();
+    }
+    for (int64_t i = c0 + t; i < c1; i += kDiffThreads) {
+        const uint4 q = a.rec[i];
+        const uint32_t w = q.x & 0xFFFFu, h = q.x >> 16;
+        uint32_t t0 = q.w;
+        for (uint32_t y = 0; y < h; ++y, t0 += q.y) {
+            if (fits) {
+                atomicAdd(&s_d[t0 - blo], 1);
+                atomicAdd(&s_d[t0 + w - blo], -1);
+            } else {
+                atomicAdd(&a.diff[t0], 1);
+                atomicAdd(&a.diff[t0 + w], -1);
+            }
+        }
+    }
+    if (fits) {
+        __syncthreads();
+        for (uint32_t k = (uint32_t)t; k <= bhi - blo; k += kDiffThreads) {
+            const int v = s_d[k];
+            if (v) atomicAdd(&a.diff[blo + k], v);
+        }
+    }
+}
+
 // One block: integrate the difference array to per-tile counts, scan them to
 // tile starts, and build the tile-digit histograms and K.
 constexpr int kRangeThreads = 1024;
@@ -179,6 +242,12 @@ hipError_t launch_tile_counts(int64_t n, const uint32_t* touched, const uint2* r
         if (ntiles <= kTileDiffLdsMaxTiles)
             hipLaunchKernelGGL(k_tile_diff<true>, dim3((unsigned)blocks), dim3(kDiffThreads),
                                sizeof(int) * (size_t)(ntiles + 1), stream, a);
+        else if (rec) {
+            int64_t chunk = (n + kDiffChunkBlocks - 1) / kDiffChunkBlocks;
+            if (chunk < kDiffChunkMin) chunk = kDiffChunkMin;
+            hipLaunchKernelGGL(k_tile_diff_chunk, dim3((unsigned)((n + chunk - 1) / chunk)), dim3(kDiffThreads),
+                               sizeof(int) * (size_t)(kTileDiffLdsMaxTiles + 1), stream, a, chunk);
+        }
         else
             hipLaunchKernelGGL(k_tile_diff<false>, dim3((unsigned)blocks), dim3(kDiffThreads), 0, stream, a);
         if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -137,11 +137,14 @@ def test_c1_forward_parity(R, sort_variant, sort_algo):
 
 
 @pytest.mark.parametrize("wh,n", [((203, 117), 30_000), ((16, 16), 30_000), ((1, 1), 30_000),
-                                  ((1237, 822), 40_000), ((8192, 300), 20_000), ((5000, 64), 9_000)])
+                                  ((1237, 822), 40_000), ((8192, 300), 20_000), ((5000, 64), 9_000),
+                                  ((2200, 2000), 30_000)])
 def test_sort_variants_bit_identical(R, wh, n):
     # every digit per key == depth digits per Gaussian + tile digits per key ==
     # depth digits per Gaussian + tile binning.  The wide images give bands of
-    # fewer than 16 tile rows and (8192x300) longer chunks for a large tile grid.
+    # fewer than 16 tile rows and (8192x300) longer chunks for a large tile grid;
+    # 2200x2000 has more tiles (17,250) than one LDS difference array holds, so
+    # its tile counts go through record chunks.
     W, H = wh
     scene = S.scene_outdoor(15, n)
     cam = S.orbit_camera(W, H, 4.0, 10.0, 0.0)
