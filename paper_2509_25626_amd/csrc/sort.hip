@@ -186,13 +186,12 @@ __device__ __forceinline__ uint32_t rect_key(uint4 q, uint32_t c) {
     // truncation is off by at most one, which one step each way corrects
     uint32_t qq = (uint32_t)((float)c * __builtin_amdgcn_rcpf((float)w));
     int32_t rem = (int32_t)c - (int32_t)(qq * w);
-    if (rem < 0) {
-        --qq;
-        rem += (int32_t)w;
-    } else if (rem >= (int32_t)w) {
-        ++qq;
-        rem -= (int32_t)w;
-    }
+    const bool low = rem < 0;  // selects, not branches
+    qq = low ? qq - 1u : qq;
+    rem = low ? rem + (int32_t)w : rem;
+    const bool high = rem >= (int32_t)w;
+    qq = high ? qq + 1u : qq;
+    rem = high ? rem - (int32_t)w : rem;
     return q.w + qq * q.y + (uint32_t)rem;
 }
 
@@ -235,9 +234,12 @@ __device__ __forceinline__ void generate_keys(const KeyGen& g, int64_t count, in
         wave_lds_sync();
         const uint4 mk = s_flag[l];
         const uint32_t mw[4] = {mk.x, mk.y, mk.z, mk.w};
-        const uint64_t le_mask = (2ull << l) - 1ull;  // lanes 0..l
-        int64_t jr = jb;                                // owner of the key before the round
-        constexpr int kGroup = 4;                       // rounds whose owner data are read together
+        // 32-bit from here: keys and offsets are below 2^30, window slots below 256
+        const uint32_t wb32 = (uint32_t)wbase + l;
+        const int64_t left = count - wbase;  // keys of the wave that exist
+        const uint32_t nkeys = left < (int64_t)(kWave * kRounds) ? (uint32_t)left : (uint32_t)(kWave * kRounds);
+        int kr = (int)(jb - jw);           // window slot of the owner of the key before the round
+        constexpr int kGroup = 4;          // rounds whose owner data are read together
 #pragma unroll
         for (int g0 = 0; g0 < kRounds; g0 += kGroup) {
             uint4 q[kGroup];
@@ -246,14 +248,15 @@ __device__ __forceinline__ void generate_keys(const KeyGen& g, int64_t count, in
             for (int i = 0; i < kGroup; ++i) {
                 const int r = g0 + i;
                 const uint64_t b = ballot(((mw[r >> 2] >> (8 * (r & 3))) & 0xFFu) != 0u);
-                const int k = (int)(jr - jw) + __popcll(b & le_mask);
+                // starts at lanes 0..l: those of b >> 1 below the lane, plus lane 0's
+                const int k = kr + (int)count_below(b >> 1) + (int)(b & 1u);
                 q[i] = s_rec[k];
-                c[i] = (uint32_t)(wbase + r * kWave + l - s_off[k]);
-                jr += __popcll(b);
+                c[i] = wb32 + (uint32_t)(r * kWave) - s_off[k];
+                kr += __popcll(b);
             }
 #pragma unroll
             for (int i = 0; i < kGroup; ++i) {
-                if (wbase + (g0 + i) * kWave + l < count) {
+                if ((uint32_t)((g0 + i) * kWave) + l < nkeys) {
                     key[g0 + i] = rect_key(q[i], c[i]);
                     val[g0 + i] = q[i].z;
                 }
