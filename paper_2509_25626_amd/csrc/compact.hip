@@ -143,8 +143,7 @@ hipError_t launch_compact_visible(int64_t n, const uint32_t* touched, const uint
                            key_sums);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    if ((e = launch_scan_u64(vis_sums, tiles, totals, stream)) != hipSuccess) return e;
-    if ((e = launch_scan_u64(key_sums, tiles, totals + 1, stream)) != hipSuccess) return e;
+    if ((e = launch_scan_u64_pair(vis_sums, key_sums, tiles, totals, totals + 1, stream)) != hipSuccess) return e;
     if (tiles > 0) {
         hipLaunchKernelGGL(k_vis_scatter, dim3((unsigned)tiles), dim3(kCT), 0, stream, n, touched, rect, depth_bits,
                            vis_sums, dkey, rec, depth_hist, (uint32_t)tiles_x, items, nitems);

@@ -86,6 +86,9 @@ hipError_t launch_preprocess_batch(const BatchItem* items, int nitems, int64_t t
 
 // Exclusive scan of `count` uint64 values in place (one workgroup), total to *total.
 hipError_t launch_scan_u64(uint64_t* values, int64_t count, uint64_t* total, hipStream_t stream);
+// two such scans of `count` values each in one launch
+hipError_t launch_scan_u64_pair(uint64_t* a, uint64_t* b, int64_t count, uint64_t* total_a, uint64_t* total_b,
+                                hipStream_t stream);
 
 // Tile record of a visible splat (16 B): its rectangle of tiles as runs of
 // tile ids, (width | height << 16, row stride, Gaussian index, id of the first
@@ -207,8 +210,10 @@ hipError_t launch_sort_histogram(const uint64_t* keys, int64_t count, int passes
                                  hipStream_t stream, int end_bit = 0);
 hipError_t launch_sort_histogram(const uint32_t* keys, int64_t count, int passes, int shift0, uint32_t* hist,
                                  hipStream_t stream, int end_bit = 0);
+// key_bytes: 4 when the sort's keys are 32-bit (its status words then cover
+// wide partitions from 2^23 keys on); the default clears for narrow ones, a superset
 hipError_t launch_sort_prepare(const SortWorkspace& ws, int64_t count, int passes, bool clear_hist,
-                               hipStream_t stream);
+                               hipStream_t stream, int key_bytes = 8);
 // The sort covers key bits [shift0, end_bit) (end_bit 0: shift0 + 8 * passes)
 // split over the passes by digit_plan.  keep_keys false: the last pass
 // writes only the values (its keys are left unwritten).

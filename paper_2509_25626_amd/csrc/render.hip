@@ -197,7 +197,7 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
         if (n > 0) {
             // depth sort of the compacted keys (values: compacted positions); the
             // last pass writes the records in depth order (recv) instead
-            if (sort_uses_onesweep(n, algo)) CDS_HIP(launch_sort_prepare(wd, n, 4, false, stream), "depth prepare");
+            if (sort_uses_onesweep(n, algo)) CDS_HIP(launch_sort_prepare(wd, n, 4, false, stream, 4), "depth prepare");
             CDS_HIP(launch_sort_passes((const uint32_t*)f->dkeyc.p, nullptr, (uint32_t*)f->dkey0.p,
                                        (uint32_t*)f->order0.p, (uint32_t*)f->dkey1.p, (uint32_t*)f->order1.p, n, 4,
                                        0, wd, algo, stream, 32, false, nullptr, value_bits_for(n - 1), nullptr,
@@ -274,7 +274,7 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
         if (K > 0) {
             if (compact) {
                 // the onesweep passes take the tile-digit histograms made from the rectangles
-                if (onesweep) CDS_HIP(launch_sort_prepare(ws, (int64_t)K, passes, false, stream), "sort prepare");
+                if (onesweep) CDS_HIP(launch_sort_prepare(ws, (int64_t)K, passes, false, stream, 4), "sort prepare");
                 ws.hist = (uint32_t*)f->thist.p;
                 if (!fused)
                     CDS_HIP(launch_duplicate(nvis, nullptr, (const uint32_t*)f->offsets.p, nullptr, nullptr,

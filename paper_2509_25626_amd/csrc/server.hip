@@ -206,7 +206,7 @@ cds_status run_batch(cds_server* s, Workspace& w) {
     if (nvis > 0) {
         // depth order of the visible splats, their records in that order, key
         // offsets and the owner of every 1024th key
-        if (sort_uses_onesweep(nvis, algo)) SRV_HIP(launch_sort_prepare(wd, nvis, 4, false, stream), "depth prepare");
+        if (sort_uses_onesweep(nvis, algo)) SRV_HIP(launch_sort_prepare(wd, nvis, 4, false, stream, 4), "depth prepare");
         SRV_HIP(launch_sort_passes((const uint32_t*)f->dkeyc.p, nullptr, (uint32_t*)f->dkey0.p, (uint32_t*)f->order0.p,
                                    (uint32_t*)f->dkey1.p, (uint32_t*)f->order1.p, nvis, 4, 0, wd, algo, stream, 32,
                                    false, nullptr, value_bits_for(nvis - 1), nullptr, (const uint4*)f->recc.p,
@@ -236,7 +236,7 @@ cds_status run_batch(cds_server* s, Workspace& w) {
     SortWorkspace ws = sort_ws(ctx, f->sort);
     if (K > 0) {
         if (sort_uses_onesweep((int64_t)K, algo) && tile_passes > 0)
-            SRV_HIP(launch_sort_prepare(ws, (int64_t)K, tile_passes, false, stream), "sort prepare");
+            SRV_HIP(launch_sort_prepare(ws, (int64_t)K, tile_passes, false, stream, 4), "sort prepare");
         ws.hist = (uint32_t*)f->thist.p;
         KeyGen gen;
         gen.off = (const uint32_t*)f->offsets.p;

@@ -957,8 +957,10 @@ hipError_t launch_sort_histogram(const uint32_t* keys, int64_t count, int passes
 }
 
 hipError_t launch_sort_prepare(const SortWorkspace& ws, int64_t count, int passes, bool clear_hist,
-                               hipStream_t stream) {
-    const int64_t parts = sort_partitions(count);
+                               hipStream_t stream, int key_bytes) {
+    // the partitions the passes will use: 32-bit keys from 2^23 on run wide
+    // (a reduce-then-scan sort uses no status words at all)
+    const int64_t parts = key_bytes == 4 && sort_uses_wide(count) ? sort_partitions_wide(count) : sort_partitions(count);
     hipError_t e = launch_fill_u32(ws.status, (int64_t)passes * parts * 256, 0u, stream);
     if (e != hipSuccess) return e;
     e = launch_fill_u32(ws.counters, passes, 0u, stream);
