@@ -296,16 +296,25 @@ void worker_main(cds_server* s) {
         s->cv.notify_all();
         int nbusy = 0;
         Workspace* free_ws = nullptr;
+        int nfree = 0;
         for (Workspace& w : s->ws) {
             if (w.busy) ++nbusy;
-            else if (!free_ws) free_ws = &w;
+            else {
+                ++nfree;
+                if (!free_ws) free_ws = &w;
+            }
         }
         if (s->stop && s->pending.empty() && nbusy == 0) break;
         // admit: arrival order, slot limit, batch limit, HBM budget
         if (free_ws && !s->pending.empty()) {
             std::vector<SrvRequest*> batch;
             int64_t bytes = 0, tiles = 0, gaussians = 0;
-            while (!s->pending.empty() && (int)batch.size() < s->opts.max_batch &&
+            // a short queue is spread over the free workspaces (their batches
+            // run side by side) rather than packed into one batch that all of
+            // its requests wait for; a long one still fills batches
+            const int share = (int)((s->pending.size() + (size_t)nfree - 1) / (size_t)nfree);
+            const int limit = std::min(s->opts.max_batch, std::max(1, share));
+            while (!s->pending.empty() && (int)batch.size() < limit &&
                    s->inflight + (int)batch.size() < s->opts.max_slots) {
                 SrvRequest* r = s->pending.front();
                 const bool alone = batch.empty() && s->reserved == 0;
