@@ -304,7 +304,8 @@ cds_status cds_check_device(cds_ctx* ctx, void* stream);
 
 typedef struct cds_server_opts {
     int32_t max_slots;          /* requests in flight at once (1..64) */
-    int32_t max_batch;          /* requests fused into one batched launch (1..max_slots) */
+    int32_t max_batch;          /* at most this many requests fused into one batched launch (1..max_slots);
+                                   fewer when the queue is short or the batch reaches 16,383 tiles or 2^25 Gaussians */
     int64_t hbm_budget_bytes;   /* workspace budget for admitted requests; 0 = free HBM at create */
 } cds_server_opts;
 

@@ -4,7 +4,11 @@
 // scheduler thread admits queued requests in arrival order whenever a batch
 // workspace is free, the number of requests in flight is below the slot
 // limit, and the estimated workspace of the admitted requests fits the HBM
-// budget.  Each admitted batch runs as one pass of batched kernels:
+// budget.  A batch takes at most max_batch requests and at most its share of
+// the queue over the free workspaces (a short queue runs as batches side by
+// side), and stops before its global tile ids pass 14 bits or its Gaussian
+// indices 25, so that it sorts like a single render.  Each admitted batch
+// runs as one pass of batched kernels:
 // preprocess over the concatenated Gaussians of all its scenes, compaction
 // of the visible splats into tile records in global tile ids (request tile
 // bases) and the key-count read-back, one depth sort, the key offsets, the
