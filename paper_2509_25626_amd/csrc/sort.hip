@@ -6,7 +6,8 @@
 // key bits are split evenly over the passes).  A workgroup (256 threads over
 // 4096 keys, or 512 over 8192 for onesweep sorts of 2^23+ 32-bit keys) ranks
 // its keys stably in LDS, reorders them by digit and writes each digit run as
-// one contiguous, coalesced store.  Ranking is wave64
+// one contiguous, coalesced store (the 8192-key packed-word pass reorders wave
+// by wave, so each wave writes its own runs and needs fewer registers).  Ranking is wave64
 // native: keys are held "wave-striped" (round r of a wave covers 64
 // consecutive input keys), lanes with the same digit are found with one
 // ballot per digit bit, and a per-wave per-digit counter in LDS gives each key
