@@ -121,12 +121,6 @@ __global__ __launch_bounds__(kCT) void k_vis_scatter(int64_t n, const uint32_t* 
     }
 }
 
-__global__ __launch_bounds__(256) void k_rec_gather(int64_t count, const uint32_t* __restrict__ order,
-                                                    const uint4* __restrict__ src, uint4* __restrict__ dst) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < count) dst[j] = src[order[j]];
-}
-
 }  // namespace
 
 int64_t compact_sums_size(int64_t n) { return (n + kCTile - 1) / kCTile + 1; }
@@ -150,13 +144,6 @@ hipError_t launch_compact_visible(int64_t n, const uint32_t* touched, const uint
         e = hipGetLastError();
     }
     return e;
-}
-
-hipError_t launch_rec_gather(int64_t count, const uint32_t* order, const uint4* src, uint4* dst, hipStream_t stream) {
-    if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_rec_gather, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, stream, count, order, src,
-                       dst);
-    return hipGetLastError();
 }
 
 }  // namespace cds

@@ -84,9 +84,8 @@ __device__ __forceinline__ int find_item_by_tile(const BatchItem* items, int nit
 hipError_t launch_preprocess_batch(const BatchItem* items, int nitems, int64_t total, const SplatBuffers& out,
                                    hipStream_t stream);
 
-// Exclusive scan of `count` uint64 values in place (one workgroup), total to *total.
-hipError_t launch_scan_u64(uint64_t* values, int64_t count, uint64_t* total, hipStream_t stream);
-// two such scans of `count` values each in one launch
+// Two exclusive in-place scans of `count` uint64 values each (one workgroup
+// per array, one launch); the totals go to *total_a and *total_b.
 hipError_t launch_scan_u64_pair(uint64_t* a, uint64_t* b, int64_t count, uint64_t* total_a, uint64_t* total_b,
                                 hipStream_t stream);
 
@@ -113,8 +112,6 @@ hipError_t launch_compact_visible(int64_t n, const uint32_t* touched, const uint
                                   uint64_t* vis_sums, uint64_t* key_sums, uint64_t* totals, uint32_t* dkey,
                                   uint4* rec, uint32_t* depth_hist, hipStream_t stream, int tiles_x,
                                   const BatchItem* items = nullptr, int nitems = 0);
-// dst[j] = src[order[j]]
-hipError_t launch_rec_gather(int64_t count, const uint32_t* order, const uint4* src, uint4* dst, hipStream_t stream);
 
 // Exclusive scan of n uint32 values (read as in[gather[i]] when gather is
 // not null); the total (uint64, device) is written too.  `block_sums` needs

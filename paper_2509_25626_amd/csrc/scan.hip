@@ -118,11 +118,6 @@ __global__ __launch_bounds__(kNT) void k_scan_down(ScanSrc src, int64_t n, const
 
 int64_t scan_block_sums_size(int64_t n) { return (n + kTileItems - 1) / kTileItems + 1; }
 
-hipError_t launch_scan_u64(uint64_t* values, int64_t count, uint64_t* total, hipStream_t stream) {
-    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, stream, values, count, total, nullptr, nullptr);
-    return hipGetLastError();
-}
-
 hipError_t launch_scan_u64_pair(uint64_t* a, uint64_t* b, int64_t count, uint64_t* total_a, uint64_t* total_b,
                                 hipStream_t stream) {
     hipLaunchKernelGGL(k_scan_sums, dim3(2), dim3(1024), 0, stream, a, count, total_a, b, total_b);
