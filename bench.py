@@ -96,10 +96,28 @@ def roofline(stages, scene, K, passes, info, first_pass_ms, variant, algo):
     if dom == "sort_ms":  # the first pass alone, from its own event
         per_launch_ms = first_pass_ms
     achieved = nbytes / (per_launch_ms * 1e-3) / 1e9
+    traffic = measured_traffic(kernel)
     return {"kernel": kernel, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kernel),
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "algorithmic_bytes_per_launch": int(nbytes), "launches_per_frame": launches,
-            "avg_launch_ms": round(per_launch_ms, 4)}
+            "avg_launch_ms": round(per_launch_ms, 4),
+            # what bounds it instead: the VALU-busy fraction of the same profile
+            # (reported with the traffic, i.e. while the kernel source is unchanged)
+            "valu_busy": measured_valu_busy(kernel) if traffic is not None else None}
+
+
+def measured_valu_busy(kernel):
+    """VALU-busy fraction of `kernel` from the committed rocprofv3 activity
+    table (SQ_ACTIVE_INST_VALU over SIMD cycles), or None."""
+    path = os.path.join(ROOT, "profiles", "c2_utilisation.txt")
+    try:
+        with open(path) as f:
+            for line in f:
+                if line.startswith(kernel + " ") or line.startswith(kernel[:34] + " "):
+                    return float(line[34:].split()[1])
+    except (OSError, ValueError, IndexError):
+        return None
+    return None
 
 
 def measured_traffic(kernel):
