@@ -109,8 +109,12 @@ __global__ __launch_bounds__(kCT) void k_vis_scatter(int64_t n, const uint32_t* 
             }
             dkey[pos] = d;
             rec[pos] = make_tile_rec(rc, tx, tb, (uint32_t)i);
+            // the three low depth bytes spread over their 256 values: plain
+            // atomics; the top byte (sign and exponent) takes few values, so
+            // its equal digits are merged first
 #pragma unroll
-            for (int p = 0; p < 4; ++p) hist_add(s_hist + p * 256, (d >> (8 * p)) & 255u);
+            for (int p = 0; p < 3; ++p) atomicAdd(&s_hist[p * 256 + ((d >> (8 * p)) & 255u)], 1u);
+            hist_add(s_hist + 3 * 256, d >> 24);
         }
         slot += (uint32_t)__popcll(m);
     }
