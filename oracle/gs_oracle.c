@@ -41,6 +41,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define TILE 16
 
@@ -73,6 +76,12 @@ static double t_min(void) { volatile float f = 0.0001f; return (double)f; }
 #define CF_JX 8u
 #define CF_JY 16u
 
+/* True when v lies within a millionth of an ulp of a float32 rounding
+ * midpoint without sitting exactly on it.  A value exactly on a midpoint
+ * rounds to even in every IEEE implementation, so it is only ambiguous when a
+ * different evaluation order could land on either side; the callers use this
+ * for values the pipeline computes in one fixed order of double operations,
+ * where an exact tie is reproduced exactly and is not a disagreement. */
 static int near_f32_midpoint(double v) {
     float f = (float)v;
     double df = (double)f;
@@ -80,7 +89,7 @@ static int near_f32_midpoint(double v) {
     double dn = (double)nextafterf(f, -INFINITY);
     double ulp = up - df;
     double mid_hi = 0.5 * (df + up), mid_lo = 0.5 * (df + dn);
-    return fabs(v - mid_hi) < 1e-6 * ulp || fabs(v - mid_lo) < 1e-6 * (df - dn);
+    return (v != mid_hi && fabs(v - mid_hi) < 1e-6 * ulp) || (v != mid_lo && fabs(v - mid_lo) < 1e-6 * (df - dn));
 }
 
 static double round_to_f32(double v) { return (double)(float)v; }
@@ -447,6 +456,8 @@ typedef struct {
     double D;                     /* expected inverse depth: sum of a T / depth */
     uint32_t ncontrib;
     uint32_t nused;               /* Gaussians actually blended */
+    uint32_t neval;               /* list entries examined: up to and including the
+                                     one that stops the pixel, else the whole list */
     double m_power, m_alpha, m_T; /* smallest relative decision margins */
 } pixres;
 
@@ -492,7 +503,7 @@ static void blend_pixel(int px, int py, const uint32_t* list, int64_t len, int64
             double mt = fabs(Tn / tmin - 1.0);
             if (mt < m_T) m_T = mt;
         }
-        if (Tn < tmin) break;
+        if (Tn < tmin) { ++j; break; }
         if (c_count) {
             c_pos[nc] = j; c_T[nc] = T; c_alpha[nc] = a; c_G[nc] = G; c_clamped[nc] = clamped;
         }
@@ -510,14 +521,16 @@ static void blend_pixel(int px, int py, const uint32_t* list, int64_t len, int64
     out->D = D;
     out->ncontrib = last;
     out->nused = (uint32_t)nc;
+    out->neval = (uint32_t)j;
     out->m_power = m_power; out->m_alpha = m_alpha; out->m_T = m_T;
 }
 
 static void store_pixel(const pixres* r, int64_t pix, int64_t npix, const double* bg,
                         double* out_rgb, double* out_T, uint32_t* n_contrib, double* margins,
-                        uint32_t* n_used, double* out_invdepth) {
+                        uint32_t* n_used, double* out_invdepth, uint32_t* n_eval) {
     int ch;
     if (n_used) n_used[pix] = r->nused;
+    if (n_eval) n_eval[pix] = r->neval;
     if (out_invdepth) out_invdepth[pix] = r->D;
     for (ch = 0; ch < 3; ++ch) out_rgb[ch * npix + pix] = r->C[ch] + r->Tfinal * bg[ch];
     out_T[pix] = r->Tfinal;
@@ -537,7 +550,7 @@ int ora_blend_tiles(int W, int H, int64_t n, const uint32_t* ranges, const uint3
                     double* out_rgb /*[3][H][W]*/, double* out_T /*[H][W]*/,
                     uint32_t* n_contrib /*[H][W]*/, double* margins /*[3][H][W] or NULL*/,
                     uint32_t* n_used /*[H][W] or NULL*/, const double* invd /*[n] or NULL*/,
-                    double* out_invdepth /*[H][W] or NULL*/) {
+                    double* out_invdepth /*[H][W] or NULL*/, uint32_t* n_eval /*[H][W] or NULL*/) {
     const int tiles_x = (W + TILE - 1) / TILE;
     const int64_t npix = (int64_t)W * H;
     int64_t p;
@@ -549,7 +562,7 @@ int ora_blend_tiles(int W, int H, int64_t n, const uint32_t* ranges, const uint3
         pixres r;
         blend_pixel(x, y, point_list + s, (int64_t)e - s, n, mean2d, conic, opacity, rgb, invd, &r,
                     NULL, NULL, NULL, NULL, NULL, NULL);
-        store_pixel(&r, p, npix, bg, out_rgb, out_T, n_contrib, margins, n_used, out_invdepth);
+        store_pixel(&r, p, npix, bg, out_rgb, out_T, n_contrib, margins, n_used, out_invdepth, n_eval);
     }
     return 0;
 }
@@ -602,7 +615,7 @@ int ora_blend_brute(int W, int H, int64_t n, const int32_t* radius, const int32_
         }
         blend_pixel(x, y, list, len, n, mean2d, conic, opacity, rgb, invd, &r, NULL, NULL, NULL, NULL, NULL,
                     NULL);
-        store_pixel(&r, p, npix, bg, out_rgb, out_T, n_contrib, margins, n_used, out_invdepth);
+        store_pixel(&r, p, npix, bg, out_rgb, out_T, n_contrib, margins, n_used, out_invdepth, NULL);
         free(list);
     }
     free(sorted);
@@ -635,70 +648,111 @@ int ora_backward_2d(int W, int H, int64_t n, const uint32_t* ranges, const uint3
                     const double* invd /*[n] or NULL*/, const double* dL_dinvdepth /*[H][W] or NULL*/,
                     double* g_invd /*[n] or NULL*/) {
     const int depth_on = invd && dL_dinvdepth && g_invd;
-    const int tiles_x = (W + TILE - 1) / TILE;
+    const int tiles_x = (W + TILE - 1) / TILE, tiles_y = (H + TILE - 1) / TILE;
     const int64_t npix = (int64_t)W * H;
-    int64_t p, maxlen = 0, t, ntiles = (int64_t)tiles_x * ((H + TILE - 1) / TILE);
-    int64_t *c_pos;
-    double *c_T, *c_alpha, *c_G;
-    int* c_clamped;
-    memset(g_mean2d, 0, sizeof(double) * 2 * (size_t)n);
-    memset(g_conic, 0, sizeof(double) * 3 * (size_t)n);
-    memset(g_opacity, 0, sizeof(double) * (size_t)n);
-    memset(g_rgb, 0, sizeof(double) * 3 * (size_t)n);
-    if (g_invd) memset(g_invd, 0, sizeof(double) * (size_t)n);
+    /* per-thread accumulator: mean2d[2][n] conic[3][n] opacity[n] rgb[3][n] invd[n] */
+    const int64_t nacc = 10 * n;
+    int64_t maxlen = 0, t, ntiles = (int64_t)tiles_x * tiles_y;
+    int nthreads = 1, failed = 0;
+    double* acc;
     for (t = 0; t < ntiles; ++t) {
         int64_t len = (int64_t)ranges[2 * t + 1] - ranges[2 * t];
         if (len > maxlen) maxlen = len;
     }
-    c_pos = (int64_t*)malloc(sizeof(int64_t) * (size_t)(maxlen + 1));
-    c_T = (double*)malloc(sizeof(double) * (size_t)(maxlen + 1));
-    c_alpha = (double*)malloc(sizeof(double) * (size_t)(maxlen + 1));
-    c_G = (double*)malloc(sizeof(double) * (size_t)(maxlen + 1));
-    c_clamped = (int*)malloc(sizeof(int) * (size_t)(maxlen + 1));
-    if (!c_pos || !c_T || !c_alpha || !c_G || !c_clamped) return 2;
-    for (p = 0; p < npix; ++p) {
-        const int x = (int)(p % W), y = (int)(p / W);
-        const int tt = (y / TILE) * tiles_x + x / TILE;
-        const uint32_t s = ranges[2 * tt], e = ranges[2 * tt + 1];
-        const uint32_t* list = point_list + s;
-        double go[3], S[3], gd = 0.0, Sd = 0.0;
-        int64_t nc = 0, k;
-        int ch;
-        pixres r;
-        blend_pixel(x, y, list, (int64_t)e - s, n, mean2d, conic, opacity, rgb, NULL, &r,
-                    c_pos, c_T, c_alpha, c_G, c_clamped, &nc);
-        for (ch = 0; ch < 3; ++ch) { go[ch] = dL_dout[ch * npix + p]; S[ch] = bg[ch]; }
-        if (depth_on) gd = dL_dinvdepth[p];
-        for (k = nc - 1; k >= 0; --k) {
-            const uint32_t g = list[c_pos[k]];
-            const double a = c_alpha[k], T = c_T[k], G = c_G[k];
-            const double dx = mean2d[g] - x, dy = mean2d[n + g] - y;
-            const double A = conic[g], B = conic[n + g], Cc = conic[2 * n + g];
-            double dLda = 0.0;
-            for (ch = 0; ch < 3; ++ch) {
-                const double c = rgb[ch * n + g];
-                g_rgb[ch * n + g] += a * T * go[ch];
-                dLda += T * (c - S[ch]) * go[ch];
-                S[ch] = a * c + (1.0 - a) * S[ch];
-            }
-            if (depth_on) {
-                g_invd[g] += a * T * gd;
-                dLda += T * (invd[g] - Sd) * gd;
-                Sd = a * invd[g] + (1.0 - a) * Sd;
-            }
-            if (!c_clamped[k]) {
-                const double dLdp = dLda * a;
-                g_opacity[g] += dLda * G;
-                /* power = -0.5 (A dx^2 + C dy^2) - B dx dy, dx = mean_x - px */
-                g_mean2d[g] += dLdp * (-(A * dx + B * dy));
-                g_mean2d[n + g] += dLdp * (-(Cc * dy + B * dx));
-                g_conic[g] += dLdp * (-0.5 * dx * dx);
-                g_conic[n + g] += dLdp * (-dx * dy);
-                g_conic[2 * n + g] += dLdp * (-0.5 * dy * dy);
-            }
+#ifdef _OPENMP
+    nthreads = omp_get_max_threads();
+#endif
+    acc = (double*)calloc((size_t)(nacc > 0 ? nacc : 1) * (size_t)nthreads, sizeof(double));
+    if (!acc) return 2;
+    /* Tiles are dealt to threads round-robin (a fixed assignment for a fixed
+     * thread count); each thread sums into its own accumulator, and the
+     * accumulators are added in thread order at the end. */
+#pragma omp parallel num_threads(nthreads) reduction(| : failed)
+    {
+        int tid = 0;
+        double *a_mean, *a_conic, *a_op, *a_rgb, *a_invd;
+        int64_t* c_pos = (int64_t*)malloc(sizeof(int64_t) * (size_t)(maxlen + 1));
+        double* c_T = (double*)malloc(sizeof(double) * (size_t)(maxlen + 1));
+        double* c_alpha = (double*)malloc(sizeof(double) * (size_t)(maxlen + 1));
+        double* c_G = (double*)malloc(sizeof(double) * (size_t)(maxlen + 1));
+        int* c_clamped = (int*)malloc(sizeof(int) * (size_t)(maxlen + 1));
+        int64_t tt;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        a_mean = acc + (size_t)tid * (size_t)nacc;
+        a_conic = a_mean + 2 * n;
+        a_op = a_conic + 3 * n;
+        a_rgb = a_op + n;
+        a_invd = a_rgb + 3 * n;
+        if (!c_pos || !c_T || !c_alpha || !c_G || !c_clamped) failed = 1;
+#pragma omp for schedule(static, 1)
+        for (tt = 0; tt < ntiles; ++tt) {
+            const int tx = (int)(tt % tiles_x), ty = (int)(tt / tiles_x);
+            const uint32_t s = ranges[2 * tt], e = ranges[2 * tt + 1];
+            const uint32_t* list = point_list + s;
+            int x, y;
+            if (failed) continue;
+            for (y = ty * TILE; y < H && y < (ty + 1) * TILE; ++y)
+                for (x = tx * TILE; x < W && x < (tx + 1) * TILE; ++x) {
+                    const int64_t p = (int64_t)y * W + x;
+                    double go[3], S[3], gd = 0.0, Sd = 0.0;
+                    int64_t nc = 0, k;
+                    int ch;
+                    pixres r;
+                    blend_pixel(x, y, list, (int64_t)e - s, n, mean2d, conic, opacity, rgb, NULL, &r,
+                                c_pos, c_T, c_alpha, c_G, c_clamped, &nc);
+                    for (ch = 0; ch < 3; ++ch) { go[ch] = dL_dout[ch * npix + p]; S[ch] = bg[ch]; }
+                    if (depth_on) gd = dL_dinvdepth[p];
+                    for (k = nc - 1; k >= 0; --k) {
+                        const uint32_t g = list[c_pos[k]];
+                        const double a = c_alpha[k], T = c_T[k], G = c_G[k];
+                        const double dx = mean2d[g] - x, dy = mean2d[n + g] - y;
+                        const double A = conic[g], B = conic[n + g], Cc = conic[2 * n + g];
+                        double dLda = 0.0;
+                        for (ch = 0; ch < 3; ++ch) {
+                            const double c = rgb[ch * n + g];
+                            a_rgb[ch * n + g] += a * T * go[ch];
+                            dLda += T * (c - S[ch]) * go[ch];
+                            S[ch] = a * c + (1.0 - a) * S[ch];
+                        }
+                        if (depth_on) {
+                            a_invd[g] += a * T * gd;
+                            dLda += T * (invd[g] - Sd) * gd;
+                            Sd = a * invd[g] + (1.0 - a) * Sd;
+                        }
+                        if (!c_clamped[k]) {
+                            const double dLdp = dLda * a;
+                            a_op[g] += dLda * G;
+                            /* power = -0.5 (A dx^2 + C dy^2) - B dx dy, dx = mean_x - px */
+                            a_mean[g] += dLdp * (-(A * dx + B * dy));
+                            a_mean[n + g] += dLdp * (-(Cc * dy + B * dx));
+                            a_conic[g] += dLdp * (-0.5 * dx * dx);
+                            a_conic[n + g] += dLdp * (-dx * dy);
+                            a_conic[2 * n + g] += dLdp * (-0.5 * dy * dy);
+                        }
+                    }
+                }
         }
+        free(c_pos); free(c_T); free(c_alpha); free(c_G); free(c_clamped);
     }
-    free(c_pos); free(c_T); free(c_alpha); free(c_G); free(c_clamped);
+    if (failed) { free(acc); return 2; }
+    /* sum the accumulators in thread order */
+#pragma omp parallel for schedule(static)
+    for (t = 0; t < n; ++t) {
+        double s[10] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        int th, k;
+        for (th = 0; th < nthreads; ++th) {
+            const double* b = acc + (size_t)th * (size_t)nacc;
+            for (k = 0; k < 10; ++k) s[k] += b[k * n + t];
+        }
+        g_mean2d[t] = s[0]; g_mean2d[n + t] = s[1];
+        g_conic[t] = s[2]; g_conic[n + t] = s[3]; g_conic[2 * n + t] = s[4];
+        g_opacity[t] = s[5];
+        g_rgb[t] = s[6]; g_rgb[n + t] = s[7]; g_rgb[2 * n + t] = s[8];
+        if (g_invd) g_invd[t] = s[9];
+    }
+    free(acc);
     return 0;
 }
 
@@ -836,6 +890,23 @@ int ora_backward_params(int64_t n, int degree,
         for (c = 0; c < 3; ++c) g_means[c * n + i] = gm[c];
     }
     return 0;
+}
+
+/* Threads the OpenMP loops use from now on (the CPU baseline's one-thread run). */
+void ora_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+int ora_get_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 const char* ora_version(void) { return "gs_oracle 1"; }

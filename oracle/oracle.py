@@ -66,7 +66,11 @@ def lib():
         L.ora_build_keys.argtypes = [i64, P, P, P, i32, P, P]
         L.ora_sort_keys.argtypes = [i64, P, P]
         L.ora_ranges.argtypes = [i64, P, i32, P]
-        L.ora_blend_tiles.argtypes = [i32, i32, i64, P, P, P, P, P, P, P, P, P, P, P, P, P, P]
+        L.ora_blend_tiles.argtypes = [i32, i32, i64, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P]
+        L.ora_set_threads.argtypes = [i32]
+        L.ora_set_threads.restype = None
+        L.ora_get_threads.argtypes = []
+        L.ora_get_threads.restype = i32
         L.ora_blend_brute.argtypes = [i32, i32, i64, P, P, P, i32, P, P, P, P, P, P, P, P, P, P, P, P]
         L.ora_backward_2d.argtypes = [i32, i32, i64, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P]
         L.ora_backward_params.argtypes = [i64, i32, P, P, P, P, P, ctypes.POINTER(OraCamera)] + [P] * 10
@@ -175,9 +179,19 @@ def inverse_depth(proj):
     return out
 
 
-def blend_tiles(proj, rng, point_list, cam, invdepth=None):
+def set_threads(n):
+    """Threads of the oracle's OpenMP loops from now on."""
+    lib().ora_set_threads(int(n))
+
+
+def get_threads():
+    return int(lib().ora_get_threads())
+
+
+def blend_tiles(proj, rng, point_list, cam, invdepth=None, n_eval=None):
     """Tile-list blend; with `invdepth` (an [H, W] array) also the expected
-    inverse depth."""
+    inverse depth; with `n_eval` (an [H, W] uint32 array) the number of list
+    entries each pixel examines (through the one that stops it, else all)."""
     c = make_camera(cam)
     W, H, n = c.width, c.height, proj["n"]
     bg = np.array([c.bg[0], c.bg[1], c.bg[2]])
@@ -191,7 +205,7 @@ def blend_tiles(proj, rng, point_list, cam, invdepth=None):
                                  _p(np.ascontiguousarray(point_list, np.uint32)),
                                  _p(proj["mean2d"]), _p(proj["conic"]), _p(proj["opacity"]),
                                  _p(proj["rgb"]), _p(bg), _p(img), _p(T), _p(nc), _p(margins),
-                                 _p(used), _p(invd), _p(invdepth)),
+                                 _p(used), _p(invd), _p(invdepth), _p(n_eval)),
            "blend_tiles")
     return img, T, nc, margins, used
 
@@ -226,10 +240,11 @@ def render(scene, cam, round_f32=True):
     ks, vs = sort_keys(k0, v0)
     rg = ranges(ks, W, H)
     invdepth = np.zeros((H, W))
-    img, T, nc, margins, used = blend_tiles(proj, rg, vs, cam, invdepth=invdepth)
+    n_eval = np.zeros((H, W), np.uint32)
+    img, T, nc, margins, used = blend_tiles(proj, rg, vs, cam, invdepth=invdepth, n_eval=n_eval)
     return dict(proj=proj, keys_unsorted=k0, vals_unsorted=v0, keys=ks, vals=vs, ranges=rg,
                 image=img, final_T=T, n_contrib=nc, margins=margins, n_used=used, K=int(ks.size),
-                invdepth=invdepth)
+                invdepth=invdepth, n_eval=n_eval)
 
 
 def backward(scene, cam, dL_dout, fwd=None, round_f32=True, dL_dinvdepth=None):
@@ -279,7 +294,22 @@ def l1_loss_grad(image, target):
     return np.sign(np.asarray(image, np.float64) - target) / image.size
 
 
-def flip_eligible_pixels(margins, n_contrib=None, tol_power=1e-4, tol_alpha=2e-5, tol_T=1e-4):
-    """Pixels where a blending decision sits so close to its threshold that an
-    independent float32 evaluation may legitimately take the other branch."""
+def flip_eligible_pixels(margins, n_used, tol_power=1e-9, tol_alpha=4e-6):
+    """Pixels where a blending decision (Alg. 1: skip at power > 0, skip at
+    alpha < 1/255, stop at T (1 - alpha) < 1e-4) sits so close to its
+    threshold that an independent float32 evaluation may legitimately take the
+    other branch.  Margins are relative distances to the threshold (the
+    smallest over a pixel's examined splats).
+
+    - power: its sign is taken in float64 from the same float32 inputs on any
+      faithful implementation, so only rounding of ~1e-16 relative separates
+      two evaluations; 1e-9 leaves a wide allowance.
+    - alpha: a float32 evaluation of o exp(power) near 1/255 carries the
+      rounding of the exponent (|log2 e * power| <= 8 there: <= 4.8e-7
+      absolute, 3.3e-7 relative in exp), an exp of about 1 ulp and the
+      product's half ulp, about 5e-7 relative in all; 4e-6 allows 8x that.
+    - T: a float32 product over n blended splats drifts by up to ~n ulp;
+      1e-6 + 3e-7 n relative.
+    """
+    tol_T = 1e-6 + 3e-7 * np.asarray(n_used, np.float64)
     return (margins[0] < tol_power) | (margins[1] < tol_alpha) | (margins[2] < tol_T)

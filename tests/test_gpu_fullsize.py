@@ -1,15 +1,19 @@
 """Parity at the full benchmark sizes, in the configuration the benchmark
 times (default sort variant and blend kernel): every Gaussian's projection,
-every sorted key and value, every tile range and every pixel against the FP64
-oracle, with the same tolerances and flip-eligible exclusions as the small
-cases."""
+K, every key offset, sorted key and value, every tile range and every pixel
+against the FP64 oracle, with the same tolerances and flip-eligible
+exclusions as the small cases.  Gaussians whose projection the oracle flags
+as within rounding of a boundary are reconciled (either rounding accepted,
+the oracle's key list rebuilt with the GPU's choice) and then compared like
+all others."""
 import numpy as np
 import pytest
 
 from oracle import oracle as O
 from paper_2509_25626_amd import scenes as S
 from tests.conftest import gpu_available
-from tests.test_gpu_parity import compare_images, compare_keys, compare_projection, gpu_render
+from tests.test_gpu_parity import (compare_images, compare_keys, compare_projection, gpu_render,
+                                   reconcile_flagged)
 
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
@@ -23,15 +27,67 @@ def R():
     r.close()
 
 
-@pytest.mark.parametrize("name", ["c2", "c4"])
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("name", ["c1", "c4", "c2", "c3"])
 def test_full_size_forward_parity(R, name):
     scene, cam = S.config_scene(name)
     print(f"{name}: {scene['n']} Gaussians, {cam.width}x{cam.height}", flush=True)
     g = gpu_render(R, scene, cam)
     o = O.render(scene, cam, round_f32=True)
     flagged = compare_projection(g, o)
-    exact = compare_keys(g, o, flagged, 0)
+    o, replaced = reconcile_flagged(g, o, flagged, cam)
+    compare_keys(g, o, 0)
     nflip = compare_images(g, o)
-    print(f"{name}: K={g['K']} keys exact={exact} flagged Gaussians={int(flagged.sum())} "
-          f"flip-eligible pixels={nflip}", flush=True)
-    assert g["K"] == o["K"] or not exact
+    print(f"{name}: K={g['K']} (oracle {o['K']}) keys, offsets and ranges bit-exact; "
+          f"flagged Gaussians={int(flagged.sum())} replaced={replaced} "
+          f"flip-eligible pixels={nflip} ({nflip / (cam.width * cam.height):.2e})", flush=True)
+    assert g["K"] == o["K"]
+
+
+@pytest.mark.timeout(900)
+def test_full_size_backward_parity_c4(R):
+    """Differentiable render at full size: 1M Gaussians (SH3), 1280x720, L1
+    loss against the seeded U(0,1) target (seed 40).  The loss gradient is
+    taken once from the GPU image and fed to both sides; flip-eligible pixels
+    (where an independent float32 evaluation may take the other blending
+    branch) get zero incoming gradient on both sides, so every remaining pixel
+    follows the same decisions.  Per parameter group: relative L2 error at
+    most 1e-4, and at least 99.9% of elements within 1e-3 |g| + 1e-6 max |g|."""
+    import torch
+    from paper_2509_25626_amd.render import GaussianScene
+    from tests.test_gpu_parity import flip_mask
+    scene, cam = S.config_scene("c4")
+    H, W = cam.height, cam.width
+    gs = GaussianScene.from_numpy(scene)
+    target = torch.from_numpy(S.target_image(40, W, H)).cuda()
+    rgb, T, nc, frame = R.forward(gs, cam)
+    dl, loss = R.l1_loss_grad(rgb, target)
+    torch.cuda.synchronize()
+    o = O.render(scene, cam, round_f32=True)
+    g = dict(image=rgb.cpu().numpy(), final_T=T.cpu().numpy(), n_contrib=nc.cpu().numpy().view(np.uint32))
+    g.update(frame.fetch())
+    flagged = compare_projection(g, o)
+    o, replaced = reconcile_flagged(g, o, flagged, cam)
+    compare_keys(g, o, 0)
+    nflip = compare_images(g, o)
+    flip = flip_mask(o)
+    dl_np = dl.cpu().numpy()
+    dl_np[:, flip] = 0.0
+    assert set(np.unique(np.abs(dl_np)).tolist()) <= {0.0, float(np.float32(1.0 / (3 * H * W)))}
+    grads = R.backward(frame, gs, cam, T, nc, torch.from_numpy(dl_np).cuda())
+    torch.cuda.synchronize()
+    R.check_device()
+    R.release_frame(frame)
+    og = O.backward(scene, cam, dl_np.astype(np.float64), fwd=o, round_f32=True)
+    report = {}
+    for k in ("means", "log_scales", "quats", "opacity_logits", "sh"):
+        gg = grads[k].cpu().numpy().astype(np.float64).reshape(-1)
+        oo = og[k].reshape(-1)
+        rel = np.linalg.norm(gg - oo) / max(np.linalg.norm(oo), 1e-30)
+        elem_ok = np.abs(gg - oo) <= 1e-3 * np.abs(oo) + 1e-6 * np.abs(oo).max()
+        report[k] = (float(rel), float(elem_ok.mean()))
+    print(f"c4 backward: loss={loss.item():.6f} flip-eligible pixels={nflip} replaced={replaced} "
+          + " ".join(f"{k}: rel={r:.2e} within={w:.5f}" for k, (r, w) in report.items()), flush=True)
+    for k, (rel, within) in report.items():
+        assert rel <= 1e-4, (k, rel)
+        assert within >= 0.999, (k, within)

@@ -49,12 +49,14 @@ def unpack_rect(tr):
 
 def flip_mask(ora):
     """Pixels where float32 and float64 may legitimately take different blending branches."""
-    m = ora["margins"]
-    tol_T = 1e-6 + 3e-7 * ora["n_used"].astype(np.float64)
-    return (m[0] < 1e-4) | (m[1] < 2e-5) | (m[2] < tol_T)
+    return O.flip_eligible_pixels(ora["margins"], ora["n_used"])
 
 
 def compare_projection(g, o):
+    """Per-Gaussian projection.  Returns the Gaussians whose discrete outputs
+    the oracle flags as within rounding of a decision boundary; their GPU
+    values are checked to be one of the legitimate alternatives here and are
+    reconciled with the oracle's key list by `reconcile_flagged`."""
     p = o["proj"]
     flagged = (p["near_flags"] & O.NF_KEY_DECISIONS) != 0
     ok = ~flagged
@@ -69,7 +71,58 @@ def compare_projection(g, o):
     np.testing.assert_allclose(g["conic_opacity"][vis, 3], p["opacity"][vis], rtol=2.5e-7, atol=1e-9)
     # colour: float32 SH evaluation
     np.testing.assert_allclose(g["rgb"][vis, :3].T, p["rgb"][:, vis], rtol=0, atol=2e-6)
+    # flagged: the GPU took one of the two roundings the oracle's margin allows
+    both = flagged & (p["radius"] > 0) & (g["radius"] > 0)
+    if both.any():
+        assert np.abs(g["radius"][both].astype(np.int64) - p["radius"][both]).max() <= 1
+        assert np.abs(g["depth_bits"][both].astype(np.int64) - p["depth_bits"][both].astype(np.int64)).max() <= 1
+        np.testing.assert_allclose(g["mean2d"][both].T, p["mean2d"][:, both], rtol=2.5e-7, atol=1e-6)
+        d = np.abs(unpack_rect(g["tile_rect"])[:, both] - p["rect"][:, both])
+        assert d.max() <= 1
     return flagged
+
+
+def reconcile_flagged(g, o, flagged, cam):
+    """Oracle result to compare against when flagged Gaussians exist.
+
+    A flagged Gaussian's radius, 2D mean, rectangle or depth bits sit within
+    rounding of a boundary, so either neighbouring value is correct.  Where
+    the GPU took the other one, the oracle's values for that Gaussian are
+    replaced by the GPU's and the oracle's own key build, sort, ranges and
+    blend run again; everything is then compared in full.  Returns the
+    (possibly recomputed) oracle result and the number of Gaussians replaced.
+    """
+    if not flagged.any():
+        return o, 0
+    p = o["proj"]
+    rect_g = unpack_rect(g["tile_rect"])
+    vis_g = g["radius"] > 0
+    diff = flagged & ((g["radius"] != p["radius"]) | (g["depth_bits"] != p["depth_bits"])
+                      | (g["tiles_touched"] != p["tiles_touched"])
+                      | np.any(np.where(vis_g, rect_g, 0) != p["rect"], axis=0)
+                      | np.any(g["mean2d"].T.astype(np.float64) != p["mean2d"], axis=0))
+    idx = np.nonzero(diff)[0]
+    if idx.size == 0:
+        return o, 0
+    q = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in p.items()}
+    q["radius"][idx] = g["radius"][idx]
+    q["tiles_touched"][idx] = g["tiles_touched"][idx]
+    q["depth_bits"][idx] = g["depth_bits"][idx]
+    q["rect"][:, idx] = np.where(vis_g[idx], rect_g[:, idx], 0)
+    q["mean2d"][:, idx] = g["mean2d"][idx].T.astype(np.float64)
+    # a Gaussian only the GPU keeps visible blends with the GPU's float32 values
+    only_g = idx[(p["radius"][idx] == 0) & vis_g[idx]]
+    q["conic"][:, only_g] = g["conic_opacity"][only_g, :3].T
+    q["opacity"][only_g] = g["conic_opacity"][only_g, 3]
+    q["rgb"][:, only_g] = g["rgb"][only_g, :3].T
+    W, H = cam.width, cam.height
+    k0, v0 = O.keys_unsorted(q, W)
+    ks, vs = O.sort_keys(k0, v0)
+    rg = O.ranges(ks, W, H)
+    img, T, nc, margins, used = O.blend_tiles(q, rg, vs, cam)
+    o2 = dict(o, proj=q, keys_unsorted=k0, vals_unsorted=v0, keys=ks, vals=vs, ranges=rg,
+              image=img, final_T=T, n_contrib=nc, margins=margins, n_used=used, K=int(ks.size))
+    return o2, int(idx.size)
 
 
 def effective_sort_variant(sort_variant):
@@ -87,23 +140,21 @@ def expected_offsets(o, sort_variant):
     return np.concatenate([[0], np.cumsum(t)[:-1]]).astype(np.uint32) if t.size else np.zeros(0, np.uint32)
 
 
-def compare_keys(g, o, flagged, sort_variant=0):
-    if flagged.any():
-        bad = set(np.nonzero(flagged)[0].tolist())
-        keep_g = np.array([v not in bad for v in g["values"]], bool)
-        keep_o = np.array([v not in bad for v in o["vals"]], bool)
-        assert np.array_equal(g["keys"][keep_g], o["keys"][keep_o])
-        assert np.array_equal(g["values"][keep_g], o["vals"][keep_o])
-        return False
+def compare_keys(g, o, sort_variant=0):
+    """K, key offsets, every sorted key and value, and every tile range,
+    bit-exact against the oracle (Sec. II-B(1) duplication and sort, Alg. 1
+    ranges).  `o` is the oracle result after `reconcile_flagged`."""
     assert g["K"] == o["K"]
+    assert np.array_equal(g["tiles_touched"], o["proj"]["tiles_touched"])
+    vis = o["proj"]["radius"] > 0
+    assert np.array_equal(unpack_rect(g["tile_rect"])[:, vis], o["proj"]["rect"][:, vis])
     assert np.array_equal(g["offsets"], expected_offsets(o, sort_variant))
     assert np.array_equal(g["keys"], o["keys"])
     assert np.array_equal(g["values"], o["vals"])
     assert np.array_equal(g["ranges"], o["ranges"])
-    return True
 
 
-def compare_images(g, o, max_flip_frac=2e-3):
+def compare_images(g, o, max_flip_frac=1e-3):
     flip = flip_mask(o)
     good = ~flip
     assert flip.mean() <= max_flip_frac, flip.mean()
@@ -118,7 +169,8 @@ def full_check(R, scene, cam, variant=0, sort_variant=0, sort_algo="auto"):
     g = gpu_render(R, scene, cam, variant, sort_variant, sort_algo)
     o = O.render(scene, cam, round_f32=True)
     flagged = compare_projection(g, o)
-    compare_keys(g, o, flagged, sort_variant)
+    o, _ = reconcile_flagged(g, o, flagged, cam)
+    compare_keys(g, o, sort_variant)
     nflip = compare_images(g, o)
     return g, o, nflip
 

@@ -181,6 +181,24 @@ def test_depth_bits_are_float32_of_view_depth():
     assert np.array_equal(order_bits, order_vals)
 
 
+def test_depth_tie_rounds_to_even_and_is_not_flagged():
+    # A view depth exactly on a float32 rounding midpoint (4 + 2^-22 lies
+    # halfway between 4 and the next float32 above it) is an exact tie: IEEE
+    # round-to-nearest-even takes 4.0 in any implementation that computes the
+    # same double, so it is not ambiguous and carries no flag.  A depth a
+    # hair above the midpoint (2^-45, a 6e-8 ulp margin) is ambiguous between
+    # evaluation orders and is flagged; it rounds up.
+    tie = np.float32(2.0 ** -22)
+    above = np.nextafter(tie, np.float32(1.0))
+    sc = mk_scene(np.array([[0.0, 0.0], [0.0, 0.0], [tie, above]]), [-3.0, -3.0])
+    p = O.project(sc, _cam(), round_f32=True)
+    assert p["depth"][0] == 4.0 + 2.0 ** -22 and p["depth"][1] > p["depth"][0]
+    assert p["depth_bits"][0] == np.float32(4.0).view(np.uint32)
+    assert p["depth_bits"][1] == np.nextafter(np.float32(4.0), np.float32(5.0)).view(np.uint32)
+    assert p["near_flags"][0] & O.NF_DEPTH_ROUND == 0
+    assert p["near_flags"][1] & O.NF_DEPTH_ROUND != 0
+
+
 def test_colour_on_axis_closed_form():
     # Straight ahead of an R = I camera the view direction is (0, 0, 1): only the
     # m = 0 harmonics survive, Y_00 = 1/(2 sqrt(pi)), Y_10 = sqrt(3/(4 pi)) z,
