@@ -119,7 +119,8 @@ typedef struct cds_render_opts {
                                2 = depth digits sorted once per Gaussian, then the tile digits of
                                    32-bit tile ids radix-sorted per key;
                                3 = depth digits per Gaussian, then a counting sort on the whole tile id
-                                   fused with duplication (needs at most 4096 tiles per row);
+                                   fused with duplication (needs at most 512 tiles per row, i.e.
+                                   images up to 8192 pixels wide; wider ones are rejected);
                                0 = default: 2. */
     int32_t reserved;
 } cds_render_opts;
@@ -294,8 +295,14 @@ cds_status cds_exclusive_scan_u32(cds_ctx* ctx, const uint32_t* in, int64_t coun
                                   uint64_t* total, void* stream);
 
 /* Synchronise `stream` and report device-side errors raised since the last
- * check (a bounded wait that gave up, a capacity overrun): CDS_OK or
- * CDS_ERR_DEVICE with a message. */
+ * check, then clear them: CDS_OK or CDS_ERR_DEVICE with a message naming the
+ * bits of the device error word.  Bits: 1 a sort's bounded look-back gave up
+ * waiting; 2 a sort's record gather met an index at or past the key count;
+ * 4 / 8 tile binning found counts that disagree; 16 a blend (forward,
+ * backward or batched) met a tile-list entry at or past the splat count.
+ * Each of these can only follow a logic error or corrupted input; the kernel
+ * that detects it substitutes an in-bounds value, so outputs are then wrong
+ * but no memory outside the buffers is touched. */
 cds_status cds_check_device(cds_ctx* ctx, void* stream);
 
 /* ------------------------------------------------------------------------ */

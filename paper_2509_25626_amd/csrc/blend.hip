@@ -119,8 +119,14 @@ __device__ __forceinline__ bool splat_alpha(double adx2, double bdx, double c2, 
 }
 
 // A list entry is a splat index below n; one at or past n can only come from
-// a corrupted list, and is replaced by splat 0 rather than read out of bounds.
-__device__ __forceinline__ uint32_t splat_id(uint32_t id, int64_t n) { return (int64_t)id < n ? id : 0u; }
+// a corrupted list: it is replaced by splat 0 rather than read out of bounds,
+// and bit 16 of the device error word is set so the corruption is reported.
+constexpr uint32_t kErrBadListEntry = 16u;
+__device__ __forceinline__ uint32_t splat_id(uint32_t id, int64_t n, uint32_t* err) {
+    if ((int64_t)id < n) return id;
+    atomicOr(err, kErrBadListEntry);
+    return 0u;
+}
 
 // One 16x16 tile: stage its sorted splats through LDS in batches and blend
 // each pixel front to back.  Shared by the single-render kernel and the
@@ -128,7 +134,7 @@ __device__ __forceinline__ uint32_t splat_id(uint32_t id, int64_t n) { return (i
 // Every thread of the workgroup must call it (it contains barriers).
 template <int PPT, bool kDepth = false>
 __device__ __forceinline__ void blend_tile(int tx, int ty, int width, int height, uint2 range,
-                                           const uint32_t* __restrict__ point_list, int64_t n,
+                                           const uint32_t* __restrict__ point_list, int64_t n, uint32_t* err,
                                            const float2* __restrict__ mean2d,
                                            const float4* __restrict__ conic_opacity,
                                            const float4* __restrict__ rgb, float bg0, float bg1, float bg2,
@@ -168,7 +174,7 @@ __device__ __forceinline__ void blend_tile(int tx, int ty, int width, int height
         for (int k = t; k < kBatch; k += NT) {
             const int idx = base + k;
             if (idx < todo) {
-                const uint32_t id = splat_id(point_list[range.x + idx], n);
+                const uint32_t id = splat_id(point_list[range.x + idx], n, err);
                 stage_splat(mean2d, conic_opacity, rgb, id, s_q, s_c, s_f, s_b, k, tx * kTile, ty * kTile);
                 if constexpr (kDepth) s_d[k] = 1.0f / __uint_as_float(depth_bits[id]);
             }
@@ -255,7 +261,8 @@ __global__ __launch_bounds__(256 / PPT) void k_blend(BlendArgs a, uint32_t per_x
     const uint32_t tile = xcd_band(blockIdx.x, per_xcd);
     if (tile >= (uint32_t)(a.tiles_x * a.tiles_y)) return;  // whole block: padding
     const int tx = (int)(tile % (uint32_t)a.tiles_x), ty = (int)(tile / (uint32_t)a.tiles_x);
-    blend_tile<PPT, kDepth>(tx, ty, a.width, a.height, a.ranges[tile], a.point_list, a.n, a.mean2d, a.conic_opacity,
+    blend_tile<PPT, kDepth>(tx, ty, a.width, a.height, a.ranges[tile], a.point_list, a.n, a.err, a.mean2d,
+                            a.conic_opacity,
                             a.rgb, a.bg[0], a.bg[1], a.bg[2], a.out_rgb, a.out_T, a.out_ncontrib, s_q, s_c, s_f,
                             s_b, a.depth_bits, a.out_invdepth, s_d);
 }
@@ -305,7 +312,7 @@ __device__ __forceinline__ void blend_half_tile(const BlendArgs& a, uint32_t til
         for (int k = (int)lane; k < kWaveBatch; k += kWave) {
             const int idx = base + k;
             if (idx < todo) {
-                const uint32_t id = splat_id(a.point_list[range.x + idx], a.n);
+                const uint32_t id = splat_id(a.point_list[range.x + idx], a.n, a.err);
                 stage_splat(a.mean2d, a.conic_opacity, a.rgb, id, s_q, s_c, s_f, s_b, k, tx * kTile, ty * kTile);
                 if constexpr (kDepth) s_d[k] = 1.0f / __uint_as_float(a.depth_bits[id]);
             }
@@ -407,7 +414,8 @@ __global__ __launch_bounds__(256 / PPT) void k_blend_batch(const BatchItem* __re
                                                            const uint32_t* __restrict__ point_list, int64_t n,
                                                            const float2* __restrict__ mean2d,
                                                            const float4* __restrict__ conic_opacity,
-                                                           const float4* __restrict__ rgb, uint32_t* counter) {
+                                                           const float4* __restrict__ rgb, uint32_t* counter,
+                                                           uint32_t* err) {
     __shared__ double4 s_q[kBatch];
     __shared__ double s_c[kBatch];
     __shared__ float4 s_f[kBatch];
@@ -423,7 +431,7 @@ __global__ __launch_bounds__(256 / PPT) void k_blend_batch(const BatchItem* __re
         const BatchItem& it = items[r];
         const uint32_t local = g - (uint32_t)it.tile_base;
         const int tx = (int)(local % (uint32_t)it.P.tiles_x), ty = (int)(local / (uint32_t)it.P.tiles_x);
-        blend_tile<PPT>(tx, ty, it.P.width, it.P.height, ranges[g], point_list, n, mean2d, conic_opacity, rgb,
+        blend_tile<PPT>(tx, ty, it.P.width, it.P.height, ranges[g], point_list, n, err, mean2d, conic_opacity, rgb,
                         it.bg[0], it.bg[1], it.bg[2], it.out_rgb, it.out_T, it.out_ncontrib, s_q, s_c, s_f, s_b);
     }
 }
@@ -503,7 +511,7 @@ __global__ __launch_bounds__(256 / PPT) void k_blend_bwd(BlendBwdArgs a, uint32_
         const int begin = end - kBwdBatch > 0 ? end - kBwdBatch : 0;
         __syncthreads();  // the previous batch is fully consumed
         for (int k = t; k < end - begin; k += NT) {
-            const uint32_t id = splat_id(a.point_list[range.x + begin + k], a.n);
+            const uint32_t id = splat_id(a.point_list[range.x + begin + k], a.n, a.err);
             s_id[k] = id;
             stage_splat(a.mean2d, a.conic_opacity, a.rgb, id, s_q, s_c, s_f, s_b, k, tx * kTile, ty * kTile);
             if constexpr (kDepth) s_d[k] = 1.0f / __uint_as_float(a.depth_bits[id]);
@@ -636,6 +644,7 @@ static uint32_t xcd_per(int64_t tiles) { return (uint32_t)((tiles + 7) / 8); }
 hipError_t launch_blend(const BlendArgs& a, int variant, hipStream_t stream) {
     const int64_t tiles = (int64_t)a.tiles_x * a.tiles_y;
     if (tiles == 0) return hipSuccess;
+    if (!a.err) return hipErrorInvalidValue;
     const uint32_t per = xcd_per(tiles);
     const dim3 grid(8 * per);
     const bool depth = a.out_invdepth != nullptr;
@@ -687,18 +696,20 @@ hipError_t launch_blend(const BlendArgs& a, int variant, hipStream_t stream) {
 hipError_t launch_blend_batch(const BatchItem* items, int nitems, int64_t total_tiles, const uint2* ranges,
                               const uint32_t* point_list, int64_t n, const float2* mean2d,
                               const float4* conic_opacity, const float4* rgb, uint32_t* counter, int grid,
-                              hipStream_t stream) {
+                              uint32_t* err, hipStream_t stream) {
     if (total_tiles == 0) return hipSuccess;
+    if (!err) return hipErrorInvalidValue;
     hipError_t e = launch_fill_u32(counter, 1, 0u, stream);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_blend_batch<2>, dim3((unsigned)grid), dim3(128), 0, stream, items, nitems, total_tiles,
-                       ranges, point_list, n, mean2d, conic_opacity, rgb, counter);
+                       ranges, point_list, n, mean2d, conic_opacity, rgb, counter, err);
     return hipGetLastError();
 }
 
 hipError_t launch_blend_backward(const BlendBwdArgs& a, hipStream_t stream) {
     const int64_t tiles = (int64_t)a.tiles_x * a.tiles_y;
     if (tiles == 0) return hipSuccess;
+    if (!a.err) return hipErrorInvalidValue;
     const uint32_t per = xcd_per(tiles);
     if (a.dL_dinvdepth) {
         if (!a.depth_bits) return hipErrorInvalidValue;

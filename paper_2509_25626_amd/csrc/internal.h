@@ -319,6 +319,7 @@ struct BlendArgs {
     float* out_invdepth;         // [H][W] expected inverse depth, or null
     uint32_t* counter;           // work counter of the work-stealing variant (3)
     int64_t n;                   // number of splats: a list entry at or past it is never read
+    uint32_t* err;               // device error word: bit 16 set on a list entry at or past n
 };
 // variant: 1, 2, 4 = pixels per thread of the per-tile kernel; 3 = work-stealing half tiles
 hipError_t launch_blend(const BlendArgs& a, int variant, hipStream_t stream);
@@ -328,7 +329,7 @@ hipError_t launch_blend(const BlendArgs& a, int variant, hipStream_t stream);
 hipError_t launch_blend_batch(const BatchItem* items, int nitems, int64_t total_tiles, const uint2* ranges,
                               const uint32_t* point_list, int64_t n, const float2* mean2d,
                               const float4* conic_opacity, const float4* rgb, uint32_t* counter, int grid,
-                              hipStream_t stream);
+                              uint32_t* err, hipStream_t stream);
 
 // Per-Gaussian 2D gradients of the backward pass, one row per Gaussian:
 // mean x, mean y, conic A, B, C, opacity, r, g, b, 1 / depth.
@@ -349,6 +350,7 @@ struct BlendBwdArgs {
     const float* dL_dinvdepth;   // [H][W] gradient w.r.t. the expected inverse depth, or null
     int64_t n;
     float* grad2d;  // [n][kGrad2d], zero on entry
+    uint32_t* err;  // device error word: bit 16 set on a list entry at or past n
 };
 hipError_t launch_blend_backward(const BlendBwdArgs& a, hipStream_t stream);
 

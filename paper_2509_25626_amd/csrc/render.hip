@@ -146,6 +146,17 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
     CDS_TRY(f->record(kEvPreprocess, stream));
 
     uint64_t* d_total = (uint64_t*)f->total.p;  // [0] = n_vis (variant 2), [1] = K
+    // When the render returns early (an allocation failing after the side
+    // stream was forked), the render stream still waits for the side stream's
+    // work, so buffers freed after the error are no longer in use by it.
+    struct JoinOnExit {
+        hipStream_t stream;
+        hipEvent_t join;
+        bool armed;
+        ~JoinOnExit() {
+            if (armed) (void)hipStreamWaitEvent(stream, join, 0);
+        }
+    } side_join{stream, nullptr, false};
     SortWorkspace wd = (compact || binned) ? sort_ws(ctx, f->sort_d) : SortWorkspace{};
     const uint32_t* order = nullptr;
     if (compact) {
@@ -184,6 +195,7 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
         // meanwhile: these kernels are sized for all n Gaussians and read the
         // number of visible splats (d_total[0]) on the device.
         CDS_TRY(f->side_stream());
+        side_join.join = f->join;
         CDS_HIP(hipEventRecord(f->copied, stream), "hipEventRecord(copied)");
         // ranges and tile-digit histograms from the records (their order does not
         // matter), on the side stream while the depth sort runs
@@ -194,6 +206,7 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
                                    kTileCountBlocks, f->side, nullptr, 0, (const uint4*)f->recc.p, d_total),
                 "tile counts");
         CDS_HIP(hipEventRecord(f->join, f->side), "hipEventRecord(join)");
+        side_join.armed = true;
         if (n > 0) {
             // depth sort of the compacted keys (values: compacted positions); the
             // last pass writes the records in depth order (recv) instead
@@ -247,7 +260,10 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
                                           d_total + 2, stream, recv, (uint32_t*)f->kowner.p, d_total),
                     "offset scan");
         }
-        if (compact) CDS_HIP(hipStreamWaitEvent(stream, f->join, 0), "hipStreamWaitEvent(join)");
+        if (compact) {
+            side_join.armed = false;
+            CDS_HIP(hipStreamWaitEvent(stream, f->join, 0), "hipStreamWaitEvent(join)");
+        }
         CDS_TRY(f->record(kEvDepth, stream));
         const int passes = compact ? tile_passes : 4 + tile_passes;
         // variant 2 with onesweep passes: the first tile pass generates the keys
@@ -349,6 +365,7 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
     ba.out_invdepth = out_invdepth;
     ba.counter = reinterpret_cast<uint32_t*>(d_total + 8);  // a free word of the frame's totals
     ba.n = n;
+    ba.err = ctx->d_err;
     CDS_HIP(launch_blend(ba, blend_variant, stream), "blend kernel");
     CDS_TRY(f->record(kEvBlend, stream));
     f->valid = true;
@@ -399,6 +416,7 @@ cds_status render_backward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* sce
     b.dL_dinvdepth = dL_dinvdepth;
     b.n = n;
     b.grad2d = (float*)f->grad2d.p;
+    b.err = ctx->d_err;
     CDS_HIP(launch_blend_backward(b, stream), "blend backward kernel");
     CDS_TRY(f->record(kEvBwdBlend, stream));
     PreBwdArgs pa;

@@ -414,8 +414,9 @@ cds_status cds_check_device(cds_ctx* ctx, void* stream) {
         (void)hipMemset(ctx->d_err, 0, 4);
         return fail(CDS_ERR_DEVICE, "device-side check failed (code " + std::to_string(err) +
                                         "): 1 = a bounded wait in the radix sort gave up, "
-                                        "2 = a radix-sort scatter position was out of range, "
-                                        "4 or 8 = tile binning counts were inconsistent");
+                                        "2 = a radix-sort scatter or gather index was out of range, "
+                                        "4 or 8 = tile binning counts were inconsistent, "
+                                        "16 = a blend met a tile-list entry at or past the splat count");
     }
     return CDS_OK;
 }

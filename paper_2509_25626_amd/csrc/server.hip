@@ -260,7 +260,7 @@ cds_status run_batch(cds_server* s, Workspace& w) {
     const uint32_t* values = (const uint32_t*)(odd ? f->vals1.p : f->vals0.p);
     const int64_t grid = std::min<int64_t>(T, (int64_t)s->cus * 8);
     SRV_HIP(launch_blend_batch(w.items_dev, nitems, T, (const uint2*)f->ranges.p, values, N, sb.mean2d,
-                               sb.conic_opacity, sb.rgb, w.counter, (int)grid, stream),
+                               sb.conic_opacity, sb.rgb, w.counter, (int)grid, ctx->d_err, stream),
             "batched blend");
     SRV_HIP(hipEventRecord(w.done, stream), "hipEventRecord");
     return CDS_OK;
