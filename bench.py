@@ -42,8 +42,28 @@ def parse():
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-other-configs", action="store_true")
+    ap.add_argument("--quick-serving", action="store_true",
+                    help="300 requests per load instead of 2000")
     ap.add_argument("--cpu-budget-s", type=float, default=40.0)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="GIB",
+                    help="only run a plain device copy of GIB GiB three times (the known-size reference "
+                         "for scaling the HBM traffic counters) and exit")
     return ap.parse_args()
+
+
+def calibrate_copy(gib, reps=3):
+    """A plain device-to-device copy of exactly `gib` GiB in and out per
+    repetition: under rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, what the
+    counters read for it is the scale for every other kernel's reading."""
+    import torch
+    n = (gib << 30) // 4
+    x = torch.ones(n, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration_copy_gib": gib, "repetitions": reps}), flush=True)
 
 
 def roofline(stages, scene, K, passes, info, first_pass_ms, variant, algo):
@@ -142,130 +162,298 @@ def measured_traffic(kernel):
     return ent["bytes_per_launch"] if sha == ent["source_sha256"] else None
 
 
-def cpu_baseline(scene, cam, budget_s):
-    """The FP64 oracle, as it is, on the host cores: one full forward frame of
-    the same scene and camera (the oracle's projection, keys, sort, ranges and
-    blend).  Falls back to a 1/8 Gaussian subsample when a full frame would
-    exceed the budget; the sample is stated in the output."""
-    from oracle import oracle as O
-    import multiprocessing
-    cores = int(os.environ.get("OMP_NUM_THREADS", multiprocessing.cpu_count()))
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _subsample(scene, frac, seed=0):
     n = scene["n"]
-    # estimate from a 1/64 subsample first
-    def sub(frac):
-        m = max(1, int(n * frac))
-        idx = np.random.default_rng(0).choice(n, m, replace=False)
-        idx.sort()
-        s = {k: (np.ascontiguousarray(v[..., idx]) if isinstance(v, np.ndarray) else v)
-             for k, v in scene.items()}
-        s["n"] = m
-        return s
+    m = max(1, int(n * frac))
+    idx = np.random.default_rng(seed).choice(n, m, replace=False)
+    idx.sort()
+    s = {k: (np.ascontiguousarray(v[..., idx]) if isinstance(v, np.ndarray) else v) for k, v in scene.items()}
+    s["n"] = m
+    return s
+
+
+def cpu_baseline(scene, cam, budget_s):
+    """The FP64 oracle, as it is, on the host cores: full forward frames of the
+    same scene and camera (the oracle's projection, keys, sort, ranges and
+    blend): one warm-up frame, then the median of three timed frames on every
+    core the process may use, plus one frame on a single thread over a random
+    1/16 subsample of the Gaussians (same image).  Falls back to a 1/8
+    subsample for the all-core frames when a full frame would exceed the
+    budget; the sample is stated in the output.  Also returns the last
+    all-core oracle result (its per-pixel counts give the blend's algorithmic
+    work)."""
+    from oracle import oracle as O
+    cores = O.get_threads()
     t0 = time.perf_counter()
-    O.render(sub(1 / 64), cam)
+    O.render(_subsample(scene, 1 / 64), cam)  # loads the library; estimates the frame time
     t_small = time.perf_counter() - t0
-    frac, label = 1.0, "one full frame"
-    if t_small * 64 > budget_s:
-        frac, label = 1 / 8, "one frame of a 1/8 random subsample of the Gaussians"
-    s = scene if frac == 1.0 else sub(frac)
+    frac, label = 1.0, "full frames"
+    if t_small * 64 * 4 > budget_s:
+        frac, label = 1 / 8, "frames of a 1/8 random subsample of the Gaussians"
+    s = scene if frac == 1.0 else _subsample(scene, frac)
+    O.render(s, cam)  # warm-up
+    times, res = [], None
+    for _ in range(3):
+        t0 = time.perf_counter()
+        res = O.render(s, cam)
+        times.append(time.perf_counter() - t0)
+    dt = float(np.median(times))
+    # one thread, on a 1/16 subsample, and the same subsample on every core for the ratio
+    s16 = _subsample(scene, 1 / 16, seed=1)
     t0 = time.perf_counter()
-    O.render(s, cam)
-    dt = time.perf_counter() - t0
-    return {"value": round(1.0 / dt, 5), "unit": "frames/s", "cores": cores, "kind": "oracle",
-            "sample": f"{label} ({s['n']} Gaussians, {cam.width}x{cam.height}), FP64 C oracle, "
-                      f"OpenMP over Gaussians and pixels, single-threaded stable sort; {dt:.1f} s"}
+    O.render(s16, cam)
+    t_all16 = time.perf_counter() - t0
+    O.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        O.render(s16, cam)
+        t_one16 = time.perf_counter() - t0
+    finally:
+        O.set_threads(cores)
+    out = {"value": round(1.0 / dt, 5), "unit": "frames/s", "cores": cores, "kind": "oracle",
+           "cpu_model": cpu_model(),
+           "sample": f"{label} ({s['n']} Gaussians, {cam.width}x{cam.height}), FP64 C oracle, OpenMP over "
+                     f"Gaussians and pixels, single-threaded stable sort; 1 warm-up + median of 3 "
+                     f"({', '.join(f'{t:.2f}' for t in times)} s)",
+           "single_thread": {"value": round(1.0 / t_one16, 5), "unit": "frames/s",
+                             "sample": f"one frame of a 1/16 random subsample ({s16['n']} Gaussians, "
+                                       f"{cam.width}x{cam.height}) on one thread: {t_one16:.2f} s "
+                                       f"against {t_all16:.2f} s on {cores} threads"}}
+    return out, res
+
+
+# Algorithmic VALU issue slots of the blend per (pixel, splat) pair, counted
+# from the arithmetic Alg. 1 needs in float32: an examined pair needs the
+# offset (2 sub), the quadratic form (7 mul/fma/add), the power > 0 test, the
+# exponential (one transcendental, a quarter-rate instruction: 4 slots),
+# alpha = min(0.99, o G) (2), the 1/255 test, T (1 - alpha) (2) and its test:
+# 21 slots.  A blended pair adds the weight alpha T and three colour FMAs (4)
+# and the contributor index (1): 5 slots.  The backward pass examines each
+# position up to the pixel's last contributor (the same 21 slots to recover
+# alpha) and, per blended pair, recovers T by a reciprocal (2), updates the
+# three composited-behind colours (6), forms dL/dalpha (6) and the nine 2D
+# gradient terms (16): 30 slots.  Peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# = 39.3e12 non-packed lane slots per second.
+VALU_SLOTS_PEAK = 256 * 4 * 16 * 2.4e9
+SLOTS_EXAMINED, SLOTS_BLENDED, SLOTS_BWD_BLENDED = 21, 5, 30
+
+
+def blend_work(o):
+    """Algorithmic pair counts of one frame from the oracle's per-pixel
+    counts: examined pairs, blended pairs, and the backward pass's examined
+    positions (up to the last contributor)."""
+    ne = int(o["n_eval"].astype(np.int64).sum())
+    nb = int(o["n_used"].astype(np.int64).sum())
+    nc = int(o["n_contrib"].astype(np.int64).sum())
+    return {"examined_pairs": ne, "blended_pairs": nb, "backward_examined_pairs": nc}
+
+
+def blend_roofline(work, blend_ms, blend_bwd_ms=None):
+    fwd_slots = SLOTS_EXAMINED * work["examined_pairs"] + SLOTS_BLENDED * work["blended_pairs"]
+    out = {"bound": "alu", "unit": "lane-slots/s", "peak": VALU_SLOTS_PEAK,
+           "algorithmic_slots": fwd_slots, "avg_launch_ms": round(blend_ms, 4),
+           "achieved": round(fwd_slots / (blend_ms * 1e-3), 1),
+           "frac": round(fwd_slots / (blend_ms * 1e-3) / VALU_SLOTS_PEAK, 4), **work}
+    if blend_bwd_ms:
+        bwd_slots = SLOTS_EXAMINED * work["backward_examined_pairs"] + SLOTS_BWD_BLENDED * work["blended_pairs"]
+        out["backward"] = {"algorithmic_slots": bwd_slots, "avg_launch_ms": round(blend_bwd_ms, 4),
+                           "frac": round(bwd_slots / (blend_bwd_ms * 1e-3) / VALU_SLOTS_PEAK, 4)}
+    return out
+
+
+def tile_statistics(o, W, H):
+    """Table 3's workload shape from one frame: splats per tile (mean and
+    variance over the tiles) and the fraction of its tile's splats a pixel
+    examines (mean over pixels with a non-empty list)."""
+    lens = (o["ranges"][:, 1].astype(np.int64) - o["ranges"][:, 0])
+    tiles_x = (W + 15) // 16
+    ys, xs = np.mgrid[0:H, 0:W]
+    L = lens[(ys // 16) * tiles_x + xs // 16]
+    nz = L > 0
+    frac = float((o["n_eval"][nz] / L[nz]).mean()) if nz.any() else 0.0
+    return {"splats_per_tile_mean": round(float(lens.mean()), 1), "splats_per_tile_var": round(float(lens.var()), 1),
+            "splats_per_tile_max": int(lens.max()), "processed_fraction": round(frac, 4)}
+
+
+class Bench:
+    """Times forward and forward+backward frames of one scene on the render
+    stream, with stage times from the library's HIP events."""
+
+    def __init__(self, R, scene_np, cam, args):
+        import torch
+        from paper_2509_25626_amd.render import GaussianScene
+        self.R, self.cam, self.args = R, cam, args
+        self.dev = torch.device("cuda", 0)
+        self.scene = GaussianScene.from_numpy(scene_np, device=self.dev)
+        # two frame objects used in turn: a frame's stage events are read after
+        # the next frame has been enqueued, so reading them never stalls the stream
+        self.frames = [R.acquire_frame(), R.acquire_frame()]
+        H, W = cam.height, cam.width
+        self.out = (torch.empty((3, H, W), device=self.dev), torch.empty((H, W), device=self.dev),
+                    torch.empty((H, W), dtype=torch.int32, device=self.dev))
+
+    def fwd(self, fr, timing=False):
+        a = self.args
+        return self.R.forward(self.scene, self.cam, frame=fr, blend_variant=a.blend_variant, out=self.out,
+                              timing=timing, sort_variant=a.sort_variant, sort_algo=a.sort_algo)
+
+    @staticmethod
+    def _accumulate(acc, fr):
+        for k, v in fr.stage_times().items():
+            acc[k] = acc.get(k, 0.0) + v
+
+    def _run(self, step, steps, warmup):
+        import torch
+        for i in range(max(2, warmup)):
+            step(self.frames[i % 2])
+        torch.cuda.synchronize()
+        acc = {}
+        t0 = time.perf_counter()
+        for i in range(steps):
+            step(self.frames[i % 2], timing=True)
+            if i > 0:
+                self._accumulate(acc, self.frames[(i - 1) % 2])
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        self._accumulate(acc, self.frames[(steps - 1) % 2])
+        return dt, {k: v / steps for k, v in acc.items()}
+
+    def forward(self, steps, warmup):
+        dt, st = self._run(self.fwd, steps, warmup)
+        stages = {k: v for k, v in st.items() if not k.endswith("backward_ms") and k != "sort_first_pass_ms"}
+        return dt, stages, st.get("sort_first_pass_ms", 0.0)
+
+    def forward_backward(self, steps, warmup):
+        import torch
+        from paper_2509_25626_amd import scenes as S
+        H, W = self.cam.height, self.cam.width
+        target = torch.from_numpy(S.target_image(40, W, H)).to(self.dev)
+        grads = {k: torch.empty_like(getattr(self.scene, k)) for k in
+                 ("means", "log_scales", "quats", "opacity_logits", "sh")}
+        dl = torch.empty((3, H, W), device=self.dev)
+        loss = torch.empty(1, device=self.dev)
+
+        def step(fr, timing=False):
+            rgb, T, nc, _ = self.fwd(fr, timing)
+            self.R.l1_loss_grad(rgb, target, dl, loss)
+            self.R.backward(fr, self.scene, self.cam, T, nc, dl, grads)
+
+        dt, st = self._run(step, steps, warmup)
+        return dt, {k: v for k, v in st.items() if k.endswith("backward_ms")}
+
+    def close(self):
+        for f in self.frames:
+            self.R.release_frame(f)
+        self.scene = None
+
+
+def other_config(R, name, args, backward):
+    """Forward (and forward+backward) frames/s of another configuration with
+    the same kernels, plus its stage times."""
+    import torch
+    from paper_2509_25626_amd import scenes as S
+    scene_np, cam = S.config_scene(name)
+    b = Bench(R, scene_np, cam, args)
+    steps = max(5, args.steps // 2)
+    dt, stages, _ = b.forward(steps, max(2, args.warmup // 2))
+    info = b.frames[0].info()
+    res = {"workload": f"{name}: {scene_np['n']} Gaussians SH{scene_np['sh_degree']}, {cam.width}x{cam.height}",
+           "fwd_fps": round(1.0 / dt, 2), "fwd_ms": round(dt * 1e3, 4), "keys": int(info.num_keys),
+           "visible": int(info.num_visible), "stage_ms": {k: round(v, 4) for k, v in stages.items()}}
+    if name == "c1":
+        res["fwd_us"] = round(dt * 1e6, 1)
+    if backward:
+        dtb, bst = b.forward_backward(steps, max(2, args.warmup // 2))
+        res["fwd_bwd_fps"] = round(1.0 / dtb, 2)
+        res["fwd_bwd_ms"] = round(dtb * 1e3, 4)
+        res["backward_stage_ms"] = {k: round(v, 4) for k, v in bst.items()}
+    b.close()
+    del b
+    torch.cuda.synchronize()
+    return res, scene_np, cam, stages
 
 
 def main():
     args = parse()
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for {args.gpus}).",
               file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2509_25626_amd import scenes as S
-    from paper_2509_25626_amd.render import GaussianScene, Renderer
+    from paper_2509_25626_amd.render import Renderer
 
     scene_np, cam = S.config_scene(args.config)
-    dev = torch.device("cuda", 0)
-    scene = GaussianScene.from_numpy(scene_np, device=dev)
     R = Renderer(0)
-    # two frame objects used in turn: a frame's stage events are read after the
-    # next frame has been enqueued, so reading them never stalls the stream
-    frames = [R.acquire_frame(), R.acquire_frame()]
-    frame = frames[0]
+    b = Bench(R, scene_np, cam, args)
     H, W = cam.height, cam.width
-    out = (torch.empty((3, H, W), device=dev), torch.empty((H, W), device=dev),
-           torch.empty((H, W), dtype=torch.int32, device=dev))
-
-    def fwd(fr, timing=False):
-        return R.forward(scene, cam, frame=fr, blend_variant=args.blend_variant, out=out, timing=timing,
-                         sort_variant=args.sort_variant, sort_algo=args.sort_algo)
-
-    def accumulate(acc, fr):
-        for k, v in fr.stage_times().items():
-            acc[k] = acc.get(k, 0.0) + v
-
-    for i in range(max(2, args.warmup)):
-        fwd(frames[i % 2])
-    torch.cuda.synchronize()
-    stage_acc = {}
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        fwd(frames[i % 2], timing=True)
-        if i > 0:
-            accumulate(stage_acc, frames[(i - 1) % 2])
-    torch.cuda.synchronize()
-    t_fwd = (time.perf_counter() - t0) / args.steps
-    accumulate(stage_acc, frames[(args.steps - 1) % 2])
-    stages = {k: v / args.steps for k, v in stage_acc.items()
-              if not k.endswith("backward_ms") and k != "sort_first_pass_ms"}
-    first_pass_ms = stage_acc.get("sort_first_pass_ms", 0.0) / args.steps
-    info = frame.info()
+    t_fwd, stages, first_pass_ms = b.forward(args.steps, args.warmup)
+    info = b.frames[0].info()
     K, passes = int(info.num_keys), int(info.sort_passes)
+    roof = roofline(stages, b.scene, K, passes, info, first_pass_ms, args.sort_variant, args.sort_algo)
 
     result_extra = {}
+    bwd_stages = {}
     if not args.no_backward:
-        target = torch.from_numpy(S.target_image(40, W, H)).to(dev)
-        grads = {k: torch.empty_like(getattr(scene, k)) for k in
-                 ("means", "log_scales", "quats", "opacity_logits", "sh")}
-        dl = torch.empty((3, H, W), device=dev)
-        loss = torch.empty(1, device=dev)
-
-        def fwdbwd(fr, timing=False):
-            rgb, T, nc, _ = fwd(fr, timing)
-            R.l1_loss_grad(rgb, target, dl, loss)
-            R.backward(fr, scene, cam, T, nc, dl, grads)
-
-        for i in range(max(2, args.warmup // 2)):
-            fwdbwd(frames[i % 2])
-        torch.cuda.synchronize()
-        bw_acc = {}
-        t0 = time.perf_counter()
-        for i in range(args.steps):
-            fwdbwd(frames[i % 2], timing=True)
-            if i > 0:
-                accumulate(bw_acc, frames[(i - 1) % 2])
-        torch.cuda.synchronize()
-        t_fb = (time.perf_counter() - t0) / args.steps
-        accumulate(bw_acc, frames[(args.steps - 1) % 2])
+        t_fb, bwd_stages = b.forward_backward(args.steps, max(2, args.warmup // 2))
         result_extra["fwd_bwd_fps"] = round(1.0 / t_fb, 3)
         result_extra["fwd_bwd_ms"] = round(t_fb * 1e3, 4)
-        result_extra["backward_stage_ms"] = {k: round(v / args.steps, 4) for k, v in bw_acc.items()
-                                             if k.endswith("backward_ms")}
+        result_extra["backward_stage_ms"] = {k: round(v, 4) for k, v in bwd_stages.items()}
+    b.close()
+    del b
+    torch.cuda.synchronize()
 
-    roof = roofline(stages, scene, K, passes, info, first_pass_ms, args.sort_variant, args.sort_algo)
+    others = {}
+    if not args.no_other_configs and args.config == "c2":
+        for name in ("c1", "c4", "c3", "room"):
+            res, sc_o, cam_o, st_o = other_config(R, name, args, backward=(name == "c4"))
+            if name == "room":
+                # the paper's blend-bound regime: Table 3's statistics and the blend's work
+                from oracle import oracle as O
+                o = O.render(sc_o, cam_o, round_f32=True)
+                res["table3"] = tile_statistics(o, cam_o.width, cam_o.height)
+                res["blend_roofline"] = blend_roofline(blend_work(o), st_o["blend_ms"])
+                for v in (3, 5):
+                    args_v = argparse.Namespace(**{**vars(args), "blend_variant": v})
+                    rv, _, _, stv = other_config(R, name, args_v, backward=False)
+                    res[f"blend_variant_{v}_ms"] = round(stv["blend_ms"], 4)
+            if name == "c1":
+                for v in (3, 5):
+                    args_v = argparse.Namespace(**{**vars(args), "blend_variant": v})
+                    rv, _, _, stv = other_config(R, name, args_v, backward=False)
+                    res[f"blend_variant_{v}_ms"] = round(stv["blend_ms"], 4)
+            others[name] = res
 
     serving = None
     if not args.no_serving:
         try:
             from paper_2509_25626_amd import serve
-            serving = serve.bench_serving(quick=True)
+            serving = serve.bench_serving(quick=args.quick_serving)
         except Exception as e:  # serving is reported when available
             serving = {"error": str(e)[:200]}
 
     cpu = None
+    blend_roof = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(scene_np, cam, args.cpu_budget_s)
+        cpu, o = cpu_baseline(scene_np, cam, args.cpu_budget_s)
+        if o is not None and o["image"].shape[1:] == (H, W) and "full" in cpu["sample"]:
+            work = blend_work(o)
+            blend_roof = blend_roofline(work, stages["blend_ms"], bwd_stages.get("blend_backward_ms"))
+            blend_roof["table3"] = tile_statistics(o, W, H)
 
     fps = 1.0 / t_fwd
     line = {
@@ -280,18 +468,21 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
+        "dtype_note": "float32 storage and blending; the projection's decisions (cull, radius, tile "
+                      "rectangle, depth bits) and the blend's quadratic form are evaluated in float64",
         "data": "synthetic",
-        "config": {"workload": f"{args.config}: {scene.n} Gaussians SH{scene.sh_degree}, {W}x{H}, 16x16 tiles, "
-                               "forward render", "gaussians": scene.n, "width": W, "height": H,
-                   "keys": K, "sort_passes": passes, "parallelism": "single GPU"},
+        "config": {"workload": f"{args.config}: {scene_np['n']} Gaussians SH{scene_np['sh_degree']}, {W}x{H}, "
+                               "16x16 tiles, forward render", "gaussians": scene_np["n"], "width": W,
+                   "height": H, "keys": K, "sort_passes": passes, "parallelism": "single GPU"},
         "stage_ms": {k: round(v, 4) for k, v in stages.items()},
         **result_extra,
+        "other_configs": others or None,
         "serving": serving,
         "roofline": roof,
+        "blend_roofline": blend_roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
-    R.release_frame(frame)
     R.close()
 
 
