@@ -37,7 +37,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "room"])
     ap.add_argument("--blend-variant", type=int, default=0)
-    ap.add_argument("--sort-variant", type=int, default=0, choices=[0, 1, 2, 3])
+    ap.add_argument("--sort-variant", type=int, default=0, choices=[0, 1, 2, 3, 4])
     ap.add_argument("--sort-algo", default="auto", choices=["auto", "onesweep", "reduce_scan"])
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -121,6 +121,9 @@ typedef struct cds_render_opts {
                                3 = depth digits per Gaussian, then a counting sort on the whole tile id
                                    fused with duplication (needs at most 512 tiles per row, i.e.
                                    images up to 8192 pixels wide; wider ones are rejected);
+                               4 = depth digits per Gaussian, then the tile lists by stable
+                                   placement of each splat's rectangle, first into per-tile-row
+                                   lists, then into the tiles (at most 4096 tiles per axis);
                                0 = default: 2. */
     int32_t reserved;
 } cds_render_opts;

@@ -19,11 +19,15 @@ constexpr int kCIPT = 16;
 constexpr int64_t kCTile = (int64_t)kCT * kCIPT;
 constexpr int kCWaves = kCT / kWave;
 
+// Per 4096-Gaussian tile: visible splats, keys and (with h_sums) the sum of
+// the visible splats' rectangle heights.
 __global__ __launch_bounds__(kCT) void k_vis_count(int64_t n, const uint32_t* __restrict__ touched,
-                                                   uint64_t* __restrict__ vis_sums, uint64_t* __restrict__ key_sums) {
-    __shared__ unsigned long long s_v[kCWaves], s_k[kCWaves];
+                                                   const uint2* __restrict__ rect,
+                                                   uint64_t* __restrict__ vis_sums, uint64_t* __restrict__ key_sums,
+                                                   uint64_t* __restrict__ h_sums) {
+    __shared__ unsigned long long s_v[kCWaves], s_k[kCWaves], s_h[kCWaves];
     const int64_t base = (int64_t)blockIdx.x * kCTile;
-    uint32_t v = 0;
+    uint32_t v = 0, hs = 0;
     unsigned long long k = 0;
 #pragma unroll
     for (int r = 0; r < kCIPT; ++r) {
@@ -31,28 +35,36 @@ __global__ __launch_bounds__(kCT) void k_vis_count(int64_t n, const uint32_t* __
         const uint32_t c = i < n ? touched[i] : 0u;
         v += c ? 1u : 0u;
         k += c;
+        if (h_sums && c) {
+            const uint2 rc = rect[i];
+            hs += (rc.y >> 16) - (rc.x >> 16) + 1u;
+        }
     }
-    unsigned long long vv = v;
+    unsigned long long vv = v, hh = hs;
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) {
         vv += __shfl_xor(vv, o, kWave);
         k += __shfl_xor(k, o, kWave);
+        hh += __shfl_xor(hh, o, kWave);
     }
     const int w = threadIdx.x / kWave;
     if (lane_id() == 0) {
         s_v[w] = vv;
         s_k[w] = k;
+        s_h[w] = hh;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned long long a = 0, b = 0;
+        unsigned long long a = 0, b = 0, c = 0;
 #pragma unroll
         for (int q = 0; q < kCWaves; ++q) {
             a += s_v[q];
             b += s_k[q];
+            c += s_h[q];
         }
         vis_sums[blockIdx.x] = a;
         key_sums[blockIdx.x] = b;
+        if (h_sums) h_sums[blockIdx.x] = c;
     }
 }
 
@@ -132,16 +144,19 @@ int64_t compact_sums_size(int64_t n) { return (n + kCTile - 1) / kCTile + 1; }
 hipError_t launch_compact_visible(int64_t n, const uint32_t* touched, const uint2* rect, const uint32_t* depth_bits,
                                   uint64_t* vis_sums, uint64_t* key_sums, uint64_t* totals, uint32_t* dkey,
                                   uint4* rec, uint32_t* depth_hist, hipStream_t stream, int tiles_x,
-                                  const BatchItem* items, int nitems) {
+                                  const BatchItem* items, int nitems, uint64_t* h_sums, uint64_t* sum_h) {
     const int64_t tiles = (n + kCTile - 1) / kCTile;
     hipError_t e = launch_fill_u32(depth_hist, 4 * 256, 0u, stream);
     if (e != hipSuccess) return e;
+    if (sum_h && !h_sums) return hipErrorInvalidValue;
     if (tiles > 0) {
-        hipLaunchKernelGGL(k_vis_count, dim3((unsigned)tiles), dim3(kCT), 0, stream, n, touched, vis_sums,
-                           key_sums);
+        hipLaunchKernelGGL(k_vis_count, dim3((unsigned)tiles), dim3(kCT), 0, stream, n, touched, rect, vis_sums,
+                           key_sums, sum_h ? h_sums : nullptr);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    if ((e = launch_scan_u64_pair(vis_sums, key_sums, tiles, totals, totals + 1, stream)) != hipSuccess) return e;
+    if ((e = launch_scan_u64_pair(vis_sums, key_sums, tiles, totals, totals + 1, stream, sum_h ? h_sums : nullptr,
+                                  sum_h)) != hipSuccess)
+        return e;
     if (tiles > 0) {
         hipLaunchKernelGGL(k_vis_scatter, dim3((unsigned)tiles), dim3(kCT), 0, stream, n, touched, rect, depth_bits,
                            vis_sums, dkey, rec, depth_hist, (uint32_t)tiles_x, items, nitems);

@@ -84,10 +84,11 @@ __device__ __forceinline__ int find_item_by_tile(const BatchItem* items, int nit
 hipError_t launch_preprocess_batch(const BatchItem* items, int nitems, int64_t total, const SplatBuffers& out,
                                    hipStream_t stream);
 
-// Two exclusive in-place scans of `count` uint64 values each (one workgroup
-// per array, one launch); the totals go to *total_a and *total_b.
+// Two (or, with c, three) exclusive in-place scans of `count` uint64 values
+// each (one workgroup per array, one launch); the totals go to *total_a,
+// *total_b (and *total_c).
 hipError_t launch_scan_u64_pair(uint64_t* a, uint64_t* b, int64_t count, uint64_t* total_a, uint64_t* total_b,
-                                hipStream_t stream);
+                                hipStream_t stream, uint64_t* c = nullptr, uint64_t* total_c = nullptr);
 
 // Tile record of a visible splat (16 B): its rectangle of tiles as runs of
 // tile ids, (width | height << 16, row stride, Gaussian index, id of the first
@@ -107,11 +108,14 @@ struct BatchItem;
 // give the per-request grids of a batched render, else tiles_x and tile base
 // 0), depth_hist [4][256] digit histograms of dkey, totals[0] = n_vis,
 // totals[1] = K.  vis_sums, key_sums: compact_sums_size(n) uint64 each.
+// With sum_h (and h_sums, compact_sums_size(n) more uint64 of workspace),
+// *sum_h = the sum of the visible splats' rectangle heights.
 int64_t compact_sums_size(int64_t n);
 hipError_t launch_compact_visible(int64_t n, const uint32_t* touched, const uint2* rect, const uint32_t* depth_bits,
                                   uint64_t* vis_sums, uint64_t* key_sums, uint64_t* totals, uint32_t* dkey,
                                   uint4* rec, uint32_t* depth_hist, hipStream_t stream, int tiles_x,
-                                  const BatchItem* items = nullptr, int nitems = 0);
+                                  const BatchItem* items = nullptr, int nitems = 0, uint64_t* h_sums = nullptr,
+                                  uint64_t* sum_h = nullptr);
 
 // Exclusive scan of n uint32 values (read as in[gather[i]] when gather is
 // not null); the total (uint64, device) is written too.  `block_sums` needs
@@ -300,6 +304,41 @@ hipError_t launch_bin_place(const BinPlan& p, int64_t n, const uint32_t* order, 
                             hipStream_t stream);
 hipError_t launch_keys_from_ranges(const uint2* ranges, int64_t ntiles, const uint32_t* values,
                                    const uint32_t* depth_bits, uint64_t* keys, hipStream_t stream);
+
+// Tile lists by stable interval placement, row by row (sort variant 4): the
+// visible splats' tile records in depth order go into per-tile-row lists,
+// then each row list into the tile lists at the tile ranges, without radix
+// passes over the keys.  Images of at most kRowPlaceMaxBins tiles per axis.
+constexpr int kRowPlaceMaxBins = 4096;
+bool row_place_supported(int tiles_x, int tiles_y);
+struct RowPlaceSizes {
+    int64_t chunks_a = 0;      // chunks of 1024 records
+    int64_t chunks_b_max = 0;  // bound on the chunks of the row lists
+    int64_t ha_words = 0;      // uint32 words of RowPlaceArgs::ha
+    int64_t hb_words = 0;      // uint32 words of RowPlaceArgs::hb
+    int64_t small_words = 0;   // uint32 words of RowPlaceArgs::small
+};
+// n_records: the number of records (or a bound on it); sum_h: the sum of the
+// records' rectangle heights (the number of row-list entries).
+RowPlaceSizes row_place_sizes(int64_t n_records, uint64_t sum_h, int tiles_x, int tiles_y);
+struct RowPlaceArgs {
+    const uint4* rec;            // [n] tile records in depth order (single render: tile base 0)
+    const uint64_t* count_dev;   // device: number of records
+    int64_t n_records_max;       // bound on it (sizes the grids)
+    int tiles_x = 0, tiles_y = 0;
+    uint64_t sum_h = 0;          // row-list entries
+    uint64_t K = 0;              // keys
+    const uint2* ranges;         // [tiles] ranges of the sorted list
+    hipEvent_t ranges_ready;     // recorded where the ranges are complete, or null
+    uint32_t* ha;                // workspace, row_place_sizes words each
+    uint32_t* hb;
+    uint32_t* small;
+    uint2* rowent;               // [sum_h] workspace
+    uint32_t* values;            // [K] output
+    uint32_t* err;               // device error word (bit 32: inconsistent counts)
+};
+// `rows_done`, when given, is recorded on `stream` once the row lists are complete.
+hipError_t launch_row_place(const RowPlaceArgs& a, hipStream_t stream, hipEvent_t rows_done = nullptr);
 
 hipError_t launch_ranges(const uint32_t* tile_words, int stride, int64_t count, uint2* ranges,
                          int64_t ntiles, hipStream_t stream);

@@ -32,7 +32,8 @@ void release_frame_buffers(cds_frame* f) {
                       &f->dkey0, &f->dkey1, &f->sort_d.hist, &f->sort_d.status, &f->sort_d.counters,
                       &f->sort_d.part_hist, &f->sort_d.bases, &f->sort_d.scan_sums, &f->sort_d.scan_total,
                       &f->vrect, &f->binM, &f->binE, &f->binP, &f->tsum, &f->tdiff, &f->thist,
-                      &f->dkeyc, &f->recc, &f->recv, &f->vsums, &f->ksums,
+                      &f->dkeyc, &f->recc, &f->recv, &f->vsums, &f->ksums, &f->hsums, &f->rp_ha, &f->rp_hb,
+                      &f->rp_small, &f->rp_rowent,
                       &f->keys0, &f->keys1, &f->tk0, &f->tk1, &f->vals0, &f->vals1, &f->sort.hist,
                       &f->sort.status, &f->sort.counters, &f->sort.part_hist, &f->sort.bases,
                       &f->sort.scan_sums, &f->sort.scan_total, &f->ranges, &f->grad2d};
@@ -90,7 +91,11 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
     if (sort_variant == 0) sort_variant = 2;
     if (sort_variant == 3 && !can_bin)
         return fail(CDS_ERR_INVALID_ARG, "tile binning needs at most 512 tiles per row");
-    const bool compact = sort_variant == 2;
+    if (sort_variant == 4 && !row_place_supported(P.tiles_x, P.tiles_y))
+        return fail(CDS_ERR_INVALID_ARG, "row-wise tile placement needs at most 4096 tiles per axis");
+    // variants 2 and 4 both start from the compacted visible splats in depth order
+    const bool compact = sort_variant == 2 || sort_variant == 4;
+    const bool rowplace = sort_variant == 4;
     const bool binned = sort_variant == 3;
 
     CDS_TRY(ensure(ctx, f->mean2d, sizeof(float2) * nn, 1.1));
@@ -115,6 +120,7 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
         CDS_TRY(ensure(ctx, f->recv, sizeof(uint4) * nn, 1.1));
         CDS_TRY(ensure(ctx, f->vsums, sizeof(uint64_t) * compact_sums_size(n), 1.1));
         CDS_TRY(ensure(ctx, f->ksums, sizeof(uint64_t) * compact_sums_size(n), 1.1));
+        if (rowplace) CDS_TRY(ensure(ctx, f->hsums, sizeof(uint64_t) * compact_sums_size(n), 1.1));
     }
     if (compact || binned) {
         CDS_TRY(ensure(ctx, f->order0, sizeof(uint32_t) * nn, 1.1));
@@ -161,9 +167,11 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
     const uint32_t* order = nullptr;
     if (compact) {
         // visible splats compacted in index order, with the depth histograms; n_vis and K
+        // (row-wise placement: also the sum of the rectangle heights, d_total[3])
         CDS_HIP(launch_compact_visible(n, sb.touched, sb.rect, sb.depth_bits, (uint64_t*)f->vsums.p,
                                        (uint64_t*)f->ksums.p, d_total, (uint32_t*)f->dkeyc.p, (uint4*)f->recc.p,
-                                       wd.hist, stream, P.tiles_x),
+                                       wd.hist, stream, P.tiles_x, nullptr, 0,
+                                       rowplace ? (uint64_t*)f->hsums.p : nullptr, rowplace ? d_total + 3 : nullptr),
                 "visible compaction");
     } else if (binned) {
         // depth order of all N Gaussians: 4 passes, result in (dkey1, order1)
@@ -187,7 +195,7 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
                                       d_total + 1, stream),
                 "scan kernels");
     }
-    CDS_HIP(hipMemcpyAsync(ctx->host_pinned, d_total, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
+    CDS_HIP(hipMemcpyAsync(ctx->host_pinned, d_total, 4 * sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
             "hipMemcpyAsync(key count)");
     CDS_TRY(f->record(kEvCount, stream));
     if (compact) {
@@ -237,7 +245,44 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
     f->tiles_y = P.tiles_y;
     f->sort_variant = sort_variant;
 
-    if (binned) {
+    if (rowplace) {
+        // tile lists by interval placement over tile rows, then tile columns
+        const uint64_t sum_h = ctx->host_pinned[3];
+        const RowPlaceSizes rs = row_place_sizes(nvis, sum_h, P.tiles_x, P.tiles_y);
+        CDS_TRY(ensure(ctx, f->rp_ha, sizeof(uint32_t) * (size_t)rs.ha_words, 1.25));
+        CDS_TRY(ensure(ctx, f->rp_hb, sizeof(uint32_t) * (size_t)std::max<int64_t>(rs.hb_words, 1), 1.25));
+        CDS_TRY(ensure(ctx, f->rp_small, sizeof(uint32_t) * (size_t)rs.small_words, 1.25));
+        CDS_TRY(ensure(ctx, f->rp_rowent, sizeof(uint2) * (size_t)std::max<uint64_t>(sum_h, 1), 1.25));
+        side_join.armed = false;
+        CDS_HIP(hipStreamWaitEvent(stream, f->join, 0), "hipStreamWaitEvent(join)");
+        CDS_TRY(f->record(kEvDepth, stream));
+        CDS_TRY(f->record(kEvKeys, stream));
+        RowPlaceArgs ra;
+        ra.rec = (const uint4*)f->recv.p;
+        ra.count_dev = d_total;
+        ra.n_records_max = nvis;
+        ra.tiles_x = P.tiles_x;
+        ra.tiles_y = P.tiles_y;
+        ra.sum_h = sum_h;
+        ra.K = K;
+        ra.ranges = (const uint2*)f->ranges.p;
+        ra.ranges_ready = nullptr;  // the stream waited for the tile counts above
+        ra.ha = (uint32_t*)f->rp_ha.p;
+        ra.hb = (uint32_t*)f->rp_hb.p;
+        ra.small = (uint32_t*)f->rp_small.p;
+        ra.rowent = (uint2*)f->rp_rowent.p;
+        ra.values = (uint32_t*)f->vals0.p;
+        ra.err = ctx->d_err;
+        CDS_HIP(launch_row_place(ra, stream, f->event(kEvSortFirst)), "row-wise tile placement");
+        if (K == 0 || nvis == 0) CDS_TRY(f->record(kEvSortFirst, stream));  // nothing was placed
+        CDS_TRY(f->record(kEvSort, stream));
+        CDS_TRY(f->record(kEvRanges, stream));
+        f->res_values = (const uint32_t*)f->vals0.p;
+        f->res_tiles = nullptr;
+        f->res_tile_stride = 1;
+        f->res_keys = nullptr;
+        f->passes = 4;
+    } else if (binned) {
         CDS_TRY(f->record(kEvDepth, stream));
         CDS_HIP(launch_bin_place(bp, n, order, (const uint2*)f->vrect.p, (const uint32_t*)f->binM.p,
                                  (const uint32_t*)f->binE.p, K, (uint32_t*)f->vals0.p, ctx->d_err, stream),

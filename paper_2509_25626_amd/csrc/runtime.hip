@@ -260,8 +260,8 @@ cds_status cds_render_forward_ex(cds_ctx* ctx, cds_frame* f, const cds_scene* sc
         variant = opts->blend_variant;
         if (variant < 0 || variant > 5)
             return fail(CDS_ERR_INVALID_ARG, "blend_variant must be 0 to 5");
-        if (opts->sort_variant < 0 || opts->sort_variant > 3)
-            return fail(CDS_ERR_INVALID_ARG, "sort_variant must be 0, 1, 2 or 3");
+        if (opts->sort_variant < 0 || opts->sort_variant > 4)
+            return fail(CDS_ERR_INVALID_ARG, "sort_variant must be 0 to 4");
         sort_variant = opts->sort_variant;
     }
     hipStream_t stream = (hipStream_t)stream_;
@@ -336,7 +336,7 @@ cds_status cds_frame_get_info(cds_frame* f, cds_frame_info* o) {
     o->radius = (const int32_t*)f->radius.p;
     o->tile_rect = (const uint32_t*)f->rect.p;
     o->tiles_touched = (const uint32_t*)f->touched.p;
-    o->offsets = f->sort_variant == 3 ? nullptr : (const uint32_t*)f->offsets.p;
+    o->offsets = (f->sort_variant == 3 || f->sort_variant == 4) ? nullptr : (const uint32_t*)f->offsets.p;
     o->keys = f->res_keys;
     o->values = f->res_values;
     o->ranges = (const uint32_t*)f->ranges.p;

@@ -55,6 +55,8 @@ struct cds_frame {
     cds::DevBuf tdiff, thist;                  // per-tile counts and tile-digit histograms (variant 2)
     cds::DevBuf dkeyc, recc, recv, vsums, ksums;  // compacted visible splats (variant 2)
     cds::DevBuf kowner;                        // record owning every 1024th key (variant 2)
+    cds::DevBuf hsums;                         // per-tile rectangle-height sums (variant 4)
+    cds::DevBuf rp_ha, rp_hb, rp_small, rp_rowent;  // row-wise tile placement (variant 4)
     cds::SortState sort_d;
     // per key
     cds::DevBuf keys0, keys1;                  // 64-bit keys (variant 1; others: rebuilt on request)

@@ -44,13 +44,18 @@ __global__ __launch_bounds__(kNT) void k_scan_reduce(ScanSrc src, int64_t n, uin
 }
 
 // One block scans the tile sums (exclusive, in place) and writes the total;
-// a second block, when launched, does the same for sums2 / total2.
+// a second and a third block, when launched, do the same for sums2 / total2
+// and sums3 / total3.
 __global__ __launch_bounds__(1024) void k_scan_sums(uint64_t* __restrict__ sums, int64_t count,
                                                     uint64_t* __restrict__ total, uint64_t* __restrict__ sums2,
-                                                    uint64_t* __restrict__ total2) {
+                                                    uint64_t* __restrict__ total2, uint64_t* __restrict__ sums3,
+                                                    uint64_t* __restrict__ total3) {
     if (blockIdx.x == 1) {  // uniform
         sums = sums2;
         total = total2;
+    } else if (blockIdx.x == 2) {
+        sums = sums3;
+        total = total3;
     }
     __shared__ uint64_t wsum[1024 / kWave];
     __shared__ uint64_t carry;
@@ -119,8 +124,10 @@ __global__ __launch_bounds__(kNT) void k_scan_down(ScanSrc src, int64_t n, const
 int64_t scan_block_sums_size(int64_t n) { return (n + kTileItems - 1) / kTileItems + 1; }
 
 hipError_t launch_scan_u64_pair(uint64_t* a, uint64_t* b, int64_t count, uint64_t* total_a, uint64_t* total_b,
-                                hipStream_t stream) {
-    hipLaunchKernelGGL(k_scan_sums, dim3(2), dim3(1024), 0, stream, a, count, total_a, b, total_b);
+                                hipStream_t stream, uint64_t* c, uint64_t* total_c) {
+    if ((c != nullptr) != (total_c != nullptr)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_scan_sums, dim3(c ? 3 : 2), dim3(1024), 0, stream, a, count, total_a, b, total_b, c,
+                       total_c);
     return hipGetLastError();
 }
 
@@ -136,7 +143,8 @@ hipError_t launch_exclusive_scan(const uint32_t* in, const uint32_t* gather, uin
         hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)tiles), dim3(kNT), 0, stream, src, n, block_sums,
                            count_dev);
     }
-    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, stream, block_sums, tiles, total, nullptr, nullptr);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, stream, block_sums, tiles, total, nullptr, nullptr,
+                       nullptr, nullptr);
     if (tiles > 0) {
         hipLaunchKernelGGL(k_scan_down, dim3((unsigned)tiles), dim3(kNT), 0, stream, src, n, block_sums, out, owner,
                            count_dev);

@@ -131,7 +131,7 @@ def effective_sort_variant(sort_variant):
 
 def expected_offsets(o, sort_variant):
     sort_variant = effective_sort_variant(sort_variant)
-    if sort_variant == 3:  # binning never forms the key offsets
+    if sort_variant in (3, 4):  # binning and row-wise placement never form the key offsets
         return np.zeros(0, np.uint32)
     t = o["proj"]["tiles_touched"].astype(np.uint64)
     if sort_variant == 2:  # visible splats visited in (depth bits, index) order
@@ -177,14 +177,14 @@ def full_check(R, scene, cam, variant=0, sort_variant=0, sort_algo="auto"):
 
 # ---------------------------------------------------------------- whole pipeline
 
-@pytest.mark.parametrize("sort_variant,sort_algo", [(0, "auto"), (1, "auto"), (2, "auto"), (3, "auto"),
+@pytest.mark.parametrize("sort_variant,sort_algo", [(0, "auto"), (1, "auto"), (2, "auto"), (3, "auto"), (4, "auto"),
                                                      (2, "onesweep"), (2, "reduce_scan"), (1, "reduce_scan"),
                                                      (3, "reduce_scan")])
 def test_c1_forward_parity(R, sort_variant, sort_algo):
     scene, cam = S.config_scene("c1")
     g, o, nflip = full_check(R, scene, cam, sort_variant=sort_variant, sort_algo=sort_algo)
     # 40 key bits: 5 radix passes, 4 of them over the depth digits when presorted
-    assert g["K"] > 30000 and g["passes"] == (4 if effective_sort_variant(sort_variant) == 3 else 5)
+    assert g["K"] > 30000 and g["passes"] == (4 if effective_sort_variant(sort_variant) in (3, 4) else 5)
     print(f"c1: K={g['K']} flip-eligible pixels={nflip}")
 
 
@@ -201,7 +201,7 @@ def test_sort_variants_bit_identical(R, wh, n):
     scene = S.scene_outdoor(15, n)
     cam = S.orbit_camera(W, H, 4.0, 10.0, 0.0)
     a = gpu_render(R, scene, cam, sort_variant=1)
-    for sv in (2, 3):
+    for sv in (2, 3, 4):
         b = gpu_render(R, scene, cam, sort_variant=sv)
         for k in ("keys", "values", "ranges", "image", "final_T", "n_contrib"):
             # offsets: the visit order differs by design (index order vs depth order)
@@ -215,10 +215,11 @@ def test_binning_many_keys_per_row(R):
     scene = S.scene_outdoor(16, 12_000, log_scale_mu=-1.2, log_scale_sigma=0.3)
     cam = S.orbit_camera(1237, 822, 4.0, 30.0, 0.0)
     a = gpu_render(R, scene, cam, sort_variant=1)
-    b = gpu_render(R, scene, cam, sort_variant=3)
     assert a["K"] > 12_000 * 100
-    for k in ("keys", "values", "ranges", "image", "final_T", "n_contrib"):
-        assert np.array_equal(a[k], b[k]), k
+    for sv in (3, 4):
+        b = gpu_render(R, scene, cam, sort_variant=sv)
+        for k in ("keys", "values", "ranges", "image", "final_T", "n_contrib"):
+            assert np.array_equal(a[k], b[k]), (sv, k)
 
 
 @pytest.mark.parametrize("variant", [1, 2, 3, 4])
@@ -259,11 +260,11 @@ def test_generated_keys_match_duplication(R, mu, sigma, n):
     scene = S.scene_outdoor(18, n, log_scale_mu=mu, log_scale_sigma=sigma)
     cam = S.orbit_camera(1237, 822, 4.0, 30.0, 0.0)
     a = gpu_render(R, scene, cam, sort_variant=1)
-    for algo in ("onesweep", "reduce_scan"):
-        b = gpu_render(R, scene, cam, sort_variant=2, sort_algo=algo)
+    for sv, algo in ((2, "onesweep"), (2, "reduce_scan"), (4, "auto")):
+        b = gpu_render(R, scene, cam, sort_variant=sv, sort_algo=algo)
         assert a["K"] == b["K"]
         for k in ("keys", "values", "ranges", "image", "final_T", "n_contrib"):
-            assert np.array_equal(a[k], b[k]), (algo, k)
+            assert np.array_equal(a[k], b[k]), (sv, algo, k)
     if mu < -6:  # under 4 keys per record: more than 256 records start in most chunks
         assert a["K"] < 3 * b["n_vis"]
 
