@@ -290,6 +290,27 @@ cds_status cds_sort_pairs(cds_ctx* ctx, const uint64_t* keys_in, const uint32_t*
                           uint32_t* values_out, uint32_t flags, void* stream);
 
 /*
+ * The same sort without any allocation, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation.  Arguments, results and errors as
+ * cds_sort_pairs, except:
+ *   - count may be at most CDS_NOALLOC_MAX_PAIRS (larger: CDS_ERR_CAPACITY,
+ *     no device work);
+ *   - every buffer beyond the inputs and outputs comes from one fixed device
+ *     array of CDS_NOALLOC_SCRATCH_BYTES, held by each GPU the library runs
+ *     on until the process ends; the call makes no allocation, through the
+ *     context's allocator or otherwise;
+ *   - all calls on one GPU share that array: calls that overlap on one GPU
+ *     (on different streams or from different threads) race and must be
+ *     ordered by the caller.
+ */
+#define CDS_NOALLOC_MAX_PAIRS 1048576
+#define CDS_NOALLOC_SCRATCH_BYTES 15217152
+cds_status cds_sort_pairs_noalloc(cds_ctx* ctx, const uint64_t* keys_in, const uint32_t* values_in,
+                                  int64_t count, int32_t end_bit, uint64_t* keys_out,
+                                  uint32_t* values_out, uint32_t flags, void* stream);
+
+/*
  * Stand-alone exclusive prefix sum of `count` uint32 (DEVICE in/out, may not
  * alias); the total is written to DEVICE *total (uint64).  Used by the
  * forward render for key offsets.

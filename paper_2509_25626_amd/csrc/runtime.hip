@@ -204,6 +204,9 @@ cds_status cds_create(cds_ctx** out, int device, const cds_allocator* alloc) {
         return hip_fail(e, "hipMemset");
     }
     c->d_partial = reinterpret_cast<float*>(reinterpret_cast<char*>(c->d_err) + 256);
+    // the allocation-free sort's scratch array on this device (looked up once
+    // per device; a failure is reported by that entry point only)
+    (void)noalloc_init_device(device);
     c->scratch = new cds_frame();
     c->scratch->ctx = c;
     *out = c;

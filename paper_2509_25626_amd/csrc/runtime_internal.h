@@ -93,6 +93,9 @@ namespace cds {
 
 extern thread_local std::string g_last_error;
 cds_status fail(cds_status s, const std::string& msg);
+// Looks up `device`'s copy of the allocation-free sort's scratch array (with
+// that device current); once per device.
+hipError_t noalloc_init_device(int device);
 cds_status hip_fail(hipError_t e, const char* what);
 void* ctx_alloc(cds_ctx* c, size_t bytes);
 void ctx_free(cds_ctx* c, void* p);

@@ -73,6 +73,7 @@ class CdsStageTimes(ctypes.Structure):
 CDS_OPT_STAGE_TIMING = 1
 CDS_OPT_SORT_ONESWEEP = 2
 CDS_OPT_SORT_REDUCE_SCAN = 4
+CDS_NOALLOC_MAX_PAIRS = 1048576
 
 
 class CdsServerOpts(ctypes.Structure):
@@ -106,6 +107,7 @@ SIGNATURES = {
     "cds_frame_get_info": (ctypes.c_int, [P, ctypes.POINTER(CdsFrameInfo)]),
     "cds_frame_stage_times": (ctypes.c_int, [P, ctypes.POINTER(CdsStageTimes)]),
     "cds_sort_pairs": (ctypes.c_int, [P, P, P, ctypes.c_int64, ctypes.c_int32, P, P, ctypes.c_uint32, P]),
+    "cds_sort_pairs_noalloc": (ctypes.c_int, [P, P, P, ctypes.c_int64, ctypes.c_int32, P, P, ctypes.c_uint32, P]),
     "cds_exclusive_scan_u32": (ctypes.c_int, [P, P, ctypes.c_int64, P, P, P]),
     "cds_check_device": (ctypes.c_int, [P, P]),
     "cds_server_create": (ctypes.c_int, [P, ctypes.POINTER(CdsServerOpts), ctypes.POINTER(P)]),
