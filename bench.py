@@ -99,7 +99,12 @@ def roofline(stages, scene, K, passes, info, first_pass_ms, variant, algo):
         "sort_ms": (f"k_sort_pass_gen<{tile_digit_bits}, {512 if K >= (1 << 23) else 256}>", 1,
                     20 * nvis + 4 * (K // 1024 + 1) + word * K),
     }
-    if variant == 1:  # first pass over (u64 key, u32 value) pairs written by k_duplicate
+    if variant in (0, 4) and int(info.num_row_entries) > 0:
+        # row-wise placement: the last kernel reads each row-list entry (8 B)
+        # and writes each key's value (4 B); its time is the tile stage's
+        # minus the column counts and starts before it (its own event)
+        table["sort_ms"] = ("k_rp_place_cols", 1, 8 * int(info.num_row_entries) + 4 * K)
+    elif variant == 1:  # first pass over (u64 key, u32 value) pairs written by k_duplicate
         table["sort_ms"] = (f"k_sort_pass_onesweep<u64,{tile_digit_bits}> (first pass)", 1, 24 * K)
     elif algo == "reduce_scan":  # first pass over (u32 tile, u32 value) pairs written by k_duplicate
         table["sort_ms"] = (f"k_sort_pass_rts<u32,{tile_digit_bits}> (first pass)", 1, (8 + word) * K)
@@ -113,8 +118,8 @@ def roofline(stages, scene, K, passes, info, first_pass_ms, variant, algo):
                 "unit": None, "frac": None, "traffic": None, "stage_ms": round(stages[dom], 4)}
     kernel, launches, nbytes = table[dom]
     per_launch_ms = stages[dom] / launches
-    if dom == "sort_ms":  # the first pass alone, from its own event
-        per_launch_ms = first_pass_ms
+    if dom == "sort_ms":  # the kernel alone, from its own events
+        per_launch_ms = stages[dom] - first_pass_ms if kernel == "k_rp_place_cols" else first_pass_ms
     achieved = nbytes / (per_launch_ms * 1e-3) / 1e9
     traffic = measured_traffic(kernel)
     return {"kernel": kernel, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -124,7 +124,7 @@ typedef struct cds_render_opts {
                                4 = depth digits per Gaussian, then the tile lists by stable
                                    placement of each splat's rectangle, first into per-tile-row
                                    lists, then into the tiles (at most 4096 tiles per axis);
-                               0 = default: 2. */
+                               0 = default: 4 where the grid allows it, else 2. */
     int32_t reserved;
 } cds_render_opts;
 
@@ -247,6 +247,8 @@ typedef struct cds_frame_info {
     const uint32_t* values;        /* [K] Gaussian index of each sorted key */
     const uint32_t* ranges;        /* [tiles_x * tiles_y] uint2 [start, end), (0, 0) if empty */
     const uint8_t* clamp_flags;    /* [n] bit 0..2 colour channel clamped, 3/4 Jacobian x/y clamped */
+    int64_t num_row_entries;       /* variant 4: entries of the per-tile-row lists (the visible
+                                      splats' rectangle heights summed); 0 otherwise */
 } cds_frame_info;
 
 cds_status cds_frame_get_info(cds_frame* frame, cds_frame_info* out);
@@ -256,17 +258,22 @@ cds_status cds_frame_get_info(cds_frame* frame, cds_frame_info* out);
  * forward ran with CDS_OPT_STAGE_TIMING.  Waits for those events.
  *   preprocess_ms   projection and colour (a1, a2)
  *   scan_ms         up to the host read-back of the key count, included:
- *                   the visible-splat compaction (sort variant 2), the prefix
- *                   sum of tiles_touched (variant 1), or the depth sort and
- *                   tile counts of binning (variant 3)
- *   depth_order_ms  variant 2: depth sort of the visible splats, their key
- *                   offsets, the per-tile counts and ranges; 0 otherwise
+ *                   the visible-splat compaction (sort variants 2 and 4), the
+ *                   prefix sum of tiles_touched (variant 1), or the depth sort
+ *                   and tile counts of binning (variant 3)
+ *   depth_order_ms  variants 2 and 4: depth sort of the visible splats (with
+ *                   variant 2 also their key offsets), the per-tile counts and
+ *                   ranges; 0 otherwise
  *   duplicate_ms    key generation as its own kernel (variant 1, variant 2
  *                   with reduce-then-scan passes; variant 3: the fused
- *                   placement); about 0 when the first pass generates them
+ *                   placement; variant 4: the per-tile-row lists); about 0
+ *                   when the first radix pass generates the keys
  *   sort_ms         the per-key radix passes (0 for variant 3); with variant 2
- *                   and onesweep passes the first of them generates the keys
- *   sort_first_pass_ms  the part of sort_ms taken by the first pass
+ *                   and onesweep passes the first of them generates the keys;
+ *                   variant 4: the placement of the row lists into the tiles
+ *   sort_first_pass_ms  the part of sort_ms taken by the first pass (variant
+ *                   4: by the column counts and start slots, before the last
+ *                   kernel)
  *   ranges_ms       ranges from the sorted keys (variant 1 only)
  *   blend_ms        the per-pixel blend
  * Backward fields are 0 until a backward pass has run. */

@@ -29,16 +29,20 @@ __global__ __launch_bounds__(kCT) void k_vis_count(int64_t n, const uint32_t* __
     const int64_t base = (int64_t)blockIdx.x * kCTile;
     uint32_t v = 0, hs = 0;
     unsigned long long k = 0;
+    uint32_t c[kCIPT];
+    uint2 rc[kCIPT];
+    // all loads issued up front (one memory latency)
 #pragma unroll
     for (int r = 0; r < kCIPT; ++r) {
         const int64_t i = base + (int64_t)r * kCT + threadIdx.x;
-        const uint32_t c = i < n ? touched[i] : 0u;
-        v += c ? 1u : 0u;
-        k += c;
-        if (h_sums && c) {
-            const uint2 rc = rect[i];
-            hs += (rc.y >> 16) - (rc.x >> 16) + 1u;
-        }
+        c[r] = i < n ? touched[i] : 0u;
+        rc[r] = h_sums && i < n ? rect[i] : make_uint2(0u, 0u);
+    }
+#pragma unroll
+    for (int r = 0; r < kCIPT; ++r) {
+        v += c[r] ? 1u : 0u;
+        k += c[r];
+        hs += c[r] ? (rc[r].y >> 16) - (rc[r].x >> 16) + 1u : 0u;
     }
     unsigned long long vv = v, hh = hs;
 #pragma unroll

@@ -337,8 +337,11 @@ struct RowPlaceArgs {
     uint32_t* values;            // [K] output
     uint32_t* err;               // device error word (bit 32: inconsistent counts)
 };
-// `rows_done`, when given, is recorded on `stream` once the row lists are complete.
-hipError_t launch_row_place(const RowPlaceArgs& a, hipStream_t stream, hipEvent_t rows_done = nullptr);
+// `rows_done` and `cols_counted`, when given, are recorded on `stream` once
+// the row lists are complete and right before the last kernel (the placement
+// into the tile lists).
+hipError_t launch_row_place(const RowPlaceArgs& a, hipStream_t stream, hipEvent_t rows_done = nullptr,
+                            hipEvent_t cols_counted = nullptr);
 
 hipError_t launch_ranges(const uint32_t* tile_words, int stride, int64_t count, uint2* ranges,
                          int64_t ntiles, hipStream_t stream);

@@ -88,7 +88,8 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
     const int tile_bits = tile_bits_for(ntiles);
     const int tile_passes = (tile_bits + 7) / 8;
     const bool can_bin = bin_supported(P.tiles_x, P.tiles_y);
-    if (sort_variant == 0) sort_variant = 2;
+    // default: row-wise placement where the grid allows it, else radix-sorted tile digits
+    if (sort_variant == 0) sort_variant = row_place_supported(P.tiles_x, P.tiles_y) ? 4 : 2;
     if (sort_variant == 3 && !can_bin)
         return fail(CDS_ERR_INVALID_ARG, "tile binning needs at most 512 tiles per row");
     if (sort_variant == 4 && !row_place_supported(P.tiles_x, P.tiles_y))
@@ -238,6 +239,7 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
     CDS_TRY(ensure(ctx, f->vals0, sizeof(uint32_t) * kk, 1.25));
     f->n = n;
     f->n_vis = nvis;
+    f->row_entries = rowplace ? (int64_t)ctx->host_pinned[3] : 0;
     f->K = (int64_t)K;
     f->width = cam->width;
     f->height = cam->height;
@@ -255,8 +257,9 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
         CDS_TRY(ensure(ctx, f->rp_rowent, sizeof(uint2) * (size_t)std::max<uint64_t>(sum_h, 1), 1.25));
         side_join.armed = false;
         CDS_HIP(hipStreamWaitEvent(stream, f->join, 0), "hipStreamWaitEvent(join)");
+        // events: depth order done; row lists (kEvKeys); column counts and starts
+        // (kEvSortFirst); tile lists (kEvSort)
         CDS_TRY(f->record(kEvDepth, stream));
-        CDS_TRY(f->record(kEvKeys, stream));
         RowPlaceArgs ra;
         ra.rec = (const uint4*)f->recv.p;
         ra.count_dev = d_total;
@@ -273,8 +276,11 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
         ra.rowent = (uint2*)f->rp_rowent.p;
         ra.values = (uint32_t*)f->vals0.p;
         ra.err = ctx->d_err;
-        CDS_HIP(launch_row_place(ra, stream, f->event(kEvSortFirst)), "row-wise tile placement");
-        if (K == 0 || nvis == 0) CDS_TRY(f->record(kEvSortFirst, stream));  // nothing was placed
+        CDS_HIP(launch_row_place(ra, stream, f->event(kEvKeys), f->event(kEvSortFirst)), "row-wise tile placement");
+        if (K == 0 || nvis == 0 || sum_h == 0) {  // nothing was placed
+            CDS_TRY(f->record(kEvKeys, stream));
+            CDS_TRY(f->record(kEvSortFirst, stream));
+        }
         CDS_TRY(f->record(kEvSort, stream));
         CDS_TRY(f->record(kEvRanges, stream));
         f->res_values = (const uint32_t*)f->vals0.p;

@@ -12,15 +12,14 @@
 //   B. tile lists: each entry of row y's list goes, in list order, to every
 //      tile (x, y) with x0 <= x <= x1, at that tile's slot of the sorted
 //      value list (the tile ranges are known beforehand from the rectangles).
-// Each placement cuts its input into chunks of 1024 consecutive intervals
-// (one wave each, 16 rounds of 64), counts per chunk how many intervals cover
-// each bin (difference arrays in LDS), scans those counts over the chunks of
-// a bin, and then places: per round, for every bin b the lanes whose interval
+// Each placement cuts its input into chunks of consecutive intervals (one
+// wave each, rounds of 64), counts per chunk how many intervals cover each
+// bin (difference arrays in LDS), scans those counts over the chunks of a
+// bin, and then places: for every bin b and round, the lanes whose interval
 // covers b are found with one ballot; their rank among those lanes is the
 // mask count below them, and the bin's write pointer advances by the count.
-// The lanes of one bin write consecutive words, so each ballot becomes one
-// contiguous store.  Bins are held in blocks of 64, one per lane: a bin's pointer is read
-// with readlane and its lane updated with a select.
+// A bin's entries of the whole chunk are gathered in LDS in that order and
+// go out as full-wave stores of consecutive words.
 //
 // After each chunk every bin's write pointer must stand where the next chunk's
 // part of the bin starts (or at the bin's end); anything else can only follow
@@ -34,11 +33,23 @@
 namespace cds {
 namespace {
 
-constexpr int kRpRounds = 16;
-constexpr int kRpChunk = kWave * kRpRounds;  // intervals per wave chunk
+// A wave places a chunk of R rounds of 64 intervals: R = 4 for the records
+// (more, smaller chunks: 1.5M records give 5.7k waves), 16 for the row-list
+// entries (8M at 3M Gaussians).
+constexpr int kRoundsA = 4;
+constexpr int kRoundsB = 16;
+constexpr int kChunkA = kWave * kRoundsA;
+constexpr int kChunkB = kWave * kRoundsB;
 constexpr int kRpWaves = 4;                  // waves (chunks) per workgroup
 constexpr int kRpThreads = kRpWaves * kWave;
 constexpr uint32_t kErrRowPlace = 32u;
+// Output stores go through buffer resources sized to the output: a lane
+// whose slot is not to be written gets this offset added, past any size the
+// resource is given (at most 2^31 bytes), and the hardware range check drops
+// its store; a slot past the output is dropped the same way.
+constexpr uint32_t kDropOffset = 0x80000000u;
+constexpr uint32_t kBufferDword3 = 0x00020000u;  // raw 32-bit buffer access (gfx9 family)
+typedef int int32x2_t __attribute__((ext_vector_type(2)));
 
 // Interval of one visible splat's record: tile rows [y0, y1], columns [x0, x1]
 // (clamped to the grid, which a record of the compaction never leaves).
@@ -58,9 +69,9 @@ __device__ __forceinline__ RecSpan rec_span(uint4 q, uint32_t tiles_x, uint32_t 
     return s;
 }
 
-// Per-chunk coverage counts: out[c * nbins + b] = intervals of chunk c that
+// Per-chunk coverage counts: out[b * stride] = intervals of this chunk that
 // cover bin b.  `diff` is this wave's nbins + 1 ints of LDS.
-__device__ __forceinline__ void chunk_counts(uint32_t* diff, int nbins, uint32_t* out) {
+__device__ __forceinline__ void chunk_counts(uint32_t* diff, int nbins, uint32_t* out, int64_t stride) {
     wave_lds_sync();
     const uint32_t l = lane_id();
     uint32_t carry = 0;
@@ -68,54 +79,69 @@ __device__ __forceinline__ void chunk_counts(uint32_t* diff, int nbins, uint32_t
         const int b = b0 + (int)l;
         const uint32_t d = b < nbins ? diff[b] : 0u;
         const uint32_t inc = wave_incl_sum(d) + carry;
-        if (b < nbins) out[b] = inc;
+        if (b < nbins) out[b * stride] = inc;
         carry = (uint32_t)__builtin_amdgcn_readlane((int)inc, kWave - 1);
     }
 }
 
-// Stable placement of one round of intervals [lo, hi] (lanes with `valid`)
-// over nbins bins: for every bin, the covering lanes in lane order get
-// consecutive slots from the bin's write pointer (s_base, this wave's nbins
-// words of LDS), which then advances past them.  emit(slot) is called by each
-// covering lane with its slot.  Per block of 64 bins the pointers sit one per
-// lane; a bin's pointer is read with readlane, and after the block the
-// pointers advance by the round's coverage counts, which a difference array
-// (s_diff, 65 words of this wave's LDS) and a wave prefix sum give.
-template <typename Emit>
-__device__ __forceinline__ void place_round(bool valid, uint32_t lo, uint32_t hi, int nbins, uint32_t* s_base,
-                                            uint32_t* s_diff, Emit emit) {
+// Stable placement of one wave's chunk of R rounds of 64 intervals [lo,
+// lo + span] over nbins bins (an unused slot has lo past every bin and span
+// 0): for every bin, the covering intervals in chunk order (round, then
+// lane) get consecutive slots from the bin's write pointer (s_base, this
+// wave's nbins words of LDS), which advances past them.  Their payloads
+// (W words each) are first gathered in that order in this wave's staging
+// area s_stage (R * 64 slots of W words), then the bin's run goes out as
+// full-wave stores of 64 consecutive payloads: store(slot, value, drop) with
+// drop = kDropOffset for lanes past the run.
+// Bins go in blocks of 64, the pointers one per lane: a bin's pointer is read
+// with readlane and written back to its lane with a select.
+template <int R, int W, typename Store>
+__device__ __forceinline__ void place_chunk(const uint32_t (&lo)[R], const uint32_t (&span)[R],
+                                            const uint32_t (&payload)[R][W], int nbins, uint32_t* s_base,
+                                            uint32_t* s_stage, Store store) {
+    static_assert(W == 1 || W == 2, "one or two words per payload");
     const uint32_t l = lane_id();
-    if (!ballot(valid)) return;  // uniform
-    // bin b is covered iff b - lo <= span (unsigned); an invalid lane gets an
-    // interval no bin falls in (lo past every bin, span 0)
-    if (!valid) {
-        lo = 0xFFFF0000u;
-        hi = lo;
-    }
-    const uint32_t span = hi - lo;
     for (int b0 = 0; b0 < nbins; b0 += kWave) {
         const uint32_t bl = (uint32_t)b0, bh = (uint32_t)b0 + kWave - 1u;
-        const bool meets = valid && lo <= bh && hi >= bl;
-        if (!ballot(meets)) continue;  // uniform: no lane covers this block
+        bool meets = false;
+#pragma unroll
+        for (int r = 0; r < R; ++r) meets |= lo[r] <= bh && lo[r] + span[r] >= bl;
+        if (!ballot(meets)) continue;  // uniform: nothing of the chunk in this block
         const int nb = __builtin_amdgcn_readfirstlane(min(kWave, nbins - b0));
         uint32_t vb = (int)l < nb ? s_base[b0 + l] : 0u;
-        s_diff[l] = 0u;
-        if (l == 0) s_diff[kWave] = 0u;
         for (int j = 0; j < nb; ++j) {
-            const bool cov = (uint32_t)(b0 + j) - lo <= span;
-            const uint64_t m = ballot(cov);
+            const uint32_t b = (uint32_t)(b0 + j);
+            uint32_t run = 0;  // payloads of this bin gathered so far (uniform)
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const bool cov = b - lo[r] <= span[r];
+                const uint64_t m = ballot(cov);
+                if (cov) {
+                    const uint32_t k = run + count_below(m);
+                    if constexpr (W == 1) {
+                        s_stage[k] = payload[r][0];
+                    } else {
+                        reinterpret_cast<uint2*>(s_stage)[k] = make_uint2(payload[r][0], payload[r][1]);
+                    }
+                }
+                run += (uint32_t)__popcll(m);
+            }
+            wave_lds_sync();
             const uint32_t base = (uint32_t)__builtin_amdgcn_readlane((int)vb, j);
-            if (cov) emit(base + count_below(m));
+            for (uint32_t q = 0; q < run; q += kWave) {  // uniform
+                const uint32_t i = q + l;
+                const uint32_t drop = i < run ? 0u : kDropOffset;
+                if constexpr (W == 1) {
+                    store(base + i, make_uint2(s_stage[min(i, (uint32_t)(R * kWave) - 1u)], 0u), drop);
+                } else {
+                    store(base + i, reinterpret_cast<const uint2*>(s_stage)[min(i, (uint32_t)(R * kWave) - 1u)],
+                          drop);
+                }
+            }
+            wave_lds_sync();  // the run is read before the next bin's gathers
+            vb = l == (uint32_t)j ? base + run : vb;
         }
-        wave_lds_sync();
-        if (meets) {
-            atomicAdd(&s_diff[(lo > bl ? lo : bl) - bl], 1u);
-            atomicSub(&s_diff[(hi < bh ? hi : bh) + 1u - bl], 1u);
-        }
-        wave_lds_sync();
-        vb += wave_incl_sum(s_diff[l]);
         if ((int)l < nb) s_base[b0 + l] = vb;
-        wave_lds_sync();
     }
 }
 
@@ -123,7 +149,8 @@ struct RpArgs {
     const uint4* rec;       // [nvis] tile records in depth order
     const uint64_t* count;  // device: number of records (nvis)
     uint32_t tiles_x, tiles_y;
-    uint32_t* ha;           // [chunks_a][rows]: counts, then exclusive prefix within the row
+    uint32_t* ha;           // [rows][ha_stride]: per row and chunk, counts, then exclusive prefix
+    int64_t ha_stride;      // chunks of records (bound)
     uint32_t* rowtot;       // [rows]
     uint32_t* rowstart;     // [rows + 1]
     uint32_t* cstart;       // [rows + 1]: first B chunk of each row; cstart[rows] = B chunks
@@ -138,7 +165,7 @@ struct RpArgs {
     uint32_t* err;
 };
 
-// A1: per chunk of 1024 records, how many cover each tile row.
+// A1: per chunk of kChunkA records, how many cover each tile row.
 __global__ __launch_bounds__(kRpThreads) void k_rp_count_rows(RpArgs a) {
     extern __shared__ uint32_t s_mem[];
     const int nbins = (int)a.tiles_y;
@@ -147,20 +174,25 @@ __global__ __launch_bounds__(kRpThreads) void k_rp_count_rows(RpArgs a) {
     uint32_t* diff = s_mem + (size_t)w * (nbins + 1);
     const int64_t n = (int64_t)*a.count;
     const int64_t c = (int64_t)blockIdx.x * kRpWaves + w;
-    const int64_t base = c * kRpChunk;
+    const int64_t base = c * kChunkA;
     if (base >= n) return;  // uniform per wave; no barrier below
     for (int b = (int)l; b <= nbins; b += kWave) diff[b] = 0u;
     wave_lds_sync();
-#pragma unroll 4
-    for (int r = 0; r < kRpRounds; ++r) {
+    uint4 q[kRoundsA];
+#pragma unroll
+    for (int r = 0; r < kRoundsA; ++r) {
         const int64_t i = base + r * kWave + l;
-        if (i < n) {
-            const RecSpan s = rec_span(a.rec[i], a.tiles_x, a.tiles_y);
+        q[r] = i < n ? a.rec[i] : make_uint4(0u, 0u, 0u, 0u);
+    }
+#pragma unroll
+    for (int r = 0; r < kRoundsA; ++r) {
+        if (base + r * kWave + l < n) {
+            const RecSpan s = rec_span(q[r], a.tiles_x, a.tiles_y);
             atomicAdd(&diff[s.y0], 1u);
             atomicSub(&diff[s.y1 + 1u], 1u);
         }
     }
-    chunk_counts(diff, nbins, a.ha + (size_t)c * nbins);
+    chunk_counts(diff, nbins, a.ha + c, a.ha_stride);
 }
 
 // Exclusive prefix over the chunks of one bin column, in place, in
@@ -185,8 +217,8 @@ __global__ __launch_bounds__(kRpThreads) void k_rp_scan_rows(RpArgs a) {
     __shared__ uint32_t s_scan[kRpWaves];
     const int y = blockIdx.x;
     const int64_t n = (int64_t)*a.count;
-    const int64_t chunks = (n + kRpChunk - 1) / kRpChunk;
-    const uint32_t tot = column_excl_scan(a.ha + y, chunks, a.tiles_y, 0u, s_scan);
+    const int64_t chunks = (n + kChunkA - 1) / kChunkA;
+    const uint32_t tot = column_excl_scan(a.ha + (size_t)y * a.ha_stride, chunks, 1, 0u, s_scan);
     if (threadIdx.x == 0) a.rowtot[y] = tot;
 }
 
@@ -195,34 +227,47 @@ __global__ __launch_bounds__(kRpThreads) void k_rp_scan_rows(RpArgs a) {
 constexpr int kLayoutThreads = 1024;
 __global__ __launch_bounds__(kLayoutThreads) void k_rp_layout(RpArgs a) {
     __shared__ uint32_t s_scan[kLayoutThreads / kWave];
+    __shared__ uint32_t s_cs[kRowPlaceMaxBins + 1];
     const int rows = (int)a.tiles_y;
-    constexpr int kPer = 4;  // rows per thread (rows <= 4096)
+    constexpr int kPer = kRowPlaceMaxBins / kLayoutThreads;  // rows per thread
     const int y0 = threadIdx.x * kPer;
     uint32_t tot[kPer], nb[kPer], st = 0, sc = 0;
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
         tot[k] = y0 + k < rows ? a.rowtot[y0 + k] : 0u;
-        nb[k] = (tot[k] + kRpChunk - 1) / kRpChunk;
+        nb[k] = (tot[k] + kChunkB - 1) / kChunkB;
         st += tot[k];
         sc += nb[k];
     }
     uint32_t all_t, all_c;
     uint32_t rs = block_excl_sum<kLayoutThreads>(st, s_scan, &all_t);
     uint32_t cs = block_excl_sum<kLayoutThreads>(sc, s_scan, &all_c);
+    all_c = all_c < a.cap_b ? all_c : a.cap_b;  // more only with inconsistent counts
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
         const int y = y0 + k;
         if (y < rows) {
             a.rowstart[y] = rs;
             a.cstart[y] = cs;
-            for (uint32_t q = 0; q < nb[k] && cs + q < a.cap_b; ++q) a.rowof[cs + q] = (uint32_t)y;
+            s_cs[y] = cs;
         }
         rs += tot[k];
         cs += nb[k];
     }
     if (threadIdx.x == 0) {
         a.rowstart[rows] = all_t;
-        a.cstart[rows] = all_c < a.cap_b ? all_c : a.cap_b;  // more only with inconsistent counts
+        a.cstart[rows] = all_c;
+        s_cs[rows] = all_c;
+    }
+    __syncthreads();
+    // the row of every B chunk: the last row starting at or before it
+    for (uint32_t cb = threadIdx.x; cb < all_c; cb += kLayoutThreads) {
+        int lo = 0, hi = rows - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_cs[mid] <= cb) lo = mid; else hi = mid - 1;
+        }
+        a.rowof[cb] = (uint32_t)lo;
     }
 }
 
@@ -234,31 +279,42 @@ __global__ __launch_bounds__(kRpThreads) void k_rp_place_rows(RpArgs a) {
     const int nbins = (int)a.tiles_y;
     const int w = threadIdx.x / kWave;
     const uint32_t l = lane_id();
-    uint32_t* s_base = s_mem + (size_t)w * (nbins + kWave + 1);
-    uint32_t* s_diff = s_base + nbins;
+    uint32_t* s_stage = s_mem + (size_t)w * (nbins + 2 * kChunkA);
+    uint32_t* s_base = s_stage + 2 * kChunkA;
     const int64_t n = (int64_t)*a.count;
-    const int64_t chunks = (n + kRpChunk - 1) / kRpChunk;
+    const int64_t chunks = (n + kChunkA - 1) / kChunkA;
     const int64_t c = (int64_t)blockIdx.x * kRpWaves + w;
-    const int64_t base = c * kRpChunk;
+    const int64_t base = c * kChunkA;
     if (base >= n) return;
-    for (int b = (int)l; b < nbins; b += kWave) s_base[b] = a.rowstart[b] + a.ha[(size_t)c * nbins + b];
-    wave_lds_sync();
-    const uint32_t limit = min(a.rowstart[nbins], (uint32_t)a.sum_h);  // >= 1: launched only when sum_h > 0
-    for (int r = 0; r < kRpRounds; ++r) {
+    uint32_t lo[kRoundsA], span[kRoundsA], ent[kRoundsA][2];
+#pragma unroll
+    for (int r = 0; r < kRoundsA; ++r) {
         const int64_t i = base + r * kWave + l;
-        const bool valid = i < n;
-        RecSpan s{0u, 0u, 1u, 0u, 0u};
-        if (valid) s = rec_span(a.rec[i], a.tiles_x, a.tiles_y);
-        const uint2 ent = make_uint2(s.x0 | (s.x1 << 16), s.gid);
-        // a slot past the row lists (inconsistent counts) is clamped to the
-        // last one, so nothing outside the buffer is written; the end check
-        // below reports it
-        place_round(valid, s.y0, s.y1, nbins, s_base, s_diff,
-                    [&](uint32_t pos) { a.rowent[min(pos, limit - 1u)] = ent; });
+        lo[r] = 0xFFFF0000u;  // unused slot: past every bin
+        span[r] = 0u;
+        ent[r][0] = ent[r][1] = 0u;
+        if (i < n) {
+            const RecSpan s = rec_span(a.rec[i], a.tiles_x, a.tiles_y);
+            lo[r] = s.y0;
+            span[r] = s.y1 - s.y0;
+            ent[r][0] = s.x0 | (s.x1 << 16);
+            ent[r][1] = s.gid;
+        }
     }
+    for (int b = (int)l; b < nbins; b += kWave) s_base[b] = a.rowstart[b] + a.ha[(size_t)b * a.ha_stride + c];
+    wave_lds_sync();
+    const uint32_t limit = min(a.rowstart[nbins], (uint32_t)a.sum_h);
+    const __amdgpu_buffer_rsrc_t out =
+        __builtin_amdgcn_make_buffer_rsrc(a.rowent, 0, (int)(limit * sizeof(uint2)), (int)kBufferDword3);
+    // slots (below 2^28) times 8, plus a dropped lane's 2^31: below 2^32
+    place_chunk<kRoundsA, 2>(lo, span, ent, nbins, s_base, s_stage, [&](uint32_t slot, uint2 v, uint32_t drop) {
+        __builtin_amdgcn_raw_buffer_store_b64(int32x2_t{(int)v.x, (int)v.y}, out, (int)((slot << 3) + drop), 0,
+                                              0);
+    });
+    wave_lds_sync();
     bool bad = false;
     for (int b = (int)l; b < nbins; b += kWave) {
-        const uint32_t end = a.rowstart[b] + (c + 1 < chunks ? a.ha[(size_t)(c + 1) * nbins + b] : a.rowtot[b]);
+        const uint32_t end = a.rowstart[b] + (c + 1 < chunks ? a.ha[(size_t)b * a.ha_stride + c + 1] : a.rowtot[b]);
         bad |= s_base[b] != end;
     }
     if (bad) atomicOr(a.err, kErrRowPlace);
@@ -268,8 +324,8 @@ __global__ __launch_bounds__(kRpThreads) void k_rp_place_rows(RpArgs a) {
 __device__ __forceinline__ bool col_chunk(const RpArgs& a, int64_t cb, uint32_t& y, uint32_t& e0, uint32_t& e1) {
     if (cb >= (int64_t)a.cstart[a.tiles_y]) return false;
     y = a.rowof[cb];
-    e0 = a.rowstart[y] + (uint32_t)(cb - a.cstart[y]) * (uint32_t)kRpChunk;
-    e1 = min(min(e0 + (uint32_t)kRpChunk, a.rowstart[y + 1]), (uint32_t)a.sum_h);
+    e0 = a.rowstart[y] + (uint32_t)(cb - a.cstart[y]) * (uint32_t)kChunkB;
+    e1 = min(min(e0 + (uint32_t)kChunkB, a.rowstart[y + 1]), (uint32_t)a.sum_h);
     return true;
 }
 
@@ -285,19 +341,23 @@ __global__ __launch_bounds__(kRpThreads) void k_rp_count_cols(RpArgs a) {
     if (!col_chunk(a, cb, y, e0, e1)) return;
     for (int b = (int)l; b <= nbins; b += kWave) diff[b] = 0u;
     wave_lds_sync();
-#pragma unroll 4
-    for (int r = 0; r < kRpRounds; ++r) {
+    uint32_t xx[kRoundsB];
+#pragma unroll
+    for (int r = 0; r < kRoundsB; ++r) {
         const uint32_t e = e0 + (uint32_t)(r * kWave) + l;
-        if (e < e1) {
+        xx[r] = e < e1 ? a.rowent[e].x : 0xFFFFFFFFu;
+    }
+#pragma unroll
+    for (int r = 0; r < kRoundsB; ++r) {
+        if (xx[r] != 0xFFFFFFFFu) {
             // columns are below tiles_x; the clamp only keeps a corrupted
             // entry inside the array (its counts then fail the end check)
-            const uint32_t xx = a.rowent[e].x;
-            const uint32_t x1 = min(xx >> 16, (uint32_t)nbins - 1u);
-            atomicAdd(&diff[min(xx & 0xFFFFu, x1)], 1u);
+            const uint32_t x1 = min(xx[r] >> 16, (uint32_t)nbins - 1u);
+            atomicAdd(&diff[min(xx[r] & 0xFFFFu, x1)], 1u);
             atomicSub(&diff[x1 + 1u], 1u);
         }
     }
-    chunk_counts(diff, nbins, a.hb + (size_t)cb * nbins);
+    chunk_counts(diff, nbins, a.hb + (size_t)cb * nbins, 1);
 }
 
 // B2: per tile, the start slot of every chunk of its row: the tile's range
@@ -326,27 +386,41 @@ __global__ __launch_bounds__(kRpThreads) void k_rp_scan_cols(RpArgs a) {
 }
 
 // B3: each chunk of a row list into the tile lists; the same end check.
-__global__ __launch_bounds__(kRpThreads) void k_rp_place_cols(RpArgs a) {
+// Eight waves per SIMD: every chunk of a 3M-Gaussian frame resident at once.
+__global__ __launch_bounds__(kRpThreads, 8) void k_rp_place_cols(RpArgs a) {
     extern __shared__ uint32_t s_mem[];
     const int nbins = (int)a.tiles_x;
     const int w = threadIdx.x / kWave;
     const uint32_t l = lane_id();
-    uint32_t* s_base = s_mem + (size_t)w * (nbins + kWave + 1);
-    uint32_t* s_diff = s_base + nbins;
+    uint32_t* s_stage = s_mem + (size_t)w * (nbins + kChunkB);
+    uint32_t* s_base = s_stage + kChunkB;
     const int64_t cb = (int64_t)blockIdx.x * kRpWaves + w;
     uint32_t y, e0, e1;
     if (!col_chunk(a, cb, y, e0, e1)) return;
+    uint32_t lo[kRoundsB], span[kRoundsB], gid[kRoundsB][1];
+#pragma unroll
+    for (int r = 0; r < kRoundsB; ++r) {
+        const uint32_t e = e0 + (uint32_t)(r * kWave) + l;
+        lo[r] = 0xFFFF0000u;  // unused slot: past every bin
+        span[r] = 0u;
+        gid[r][0] = 0u;
+        if (e < e1) {
+            const uint2 ent = a.rowent[e];
+            const uint32_t x1 = min(ent.x >> 16, (uint32_t)nbins - 1u);
+            lo[r] = min(ent.x & 0xFFFFu, x1);
+            span[r] = x1 - lo[r];
+            gid[r][0] = ent.y;
+        }
+    }
     for (int b = (int)l; b < nbins; b += kWave) s_base[b] = a.hb[(size_t)cb * nbins + b];
     wave_lds_sync();
-    const uint32_t limit = (uint32_t)a.K;
-    for (int r = 0; r < kRpRounds; ++r) {
-        const uint32_t e = e0 + (uint32_t)(r * kWave) + l;
-        const bool valid = e < e1;
-        const uint2 ent = valid ? a.rowent[e] : make_uint2(1u, 0u);
-        const uint32_t x1 = min(ent.x >> 16, (uint32_t)nbins - 1u);
-        place_round(valid, min(ent.x & 0xFFFFu, x1), x1, nbins, s_base, s_diff,
-                    [&](uint32_t pos) { a.values[min(pos, limit - 1u)] = ent.y; });
-    }
+    const __amdgpu_buffer_rsrc_t out =
+        __builtin_amdgcn_make_buffer_rsrc(a.values, 0, (int)(a.K * sizeof(uint32_t)), (int)kBufferDword3);
+    // slots (below 2^29) times 4, plus a dropped lane's 2^31: below 2^32
+    place_chunk<kRoundsB, 1>(lo, span, gid, nbins, s_base, s_stage, [&](uint32_t slot, uint2 v, uint32_t drop) {
+        __builtin_amdgcn_raw_buffer_store_b32((int)v.x, out, (int)((slot << 2) + drop), 0, 0);
+    });
+    wave_lds_sync();
     const bool last = cb + 1 >= (int64_t)min(a.cstart[y + 1], a.cap_b);
     bool bad = false;
     for (int b = (int)l; b < nbins; b += kWave) {
@@ -364,18 +438,20 @@ bool row_place_supported(int tiles_x, int tiles_y) {
 
 RowPlaceSizes row_place_sizes(int64_t n_records, uint64_t sum_h, int tiles_x, int tiles_y) {
     RowPlaceSizes s;
-    s.chunks_a = (n_records + kRpChunk - 1) / kRpChunk;
-    s.chunks_b_max = (int64_t)((sum_h + kRpChunk - 1) / kRpChunk) + tiles_y;
+    s.chunks_a = (n_records + kChunkA - 1) / kChunkA;
+    s.chunks_b_max = (int64_t)((sum_h + kChunkB - 1) / kChunkB) + tiles_y;
     s.ha_words = std::max<int64_t>(s.chunks_a, 1) * tiles_y;
     s.hb_words = s.chunks_b_max * tiles_x;
     s.small_words = (int64_t)tiles_y + 2 * ((int64_t)tiles_y + 1) + s.chunks_b_max;
     return s;
 }
 
-hipError_t launch_row_place(const RowPlaceArgs& p, hipStream_t stream, hipEvent_t rows_done) {
+hipError_t launch_row_place(const RowPlaceArgs& p, hipStream_t stream, hipEvent_t rows_done,
+                            hipEvent_t cols_counted) {
     if (!row_place_supported(p.tiles_x, p.tiles_y)) return hipErrorInvalidValue;
     if (p.n_records_max <= 0 || p.K == 0 || p.sum_h == 0) return hipSuccess;
-    if (p.sum_h > (uint64_t)kSortMaxCount || p.K > (uint64_t)kSortMaxCount) return hipErrorInvalidValue;
+    // the output buffer resources hold at most 2^31 bytes
+    if (p.sum_h > (uint64_t(1) << 28) || p.K > (uint64_t(1) << 29)) return hipErrorInvalidValue;
     const RowPlaceSizes sz = row_place_sizes(p.n_records_max, p.sum_h, p.tiles_x, p.tiles_y);
     RpArgs a;
     a.rec = p.rec;
@@ -383,6 +459,7 @@ hipError_t launch_row_place(const RowPlaceArgs& p, hipStream_t stream, hipEvent_
     a.tiles_x = (uint32_t)p.tiles_x;
     a.tiles_y = (uint32_t)p.tiles_y;
     a.ha = p.ha;
+    a.ha_stride = std::max<int64_t>(sz.chunks_a, 1);
     a.rowtot = p.small;
     a.rowstart = p.small + p.tiles_y;
     a.cstart = a.rowstart + p.tiles_y + 1;
@@ -397,9 +474,12 @@ hipError_t launch_row_place(const RowPlaceArgs& p, hipStream_t stream, hipEvent_
     a.err = p.err;
     const unsigned ga = (unsigned)((sz.chunks_a + kRpWaves - 1) / kRpWaves);
     const unsigned gb = (unsigned)((sz.chunks_b_max + kRpWaves - 1) / kRpWaves);
-    // count kernels: nbins + 1 words per wave; place kernels: nbins + 65
-    const size_t lds_rows = sizeof(uint32_t) * kRpWaves * (size_t)(p.tiles_y + kWave + 1);
-    const size_t lds_cols = sizeof(uint32_t) * kRpWaves * (size_t)(p.tiles_x + kWave + 1);
+    // per wave: count kernels nbins + 1 words; place kernels nbins words of
+    // pointers and a staging area
+    const size_t lds_rows = sizeof(uint32_t) * kRpWaves * (size_t)(p.tiles_y + 1);
+    const size_t lds_cols = sizeof(uint32_t) * kRpWaves * (size_t)(p.tiles_x + 1);
+    const size_t lds_place_rows = sizeof(uint32_t) * kRpWaves * (size_t)(p.tiles_y + 2 * kChunkA);
+    const size_t lds_place_cols = sizeof(uint32_t) * kRpWaves * (size_t)(p.tiles_x + kChunkB);
     hipLaunchKernelGGL(k_rp_count_rows, dim3(ga), dim3(kRpThreads), lds_rows, stream, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -407,7 +487,7 @@ hipError_t launch_row_place(const RowPlaceArgs& p, hipStream_t stream, hipEvent_
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_rp_layout, dim3(1), dim3(kLayoutThreads), 0, stream, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rp_place_rows, dim3(ga), dim3(kRpThreads), lds_rows, stream, a);
+    hipLaunchKernelGGL(k_rp_place_rows, dim3(ga), dim3(kRpThreads), lds_place_rows, stream, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (rows_done && (e = hipEventRecord(rows_done, stream)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_rp_count_cols, dim3(gb), dim3(kRpThreads), lds_cols, stream, a);
@@ -418,7 +498,8 @@ hipError_t launch_row_place(const RowPlaceArgs& p, hipStream_t stream, hipEvent_
     }
     hipLaunchKernelGGL(k_rp_scan_cols, dim3((unsigned)p.tiles_y), dim3(kRpThreads), 0, stream, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rp_place_cols, dim3(gb), dim3(kRpThreads), lds_cols, stream, a);
+    if (cols_counted && (e = hipEventRecord(cols_counted, stream)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rp_place_cols, dim3(gb), dim3(kRpThreads), lds_place_cols, stream, a);
     return hipGetLastError();
 }
 

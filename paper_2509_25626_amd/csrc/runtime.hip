@@ -344,6 +344,7 @@ cds_status cds_frame_get_info(cds_frame* f, cds_frame_info* o) {
     o->values = f->res_values;
     o->ranges = (const uint32_t*)f->ranges.p;
     o->clamp_flags = (const uint8_t*)f->clampf.p;
+    o->num_row_entries = f->row_entries;
     return CDS_OK;
 }
 

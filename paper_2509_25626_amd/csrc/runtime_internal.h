@@ -68,6 +68,7 @@ struct cds_frame {
     // backward
     cds::DevBuf grad2d;
     int64_t n = 0, n_vis = 0, K = 0;
+    int64_t row_entries = 0;  // variant 4: entries of the per-tile-row lists
     int32_t width = 0, height = 0, tiles_x = 0, tiles_y = 0, passes = 0, sort_variant = 0;
     bool valid = false;
     // where the last render left its sorted list

@@ -61,7 +61,8 @@ class CdsFrameInfo(ctypes.Structure):
                 ("sort_passes", ctypes.c_int32), ("num_visible", ctypes.c_int32),
                 ("mean2d", P), ("conic_opacity", P), ("rgb", P), ("depth_bits", P),
                 ("radius", P), ("tile_rect", P), ("tiles_touched", P), ("offsets", P),
-                ("keys", P), ("values", P), ("ranges", P), ("clamp_flags", P)]
+                ("keys", P), ("values", P), ("ranges", P), ("clamp_flags", P),
+                ("num_row_entries", ctypes.c_int64)]
 
 
 class CdsStageTimes(ctypes.Structure):
