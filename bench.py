@@ -194,20 +194,21 @@ def cpu_baseline(scene, cam, budget_s):
     blend): one warm-up frame, then the median of three timed frames on every
     core the process may use, plus one frame on a single thread over a random
     1/16 subsample of the Gaussians (same image).  Falls back to a 1/8
-    subsample for the all-core frames when a full frame would exceed the
-    budget; the sample is stated in the output.  Also returns the last
+    subsample for the all-core frames when three full frames would exceed
+    the budget; the sample is stated in the output.  Also returns the last
     all-core oracle result (its per-pixel counts give the blend's algorithmic
     work)."""
     from oracle import oracle as O
     cores = O.get_threads()
     t0 = time.perf_counter()
-    O.render(_subsample(scene, 1 / 64), cam)  # loads the library; estimates the frame time
-    t_small = time.perf_counter() - t0
+    O.render(scene, cam)  # warm-up (loads the library), and the frame-time estimate
+    t_full = time.perf_counter() - t0
     frac, label = 1.0, "full frames"
-    if t_small * 64 * 4 > budget_s:
+    if t_full * 3 > budget_s:
         frac, label = 1 / 8, "frames of a 1/8 random subsample of the Gaussians"
     s = scene if frac == 1.0 else _subsample(scene, frac)
-    O.render(s, cam)  # warm-up
+    if frac != 1.0:
+        O.render(s, cam)  # warm-up of the sample
     times, res = [], None
     for _ in range(3):
         t0 = time.perf_counter()
@@ -432,12 +433,12 @@ def main():
                 o = O.render(sc_o, cam_o, round_f32=True)
                 res["table3"] = tile_statistics(o, cam_o.width, cam_o.height)
                 res["blend_roofline"] = blend_roofline(blend_work(o), st_o["blend_ms"])
-                for v in (3, 5):
+                for v in (1, 3, 5):
                     args_v = argparse.Namespace(**{**vars(args), "blend_variant": v})
                     rv, _, _, stv = other_config(R, name, args_v, backward=False)
                     res[f"blend_variant_{v}_ms"] = round(stv["blend_ms"], 4)
             if name == "c1":
-                for v in (3, 5):
+                for v in (1, 3, 5):
                     args_v = argparse.Namespace(**{**vars(args), "blend_variant": v})
                     rv, _, _, stv = other_config(R, name, args_v, backward=False)
                     res[f"blend_variant_{v}_ms"] = round(stv["blend_ms"], 4)
