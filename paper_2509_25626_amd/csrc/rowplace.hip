@@ -385,47 +385,163 @@ __global__ __launch_bounds__(kRpThreads) void k_rp_scan_cols(RpArgs a) {
     }
 }
 
-// B3: each chunk of a row list into the tile lists; the same end check.
-// Eight waves per SIMD: every chunk of a 3M-Gaussian frame resident at once.
-__global__ __launch_bounds__(kRpThreads, 8) void k_rp_place_cols(RpArgs a) {
+// B3: each chunk of a row list into the tile lists.  One workgroup per
+// chunk; its waves split the row's tile columns into blocks of kColBlock.  A
+// wave loads the whole chunk, compacts in chunk order into LDS the entries
+// that reach its block (their columns clipped to the block, as two 4-bit
+// offsets), reads them back as a 16-bit column mask per entry, and places
+// them bin by bin: per round one ballot, the run gathered in LDS, full-wave
+// stores.  At 3M Gaussians a row entry covers about 10 of 78 columns, so a
+// bin iterates over about a third of the chunk, and the five waves of a
+// chunk run side by side.  Every bin ends where the next chunk's base (or
+// the tile's range end) says, else error bit 32.
+constexpr int kColBlock = 16;
+constexpr int kColMaxWaves = 8;  // waves per workgroup (42 KB of LDS); more blocks are taken in turn
+constexpr int kColBatch = kRoundsB / 2;  // rounds of compacted entries held in registers at once
+static_assert(kColBatch == 8, "place_bins is instantiated for 1 to 8 rounds");
+// per wave: compacted Gaussian indices (words), compacted offsets (bytes), a dump slot per lane
+constexpr int kColWaveWords = kChunkB + kChunkB / 4 + kWave;
+static_assert(kColBlock == 16, "compacted offsets are packed as 4-bit fields");
+
+__host__ __device__ inline int col_blocks(int nbins) { return (nbins + kColBlock - 1) / kColBlock; }
+
+// The bins of one block over R rounds of compacted entries (R known at
+// compile time: no per-round checks).  Per bin and round one ballot; the
+// covering lanes write their Gaussian index to the run in LDS, the others to
+// a dump slot of their own (a select of the address, not a branch); then the run goes out in
+// full-wave stores, lanes past its end given an offset the buffer drops.
+template <int R>
+__device__ __forceinline__ void place_bins(const uint32_t (&cm)[kColBatch], const uint32_t (&cg)[kColBatch], int nb,
+                                           uint32_t* stage, uint32_t* dump, uint32_t& vb,
+                                           __amdgpu_buffer_rsrc_t out) {
+    const uint32_t l = lane_id();
+    using lds_u32 = __attribute__((address_space(3))) uint32_t;
+    lds_u32* const st = (lds_u32*)stage;
+    lds_u32* const du = (lds_u32*)dump;
+    for (int j = 0; j < nb; ++j) {
+        lds_u32* wr = st;  // the run's end (one pointer add per round)
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const bool cov = (cm[q] >> j) & 1u;
+            const uint64_t m = ballot(cov);
+            // rank among the covering lanes below, computed in every lane (the
+            // empty asm keeps the compiler from moving it under a branch)
+            uint32_t rank = count_below(m);
+            asm volatile("" : "+v"(rank));
+            lds_u32* dst = cov ? wr + rank : du + l;
+            *dst = cg[q];
+            wr += __popcll(m);
+        }
+        const uint32_t run = (uint32_t)(wr - st);
+        wave_lds_sync();
+        const uint32_t base = (uint32_t)__builtin_amdgcn_readlane((int)vb, j);
+        // slots are below 2^29, so a kept offset is below 2^31 and the
+        // dropped lanes' 2^31 is past the buffer
+        const uint32_t voff = (base + l) << 2;
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            if ((uint32_t)(t * kWave) < run) {  // uniform
+                const uint32_t v = st[t * kWave + l];
+                const uint32_t off = l < run - (uint32_t)(t * kWave) ? voff + (uint32_t)(t * kWave * 4) : kDropOffset;
+                __builtin_amdgcn_raw_buffer_store_b32((int)v, out, (int)off, 0, 0);
+            }
+        }
+        wave_lds_sync();  // the run is read before the next bin's gathers
+        vb = l == (uint32_t)j ? base + run : vb;
+    }
+}
+
+__global__ __launch_bounds__(kColMaxWaves * kWave) __attribute__((amdgpu_waves_per_eu(8)))
+void k_rp_place_cols(RpArgs a) {
     extern __shared__ uint32_t s_mem[];
     const int nbins = (int)a.tiles_x;
-    const int w = threadIdx.x / kWave;
+    const int nblk = col_blocks(nbins);
+    const int nw = (int)(blockDim.x / kWave);
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));  // uniform: LDS bases in SGPRs
     const uint32_t l = lane_id();
-    uint32_t* s_stage = s_mem + (size_t)w * (nbins + kChunkB);
-    uint32_t* s_base = s_stage + kChunkB;
-    const int64_t cb = (int64_t)blockIdx.x * kRpWaves + w;
+    uint32_t* s_cg = s_mem + (size_t)w * kColWaveWords;           // compacted Gaussian index; then the run stage
+    uint8_t* s_cx = reinterpret_cast<uint8_t*>(s_cg + kChunkB);   // compacted offset | (last - offset) << 4
+    uint32_t* s_dump = s_cg + kChunkB + kChunkB / 4;              // one slot per lane for uncovered writes
+    const int64_t cb = blockIdx.x;
     uint32_t y, e0, e1;
     if (!col_chunk(a, cb, y, e0, e1)) return;
-    uint32_t lo[kRoundsB], span[kRoundsB], gid[kRoundsB][1];
+    uint32_t ex[kRoundsB], eg[kRoundsB];  // x0 | x1 << 16 (unused slot: x0 past every bin), Gaussian index
 #pragma unroll
     for (int r = 0; r < kRoundsB; ++r) {
         const uint32_t e = e0 + (uint32_t)(r * kWave) + l;
-        lo[r] = 0xFFFF0000u;  // unused slot: past every bin
-        span[r] = 0u;
-        gid[r][0] = 0u;
+        ex[r] = 0x0000FFFFu;
+        eg[r] = 0u;
         if (e < e1) {
             const uint2 ent = a.rowent[e];
+            // columns are below tiles_x; the clamp only keeps a corrupted
+            // entry inside the row (its counts then fail the end check)
             const uint32_t x1 = min(ent.x >> 16, (uint32_t)nbins - 1u);
-            lo[r] = min(ent.x & 0xFFFFu, x1);
-            span[r] = x1 - lo[r];
-            gid[r][0] = ent.y;
+            ex[r] = min(ent.x & 0xFFFFu, x1) | (x1 << 16);
+            eg[r] = ent.y;
         }
     }
-    for (int b = (int)l; b < nbins; b += kWave) s_base[b] = a.hb[(size_t)cb * nbins + b];
-    wave_lds_sync();
+    const bool last = cb + 1 >= (int64_t)min(a.cstart[y + 1], a.cap_b);
     const __amdgpu_buffer_rsrc_t out =
         __builtin_amdgcn_make_buffer_rsrc(a.values, 0, (int)(a.K * sizeof(uint32_t)), (int)kBufferDword3);
-    // slots (below 2^29) times 4, plus a dropped lane's 2^31: below 2^32
-    place_chunk<kRoundsB, 1>(lo, span, gid, nbins, s_base, s_stage, [&](uint32_t slot, uint2 v, uint32_t drop) {
-        __builtin_amdgcn_raw_buffer_store_b32((int)v.x, out, (int)((slot << 2) + drop), 0, 0);
-    });
-    wave_lds_sync();
-    const bool last = cb + 1 >= (int64_t)min(a.cstart[y + 1], a.cap_b);
     bool bad = false;
-    for (int b = (int)l; b < nbins; b += kWave) {
-        const uint32_t end = last ? a.ranges[(size_t)y * nbins + b].y : a.hb[(size_t)(cb + 1) * nbins + b];
-        bad |= s_base[b] != end;
+    for (int blk = w; blk < nblk; blk += nw) {
+        const int b0 = blk * kColBlock;
+        const int nb = min(kColBlock, nbins - b0);
+        const uint32_t bl = (uint32_t)b0, bh = (uint32_t)(b0 + nb - 1);
+        // compaction: the entries reaching the block, in chunk order
+        uint32_t cnt = 0;
+#pragma unroll
+        for (int r = 0; r < kRoundsB; ++r) {
+            const uint32_t x0 = ex[r] & 0xFFFFu, x1 = ex[r] >> 16;
+            const bool meets = x0 <= bh && x1 >= bl;
+            const uint64_t m = ballot(meets);
+            if (meets) {
+                const uint32_t k = cnt + count_below(m);
+                const uint32_t o0 = (x0 > bl ? x0 : bl) - bl, o1 = (x1 < bh ? x1 : bh) - bl;
+                s_cx[k] = (uint8_t)(o0 | ((o1 - o0) << 4));
+                s_cg[k] = eg[r];
+            }
+            cnt += (uint32_t)__popcll(m);
+        }
+        // this block's bins start at the chunk's bases
+        uint32_t vb = (int)l < nb ? a.hb[(size_t)cb * nbins + b0 + l] : 0u;
+        // the compacted entries in batches of kColBatch rounds (one batch in
+        // the common case); a batch's slots serve as its run stage once it
+        // is in registers, and batch by batch keeps every bin in chunk order
+        for (uint32_t h = 0; h < cnt; h += kColBatch * kWave) {  // uniform
+            wave_lds_sync();
+            const uint32_t hn = min(cnt - h, (uint32_t)(kColBatch * kWave));
+            const uint32_t rounds = (hn + kWave - 1) / kWave;
+            uint32_t* stage = s_cg + h;
+            uint32_t cm[kColBatch], cg[kColBatch];  // columns of the block an entry covers (bit mask), Gaussian index
+#pragma unroll
+            for (int q = 0; q < kColBatch; ++q) {
+                const uint32_t k = (uint32_t)(q * kWave) + l;
+                cm[q] = 0u;
+                cg[q] = 0u;
+                if ((uint32_t)q < rounds && k < hn) {
+                    const uint32_t c = s_cx[h + k];
+                    cm[q] = ((2u << (c >> 4)) - 1u) << (c & 15u);
+                    cg[q] = stage[k];
+                }
+            }
+            wave_lds_sync();
+            switch (rounds) {
+                case 1: place_bins<1>(cm, cg, nb, stage, s_dump, vb, out); break;
+                case 2: place_bins<2>(cm, cg, nb, stage, s_dump, vb, out); break;
+                case 3: place_bins<3>(cm, cg, nb, stage, s_dump, vb, out); break;
+                case 4: place_bins<4>(cm, cg, nb, stage, s_dump, vb, out); break;
+                case 5: place_bins<5>(cm, cg, nb, stage, s_dump, vb, out); break;
+                case 6: place_bins<6>(cm, cg, nb, stage, s_dump, vb, out); break;
+                case 7: place_bins<7>(cm, cg, nb, stage, s_dump, vb, out); break;
+                default: place_bins<8>(cm, cg, nb, stage, s_dump, vb, out); break;
+            }
+        }
+        if ((int)l < nb) {
+            const uint32_t b = (uint32_t)b0 + l;
+            const uint32_t end = last ? a.ranges[(size_t)y * nbins + b].y : a.hb[(size_t)(cb + 1) * nbins + b];
+            bad |= vb != end;
+        }
     }
     if (bad) atomicOr(a.err, kErrRowPlace);
 }
@@ -479,7 +595,8 @@ hipError_t launch_row_place(const RowPlaceArgs& p, hipStream_t stream, hipEvent_
     const size_t lds_rows = sizeof(uint32_t) * kRpWaves * (size_t)(p.tiles_y + 1);
     const size_t lds_cols = sizeof(uint32_t) * kRpWaves * (size_t)(p.tiles_x + 1);
     const size_t lds_place_rows = sizeof(uint32_t) * kRpWaves * (size_t)(p.tiles_y + 2 * kChunkA);
-    const size_t lds_place_cols = sizeof(uint32_t) * kRpWaves * (size_t)(p.tiles_x + kChunkB);
+    const int col_waves = std::min(col_blocks((int)p.tiles_x), kColMaxWaves);
+    const size_t lds_place_cols = sizeof(uint32_t) * col_waves * (size_t)kColWaveWords;
     hipLaunchKernelGGL(k_rp_count_rows, dim3(ga), dim3(kRpThreads), lds_rows, stream, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -499,7 +616,8 @@ hipError_t launch_row_place(const RowPlaceArgs& p, hipStream_t stream, hipEvent_
     hipLaunchKernelGGL(k_rp_scan_cols, dim3((unsigned)p.tiles_y), dim3(kRpThreads), 0, stream, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (cols_counted && (e = hipEventRecord(cols_counted, stream)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rp_place_cols, dim3(gb), dim3(kRpThreads), lds_place_cols, stream, a);
+    hipLaunchKernelGGL(k_rp_place_cols, dim3((unsigned)sz.chunks_b_max), dim3(col_waves * kWave), lds_place_cols,
+                       stream, a);
     return hipGetLastError();
 }
 
