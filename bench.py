@@ -320,20 +320,27 @@ class Bench:
             acc[k] = acc.get(k, 0.0) + v
 
     def _run(self, step, steps, warmup):
+        """Seconds per step over `steps` timed steps (no stage events: the
+        events of stage timing cost the stream a few microseconds each), then
+        the stage times from a separate run of up to 10 steps with them."""
         import torch
         for i in range(max(2, warmup)):
             step(self.frames[i % 2])
         torch.cuda.synchronize()
-        acc = {}
         t0 = time.perf_counter()
         for i in range(steps):
+            step(self.frames[i % 2])
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        acc = {}
+        nst = max(2, min(steps, 10))
+        for i in range(nst):
             step(self.frames[i % 2], timing=True)
             if i > 0:
                 self._accumulate(acc, self.frames[(i - 1) % 2])
         torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / steps
-        self._accumulate(acc, self.frames[(steps - 1) % 2])
-        return dt, {k: v / steps for k, v in acc.items()}
+        self._accumulate(acc, self.frames[(nst - 1) % 2])
+        return dt, {k: v / nst for k, v in acc.items()}
 
     def forward(self, steps, warmup):
         dt, st = self._run(self.fwd, steps, warmup)

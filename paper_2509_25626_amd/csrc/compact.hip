@@ -19,14 +19,25 @@ constexpr int kCIPT = 16;
 constexpr int64_t kCTile = (int64_t)kCT * kCIPT;
 constexpr int kCWaves = kCT / kWave;
 
+// Word ranges the counting kernel clears on the side: the depth histograms
+// the scatter kernel then fills, and whatever the caller adds.
+struct ZeroJobs {
+    ZeroSpan s[1 + kZeroSpans];
+};
+
 // Per 4096-Gaussian tile: visible splats, keys and (with h_sums) the sum of
-// the visible splats' rectangle heights.
+// the visible splats' rectangle heights.  The grid also clears the word
+// ranges of z (grid-strided).
 __global__ __launch_bounds__(kCT) void k_vis_count(int64_t n, const uint32_t* __restrict__ touched,
                                                    const uint2* __restrict__ rect,
                                                    uint64_t* __restrict__ vis_sums, uint64_t* __restrict__ key_sums,
-                                                   uint64_t* __restrict__ h_sums) {
+                                                   uint64_t* __restrict__ h_sums, ZeroJobs z) {
     __shared__ unsigned long long s_v[kCWaves], s_k[kCWaves], s_h[kCWaves];
     const int64_t base = (int64_t)blockIdx.x * kCTile;
+#pragma unroll
+    for (int j = 0; j < 1 + kZeroSpans; ++j)
+        for (int64_t k = (int64_t)blockIdx.x * kCT + threadIdx.x; k < z.s[j].n; k += (int64_t)gridDim.x * kCT)
+            z.s[j].p[k] = 0u;
     uint32_t v = 0, hs = 0;
     unsigned long long k = 0;
     uint32_t c[kCIPT];
@@ -148,19 +159,29 @@ int64_t compact_sums_size(int64_t n) { return (n + kCTile - 1) / kCTile + 1; }
 hipError_t launch_compact_visible(int64_t n, const uint32_t* touched, const uint2* rect, const uint32_t* depth_bits,
                                   uint64_t* vis_sums, uint64_t* key_sums, uint64_t* totals, uint32_t* dkey,
                                   uint4* rec, uint32_t* depth_hist, hipStream_t stream, int tiles_x,
-                                  const BatchItem* items, int nitems, uint64_t* h_sums, uint64_t* sum_h) {
+                                  const BatchItem* items, int nitems, uint64_t* h_sums, uint64_t* sum_h,
+                                  const ZeroSpan* zero_spans, uint64_t* host_totals, hipEvent_t totals_ready) {
     const int64_t tiles = (n + kCTile - 1) / kCTile;
-    hipError_t e = launch_fill_u32(depth_hist, 4 * 256, 0u, stream);
-    if (e != hipSuccess) return e;
-    if (sum_h && !h_sums) return hipErrorInvalidValue;
+    if ((sum_h && !h_sums) || (host_totals && !totals_ready)) return hipErrorInvalidValue;
+    ZeroJobs z;
+    z.s[0].p = depth_hist;
+    z.s[0].n = 4 * 256;
+    for (int j = 0; j < kZeroSpans; ++j)
+        if (zero_spans) z.s[1 + j] = zero_spans[j];
+    hipError_t e = hipSuccess;
     if (tiles > 0) {
         hipLaunchKernelGGL(k_vis_count, dim3((unsigned)tiles), dim3(kCT), 0, stream, n, touched, rect, vis_sums,
-                           key_sums, sum_h ? h_sums : nullptr);
+                           key_sums, sum_h ? h_sums : nullptr, z);
         if ((e = hipGetLastError()) != hipSuccess) return e;
+    } else {
+        for (int j = 0; j < 1 + kZeroSpans; ++j)
+            if ((e = launch_fill_u32(z.s[j].p, z.s[j].n, 0u, stream)) != hipSuccess) return e;
     }
     if ((e = launch_scan_u64_pair(vis_sums, key_sums, tiles, totals, totals + 1, stream, sum_h ? h_sums : nullptr,
-                                  sum_h)) != hipSuccess)
+                                  sum_h, host_totals, host_totals ? host_totals + 1 : nullptr,
+                                  host_totals ? host_totals + 3 : nullptr)) != hipSuccess)
         return e;
+    if (totals_ready && (e = hipEventRecord(totals_ready, stream)) != hipSuccess) return e;
     if (tiles > 0) {
         hipLaunchKernelGGL(k_vis_scatter, dim3((unsigned)tiles), dim3(kCT), 0, stream, n, touched, rect, depth_bits,
                            vis_sums, dkey, rec, depth_hist, (uint32_t)tiles_x, items, nitems);

@@ -88,7 +88,8 @@ hipError_t launch_preprocess_batch(const BatchItem* items, int nitems, int64_t t
 // each (one workgroup per array, one launch); the totals go to *total_a,
 // *total_b (and *total_c).
 hipError_t launch_scan_u64_pair(uint64_t* a, uint64_t* b, int64_t count, uint64_t* total_a, uint64_t* total_b,
-                                hipStream_t stream, uint64_t* c = nullptr, uint64_t* total_c = nullptr);
+                                hipStream_t stream, uint64_t* c = nullptr, uint64_t* total_c = nullptr,
+                                uint64_t* host_a = nullptr, uint64_t* host_b = nullptr, uint64_t* host_c = nullptr);
 
 // Tile record of a visible splat (16 B): its rectangle of tiles as runs of
 // tile ids, (width | height << 16, row stride, Gaussian index, id of the first
@@ -110,12 +111,23 @@ struct BatchItem;
 // totals[1] = K.  vis_sums, key_sums: compact_sums_size(n) uint64 each.
 // With sum_h (and h_sums, compact_sums_size(n) more uint64 of workspace),
 // *sum_h = the sum of the visible splats' rectangle heights.
+// zero_spans: up to kZeroSpans more word ranges cleared by the counting
+// kernel (so the caller needs no fill launches of its own before the sort).
+// host_totals (4 words of fine-grained pinned host memory, device address):
+// totals[0], totals[1] and *sum_h are written there too, and totals_ready is
+// recorded once they are, before the scatter kernel runs.
 int64_t compact_sums_size(int64_t n);
+struct ZeroSpan {
+    uint32_t* p = nullptr;
+    int64_t n = 0;
+};
+constexpr int kZeroSpans = 2;
 hipError_t launch_compact_visible(int64_t n, const uint32_t* touched, const uint2* rect, const uint32_t* depth_bits,
                                   uint64_t* vis_sums, uint64_t* key_sums, uint64_t* totals, uint32_t* dkey,
                                   uint4* rec, uint32_t* depth_hist, hipStream_t stream, int tiles_x,
                                   const BatchItem* items = nullptr, int nitems = 0, uint64_t* h_sums = nullptr,
-                                  uint64_t* sum_h = nullptr);
+                                  uint64_t* sum_h = nullptr, const ZeroSpan* zero_spans = nullptr,
+                                  uint64_t* host_totals = nullptr, hipEvent_t totals_ready = nullptr);
 
 // Exclusive scan of n uint32 values (read as in[gather[i]] when gather is
 // not null); the total (uint64, device) is written too.  `block_sums` needs
@@ -215,6 +227,9 @@ hipError_t launch_sort_histogram(const uint32_t* keys, int64_t count, int passes
 // wide partitions from 2^23 keys on); the default clears for narrow ones, a superset
 hipError_t launch_sort_prepare(const SortWorkspace& ws, int64_t count, int passes, bool clear_hist,
                                hipStream_t stream, int key_bytes = 8);
+// The words launch_sort_prepare (clear_hist false) clears, as two spans
+// (look-back status, pass counters), for a kernel that clears them instead.
+void sort_prepare_spans(const SortWorkspace& ws, int64_t count, int passes, int key_bytes, ZeroSpan spans[2]);
 // The sort covers key bits [shift0, end_bit) (end_bit 0: shift0 + 8 * passes)
 // split over the passes by digit_plan.  keep_keys false: the last pass
 // writes only the values (its keys are left unwritten).

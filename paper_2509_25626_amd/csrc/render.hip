@@ -168,11 +168,17 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
     const uint32_t* order = nullptr;
     if (compact) {
         // visible splats compacted in index order, with the depth histograms; n_vis and K
-        // (row-wise placement: also the sum of the rectangle heights, d_total[3])
+        // (row-wise placement: also the sum of the rectangle heights, d_total[3]).  The
+        // counting kernel also clears the depth sort's look-back status and counters.
+        CDS_TRY(f->side_stream());  // its events too: f->copied is recorded by the compaction
+        ZeroSpan depth_prep[kZeroSpans];
+        const bool depth_onesweep = n > 0 && sort_uses_onesweep(n, algo);
+        if (depth_onesweep) sort_prepare_spans(wd, n, 4, 4, depth_prep);
         CDS_HIP(launch_compact_visible(n, sb.touched, sb.rect, sb.depth_bits, (uint64_t*)f->vsums.p,
                                        (uint64_t*)f->ksums.p, d_total, (uint32_t*)f->dkeyc.p, (uint4*)f->recc.p,
                                        wd.hist, stream, P.tiles_x, nullptr, 0,
-                                       rowplace ? (uint64_t*)f->hsums.p : nullptr, rowplace ? d_total + 3 : nullptr),
+                                       rowplace ? (uint64_t*)f->hsums.p : nullptr, rowplace ? d_total + 3 : nullptr,
+                                       depth_onesweep ? depth_prep : nullptr, ctx->host_pinned_dev, f->copied),
                 "visible compaction");
     } else if (binned) {
         // depth order of all N Gaussians: 4 passes, result in (dkey1, order1)
@@ -196,16 +202,17 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
                                       d_total + 1, stream),
                 "scan kernels");
     }
-    CDS_HIP(hipMemcpyAsync(ctx->host_pinned, d_total, 4 * sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
-            "hipMemcpyAsync(key count)");
+    // the compacting path's scan wrote the counts into the pinned host words
+    // itself (event f->copied); the others copy them
+    if (!compact)
+        CDS_HIP(hipMemcpyAsync(ctx->host_pinned, d_total, 4 * sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
+                "hipMemcpyAsync(key count)");
     CDS_TRY(f->record(kEvCount, stream));
     if (compact) {
         // Enqueued before the host waits for the counts, so the device is not idle
         // meanwhile: these kernels are sized for all n Gaussians and read the
         // number of visible splats (d_total[0]) on the device.
-        CDS_TRY(f->side_stream());
         side_join.join = f->join;
-        CDS_HIP(hipEventRecord(f->copied, stream), "hipEventRecord(copied)");
         // ranges and tile-digit histograms from the records (their order does not
         // matter), on the side stream while the depth sort runs
         CDS_HIP(hipEventRecord(f->fork, stream), "hipEventRecord(fork)");
@@ -219,7 +226,6 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
         if (n > 0) {
             // depth sort of the compacted keys (values: compacted positions); the
             // last pass writes the records in depth order (recv) instead
-            if (sort_uses_onesweep(n, algo)) CDS_HIP(launch_sort_prepare(wd, n, 4, false, stream, 4), "depth prepare");
             CDS_HIP(launch_sort_passes((const uint32_t*)f->dkeyc.p, nullptr, (uint32_t*)f->dkey0.p,
                                        (uint32_t*)f->order0.p, (uint32_t*)f->dkey1.p, (uint32_t*)f->order1.p, n, 4,
                                        0, wd, algo, stream, 32, false, nullptr, value_bits_for(n - 1), nullptr,

@@ -195,31 +195,36 @@ __global__ __launch_bounds__(kRpThreads) void k_rp_count_rows(RpArgs a) {
     chunk_counts(diff, nbins, a.ha + c, a.ha_stride);
 }
 
-// Exclusive prefix over the chunks of one bin column, in place, in
-// workgroup-wide tiles of 256 chunks: col[k * stride] for k < count; the
-// column total is returned to every thread.
-__device__ __forceinline__ uint32_t column_excl_scan(uint32_t* col, int64_t count, int64_t stride, uint32_t base,
-                                                     uint32_t* s_scan) {
-    uint32_t run = base;
-    for (int64_t k0 = 0; k0 < count; k0 += kRpThreads) {
-        const int64_t k = k0 + threadIdx.x;
-        const uint32_t v = k < count ? col[k * stride] : 0u;
-        uint32_t tot;
-        const uint32_t ex = block_excl_sum<kRpThreads>(v, s_scan, &tot);
-        if (k < count) col[k * stride] = run + ex;
-        run += tot;
-    }
-    return run - base;
-}
-
-// A2: per row, the exclusive prefix of the chunk counts and the row total.
+// A2: per row, the exclusive prefix of the chunk counts (in place) and the
+// row total.  A thread takes kScanPer consecutive chunks, all loaded at once
+// (one memory latency per kRpThreads * kScanPer chunks instead of one per
+// kRpThreads), sums them, and one workgroup scan gives its start.
+constexpr int kScanPer = 32;
 __global__ __launch_bounds__(kRpThreads) void k_rp_scan_rows(RpArgs a) {
     __shared__ uint32_t s_scan[kRpWaves];
     const int y = blockIdx.x;
     const int64_t n = (int64_t)*a.count;
     const int64_t chunks = (n + kChunkA - 1) / kChunkA;
-    const uint32_t tot = column_excl_scan(a.ha + (size_t)y * a.ha_stride, chunks, 1, 0u, s_scan);
-    if (threadIdx.x == 0) a.rowtot[y] = tot;
+    uint32_t* col = a.ha + (size_t)y * a.ha_stride;
+    uint32_t run = 0;
+    for (int64_t k0 = 0; k0 < chunks; k0 += (int64_t)kRpThreads * kScanPer) {  // uniform
+        const int64_t kb = k0 + (int64_t)threadIdx.x * kScanPer;
+        uint32_t v[kScanPer], sum = 0;
+#pragma unroll
+        for (int u = 0; u < kScanPer; ++u) {
+            v[u] = kb + u < chunks ? col[kb + u] : 0u;
+            sum += v[u];
+        }
+        uint32_t tot;
+        uint32_t ex = run + block_excl_sum<kRpThreads>(sum, s_scan, &tot);
+#pragma unroll
+        for (int u = 0; u < kScanPer; ++u) {
+            if (kb + u < chunks) col[kb + u] = ex;
+            ex += v[u];
+        }
+        run += tot;
+    }
+    if (threadIdx.x == 0) a.rowtot[y] = run;
 }
 
 // A3 (one workgroup): row starts of the row lists, the B chunks of every row
@@ -361,22 +366,54 @@ __global__ __launch_bounds__(kRpThreads) void k_rp_count_cols(RpArgs a) {
 }
 
 // B2: per tile, the start slot of every chunk of its row: the tile's range
-// start plus the counts of the row's earlier chunks.
+// start plus the counts of the row's earlier chunks.  Workgroup (row y,
+// group of kScanCols columns): each column's chunks are cut into
+// kRpThreads / kScanCols segments, one thread each; a thread sums its
+// segment (kScanBatch loads in flight), the segment sums are scanned in LDS,
+// and the thread writes its segment's starts (from registers when the
+// segment fits one batch, else re-read).
+constexpr int kScanCols = 16;
+constexpr int kScanSegs = kRpThreads / kScanCols;
+constexpr int kScanBatch = 16;
 __global__ __launch_bounds__(kRpThreads) void k_rp_scan_cols(RpArgs a) {
+    __shared__ uint32_t s_seg[kScanSegs][kScanCols];
     const uint32_t y = blockIdx.x;
     const uint32_t tx = a.tiles_x;
+    const uint32_t xi = threadIdx.x % kScanCols, sg = threadIdx.x / kScanCols;
+    const uint32_t x = blockIdx.y * kScanCols + xi;
     const uint32_t c1 = min(a.cstart[y + 1], a.cap_b), c0 = min(a.cstart[y], c1);
-    // one thread per tile column, 16 chunk loads in flight
-    for (uint32_t x = threadIdx.x; x < tx; x += kRpThreads) {
-        uint32_t run = a.ranges[(size_t)y * tx + x].x;
-        uint32_t* col = a.hb + x;
-        for (uint32_t cb = c0; cb < c1; cb += 16) {
-            uint32_t h[16];
+    const uint32_t len = (c1 - c0 + kScanSegs - 1) / kScanSegs;  // chunks per segment
+    const uint32_t s0 = c0 + min(sg * len, c1 - c0), s1 = min(s0 + len, c1);
+    const bool on = x < tx;
+    uint32_t* col = a.hb + (on ? x : 0u);
+    uint32_t h[kScanBatch], sum = 0;
+    for (uint32_t cb = s0; cb < s1; cb += kScanBatch) {
 #pragma unroll
-            for (int u = 0; u < 16; ++u) h[u] = cb + u < c1 ? col[(size_t)(cb + u) * tx] : 0u;
+        for (int u = 0; u < kScanBatch; ++u) {
+            h[u] = on && cb + u < s1 ? col[(size_t)(cb + u) * tx] : 0u;
+            sum += h[u];
+        }
+    }
+    s_seg[sg][xi] = sum;
+    __syncthreads();
+    if (!on) return;
+    uint32_t run = a.ranges[(size_t)y * tx + x].x;
+    for (uint32_t q = 0; q < sg; ++q) run += s_seg[q][xi];
+    if (s1 - s0 <= (uint32_t)kScanBatch) {  // the segment's counts are still in h
 #pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                if (cb + u < c1) {
+        for (int u = 0; u < kScanBatch; ++u) {
+            if (s0 + u < s1) {
+                col[(size_t)(s0 + u) * tx] = run;
+                run += h[u];
+            }
+        }
+    } else {
+        for (uint32_t cb = s0; cb < s1; cb += kScanBatch) {
+#pragma unroll
+            for (int u = 0; u < kScanBatch; ++u) h[u] = cb + u < s1 ? col[(size_t)(cb + u) * tx] : 0u;
+#pragma unroll
+            for (int u = 0; u < kScanBatch; ++u) {
+                if (cb + u < s1) {
                     col[(size_t)(cb + u) * tx] = run;
                     run += h[u];
                 }
@@ -613,7 +650,8 @@ hipError_t launch_row_place(const RowPlaceArgs& p, hipStream_t stream, hipEvent_
         e = hipStreamWaitEvent(stream, p.ranges_ready, 0);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_rp_scan_cols, dim3((unsigned)p.tiles_y), dim3(kRpThreads), 0, stream, a);
+    hipLaunchKernelGGL(k_rp_scan_cols, dim3((unsigned)p.tiles_y, (unsigned)((p.tiles_x + kScanCols - 1) / kScanCols)),
+                       dim3(kRpThreads), 0, stream, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (cols_counted && (e = hipEventRecord(cols_counted, stream)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_rp_place_cols, dim3((unsigned)sz.chunks_b_max), dim3(col_waves * kWave), lds_place_cols,

@@ -186,9 +186,16 @@ cds_status cds_create(cds_ctx** out, int device, const cds_allocator* alloc) {
     c->device = device;
     c->has_alloc = alloc != nullptr;
     if (alloc) c->alloc = *alloc;
-    if ((e = hipHostMalloc((void**)&c->host_pinned, 4096, hipHostMallocDefault)) != hipSuccess) {
+    // fine-grained (coherent) pinned words: kernels write the per-render
+    // counts straight into them, visible to the host once the kernel is done
+    if ((e = hipHostMalloc((void**)&c->host_pinned, 4096, hipHostMallocCoherent)) != hipSuccess) {
         delete c;
         return hip_fail(e, "hipHostMalloc");
+    }
+    if ((e = hipHostGetDevicePointer((void**)&c->host_pinned_dev, c->host_pinned, 0)) != hipSuccess) {
+        (void)hipHostFree(c->host_pinned);
+        delete c;
+        return hip_fail(e, "hipHostGetDevicePointer");
     }
     // one allocation: the error word (256 B) and the loss partial sums (4 KiB)
     c->d_err = (uint32_t*)ctx_alloc(c, 256 + 4096);

@@ -40,6 +40,7 @@ struct cds_ctx {
     cds_allocator alloc{};
     bool has_alloc = false;
     uint64_t* host_pinned = nullptr;  // pinned host words for the per-render key count
+    uint64_t* host_pinned_dev = nullptr;  // the same words as kernels address them (fine-grained)
     uint32_t* d_err = nullptr;        // device-side error word
     float* d_partial = nullptr;       // 1024 floats: per-block partial sums of the loss
     cds_frame* scratch = nullptr;     // buffers of the stand-alone sort / scan calls

@@ -45,17 +45,24 @@ __global__ __launch_bounds__(kNT) void k_scan_reduce(ScanSrc src, int64_t n, uin
 
 // One block scans the tile sums (exclusive, in place) and writes the total;
 // a second and a third block, when launched, do the same for sums2 / total2
-// and sums3 / total3.
+// and sums3 / total3.  A block whose host word (host_totals[block], pinned
+// host memory) is given writes its total there too.
+struct HostTotals {
+    uint64_t* p[3];
+};
 __global__ __launch_bounds__(1024) void k_scan_sums(uint64_t* __restrict__ sums, int64_t count,
                                                     uint64_t* __restrict__ total, uint64_t* __restrict__ sums2,
                                                     uint64_t* __restrict__ total2, uint64_t* __restrict__ sums3,
-                                                    uint64_t* __restrict__ total3) {
+                                                    uint64_t* __restrict__ total3, HostTotals host) {
+    uint64_t* host_total = host.p[0];
     if (blockIdx.x == 1) {  // uniform
         sums = sums2;
         total = total2;
+        host_total = host.p[1];
     } else if (blockIdx.x == 2) {
         sums = sums3;
         total = total3;
+        host_total = host.p[2];
     }
     __shared__ uint64_t wsum[1024 / kWave];
     __shared__ uint64_t carry;
@@ -86,7 +93,10 @@ __global__ __launch_bounds__(1024) void k_scan_sums(uint64_t* __restrict__ sums,
         if (threadIdx.x == 0) carry = c + all;
         __syncthreads();
     }
-    if (threadIdx.x == 0) *total = carry;
+    if (threadIdx.x == 0) {
+        *total = carry;
+        if (host_total) *host_total = carry;
+    }
 }
 
 __global__ __launch_bounds__(kNT) void k_scan_down(ScanSrc src, int64_t n, const uint64_t* __restrict__ sums,
@@ -124,10 +134,12 @@ __global__ __launch_bounds__(kNT) void k_scan_down(ScanSrc src, int64_t n, const
 int64_t scan_block_sums_size(int64_t n) { return (n + kTileItems - 1) / kTileItems + 1; }
 
 hipError_t launch_scan_u64_pair(uint64_t* a, uint64_t* b, int64_t count, uint64_t* total_a, uint64_t* total_b,
-                                hipStream_t stream, uint64_t* c, uint64_t* total_c) {
+                                hipStream_t stream, uint64_t* c, uint64_t* total_c, uint64_t* host_a,
+                                uint64_t* host_b, uint64_t* host_c) {
     if ((c != nullptr) != (total_c != nullptr)) return hipErrorInvalidValue;
+    const HostTotals host{{host_a, host_b, c ? host_c : nullptr}};
     hipLaunchKernelGGL(k_scan_sums, dim3(c ? 3 : 2), dim3(1024), 0, stream, a, count, total_a, b, total_b, c,
-                       total_c);
+                       total_c, host);
     return hipGetLastError();
 }
 
@@ -144,7 +156,7 @@ hipError_t launch_exclusive_scan(const uint32_t* in, const uint32_t* gather, uin
                            count_dev);
     }
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, stream, block_sums, tiles, total, nullptr, nullptr,
-                       nullptr, nullptr);
+                       nullptr, nullptr, HostTotals{{nullptr, nullptr, nullptr}});
     if (tiles > 0) {
         hipLaunchKernelGGL(k_scan_down, dim3((unsigned)tiles), dim3(kNT), 0, stream, src, n, block_sums, out, owner,
                            count_dev);

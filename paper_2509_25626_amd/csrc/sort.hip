@@ -957,14 +957,23 @@ hipError_t launch_sort_histogram(const uint32_t* keys, int64_t count, int passes
     return sort_histogram_impl<uint32_t>(keys, count, passes, shift0, end_bit, hist, stream);
 }
 
-hipError_t launch_sort_prepare(const SortWorkspace& ws, int64_t count, int passes, bool clear_hist,
-                               hipStream_t stream, int key_bytes) {
+void sort_prepare_spans(const SortWorkspace& ws, int64_t count, int passes, int key_bytes, ZeroSpan spans[2]) {
     // the partitions the passes will use: 32-bit keys from 2^23 on run wide
     // (a reduce-then-scan sort uses no status words at all)
     const int64_t parts = key_bytes == 4 && sort_uses_wide(count) ? sort_partitions_wide(count) : sort_partitions(count);
-    hipError_t e = launch_fill_u32(ws.status, (int64_t)passes * parts * 256, 0u, stream);
+    spans[0].p = ws.status;
+    spans[0].n = (int64_t)passes * parts * 256;
+    spans[1].p = ws.counters;
+    spans[1].n = passes;
+}
+
+hipError_t launch_sort_prepare(const SortWorkspace& ws, int64_t count, int passes, bool clear_hist,
+                               hipStream_t stream, int key_bytes) {
+    ZeroSpan sp[2];
+    sort_prepare_spans(ws, count, passes, key_bytes, sp);
+    hipError_t e = launch_fill_u32(sp[0].p, sp[0].n, 0u, stream);
     if (e != hipSuccess) return e;
-    e = launch_fill_u32(ws.counters, passes, 0u, stream);
+    e = launch_fill_u32(sp[1].p, sp[1].n, 0u, stream);
     if (e != hipSuccess) return e;
     if (clear_hist) e = launch_fill_u32(ws.hist, (int64_t)passes * 256, 0u, stream);
     return e;
