@@ -112,7 +112,8 @@ typedef struct cds_camera {
 #define CDS_OPT_SORT_REDUCE_SCAN 4u   /* radix-sort passes by reduce-then-scan (default: by size) */
 typedef struct cds_render_opts {
     uint32_t flags;         /* CDS_OPT_* bits */
-    int32_t blend_variant;  /* 0 = default; 1, 2, 4 = pixels per thread of the blend kernel */
+    int32_t blend_variant;  /* 0 = default (2 pixels per thread; 1 below ten tiles per compute unit);
+                               1, 2, 4 = pixels per thread of the blend kernel */
     int32_t sort_variant;   /* how the (tile | depth) list is ordered; every variant gives the same
                                sorted keys, values and ranges:
                                1 = 64-bit keys radix-sorted on all their digits;

@@ -28,6 +28,8 @@
 // colour channel with no background (kDepth, staged per splat in s_d).
 #include <algorithm>
 
+#include <atomic>
+
 #include "device_utils.h"
 #include "internal.h"
 
@@ -641,10 +643,28 @@ __global__ __launch_bounds__(kLossBlocks) void k_l1_loss_finish(const float* __r
 
 static uint32_t xcd_per(int64_t tiles) { return (uint32_t)((tiles + 7) / 8); }
 
+// Compute units of the current device (cached per device).
+int device_cus() {
+    static std::atomic<int> cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    int c = cache[dev].load(std::memory_order_relaxed);
+    if (c <= 0) {
+        c = 256;
+        (void)hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev);
+        cache[dev].store(c, std::memory_order_relaxed);
+    }
+    return c;
+}
+
 hipError_t launch_blend(const BlendArgs& a, int variant, hipStream_t stream) {
     const int64_t tiles = (int64_t)a.tiles_x * a.tiles_y;
     if (tiles == 0) return hipSuccess;
     if (!a.err) return hipErrorInvalidValue;
+    // default: two pixels per lane (two waves per tile) once the tiles give
+    // every SIMD several waves; fewer tiles (below ten per CU) run one pixel
+    // per lane, four waves per tile
+    if (variant == 0) variant = tiles < 10 * (int64_t)device_cus() ? 1 : 2;
     const uint32_t per = xcd_per(tiles);
     const dim3 grid(8 * per);
     const bool depth = a.out_invdepth != nullptr;
@@ -654,9 +674,7 @@ hipError_t launch_blend(const BlendArgs& a, int variant, hipStream_t stream) {
         hipError_t e = launch_fill_u32(a.counter, 1, 0u, stream);
         if (e != hipSuccess) return e;
         const uint32_t units = (uint32_t)((variant == 3 ? 2 : 1) * tiles);
-        int dev = 0, cus = 256;
-        if (hipGetDevice(&dev) == hipSuccess)
-            (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        const int cus = device_cus();
         // at most as many workgroups (two waves each) as fit, all of them busy
         const int64_t g = std::min<int64_t>((int64_t)(units + 1) / 2, (int64_t)cus * 12);
         if (variant == 3) {
