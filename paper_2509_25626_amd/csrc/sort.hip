@@ -712,6 +712,10 @@ __device__ __forceinline__ void sort_pass_kernel(const PassArgs<Key>& a_in) {
     __shared__ uint32_t s_pid;
 
     const int t = threadIdx.x;
+    // a grid sized for a bound on the count (the count read on the device):
+    // workgroups past the partitions the count needs leave before taking an
+    // id, so the serialized id atomics are only the needed ones
+    if ((int64_t)blockIdx.x * kP >= a.count) return;  // uniform
     if (t == 0) s_pid = kOnesweep ? atomicAdd(a.counter, 1u) : blockIdx.x;
     const uint32_t hist_t = (kOnesweep && t < 256) ? a.hist[t] : 0u;
     for (int k = t; k < kWaves * 256; k += kNT) (&s_whist[0][0])[k] = 0;
@@ -766,6 +770,7 @@ __global__ __launch_bounds__(kNT, kMinBlocks<kNT>) void k_sort_pass_packed(PassA
     __shared__ uint32_t s_pid;
 
     const int t = threadIdx.x;
+    if ((int64_t)blockIdx.x * kP >= a.count) return;  // uniform: as in sort_pass_kernel
     if (t == 0) s_pid = atomicAdd(a.counter, 1u);
     const uint32_t hist_t = t < 256 ? a.hist[t] : 0u;
     for (int k = t; k < kWaves * 256; k += kNT) (&s_whist[0][0])[k] = 0;
