@@ -586,13 +586,13 @@ __global__ __launch_bounds__(256 / PPT) void k_blend_bwd(BlendBwdArgs a, uint32_
                 // instruction covers them
                 const float v8[8] = {gmx * kLn2, gmy * kLn2, gA, gB, gC, go, gr, gg};
                 const float s8 = wave_reduce_scatter8(v8);
-                const float sb = wave_sum(gb);
+                const float sb = wave_sum_dpp(gb);
                 const uint32_t l = lane_id();
                 float* g = a.grad2d + (size_t)s_id[k] * kGrad2d;
                 if ((l & 7u) == 0) atomicAdd(g + (l >> 3), s8);
                 if (l == 0) atomicAdd(g + 8, sb);
                 if constexpr (kDepth) {
-                    const float sd = wave_sum(gd);
+                    const float sd = wave_sum_dpp(gd);
                     if (l == 0) atomicAdd(g + 9, sd);
                 }
             }

@@ -38,26 +38,64 @@ __device__ __forceinline__ float wave_sum(float v) {
     return v;
 }
 
+// Cross-lane exchanges without the LDS crossbar.  DPP controls (gfx9
+// encoding): quad permutations (1,0,3,2) and (2,3,0,1) are lane ^ 1 and
+// lane ^ 2; a 16-lane row rotated by 8 is lane ^ 8; the half-row mirror maps
+// lane i of each 8-lane group to 7 - i, the row mirror i of each row to 15 - i.
+constexpr int kDppQuadXor1 = 0xB1;
+constexpr int kDppQuadXor2 = 0x4E;
+constexpr int kDppRowRor8 = 0x128;
+constexpr int kDppRowHalfMirror = 0x141;
+constexpr int kDppRowMirror = 0x140;
+
+template <int kCtrl>
+__device__ __forceinline__ float dpp_f32(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kCtrl, 0xF, 0xF, false));
+}
+
+// Lane pairs 32 apart (v_permlane32_swap: lanes 32-63 of the first operand
+// trade places with lanes 0-31 of the second): lanes below 32 get the pair's
+// sum of lo, lanes from 32 on the pair's sum of hi.
+__device__ __forceinline__ float pair_sum32(float lo, float hi) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(lo), __float_as_uint(hi), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// The same for rows of 16 lanes 16 apart (v_permlane16_swap: odd rows of
+// the first operand with even rows of the second): even rows get the pair's
+// sum of lo, odd rows of hi.
+__device__ __forceinline__ float pair_sum16(float lo, float hi) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(lo), __float_as_uint(hi), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// Sum over the wave, in every lane (all lanes active).
+__device__ __forceinline__ float wave_sum_dpp(float v) {
+    v += dpp_f32<kDppQuadXor1>(v);
+    v += dpp_f32<kDppQuadXor2>(v);
+    v += dpp_f32<kDppRowHalfMirror>(v);
+    v += dpp_f32<kDppRowMirror>(v);
+    v = pair_sum16(v, v);
+    return pair_sum32(v, v);
+}
+
 // Wave sums of eight per-lane values, scattered over the lanes: afterwards
-// every lane holds the total of value index (lane >> 3) & 7.  Each butterfly
-// step sends half of the values still held and keeps the other half, so the
-// eight sums cost 4 + 2 + 1 + 3 = 10 cross-lane exchanges instead of 8 * 6.
+// every lane holds the total of value index (lane >> 3) & 7 (all lanes
+// active).  Each butterfly step sends half of the values still held and keeps
+// the other half, so the eight sums cost 4 + 2 + 1 + 3 = 10 exchanges instead
+// of 8 * 6, all of them permlane swaps and DPP (no LDS round trips).
 __device__ __forceinline__ float wave_reduce_scatter8(const float (&v)[8]) {
     const uint32_t l = lane_id();
     float a[4], b[2];
-    const bool h5 = (l & 32u) != 0;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-        a[i] = (h5 ? v[4 + i] : v[i]) + __shfl_xor(h5 ? v[i] : v[4 + i], 32, kWave);
-    const bool h4 = (l & 16u) != 0;
+    for (int i = 0; i < 4; ++i) a[i] = pair_sum32(v[i], v[4 + i]);  // lanes < 32: values 0-3; else 4-7
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-        b[i] = (h4 ? a[2 + i] : a[i]) + __shfl_xor(h4 ? a[i] : a[2 + i], 16, kWave);
+    for (int i = 0; i < 2; ++i) b[i] = pair_sum16(a[i], a[2 + i]);  // even rows: the lower two
     const bool h3 = (l & 8u) != 0;
-    float c = (h3 ? b[1] : b[0]) + __shfl_xor(h3 ? b[0] : b[1], 8, kWave);
-    c += __shfl_xor(c, 4, kWave);
-    c += __shfl_xor(c, 2, kWave);
-    c += __shfl_xor(c, 1, kWave);
+    float c = (h3 ? b[1] : b[0]) + dpp_f32<kDppRowRor8>(h3 ? b[0] : b[1]);
+    c += dpp_f32<kDppQuadXor1>(c);
+    c += dpp_f32<kDppQuadXor2>(c);
+    c += dpp_f32<kDppRowHalfMirror>(c);
     return c;
 }
 
