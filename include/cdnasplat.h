@@ -351,8 +351,11 @@ typedef struct cds_server_opts {
 typedef struct cds_server_stats {
     int64_t submitted, completed, rejected;
     int64_t batches;            /* batched launches issued */
-    int64_t workspace_bytes;    /* workspace currently reserved by admitted requests */
+    int64_t workspace_bytes;    /* workspace currently reserved by admitted requests (estimate) */
     int64_t peak_workspace_bytes;
+    int64_t held_bytes;         /* device memory the workspaces' buffers hold now (measured) */
+    int64_t peak_held_bytes;    /* its maximum; admission keeps it within the HBM budget
+                                   except for a request that runs alone */
 } cds_server_stats;
 
 /* Create a server on a context.  The server owns one HIP stream pair and a

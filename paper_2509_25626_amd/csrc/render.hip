@@ -25,8 +25,9 @@ void release_frame_events(cds_frame* f) {
     }
 }
 
-void release_frame_buffers(cds_frame* f) {
-    cds_ctx* c = f->ctx;
+// Every device buffer a frame may hold.
+template <typename F>
+void for_each_frame_buffer(cds_frame* f, F&& fn) {
     DevBuf* bufs[] = {&f->mean2d, &f->conic, &f->rgb, &f->depth, &f->radius, &f->rect, &f->touched,
                       &f->offsets, &f->kowner, &f->clampf, &f->blocksums, &f->total, &f->order0, &f->order1,
                       &f->dkey0, &f->dkey1, &f->sort_d.hist, &f->sort_d.status, &f->sort_d.counters,
@@ -37,8 +38,19 @@ void release_frame_buffers(cds_frame* f) {
                       &f->keys0, &f->keys1, &f->tk0, &f->tk1, &f->vals0, &f->vals1, &f->sort.hist,
                       &f->sort.status, &f->sort.counters, &f->sort.part_hist, &f->sort.bases,
                       &f->sort.scan_sums, &f->sort.scan_total, &f->ranges, &f->grad2d};
-    for (DevBuf* b : bufs) release(c, *b);
+    for (DevBuf* b : bufs) fn(*b);
+}
+
+void release_frame_buffers(cds_frame* f) {
+    cds_ctx* c = f->ctx;
+    for_each_frame_buffer(f, [c](DevBuf& b) { release(c, b); });
     f->valid = false;
+}
+
+int64_t frame_held_bytes(cds_frame* f) {
+    int64_t held = 0;
+    for_each_frame_buffer(f, [&held](DevBuf& b) { held += b.p ? (int64_t)b.bytes : 0; });
+    return held;
 }
 
 #define CDS_HIP(expr, what)                          \

@@ -110,6 +110,9 @@ SceneParams make_scene(const cds_scene* s);
 cds_status ensure_sort_workspace(cds_ctx* ctx, SortState& s, int64_t count, int passes);
 SortWorkspace sort_ws(cds_ctx* ctx, SortState& s);
 
+void release_frame_buffers(cds_frame* f);
+int64_t frame_held_bytes(cds_frame* f);  // device bytes the frame's buffers hold now
+
 cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scene, const cds_camera* cam,
                                int blend_variant, int sort_variant, SortAlgo algo, float* out_rgb, float* out_T,
                                uint32_t* out_ncontrib, float* out_invdepth, hipStream_t stream);

@@ -72,6 +72,7 @@ struct Workspace {
     bool busy = false;
     std::vector<SrvRequest*> reqs;
     int64_t reserved = 0;
+    int64_t held = 0;  // device bytes its frame buffers hold (measured after each batch is enqueued)
 };
 
 }  // namespace
@@ -90,6 +91,7 @@ struct cds_server {
     bool stop = false;
     Workspace ws[kWorkspaces];
     int64_t budget = 0, reserved = 0;
+    int64_t held = 0;  // sum of the workspaces' held bytes
     int inflight = 0;
     double key_scale = 1.0;  // learned ratio of actual to estimated keys
     cds_server_stats stats{};
@@ -266,6 +268,15 @@ cds_status run_batch(cds_server* s, Workspace& w) {
     return CDS_OK;
 }
 
+// Frees an idle workspace's frame buffers (the next batch there allocates again).
+void release_workspace(cds_server* s, Workspace& w) {
+    (void)hipStreamSynchronize(w.stream);  // idle already; the buffers must not be in use
+    release_frame_buffers(w.frame);
+    s->held -= w.held;
+    w.held = 0;
+    s->stats.held_bytes = s->held;
+}
+
 void finish(cds_server* s, Workspace& w, cds_status st, const std::string& err) {
     const double t = now_ms();
     for (SrvRequest* r : w.reqs) {
@@ -282,6 +293,9 @@ void finish(cds_server* s, Workspace& w, cds_status st, const std::string& err) 
     w.reqs.clear();
     w.reserved = 0;
     w.busy = false;
+    // buffers grown past the workspace's share of the budget (an oversized
+    // batch) are given back once its work is done
+    if (w.held > s->budget / kWorkspaces) release_workspace(s, w);
 }
 
 void worker_main(cds_server* s) {
@@ -318,11 +332,24 @@ void worker_main(cds_server* s) {
             // its requests wait for; a long one still fills batches
             const int share = (int)((s->pending.size() + (size_t)nfree - 1) / (size_t)nfree);
             const int limit = std::min(s->opts.max_batch, std::max(1, share));
+            // the device memory the batch would leave held: the other
+            // workspaces' buffers plus this one's grown to the estimate (with
+            // the allocator's 1.25 growth); idle workspaces give theirs back
+            // when that is what keeps it within the budget
+            const auto projected = [&](int64_t est) {
+                const int64_t need = est + est / 4;
+                return s->held - free_ws->held + std::max(free_ws->held, need);
+            };
             while (!s->pending.empty() && (int)batch.size() < limit &&
                    s->inflight + (int)batch.size() < s->opts.max_slots) {
                 SrvRequest* r = s->pending.front();
                 const bool alone = batch.empty() && s->reserved == 0;
-                if (!alone && s->reserved + bytes + r->est_bytes > s->budget) break;
+                if (projected(bytes + r->est_bytes) > s->budget)
+                    for (Workspace& o : s->ws)
+                        if (&o != free_ws && !o.busy && o.held > 0) release_workspace(s, o);
+                if (!alone && (s->reserved + bytes + r->est_bytes > s->budget ||
+                               projected(bytes + r->est_bytes) > s->budget))
+                    break;
                 // a batch's global tile ids and Gaussian indices stay small enough
                 // for the single render's sort shape: tile counts in one LDS array,
                 // two tile passes of at most 7-bit digits, and the second pass's
@@ -349,7 +376,12 @@ void worker_main(cds_server* s) {
                 lk.unlock();
                 const cds_status st = run_batch(s, w);
                 const std::string err = st == CDS_OK ? "" : g_last_error;
+                const int64_t held = frame_held_bytes(w.frame);
                 lk.lock();
+                s->held += held - w.held;
+                w.held = held;
+                s->stats.held_bytes = s->held;
+                s->stats.peak_held_bytes = std::max(s->stats.peak_held_bytes, s->held);
                 if (st != CDS_OK) finish(s, w, st, err);
                 continue;
             }

@@ -85,7 +85,8 @@ class CdsServerOpts(ctypes.Structure):
 class CdsServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
                 ("rejected", ctypes.c_int64), ("batches", ctypes.c_int64),
-                ("workspace_bytes", ctypes.c_int64), ("peak_workspace_bytes", ctypes.c_int64)]
+                ("workspace_bytes", ctypes.c_int64), ("peak_workspace_bytes", ctypes.c_int64),
+                ("held_bytes", ctypes.c_int64), ("peak_held_bytes", ctypes.c_int64)]
 
 
 # name -> (restype, argtypes)

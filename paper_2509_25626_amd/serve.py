@@ -192,7 +192,8 @@ def _summary(lat, span, stats):
     return {"p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
             "mean_ms": round(float(lat.mean()), 3), "frames_per_s": round(len(lat) / span, 2) if span > 0 else None,
             "requests": int(len(lat)), "batches": stats["batches"],
-            "peak_workspace_gb": round(stats["peak_workspace_bytes"] / 1e9, 3)}
+            "peak_workspace_gb": round(stats["peak_workspace_bytes"] / 1e9, 3),
+            "peak_held_gb": round(stats["peak_held_bytes"] / 1e9, 3)}
 
 
 def bench_serving(quick: bool = True, device: int = 0, loads=(0.5, 0.8, 0.95), requests_per_load=None,
@@ -242,7 +243,8 @@ def bench_serving(quick: bool = True, device: int = 0, loads=(0.5, 0.8, 0.95), r
                 s0 = srv.stats()
                 lat, span = _replay(srv, ids[name], reqs, ring)
                 s1 = srv.stats()
-                st = {"batches": s1["batches"] - s0["batches"], "peak_workspace_bytes": s1["peak_workspace_bytes"]}
+                st = {"batches": s1["batches"] - s0["batches"], "peak_workspace_bytes": s1["peak_workspace_bytes"],
+                      "peak_held_bytes": s1["peak_held_bytes"]}
                 res[name] = _summary(lat, span, st)
             out["loads"][str(load)] = res
         # saturation: the whole trace at once through the batched server
@@ -252,7 +254,8 @@ def bench_serving(quick: bool = True, device: int = 0, loads=(0.5, 0.8, 0.95), r
         s1 = batched.stats()
         out["batched_capacity_rps"] = round(len(sat) / span, 2)
         out["batched_saturation"] = _summary(lat, span, {"batches": s1["batches"] - s0["batches"],
-                                                         "peak_workspace_bytes": s1["peak_workspace_bytes"]})
+                                                         "peak_workspace_bytes": s1["peak_workspace_bytes"],
+                                                         "peak_held_bytes": s1["peak_held_bytes"]})
     finally:
         fifo.close()
         batched.close()

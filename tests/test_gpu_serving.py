@@ -144,7 +144,8 @@ def test_budget_rejects_oversized_request(resident):
 
 def test_budget_binds_admission(R, resident):
     """A budget that holds about one large request: requests still all complete,
-    with identical images, and the reserved workspace never exceeds the budget."""
+    with identical images, and neither the reserved workspace nor the device
+    memory the workspaces' buffers actually hold ever exceeds the budget."""
     from paper_2509_25626_amd.serve import Server
     _, scenes = resident
     reqs = [(3, S.orbit_camera(640, 360, azimuth_deg=30.0 * k)) for k in range(6)]
@@ -157,6 +158,8 @@ def test_budget_binds_admission(R, resident):
     for a, b in zip(got, ref):
         assert torch.equal(a, b)
     assert 0 < st["peak_workspace_bytes"] <= budget
+    assert 0 < st["peak_held_bytes"] <= budget, st
+    assert st["held_bytes"] <= budget
     assert st["batches"] >= 2
 
 
