@@ -409,7 +409,8 @@ __global__ __launch_bounds__(128) void k_blend_steal(BlendArgs a, uint32_t* coun
 // Persistent blend over every tile of a batch of renders: each workgroup
 // takes the next global tile id from an atomic counter until none is left
 // (every wave reaches the exit), finds the owning request by binary search
-// over the tile bases, and blends that tile.
+// over the tile bases, and blends that tile (its range found by global or
+// stacked tile id, as the item says).
 template <int PPT>
 __global__ __launch_bounds__(256 / PPT) void k_blend_batch(const BatchItem* __restrict__ items, int nitems,
                                                            int64_t total_tiles, const uint2* __restrict__ ranges,
@@ -433,7 +434,9 @@ __global__ __launch_bounds__(256 / PPT) void k_blend_batch(const BatchItem* __re
         const BatchItem& it = items[r];
         const uint32_t local = g - (uint32_t)it.tile_base;
         const int tx = (int)(local % (uint32_t)it.P.tiles_x), ty = (int)(local / (uint32_t)it.P.tiles_x);
-        blend_tile<PPT>(tx, ty, it.P.width, it.P.height, ranges[g], point_list, n, err, mean2d, conic_opacity, rgb,
+        // ranges by global tile id, or by stacked tile id (row-wise placement)
+        const int64_t rt = it.rec_stride > 0 ? it.rec_base + (int64_t)ty * it.rec_stride + tx : (int64_t)g;
+        blend_tile<PPT>(tx, ty, it.P.width, it.P.height, ranges[rt], point_list, n, err, mean2d, conic_opacity, rgb,
                         it.bg[0], it.bg[1], it.bg[2], it.out_rgb, it.out_T, it.out_ncontrib, s_q, s_c, s_f, s_b);
     }
 }

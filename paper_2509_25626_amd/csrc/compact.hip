@@ -131,8 +131,9 @@ __global__ __launch_bounds__(kCT) void k_vis_scatter(int64_t n, const uint32_t* 
             uint32_t tx = tiles_x, tb = 0;
             if (items) {
                 const int it = find_item_by_gaussian(items, nitems, i);
-                tx = (uint32_t)items[it].P.tiles_x;
-                tb = (uint32_t)items[it].tile_base;
+                const bool stacked = items[it].rec_stride > 0;
+                tx = (uint32_t)(stacked ? items[it].rec_stride : items[it].P.tiles_x);
+                tb = (uint32_t)(stacked ? items[it].rec_base : items[it].tile_base);
             }
             dkey[pos] = d;
             rec[pos] = make_tile_rec(rc, tx, tb, (uint32_t)i);

@@ -61,6 +61,12 @@ struct BatchItem {
     float* out_rgb;
     float* out_T;            // may be null
     uint32_t* out_ncontrib;  // may be null
+    // With rec_stride > 0 the batch's tiles also live on a stacked grid for
+    // the row-wise placement: the requests' tile rows one below the other,
+    // every row rec_stride tiles wide; tile (x, y) of this item is stacked
+    // tile rec_base + y * rec_stride + x (its tile records and ranges use it).
+    int64_t rec_base;
+    int32_t rec_stride;
 };
 
 // Item owning global Gaussian g / global tile t (items sorted by base).

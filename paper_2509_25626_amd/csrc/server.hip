@@ -145,7 +145,24 @@ cds_status run_batch(cds_server* s, Workspace& w) {
         T += (int64_t)it.P.tiles_x * it.P.tiles_y;
     }
     if (N > (int64_t)0x7FFFFFFF || T > (int64_t)0x7FFFFFFF) return fail(CDS_ERR_CAPACITY, "batch too large");
-    const int tile_passes = (tile_bits_for(T) + 7) / 8;
+    // The stacked tile grid of the row-wise placement: every request's tile
+    // rows one below the other, all as wide as the widest request.  Its tile
+    // order restricted to the real tiles is the global tile order, so the
+    // sorted list is the same; records, ranges and the blend use its ids.
+    int64_t W = 0, Rows = 0;
+    for (int k = 0; k < nitems; ++k) W = std::max<int64_t>(W, w.items_host[k].P.tiles_x);
+    for (int k = 0; k < nitems; ++k) Rows += w.items_host[k].P.tiles_y;
+    const bool stacked = row_place_supported((int)std::min<int64_t>(W, INT32_MAX),
+                                             (int)std::min<int64_t>(Rows, INT32_MAX));
+    int64_t row_base = 0;
+    for (int k = 0; k < nitems && stacked; ++k) {
+        BatchItem& it = w.items_host[k];
+        it.rec_stride = (int32_t)W;
+        it.rec_base = row_base * W;
+        row_base += it.P.tiles_y;
+    }
+    const int64_t Tg = stacked ? W * Rows : T;  // tile ids of the records, the ranges and the blend
+    const int tile_passes = (tile_bits_for(Tg) + 7) / 8;
     SRV_HIP(hipMemcpyAsync(w.items_dev, w.items_host, sizeof(BatchItem) * nitems, hipMemcpyHostToDevice, stream),
             "hipMemcpyAsync(batch items)");
     const size_t nn = (size_t)std::max<int64_t>(N, 1);
@@ -169,8 +186,9 @@ cds_status run_batch(cds_server* s, Workspace& w) {
     SRV_TRY(ensure(ctx, f->recv, sizeof(uint4) * nn, 1.25));
     SRV_TRY(ensure(ctx, f->vsums, sizeof(uint64_t) * compact_sums_size(N), 1.25));
     SRV_TRY(ensure(ctx, f->ksums, sizeof(uint64_t) * compact_sums_size(N), 1.25));
-    SRV_TRY(ensure(ctx, f->ranges, sizeof(uint2) * (size_t)std::max<int64_t>(T, 1), 1.25));
-    SRV_TRY(ensure(ctx, f->tdiff, sizeof(int) * (size_t)(T + 1), 1.25));
+    SRV_TRY(ensure(ctx, f->ranges, sizeof(uint2) * (size_t)std::max<int64_t>(Tg, 1), 1.25));
+    SRV_TRY(ensure(ctx, f->tdiff, sizeof(int) * (size_t)(Tg + 1), 1.25));
+    if (stacked) SRV_TRY(ensure(ctx, f->hsums, sizeof(uint64_t) * compact_sums_size(N), 1.25));
     SRV_TRY(ensure(ctx, f->thist, sizeof(uint32_t) * 4 * 256));
     SRV_TRY(ensure_sort_workspace(ctx, f->sort_d, N, 4));
 
@@ -191,13 +209,17 @@ cds_status run_batch(cds_server* s, Workspace& w) {
     // depth histograms, n_vis and K
     SRV_HIP(launch_compact_visible(N, sb.touched, sb.rect, sb.depth_bits, (uint64_t*)f->vsums.p,
                                    (uint64_t*)f->ksums.p, d_total, (uint32_t*)f->dkeyc.p, (uint4*)f->recc.p,
-                                   wd.hist, stream, 0, w.items_dev, nitems),
+                                   wd.hist, stream, 0, w.items_dev, nitems,
+                                   stacked ? (uint64_t*)f->hsums.p : nullptr, stacked ? d_total + 3 : nullptr),
             "batched compaction");
-    SRV_HIP(hipMemcpyAsync(w.pinned, d_total, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
+    SRV_HIP(hipMemcpyAsync(w.pinned, d_total, 4 * sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
             "hipMemcpyAsync(key count)");
     SRV_HIP(hipStreamSynchronize(stream), "hipStreamSynchronize(key count)");
     const int64_t nvis = (int64_t)w.pinned[0];
     const uint64_t K = w.pinned[1];
+    const uint64_t sum_h = stacked ? w.pinned[3] : 0;
+    // the row-wise placement's limits (buffer offsets below 2^31 bytes)
+    const bool rowplace = stacked && K > 0 && K <= (uint64_t(1) << 29) && sum_h <= (uint64_t(1) << 28);
     if (K > (uint64_t)kSortMaxCount) return fail(CDS_ERR_CAPACITY, "batch needs more than 2^30-1 tile keys");
     int64_t est = 0;
     for (const SrvRequest* r : w.reqs) {
@@ -218,17 +240,52 @@ cds_status run_batch(cds_server* s, Workspace& w) {
                                    false, nullptr, value_bits_for(nvis - 1), nullptr, (const uint4*)f->recc.p,
                                    (uint4*)f->recv.p),
                 "depth sort (records in depth order)");
-        SRV_TRY(ensure(ctx, f->kowner, sizeof(uint32_t) * (size_t)(K / kKeyGenChunk + 1), 1.25));
-        SRV_HIP(launch_exclusive_scan(nullptr, nullptr, (uint32_t*)f->offsets.p, nvis, (uint64_t*)f->blocksums.p,
-                                      d_total + 2, stream, recv, (uint32_t*)f->kowner.p),
-                "offset scan");
+        if (!rowplace) {
+            SRV_TRY(ensure(ctx, f->kowner, sizeof(uint32_t) * (size_t)(K / kKeyGenChunk + 1), 1.25));
+            SRV_HIP(launch_exclusive_scan(nullptr, nullptr, (uint32_t*)f->offsets.p, nvis,
+                                          (uint64_t*)f->blocksums.p, d_total + 2, stream, recv,
+                                          (uint32_t*)f->kowner.p),
+                    "offset scan");
+        }
     }
-    // ranges and tile-digit histograms from the records (global tile ids)
-    const int tile_bits = tile_bits_for(T);
-    SRV_HIP(launch_tile_counts(nvis, nullptr, nullptr, 0, T, (int*)f->tdiff.p, (uint2*)f->ranges.p,
+    // ranges and tile-digit histograms from the records (global or stacked tile ids)
+    const int tile_bits = tile_bits_for(Tg);
+    SRV_HIP(launch_tile_counts(nvis, nullptr, nullptr, 0, Tg, (int*)f->tdiff.p, (uint2*)f->ranges.p,
                                (uint32_t*)f->thist.p, digit_plan(tile_passes, 0, tile_bits), nullptr, kTileCountBlocks,
                                stream, nullptr, 0, (const uint4*)f->recc.p),  // index order: chunks stay in one request
             "batched tile counts");
+    if (rowplace) {
+        // tile lists by stable placement over the stacked tile rows, then columns
+        const RowPlaceSizes rs = row_place_sizes(nvis, sum_h, (int)W, (int)Rows);
+        SRV_TRY(ensure(ctx, f->rp_ha, sizeof(uint32_t) * (size_t)rs.ha_words, 1.25));
+        SRV_TRY(ensure(ctx, f->rp_hb, sizeof(uint32_t) * (size_t)std::max<int64_t>(rs.hb_words, 1), 1.25));
+        SRV_TRY(ensure(ctx, f->rp_small, sizeof(uint32_t) * (size_t)rs.small_words, 1.25));
+        SRV_TRY(ensure(ctx, f->rp_rowent, sizeof(uint2) * (size_t)std::max<uint64_t>(sum_h, 1), 1.25));
+        SRV_TRY(ensure(ctx, f->vals0, sizeof(uint32_t) * (size_t)K, 1.25));
+        RowPlaceArgs ra;
+        ra.rec = recv;
+        ra.count_dev = d_total;
+        ra.n_records_max = nvis;
+        ra.tiles_x = (int)W;
+        ra.tiles_y = (int)Rows;
+        ra.sum_h = sum_h;
+        ra.K = K;
+        ra.ranges = (const uint2*)f->ranges.p;
+        ra.ranges_ready = nullptr;  // same stream
+        ra.ha = (uint32_t*)f->rp_ha.p;
+        ra.hb = (uint32_t*)f->rp_hb.p;
+        ra.small = (uint32_t*)f->rp_small.p;
+        ra.rowent = (uint2*)f->rp_rowent.p;
+        ra.values = (uint32_t*)f->vals0.p;
+        ra.err = ctx->d_err;
+        SRV_HIP(launch_row_place(ra, stream), "batched row-wise tile placement");
+        const int64_t grid = std::min<int64_t>(T, (int64_t)s->cus * 8);
+        SRV_HIP(launch_blend_batch(w.items_dev, nitems, T, (const uint2*)f->ranges.p, (const uint32_t*)f->vals0.p, N,
+                                   sb.mean2d, sb.conic_opacity, sb.rgb, w.counter, (int)grid, ctx->d_err, stream),
+                "batched blend");
+        SRV_HIP(hipEventRecord(w.done, stream), "hipEventRecord");
+        return CDS_OK;
+    }
     const size_t kk = (size_t)std::max<uint64_t>(K, 1);
     const bool fused = sort_uses_onesweep((int64_t)K, algo) && tile_passes > 0;
     const int vbits = value_bits_for(N - 1);
