@@ -163,7 +163,7 @@ hipError_t launch_compact_visible(int64_t n, const uint32_t* touched, const uint
                                   const BatchItem* items, int nitems, uint64_t* h_sums, uint64_t* sum_h,
                                   const ZeroSpan* zero_spans, uint64_t* host_totals, hipEvent_t totals_ready) {
     const int64_t tiles = (n + kCTile - 1) / kCTile;
-    if ((sum_h && !h_sums) || (host_totals && !totals_ready)) return hipErrorInvalidValue;
+    if (sum_h && !h_sums) return hipErrorInvalidValue;
     ZeroJobs z;
     z.s[0].p = depth_hist;
     z.s[0].n = 4 * 256;

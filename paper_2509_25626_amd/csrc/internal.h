@@ -120,8 +120,9 @@ struct BatchItem;
 // zero_spans: up to kZeroSpans more word ranges cleared by the counting
 // kernel (so the caller needs no fill launches of its own before the sort).
 // host_totals (4 words of fine-grained pinned host memory, device address):
-// totals[0], totals[1] and *sum_h are written there too, and totals_ready is
-// recorded once they are, before the scatter kernel runs.
+// totals[0], totals[1] and *sum_h are written there too; totals_ready, if
+// given, is recorded once they are, before the scatter kernel runs (else the
+// caller records its own event after the compaction).
 int64_t compact_sums_size(int64_t n);
 struct ZeroSpan {
     uint32_t* p = nullptr;

@@ -190,7 +190,7 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
                                        (uint64_t*)f->ksums.p, d_total, (uint32_t*)f->dkeyc.p, (uint4*)f->recc.p,
                                        wd.hist, stream, P.tiles_x, nullptr, 0,
                                        rowplace ? (uint64_t*)f->hsums.p : nullptr, rowplace ? d_total + 3 : nullptr,
-                                       depth_onesweep ? depth_prep : nullptr, ctx->host_pinned_dev, f->copied),
+                                       depth_onesweep ? depth_prep : nullptr, ctx->host_pinned_dev, nullptr),
                 "visible compaction");
     } else if (binned) {
         // depth order of all N Gaussians: 4 passes, result in (dkey1, order1)
@@ -215,7 +215,8 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
                 "scan kernels");
     }
     // the compacting path's scan wrote the counts into the pinned host words
-    // itself (event f->copied); the others copy them
+    // itself (the host waits for f->copied, recorded after the compaction
+    // below); the others copy them
     if (!compact)
         CDS_HIP(hipMemcpyAsync(ctx->host_pinned, d_total, 4 * sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
                 "hipMemcpyAsync(key count)");
@@ -226,9 +227,10 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
         // number of visible splats (d_total[0]) on the device.
         side_join.join = f->join;
         // ranges and tile-digit histograms from the records (their order does not
-        // matter), on the side stream while the depth sort runs
-        CDS_HIP(hipEventRecord(f->fork, stream), "hipEventRecord(fork)");
-        CDS_HIP(hipStreamWaitEvent(f->side, f->fork, 0), "hipStreamWaitEvent(fork)");
+        // matter), on the side stream while the depth sort runs; one event marks
+        // both the records complete (the fork) and the counts in the host words
+        CDS_HIP(hipEventRecord(f->copied, stream), "hipEventRecord(copied)");
+        CDS_HIP(hipStreamWaitEvent(f->side, f->copied, 0), "hipStreamWaitEvent(fork)");
         CDS_HIP(launch_tile_counts(n, nullptr, nullptr, P.tiles_x, ntiles, (int*)f->tdiff.p, (uint2*)f->ranges.p,
                                    (uint32_t*)f->thist.p, digit_plan(tile_passes, 0, tile_bits), nullptr,
                                    kTileCountBlocks, f->side, nullptr, 0, (const uint4*)f->recc.p, d_total),
