@@ -27,6 +27,8 @@
 // clamped to the output, so even then nothing outside it is written.
 #include <algorithm>
 
+#include <type_traits>
+
 #include "device_utils.h"
 #include "internal.h"
 
@@ -81,67 +83,6 @@ __device__ __forceinline__ void chunk_counts(uint32_t* diff, int nbins, uint32_t
         const uint32_t inc = wave_incl_sum(d) + carry;
         if (b < nbins) out[b * stride] = inc;
         carry = (uint32_t)__builtin_amdgcn_readlane((int)inc, kWave - 1);
-    }
-}
-
-// Stable placement of one wave's chunk of R rounds of 64 intervals [lo,
-// lo + span] over nbins bins (an unused slot has lo past every bin and span
-// 0): for every bin, the covering intervals in chunk order (round, then
-// lane) get consecutive slots from the bin's write pointer (s_base, this
-// wave's nbins words of LDS), which advances past them.  Their payloads
-// (W words each) are first gathered in that order in this wave's staging
-// area s_stage (R * 64 slots of W words), then the bin's run goes out as
-// full-wave stores of 64 consecutive payloads: store(slot, value, drop) with
-// drop = kDropOffset for lanes past the run.
-// Bins go in blocks of 64, the pointers one per lane: a bin's pointer is read
-// with readlane and written back to its lane with a select.
-template <int R, int W, typename Store>
-__device__ __forceinline__ void place_chunk(const uint32_t (&lo)[R], const uint32_t (&span)[R],
-                                            const uint32_t (&payload)[R][W], int nbins, uint32_t* s_base,
-                                            uint32_t* s_stage, Store store) {
-    static_assert(W == 1 || W == 2, "one or two words per payload");
-    const uint32_t l = lane_id();
-    for (int b0 = 0; b0 < nbins; b0 += kWave) {
-        const uint32_t bl = (uint32_t)b0, bh = (uint32_t)b0 + kWave - 1u;
-        bool meets = false;
-#pragma unroll
-        for (int r = 0; r < R; ++r) meets |= lo[r] <= bh && lo[r] + span[r] >= bl;
-        if (!ballot(meets)) continue;  // uniform: nothing of the chunk in this block
-        const int nb = __builtin_amdgcn_readfirstlane(min(kWave, nbins - b0));
-        uint32_t vb = (int)l < nb ? s_base[b0 + l] : 0u;
-        for (int j = 0; j < nb; ++j) {
-            const uint32_t b = (uint32_t)(b0 + j);
-            uint32_t run = 0;  // payloads of this bin gathered so far (uniform)
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const bool cov = b - lo[r] <= span[r];
-                const uint64_t m = ballot(cov);
-                if (cov) {
-                    const uint32_t k = run + count_below(m);
-                    if constexpr (W == 1) {
-                        s_stage[k] = payload[r][0];
-                    } else {
-                        reinterpret_cast<uint2*>(s_stage)[k] = make_uint2(payload[r][0], payload[r][1]);
-                    }
-                }
-                run += (uint32_t)__popcll(m);
-            }
-            wave_lds_sync();
-            const uint32_t base = (uint32_t)__builtin_amdgcn_readlane((int)vb, j);
-            for (uint32_t q = 0; q < run; q += kWave) {  // uniform
-                const uint32_t i = q + l;
-                const uint32_t drop = i < run ? 0u : kDropOffset;
-                if constexpr (W == 1) {
-                    store(base + i, make_uint2(s_stage[min(i, (uint32_t)(R * kWave) - 1u)], 0u), drop);
-                } else {
-                    store(base + i, reinterpret_cast<const uint2*>(s_stage)[min(i, (uint32_t)(R * kWave) - 1u)],
-                          drop);
-                }
-            }
-            wave_lds_sync();  // the run is read before the next bin's gathers
-            vb = l == (uint32_t)j ? base + run : vb;
-        }
-        if ((int)l < nb) s_base[b0 + l] = vb;
     }
 }
 
@@ -276,54 +217,6 @@ __global__ __launch_bounds__(kLayoutThreads) void k_rp_layout(RpArgs a) {
     }
 }
 
-// A4: each chunk of records into the row lists.  Afterwards every row's
-// write pointer must stand where the next chunk's part of the row starts (or
-// at the row's end); otherwise the counts were inconsistent (error bit).
-__global__ __launch_bounds__(kRpThreads) void k_rp_place_rows(RpArgs a) {
-    extern __shared__ uint32_t s_mem[];
-    const int nbins = (int)a.tiles_y;
-    const int w = threadIdx.x / kWave;
-    const uint32_t l = lane_id();
-    uint32_t* s_stage = s_mem + (size_t)w * (nbins + 2 * kChunkA);
-    uint32_t* s_base = s_stage + 2 * kChunkA;
-    const int64_t n = (int64_t)*a.count;
-    const int64_t chunks = (n + kChunkA - 1) / kChunkA;
-    const int64_t c = (int64_t)blockIdx.x * kRpWaves + w;
-    const int64_t base = c * kChunkA;
-    if (base >= n) return;
-    uint32_t lo[kRoundsA], span[kRoundsA], ent[kRoundsA][2];
-#pragma unroll
-    for (int r = 0; r < kRoundsA; ++r) {
-        const int64_t i = base + r * kWave + l;
-        lo[r] = 0xFFFF0000u;  // unused slot: past every bin
-        span[r] = 0u;
-        ent[r][0] = ent[r][1] = 0u;
-        if (i < n) {
-            const RecSpan s = rec_span(a.rec[i], a.tiles_x, a.tiles_y);
-            lo[r] = s.y0;
-            span[r] = s.y1 - s.y0;
-            ent[r][0] = s.x0 | (s.x1 << 16);
-            ent[r][1] = s.gid;
-        }
-    }
-    for (int b = (int)l; b < nbins; b += kWave) s_base[b] = a.rowstart[b] + a.ha[(size_t)b * a.ha_stride + c];
-    wave_lds_sync();
-    const uint32_t limit = min(a.rowstart[nbins], (uint32_t)a.sum_h);
-    const __amdgpu_buffer_rsrc_t out =
-        __builtin_amdgcn_make_buffer_rsrc(a.rowent, 0, (int)(limit * sizeof(uint2)), (int)kBufferDword3);
-    // slots (below 2^28) times 8, plus a dropped lane's 2^31: below 2^32
-    place_chunk<kRoundsA, 2>(lo, span, ent, nbins, s_base, s_stage, [&](uint32_t slot, uint2 v, uint32_t drop) {
-        __builtin_amdgcn_raw_buffer_store_b64(int32x2_t{(int)v.x, (int)v.y}, out, (int)((slot << 3) + drop), 0,
-                                              0);
-    });
-    wave_lds_sync();
-    bool bad = false;
-    for (int b = (int)l; b < nbins; b += kWave) {
-        const uint32_t end = a.rowstart[b] + (c + 1 < chunks ? a.ha[(size_t)b * a.ha_stride + c + 1] : a.rowtot[b]);
-        bad |= s_base[b] != end;
-    }
-    if (bad) atomicOr(a.err, kErrRowPlace);
-}
 
 // Row and entry range of B chunk cb (false past the last chunk).
 __device__ __forceinline__ bool col_chunk(const RpArgs& a, int64_t cb, uint32_t& y, uint32_t& e0, uint32_t& e1) {
@@ -447,16 +340,18 @@ __host__ __device__ inline int col_blocks(int nbins) { return (nbins + kColBlock
 // covering lanes write their Gaussian index to the run in LDS, the others to
 // a dump slot of their own (a select of the address, not a branch); then the run goes out in
 // full-wave stores, lanes past its end given an offset the buffer drops.
-template <int R>
-__device__ __forceinline__ void place_bins(const uint32_t (&cm)[kColBatch], const uint32_t (&cg)[kColBatch], int nb,
+template <int R, int W>
+__device__ __forceinline__ void place_bins(const uint32_t (&cm)[kColBatch], const uint32_t (&cg)[kColBatch][W], int nb,
                                            uint32_t* stage, uint32_t* dump, uint32_t& vb,
                                            __amdgpu_buffer_rsrc_t out) {
+    static_assert(W == 1 || W == 2, "payloads of one or two words");
+    using u32x2 = uint32_t __attribute__((ext_vector_type(2)));
+    using lds_w = __attribute__((address_space(3))) typename std::conditional<W == 1, uint32_t, u32x2>::type;
     const uint32_t l = lane_id();
-    using lds_u32 = __attribute__((address_space(3))) uint32_t;
-    lds_u32* const st = (lds_u32*)stage;
-    lds_u32* const du = (lds_u32*)dump;
+    lds_w* const st = (lds_w*)stage;
+    lds_w* const du = (lds_w*)dump;
     for (int j = 0; j < nb; ++j) {
-        lds_u32* wr = st;  // the run's end (one pointer add per round)
+        lds_w* wr = st;  // the run's end (one pointer add per round)
 #pragma unroll
         for (int q = 0; q < R; ++q) {
             const bool cov = (cm[q] >> j) & 1u;
@@ -465,22 +360,31 @@ __device__ __forceinline__ void place_bins(const uint32_t (&cm)[kColBatch], cons
             // empty asm keeps the compiler from moving it under a branch)
             uint32_t rank = count_below(m);
             asm volatile("" : "+v"(rank));
-            lds_u32* dst = cov ? wr + rank : du + l;
-            *dst = cg[q];
+            lds_w* dst = cov ? wr + rank : du + l;
+            if constexpr (W == 1)
+                *dst = cg[q][0];
+            else
+                *dst = u32x2{cg[q][0], cg[q][1]};
             wr += __popcll(m);
         }
         const uint32_t run = (uint32_t)(wr - st);
         wave_lds_sync();
         const uint32_t base = (uint32_t)__builtin_amdgcn_readlane((int)vb, j);
-        // slots are below 2^29, so a kept offset is below 2^31 and the
-        // dropped lanes' 2^31 is past the buffer
-        const uint32_t voff = (base + l) << 2;
+        // slots are below 2^29 (one word) or 2^28 (two), so a kept offset is
+        // below 2^31 and the dropped lanes' 2^31 is past the buffer
+        const uint32_t voff = (base + l) * (uint32_t)(4 * W);
 #pragma unroll
         for (int t = 0; t < R; ++t) {
             if ((uint32_t)(t * kWave) < run) {  // uniform
-                const uint32_t v = st[t * kWave + l];
-                const uint32_t off = l < run - (uint32_t)(t * kWave) ? voff + (uint32_t)(t * kWave * 4) : kDropOffset;
-                __builtin_amdgcn_raw_buffer_store_b32((int)v, out, (int)off, 0, 0);
+                const uint32_t off =
+                    l < run - (uint32_t)(t * kWave) ? voff + (uint32_t)(t * kWave * 4 * W) : kDropOffset;
+                if constexpr (W == 1) {
+                    const uint32_t v = st[t * kWave + l];
+                    __builtin_amdgcn_raw_buffer_store_b32((int)v, out, (int)off, 0, 0);
+                } else {
+                    const u32x2 v = st[t * kWave + l];
+                    __builtin_amdgcn_raw_buffer_store_b64(int32x2_t{(int)v.x, (int)v.y}, out, (int)off, 0, 0);
+                }
             }
         }
         wave_lds_sync();  // the run is read before the next bin's gathers
@@ -550,33 +454,136 @@ void k_rp_place_cols(RpArgs a) {
             const uint32_t hn = min(cnt - h, (uint32_t)(kColBatch * kWave));
             const uint32_t rounds = (hn + kWave - 1) / kWave;
             uint32_t* stage = s_cg + h;
-            uint32_t cm[kColBatch], cg[kColBatch];  // columns of the block an entry covers (bit mask), Gaussian index
+            uint32_t cm[kColBatch], cg[kColBatch][1];  // columns of the block an entry covers (bit mask), Gaussian index
 #pragma unroll
             for (int q = 0; q < kColBatch; ++q) {
                 const uint32_t k = (uint32_t)(q * kWave) + l;
                 cm[q] = 0u;
-                cg[q] = 0u;
+                cg[q][0] = 0u;
                 if ((uint32_t)q < rounds && k < hn) {
                     const uint32_t c = s_cx[h + k];
                     cm[q] = ((2u << (c >> 4)) - 1u) << (c & 15u);
-                    cg[q] = stage[k];
+                    cg[q][0] = stage[k];
                 }
             }
             wave_lds_sync();
             switch (rounds) {
-                case 1: place_bins<1>(cm, cg, nb, stage, s_dump, vb, out); break;
-                case 2: place_bins<2>(cm, cg, nb, stage, s_dump, vb, out); break;
-                case 3: place_bins<3>(cm, cg, nb, stage, s_dump, vb, out); break;
-                case 4: place_bins<4>(cm, cg, nb, stage, s_dump, vb, out); break;
-                case 5: place_bins<5>(cm, cg, nb, stage, s_dump, vb, out); break;
-                case 6: place_bins<6>(cm, cg, nb, stage, s_dump, vb, out); break;
-                case 7: place_bins<7>(cm, cg, nb, stage, s_dump, vb, out); break;
-                default: place_bins<8>(cm, cg, nb, stage, s_dump, vb, out); break;
+                case 1: place_bins<1, 1>(cm, cg, nb, stage, s_dump, vb, out); break;
+                case 2: place_bins<2, 1>(cm, cg, nb, stage, s_dump, vb, out); break;
+                case 3: place_bins<3, 1>(cm, cg, nb, stage, s_dump, vb, out); break;
+                case 4: place_bins<4, 1>(cm, cg, nb, stage, s_dump, vb, out); break;
+                case 5: place_bins<5, 1>(cm, cg, nb, stage, s_dump, vb, out); break;
+                case 6: place_bins<6, 1>(cm, cg, nb, stage, s_dump, vb, out); break;
+                case 7: place_bins<7, 1>(cm, cg, nb, stage, s_dump, vb, out); break;
+                default: place_bins<8, 1>(cm, cg, nb, stage, s_dump, vb, out); break;
             }
         }
         if ((int)l < nb) {
             const uint32_t b = (uint32_t)b0 + l;
             const uint32_t end = last ? a.ranges[(size_t)y * nbins + b].y : a.hb[(size_t)(cb + 1) * nbins + b];
+            bad |= vb != end;
+        }
+    }
+    if (bad) atomicOr(a.err, kErrRowPlace);
+}
+
+
+// A4: each chunk of kChunkA records into the row lists, the way B3 places
+// row entries into tiles: one workgroup per chunk, one wave per block of
+// kColBlock tile rows, the records reaching the block compacted in chunk
+// order (rows clipped to the block as two 4-bit offsets), then placed row by
+// row with their 8-byte entries (x0 | x1 << 16, Gaussian index) gathered in
+// LDS and written as full-wave stores.  Afterwards every row's write pointer
+// must stand where the next chunk's part of the row starts (or at the row's
+// end), else error bit 32.
+constexpr int kRowWaveWords = 2 * kChunkA + kChunkA / 4 + 2 * kWave;  // entries (2 words), offsets (bytes), dump
+static_assert(kRoundsA <= kColBatch, "a chunk of records is one batch");
+
+__global__ __launch_bounds__(kColMaxWaves * kWave) __attribute__((amdgpu_waves_per_eu(8)))
+void k_rp_place_rows(RpArgs a) {
+    extern __shared__ uint32_t s_mem[];
+    const int nbins = (int)a.tiles_y;
+    const int nblk = col_blocks(nbins);
+    const int nw = (int)(blockDim.x / kWave);
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));  // uniform: LDS bases in SGPRs
+    const uint32_t l = lane_id();
+    uint32_t* s_cg = s_mem + (size_t)w * kRowWaveWords;              // compacted entries; then the run stage
+    uint8_t* s_cx = reinterpret_cast<uint8_t*>(s_cg + 2 * kChunkA);  // compacted offset | (last - offset) << 4
+    uint32_t* s_dump = s_cg + 2 * kChunkA + kChunkA / 4;            // two words per lane for uncovered writes
+    const int64_t n = (int64_t)*a.count;
+    const int64_t chunks = (n + kChunkA - 1) / kChunkA;
+    const int64_t c = blockIdx.x;
+    const int64_t base = c * kChunkA;
+    if (base >= n) return;  // uniform over the workgroup
+    uint32_t ey[kRoundsA], e0[kRoundsA], e1[kRoundsA];  // y0 | y1 << 16 (unused: y0 past every bin); the entry
+#pragma unroll
+    for (int r = 0; r < kRoundsA; ++r) {
+        const int64_t i = base + r * kWave + l;
+        ey[r] = 0x0000FFFFu;
+        e0[r] = e1[r] = 0u;
+        if (i < n) {
+            const RecSpan sp = rec_span(a.rec[i], a.tiles_x, a.tiles_y);
+            ey[r] = sp.y0 | (sp.y1 << 16);
+            e0[r] = sp.x0 | (sp.x1 << 16);
+            e1[r] = sp.gid;
+        }
+    }
+    const uint32_t limit = min(a.rowstart[nbins], (uint32_t)a.sum_h);
+    const __amdgpu_buffer_rsrc_t out =
+        __builtin_amdgcn_make_buffer_rsrc(a.rowent, 0, (int)(limit * sizeof(uint2)), (int)kBufferDword3);
+    bool bad = false;
+    for (int blk = w; blk < nblk; blk += nw) {
+        const int b0 = blk * kColBlock;
+        const int nb = min(kColBlock, nbins - b0);
+        const uint32_t bl = (uint32_t)b0, bh = (uint32_t)(b0 + nb - 1);
+        uint32_t cnt = 0;
+#pragma unroll
+        for (int r = 0; r < kRoundsA; ++r) {
+            const uint32_t y0 = ey[r] & 0xFFFFu, y1 = ey[r] >> 16;
+            const bool meets = y0 <= bh && y1 >= bl;
+            const uint64_t m = ballot(meets);
+            if (meets) {
+                const uint32_t k = cnt + count_below(m);
+                const uint32_t o0 = (y0 > bl ? y0 : bl) - bl, o1 = (y1 < bh ? y1 : bh) - bl;
+                s_cx[k] = (uint8_t)(o0 | ((o1 - o0) << 4));
+                s_cg[2 * k] = e0[r];
+                s_cg[2 * k + 1] = e1[r];
+            }
+            cnt += (uint32_t)__popcll(m);
+        }
+        // this block's rows start at the chunk's part of each row list
+        const uint32_t b = (uint32_t)b0 + l;
+        uint32_t vb = (int)l < nb ? a.rowstart[b] + a.ha[(size_t)b * a.ha_stride + c] : 0u;
+        if (cnt > 0) {  // uniform
+            wave_lds_sync();
+            const uint32_t rounds = (cnt + kWave - 1) / kWave;
+            uint32_t cm[kColBatch], cg[kColBatch][2];  // rows of the block an entry covers (bit mask), the entry
+#pragma unroll
+            for (int q = 0; q < kColBatch; ++q) {
+                const uint32_t k = (uint32_t)(q * kWave) + l;
+                cm[q] = 0u;
+                cg[q][0] = cg[q][1] = 0u;
+                if (q < kRoundsA && (uint32_t)q < rounds && k < cnt) {
+                    const uint32_t cx = s_cx[k];
+                    cm[q] = ((2u << (cx >> 4)) - 1u) << (cx & 15u);
+                    cg[q][0] = s_cg[2 * k];
+                    cg[q][1] = s_cg[2 * k + 1];
+                }
+            }
+            wave_lds_sync();  // the staged entries are the run stage from here
+            switch (rounds) {
+                case 1: place_bins<1, 2>(cm, cg, nb, s_cg, s_dump, vb, out); break;
+                case 2: place_bins<2, 2>(cm, cg, nb, s_cg, s_dump, vb, out); break;
+                case 3: place_bins<3, 2>(cm, cg, nb, s_cg, s_dump, vb, out); break;
+                case 4: place_bins<4, 2>(cm, cg, nb, s_cg, s_dump, vb, out); break;
+                case 5: place_bins<5, 2>(cm, cg, nb, s_cg, s_dump, vb, out); break;
+                case 6: place_bins<6, 2>(cm, cg, nb, s_cg, s_dump, vb, out); break;
+                case 7: place_bins<7, 2>(cm, cg, nb, s_cg, s_dump, vb, out); break;
+                default: place_bins<8, 2>(cm, cg, nb, s_cg, s_dump, vb, out); break;
+            }
+        }
+        if ((int)l < nb) {
+            const uint32_t end = a.rowstart[b] + (c + 1 < chunks ? a.ha[(size_t)b * a.ha_stride + c + 1] : a.rowtot[b]);
             bad |= vb != end;
         }
     }
@@ -631,7 +638,8 @@ hipError_t launch_row_place(const RowPlaceArgs& p, hipStream_t stream, hipEvent_
     // pointers and a staging area
     const size_t lds_rows = sizeof(uint32_t) * kRpWaves * (size_t)(p.tiles_y + 1);
     const size_t lds_cols = sizeof(uint32_t) * kRpWaves * (size_t)(p.tiles_x + 1);
-    const size_t lds_place_rows = sizeof(uint32_t) * kRpWaves * (size_t)(p.tiles_y + 2 * kChunkA);
+    const int row_waves = std::min(col_blocks((int)p.tiles_y), kColMaxWaves);
+    const size_t lds_place_rows = sizeof(uint32_t) * row_waves * (size_t)kRowWaveWords;
     const int col_waves = std::min(col_blocks((int)p.tiles_x), kColMaxWaves);
     const size_t lds_place_cols = sizeof(uint32_t) * col_waves * (size_t)kColWaveWords;
     hipLaunchKernelGGL(k_rp_count_rows, dim3(ga), dim3(kRpThreads), lds_rows, stream, a);
@@ -641,7 +649,8 @@ hipError_t launch_row_place(const RowPlaceArgs& p, hipStream_t stream, hipEvent_
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_rp_layout, dim3(1), dim3(kLayoutThreads), 0, stream, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rp_place_rows, dim3(ga), dim3(kRpThreads), lds_place_rows, stream, a);
+    hipLaunchKernelGGL(k_rp_place_rows, dim3((unsigned)sz.chunks_a), dim3(row_waves * kWave), lds_place_rows,
+                       stream, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (rows_done && (e = hipEventRecord(rows_done, stream)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_rp_count_cols, dim3(gb), dim3(kRpThreads), lds_cols, stream, a);
