@@ -346,6 +346,10 @@ typedef struct cds_server_opts {
     int32_t max_batch;          /* at most this many requests fused into one batched launch (1..max_slots);
                                    fewer when the queue is short or the batch reaches 16,383 tiles or 2^25 Gaussians */
     int64_t hbm_budget_bytes;   /* workspace budget for admitted requests; 0 = free HBM at create */
+    int32_t sort_variant;       /* how a batch's tile lists are ordered: 0 = default (4: row-wise placement
+                                   over the stacked tile grid; 2 for batches past its limits);
+                                   2 = radix-sorted tile keys (sort variant 2); the lists are the same */
+    int32_t reserved;
 } cds_server_opts;
 
 typedef struct cds_server_stats {

@@ -219,7 +219,8 @@ cds_status run_batch(cds_server* s, Workspace& w) {
     const uint64_t K = w.pinned[1];
     const uint64_t sum_h = stacked ? w.pinned[3] : 0;
     // the row-wise placement's limits (buffer offsets below 2^31 bytes)
-    const bool rowplace = stacked && K > 0 && K <= (uint64_t(1) << 29) && sum_h <= (uint64_t(1) << 28);
+    const bool rowplace = stacked && s->opts.sort_variant != 2 && K > 0 && K <= (uint64_t(1) << 29) &&
+                          sum_h <= (uint64_t(1) << 28);
     if (K > (uint64_t)kSortMaxCount) return fail(CDS_ERR_CAPACITY, "batch needs more than 2^30-1 tile keys");
     int64_t est = 0;
     for (const SrvRequest* r : w.reqs) {
@@ -485,6 +486,8 @@ cds_status cds_server_create(cds_ctx* ctx, const cds_server_opts* opts, cds_serv
     if (out) *out = nullptr;
     if (!ctx || !opts || !out) return fail(CDS_ERR_INVALID_ARG, "NULL argument");
     if (opts->max_slots < 1 || opts->max_slots > kMaxSlots) return fail(CDS_ERR_INVALID_ARG, "max_slots must be 1..64");
+    if (opts->sort_variant != 0 && opts->sort_variant != 2 && opts->sort_variant != 4)
+        return fail(CDS_ERR_INVALID_ARG, "server sort_variant must be 0, 2 or 4");
     if (opts->max_batch < 1 || opts->max_batch > opts->max_slots)
         return fail(CDS_ERR_INVALID_ARG, "max_batch must be 1..max_slots");
     if (opts->hbm_budget_bytes < 0) return fail(CDS_ERR_INVALID_ARG, "hbm_budget_bytes < 0");

@@ -79,7 +79,8 @@ CDS_NOALLOC_MAX_PAIRS = 1048576
 
 class CdsServerOpts(ctypes.Structure):
     _fields_ = [("max_slots", ctypes.c_int32), ("max_batch", ctypes.c_int32),
-                ("hbm_budget_bytes", ctypes.c_int64)]
+                ("hbm_budget_bytes", ctypes.c_int64), ("sort_variant", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class CdsServerStats(ctypes.Structure):

@@ -31,13 +31,14 @@ class Server:
     """A render server on its own library context (device memory from hipMalloc,
     so the scheduler thread never calls back into Python)."""
 
-    def __init__(self, device: int = 0, max_slots: int = 16, max_batch: int = 8, hbm_budget_bytes: int = 0):
+    def __init__(self, device: int = 0, max_slots: int = 16, max_batch: int = 8, hbm_budget_bytes: int = 0,
+                 sort_variant: int = 0):
         self.L = native.load()
         self.device = torch.device("cuda", device)
         ctx = P()
         check(self.L.cds_create(ctypes.byref(ctx), device, None))
         self._ctx = ctx
-        opts = native.CdsServerOpts(int(max_slots), int(max_batch), int(hbm_budget_bytes))
+        opts = native.CdsServerOpts(int(max_slots), int(max_batch), int(hbm_budget_bytes), int(sort_variant), 0)
         h = P()
         try:
             check(self.L.cds_server_create(ctx, ctypes.byref(opts), ctypes.byref(h)))

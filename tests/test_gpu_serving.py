@@ -70,13 +70,16 @@ def single_renders(R, scenes, reqs):
     return out
 
 
-@pytest.mark.parametrize("max_slots,max_batch", [(16, 8), (1, 1), (64, 64)])
-def test_served_equals_single_render(R, resident, max_slots, max_batch):
+@pytest.mark.parametrize("max_slots,max_batch,sort_variant", [(16, 8, 0), (1, 1, 0), (64, 64, 0), (16, 8, 2)])
+def test_served_equals_single_render(R, resident, max_slots, max_batch, sort_variant):
+    """Served images equal single renders bit for bit, with the batches' tile
+    lists by row-wise placement over the stacked tile grid (default) or by
+    radix-sorted stacked tile keys (sort variant 2)."""
     from paper_2509_25626_amd.serve import Server
     _, scenes = resident
     reqs = make_requests(11 + max_batch, 24, len(scenes))
     ref = single_renders(R, scenes, reqs)
-    with Server(0, max_slots=max_slots, max_batch=max_batch) as srv:
+    with Server(0, max_slots=max_slots, max_batch=max_batch, sort_variant=sort_variant) as srv:
         ids = [srv.add_scene(s) for s in scenes]
         got = serve_all(srv, ids, reqs)
         st = srv.stats()
@@ -174,6 +177,11 @@ def test_invalid_requests(resident):
         assert ei.value.status == native.CDS_ERR_INVALID_ARG
         with pytest.raises(native.CdsError):
             srv.poll(12345)
+    with pytest.raises(native.CdsError) as ei:
+        Server(0, max_slots=2, max_batch=2, sort_variant=3)
+    assert ei.value.status == native.CDS_ERR_INVALID_ARG
+    with Server(0, max_slots=2, max_batch=2) as srv:
+        sid = srv.add_scene(scenes[0])
         t, _ = srv.submit(sid, S.orbit_camera(64, 64))
         srv.drain()
         assert srv.poll(t)[0]
