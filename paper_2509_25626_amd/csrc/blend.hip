@@ -133,8 +133,12 @@ __device__ __forceinline__ uint32_t splat_id(uint32_t id, int64_t n, uint32_t* e
 // One 16x16 tile: stage its sorted splats through LDS in batches and blend
 // each pixel front to back.  Shared by the single-render kernel and the
 // persistent batched kernel so a request renders bit-identically in both.
-// Every thread of the workgroup must call it (it contains barriers).
-template <int PPT, bool kDepth = false>
+// Every thread of the workgroup must call it (it contains barriers).  kU
+// candidate splats are taken per step: their alphas do not depend on each
+// other (only the accumulation is sequential), which shortens the chain of
+// dependent instructions a wave walks through a long list; the accumulation
+// order, and so every result bit, does not depend on kU.
+template <int PPT, bool kDepth = false, int kU = 2>
 __device__ __forceinline__ void blend_tile(int tx, int ty, int width, int height, uint2 range,
                                            const uint32_t* __restrict__ point_list, int64_t n, uint32_t* err,
                                            const float2* __restrict__ mean2d,
@@ -192,12 +196,33 @@ __device__ __forceinline__ void blend_tile(int tx, int ty, int width, int height
         }
         int visited = 0;
         bool wave_done = false;
+        // the accumulation of one splat into a pixel (front to back, in list order)
+        const auto accumulate = [&](int p, int j, float alpha, const float4& f) {
+            const float test_T = T[p] * (1.0f - alpha);
+            if (test_T < kTMin) {
+                done[p] = true;
+            } else {
+                const float wgt = alpha * T[p];
+                C0[p] = fmaf(f.y, wgt, C0[p]);
+                C1[p] = fmaf(f.z, wgt, C1[p]);
+                C2[p] = fmaf(f.w, wgt, C2[p]);
+                if constexpr (kDepth) D[p] = fmaf(s_d[j], wgt, D[p]);
+                T[p] = test_T;
+                last[p] = (uint32_t)(base + j + 1);
+            }
+        };
         for (int q = 0; q < kBatch / kWave && !wave_done; ++q) {
             uint64_t m = cand[q];
             while (m) {
-            const int j = q * kWave + __builtin_ctzll(m);
-            m &= m - 1;
-            if ((visited++ & 31) == 0) {
+            int js[kU];
+            bool has[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                has[u] = m != 0;  // uniform
+                js[u] = has[u] ? q * kWave + __builtin_ctzll(m) : js[0];
+                if (has[u]) m &= m - 1;
+            }
+            if ((visited++ & 15) == 0) {
                 int live = 0;
 #pragma unroll
                 for (int p = 0; p < PPT; ++p) live |= done[p] ? 0 : 1;
@@ -206,32 +231,29 @@ __device__ __forceinline__ void blend_tile(int tx, int ty, int width, int height
                     break;
                 }
             }
-            const double4 q = s_q[j];
-            const double c2 = s_c[j];
-            const float4 f = s_f[j];
-            const double dx = q.x - fpx;
-            const double adx2 = (q.z * dx) * dx;
-            const double bdx = q.w * dx;
+            double adx2[kU], bdx[kU], cc[kU], qy[kU];
+            float4 fs[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const double4 qq = s_q[js[u]];
+                cc[u] = s_c[js[u]];
+                fs[u] = s_f[js[u]];
+                const double dx = qq.x - fpx;
+                adx2[u] = (qq.z * dx) * dx;
+                bdx[u] = qq.w * dx;
+                qy[u] = qq.y;
+            }
             // alpha and the skip test without branches; one branch around the
             // (mostly skipped) accumulation
 #pragma unroll
             for (int p = 0; p < PPT; ++p) {
-                float alpha, G;
-                const bool hit = splat_alpha(adx2, bdx, c2, q.y - fpy[p], f.x, alpha, G) && !done[p];
-                if (hit) {
-                    const float test_T = T[p] * (1.0f - alpha);
-                    if (test_T < kTMin) {
-                        done[p] = true;
-                    } else {
-                        const float wgt = alpha * T[p];
-                        C0[p] = fmaf(f.y, wgt, C0[p]);
-                        C1[p] = fmaf(f.z, wgt, C1[p]);
-                        C2[p] = fmaf(f.w, wgt, C2[p]);
-                        if constexpr (kDepth) D[p] = fmaf(s_d[j], wgt, D[p]);
-                        T[p] = test_T;
-                        last[p] = (uint32_t)(base + j + 1);
-                    }
-                }
+                float alpha[kU], G[kU];
+                bool ok[kU];
+#pragma unroll
+                for (int u = 0; u < kU; ++u) ok[u] = splat_alpha(adx2[u], bdx[u], cc[u], qy[u] - fpy[p], fs[u].x, alpha[u], G[u]);
+#pragma unroll
+                for (int u = 0; u < kU; ++u)
+                    if (has[u] && ok[u] && !done[p]) accumulate(p, js[u], alpha[u], fs[u]);
             }
             }
         }
@@ -253,7 +275,7 @@ __device__ __forceinline__ void blend_tile(int tx, int ty, int width, int height
     }
 }
 
-template <int PPT, bool kDepth>
+template <int PPT, bool kDepth, int kU = 2>
 __global__ __launch_bounds__(256 / PPT) void k_blend(BlendArgs a, uint32_t per_xcd) {
     __shared__ double4 s_q[kBatch];
     __shared__ double s_c[kBatch];
@@ -263,7 +285,7 @@ __global__ __launch_bounds__(256 / PPT) void k_blend(BlendArgs a, uint32_t per_x
     const uint32_t tile = xcd_band(blockIdx.x, per_xcd);
     if (tile >= (uint32_t)(a.tiles_x * a.tiles_y)) return;  // whole block: padding
     const int tx = (int)(tile % (uint32_t)a.tiles_x), ty = (int)(tile / (uint32_t)a.tiles_x);
-    blend_tile<PPT, kDepth>(tx, ty, a.width, a.height, a.ranges[tile], a.point_list, a.n, a.err, a.mean2d,
+    blend_tile<PPT, kDepth, kU>(tx, ty, a.width, a.height, a.ranges[tile], a.point_list, a.n, a.err, a.mean2d,
                             a.conic_opacity,
                             a.rgb, a.bg[0], a.bg[1], a.bg[2], a.out_rgb, a.out_T, a.out_ncontrib, s_q, s_c, s_f,
                             s_b, a.depth_bits, a.out_invdepth, s_d);
@@ -699,8 +721,15 @@ hipError_t launch_blend(const BlendArgs& a, int variant, hipStream_t stream) {
     }
     switch (variant) {
         case 1:
-            if (depth) hipLaunchKernelGGL((k_blend<1, true>), grid, dim3(256), 0, stream, a, per);
-            else hipLaunchKernelGGL((k_blend<1, false>), grid, dim3(256), 0, stream, a, per);
+            // with fewer tiles than four per compute unit a wave has its SIMD
+            // to itself: four candidates per step hide more of its latency
+            if (tiles < 4 * (int64_t)device_cus()) {
+                if (depth) hipLaunchKernelGGL((k_blend<1, true, 4>), grid, dim3(256), 0, stream, a, per);
+                else hipLaunchKernelGGL((k_blend<1, false, 4>), grid, dim3(256), 0, stream, a, per);
+            } else {
+                if (depth) hipLaunchKernelGGL((k_blend<1, true>), grid, dim3(256), 0, stream, a, per);
+                else hipLaunchKernelGGL((k_blend<1, false>), grid, dim3(256), 0, stream, a, per);
+            }
             break;
         case 4:
             if (depth) hipLaunchKernelGGL((k_blend<4, true>), grid, dim3(64), 0, stream, a, per);
