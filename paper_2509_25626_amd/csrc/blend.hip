@@ -471,7 +471,7 @@ __global__ __launch_bounds__(256 / PPT) void k_blend_batch(const BatchItem* __re
 //   dL/dalpha_i = T_i (rgb_i - S_i) . dL/dC,   S_{i-1} = alpha_i rgb_i + (1 - alpha_i) S_i
 // alpha = min(0.99, o G): when unclamped dalpha/do = G and dalpha/dpower = alpha.
 // Per-splat sums over the wave are reduced with cross-lane shuffles and
-// added to the per-Gaussian 2D gradients ([n][9]) with atomics.  A wave
+// added to the per-Gaussian 2D gradient sums ([n][kGrad2d]) with atomics.  A wave
 // visits only the splats whose box meets its pixels (as in the forward
 // pass): the others contribute nothing.
 template <int PPT, bool kDepth>
@@ -564,62 +564,79 @@ __global__ __launch_bounds__(256 / PPT) void k_blend_bwd(BlendBwdArgs a, uint32_
             const double dx = q.x - fpx;
             const double adx2 = (q.z * dx) * dx;
             const double bdx = q.w * dx;
-            const float dxf = (float)dx;
-            float gmx = 0.f, gmy = 0.f, gA = 0.f, gB = 0.f, gC = 0.f, go = 0.f, gr = 0.f, gg = 0.f,
-                  gb = 0.f, gd = 0.f;
             const float invd = kDepth ? s_d[k] : 0.0f;
+            // Per-lane sums over the lane's pixels (one column, so dx is
+            // common): sp = sum dL/dpower, spy and spyy its dy and dy^2
+            // moments; the mean and conic gradients are linear in these and
+            // dx (kGrad2d).  A pixel the splat does not
+            // reach takes alpha = 0, which leaves T and the colours behind it
+            // unchanged and makes every term zero, so no pixel branches.
+            float sp = 0.f, spy = 0.f, spyy = 0.f, go = 0.f, gr = 0.f, gg = 0.f, gb = 0.f, gd = 0.f;
             bool any = false;
 #pragma unroll
             for (int p = 0; p < PPT; ++p) {
-                if ((uint32_t)j >= last[p]) continue;
                 const double dy = q.y - fpy[p];
                 float alpha, G;
-                if (!splat_alpha(adx2, bdx, c2, dy, f.x, alpha, G)) continue;
-                any = true;
-                const float dyf = (float)dy;
-                const float one_m = 1.0f - alpha;
-                T[p] = T[p] * __builtin_amdgcn_rcpf(one_m);  // 1 ulp; alpha <= 0.99
+                const bool hit = splat_alpha(adx2, bdx, c2, dy, f.x, alpha, G) && (uint32_t)j < last[p];
+                any |= hit;
+                const float al = hit ? alpha : 0.0f;
+                const float one_m = 1.0f - al;
+                const float Tr = T[p] * __builtin_amdgcn_rcpf(one_m);  // 1 ulp; alpha <= 0.99
+                T[p] = hit ? Tr : T[p];
                 const float Tp = T[p];
                 float dLda = Tp * ((f.y - S0[p]) * D0[p] + (f.z - S1[p]) * D1[p] +
                                    (f.w - S2[p]) * D2[p]);
-                S0[p] = alpha * f.y + one_m * S0[p];
-                S1[p] = alpha * f.z + one_m * S1[p];
-                S2[p] = alpha * f.w + one_m * S2[p];
-                const float wgt = alpha * Tp;
-                gr += wgt * D0[p];
-                gg += wgt * D1[p];
-                gb += wgt * D2[p];
+                S0[p] = al * f.y + one_m * S0[p];
+                S1[p] = al * f.z + one_m * S1[p];
+                S2[p] = al * f.w + one_m * S2[p];
+                const float wgt = al * Tp;
+                // the first pixel starts each sum (no addition to zero)
+                auto acc = [p](float& s, float v) { s = p == 0 ? v : s + v; };
+                acc(gr, wgt * D0[p]);
+                acc(gg, wgt * D1[p]);
+                acc(gb, wgt * D2[p]);
                 if constexpr (kDepth) {
                     dLda += Tp * (invd - Sd[p]) * Dd[p];
-                    Sd[p] = alpha * invd + one_m * Sd[p];
-                    gd += wgt * Dd[p];
+                    Sd[p] = al * invd + one_m * Sd[p];
+                    acc(gd, wgt * Dd[p]);
                 }
-                if (!(f.x * G > kAlphaMax)) {
-                    go += dLda * G;
-                    const float dLdp = dLda * alpha;
-                    // power = (A' dx^2 + B' dx dy + C' dy^2) / log2(e), dx = mean_x - pixel_x
-                    gmx += dLdp * (2.0f * (float)q.z * dxf + (float)q.w * dyf);
-                    gmy += dLdp * (2.0f * (float)c2 * dyf + (float)q.w * dxf);
-                    gA += dLdp * (-0.5f * dxf * dxf);
-                    gB += dLdp * (-dxf * dyf);
-                    gC += dLdp * (-0.5f * dyf * dyf);
-                }
+                const bool unclamped = hit && !(f.x * G > kAlphaMax);
+                acc(go, unclamped ? dLda * G : 0.0f);
+                const float dLdp = unclamped ? dLda * alpha : 0.0f;
+                const float dyf = (float)dy;
+                const float e = dLdp * dyf;
+                acc(sp, dLdp);
+                acc(spy, e);
+                acc(spyy, e * dyf);
             }
             if (__any(any)) {
-                // nine wave sums: eight scattered over lane groups, one full;
-                // each Gaussian's nine gradients are contiguous, so one atomic
-                // instruction covers them
-                const float v8[8] = {gmx * kLn2, gmy * kLn2, gA, gB, gC, go, gr, gg};
+                // nine (ten) wave sums: eight scattered over lane groups, the
+                // rest full; each Gaussian's sums are contiguous, so a single
+                // atomic instruction adds them all (lanes 8i: sum i, lane 1:
+                // sum 8, lane 2: sum 9).  One instruction rather than two per
+                // visit matters: the second, single-lane one cost 0.2 of the
+                // kernel's time.
+                const float dxf = (float)dx;
+                const float spx = sp * dxf;
+                const float v8[8] = {spx, spy, spx * dxf, spy * dxf, spyy, go, gr, gg};
                 const float s8 = wave_reduce_scatter8(v8);
                 const float sb = wave_sum_dpp(gb);
                 const uint32_t l = lane_id();
-                float* g = a.grad2d + (size_t)s_id[k] * kGrad2d;
-                if ((l & 7u) == 0) atomicAdd(g + (l >> 3), s8);
-                if (l == 0) atomicAdd(g + 8, sb);
+                float v = s8;
+                uint32_t slot = l >> 3;
+                if (l == 1) {
+                    v = sb;
+                    slot = 8;
+                }
                 if constexpr (kDepth) {
                     const float sd = wave_sum_dpp(gd);
-                    if (l == 0) atomicAdd(g + 9, sd);
+                    if (l == 2) {
+                        v = sd;
+                        slot = 9;
+                    }
                 }
+                if ((l & 7u) == 0 || l == 1 || (kDepth && l == 2))
+                    atomicAdd(a.grad2d + (size_t)s_id[k] * kGrad2d + slot, v);
             }
             }
         }

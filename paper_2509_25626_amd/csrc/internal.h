@@ -395,8 +395,11 @@ hipError_t launch_blend_batch(const BatchItem* items, int nitems, int64_t total_
                               const float4* conic_opacity, const float4* rgb, uint32_t* counter, int grid,
                               uint32_t* err, hipStream_t stream);
 
-// Per-Gaussian 2D gradients of the backward pass, one row per Gaussian:
-// mean x, mean y, conic A, B, C, opacity, r, g, b, 1 / depth.
+// Per-Gaussian 2D gradient sums of the backward pass, one row per Gaussian:
+// the sums over its pixels of dL/dpower times dx, dy, dx^2, dx dy and dy^2
+// (dx, dy = 2D mean - pixel; power = the exponent of G), from which the
+// backward preprocessing forms the 2D mean and conic gradients; then
+// dL/dopacity, dL/d(r, g, b) and dL/d(1 / depth).
 constexpr int kGrad2d = 10;
 
 struct BlendBwdArgs {

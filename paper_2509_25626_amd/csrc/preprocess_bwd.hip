@@ -72,11 +72,6 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(ProjParams P, SceneParam
     auto put = [live](float* dst, double v) { *dst = live ? (float)v : 0.0f; };
     const uint8_t flags = A.clamp_flags[i];
     const float* G2 = A.grad2d + (size_t)i * kGrad2d;
-    const double gmx = G2[0], gmy = G2[1];
-    const double gA = G2[2], gB = G2[3], gC = G2[4];
-    const double go = G2[5];
-    double grgb[3] = {G2[6], G2[7], G2[8]};
-    const double ginvd = G2[9];  // dL / d(1 / depth), depth = t_cam z
 
     // ---- recompute the forward projection (float64)
     const double m0 = S.means[i], m1 = S.means[n + i], m2 = S.means[2 * n + i];
@@ -118,7 +113,22 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(ProjParams P, SceneParam
     const double b = MS[0] * M[3] + MS[1] * M[4] + MS[2] * M[5];
     const double c = MS[3] * M[3] + MS[4] * M[4] + MS[5] * M[5] + 0.3;
     const double det = a * c - b * b;
-    const double id2 = 1.0 / (det * det);
+    const double idet = 1.0 / det;
+    const double id2 = idet * idet;
+    // sums over the splat's pixels of dL/dpower times dx, dy, dx^2, dx dy, dy^2
+    // (dx, dy = 2D mean - pixel)
+    const double s_x = G2[0], s_y = G2[1], s_xx = G2[2], s_xy = G2[3], s_yy = G2[4];
+    // power = -(a' dx^2 + 2 b' dx dy + c' dy^2) / 2 with the conic (a', b', c') = (c, -b, a) / det:
+    // dpower/dmean = -(a' dx + b' dy, b' dx + c' dy), dpower/d(a', b', c') = -(dx^2 / 2, dx dy, dy^2 / 2)
+    const double gmx = -(c * s_x - b * s_y) * idet;
+    const double gmy = -(a * s_y - b * s_x) * idet;
+    const double gA = -0.5 * s_xx, gB = -s_xy, gC = -0.5 * s_yy;
+    // 2D mean = (fx tx / tz, fy ty / tz) + principal point
+    const double itz2 = itz * itz, itz3 = itz2 * itz;
+    double gt0 = gmx * P.fx * itz;
+    double gt1 = gmy * P.fy * itz;
+    double gt2 = -gmx * P.fx * tx * itz2 - gmy * P.fy * ty * itz2;
+    gt2 += -(double)G2[9] * itz2;  // dL / d(1 / depth), depth = t_cam z
 
     // ---- conic (c, -b, a)/det -> (a, b, c)
     const double ga = (gA * (-c * c) + gB * (b * c) + gC * (-b * b)) * id2;
@@ -140,19 +150,11 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(ProjParams P, SceneParam
     for (int r = 0; r < 2; ++r)
         for (int k = 0; k < 3; ++k)
             gJ[3 * r + k] = gM[3 * r] * R[3 * k] + gM[3 * r + 1] * R[3 * k + 1] + gM[3 * r + 2] * R[3 * k + 2];
-    double gt0 = 0.0, gt1 = 0.0, gt2 = 0.0;
-    const double itz2 = itz * itz, itz3 = itz2 * itz;
     gt2 += gJ[0] * (-P.fx * itz2) + gJ[4] * (-P.fy * itz2);
     if (!clx) { gt0 += gJ[2] * (-P.fx * itz2); gt2 += gJ[2] * (2.0 * P.fx * tx * itz3); }
     else      { gt2 += gJ[2] * (P.fx * ux * itz2); }
     if (!cly) { gt1 += gJ[5] * (-P.fy * itz2); gt2 += gJ[5] * (2.0 * P.fy * ty * itz3); }
     else      { gt2 += gJ[5] * (P.fy * uy * itz2); }
-    // 2D mean
-    gt0 += gmx * P.fx * itz;
-    gt1 += gmy * P.fy * itz;
-    gt2 += -gmx * P.fx * tx * itz2 - gmy * P.fy * ty * itz2;
-    // expected inverse depth
-    gt2 += -ginvd * itz2;
 
     // ---- Sigma = Rq diag(s2) Rq^T
     double GR[9];  // gSig Rq
@@ -179,12 +181,14 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(ProjParams P, SceneParam
     for (int k = 0; k < 4; ++k) put(&A.g_quats[k * n + i], (gq[k] - q[k] * dot) * iqn);
 
     // ---- opacity
+    const double go = G2[5];
     const double o = 1.0 / (1.0 + exp(-(double)S.opacity_logits[i]));
     put(&A.g_opacity_logits[i], go * o * (1.0 - o));
 
     // ---- colour
     double gm[3] = {0.0, 0.0, 0.0};
     {
+        double grgb[3] = {G2[6], G2[7], G2[8]};
         for (int ch = 0; ch < 3; ++ch)
             if (flags & (1u << ch)) grgb[ch] = 0.0;
         double v[3] = {m0 - P.campos[0], m1 - P.campos[1], m2 - P.campos[2]};
