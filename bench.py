@@ -309,10 +309,11 @@ class Bench:
         self.out = (torch.empty((3, H, W), device=self.dev), torch.empty((H, W), device=self.dev),
                     torch.empty((H, W), dtype=torch.int32, device=self.dev))
 
-    def fwd(self, fr, timing=False):
+    def fwd(self, fr, timing=False, for_backward=False):
         a = self.args
         return self.R.forward(self.scene, self.cam, frame=fr, blend_variant=a.blend_variant, out=self.out,
-                              timing=timing, sort_variant=a.sort_variant, sort_algo=a.sort_algo)
+                              timing=timing, sort_variant=a.sort_variant, sort_algo=a.sort_algo,
+                              for_backward=for_backward)
 
     @staticmethod
     def _accumulate(acc, fr):
@@ -358,7 +359,7 @@ class Bench:
         loss = torch.empty(1, device=self.dev)
 
         def step(fr, timing=False):
-            rgb, T, nc, _ = self.fwd(fr, timing)
+            rgb, T, nc, _ = self.fwd(fr, timing, for_backward=True)
             self.R.l1_loss_grad(rgb, target, dl, loss)
             self.R.backward(fr, self.scene, self.cam, T, nc, dl, grads)
 

@@ -110,6 +110,11 @@ typedef struct cds_camera {
 #define CDS_OPT_STAGE_TIMING 1u      /* record HIP events around every stage (forward and backward) */
 #define CDS_OPT_SORT_ONESWEEP 2u      /* radix-sort passes by decoupled look-back (default: by size) */
 #define CDS_OPT_SORT_REDUCE_SCAN 4u   /* radix-sort passes by reduce-then-scan (default: by size) */
+#define CDS_OPT_KEEP_FOR_BACKWARD 8u  /* the render will be differentiated: with SH degree > 0 the forward
+                                         also stores per Gaussian the colour's derivative with respect to
+                                         the view direction (36 bytes, in the frame), which the backward
+                                         then reads instead of the SH coefficients (up to 192 bytes);
+                                         the gradients are the same either way, up to rounding */
 typedef struct cds_render_opts {
     uint32_t flags;         /* CDS_OPT_* bits */
     int32_t blend_variant;  /* 0 = default (2 pixels per thread; 1 below ten tiles per compute unit);

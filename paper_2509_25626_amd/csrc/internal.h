@@ -41,6 +41,9 @@ struct SplatBuffers {
     uint2* rect;
     uint32_t* touched;
     uint8_t* clamp_flags;
+    // [9][n] or null: d rgb_ch / d dir_c at 3 ch + c (dir = unit view
+    // direction), written for renders kept for the backward pass (SH degree > 0)
+    float* jac = nullptr;
 };
 
 struct GradBuffers2D {  // [9][n]: mean x, mean y, conic A, B, C, opacity, r, g, b
@@ -425,6 +428,7 @@ struct PreBwdArgs {
     const int32_t* radius;
     const uint8_t* clamp_flags;
     const float* grad2d;  // [n][kGrad2d]
+    const float* jac = nullptr;  // SplatBuffers::jac of the forward render, or null (read the SH)
     float* g_means;
     float* g_log_scales;
     float* g_quats;

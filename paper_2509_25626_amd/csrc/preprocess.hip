@@ -56,10 +56,14 @@ __device__ __forceinline__ void sh_basis_f32(float x, float y, float z, int degr
 
 // colour = sum_k basis[k] sh[k] over the kNB coefficients, each channel
 // accumulated in coefficient order; all coefficient loads are issued before
-// the first product
+// the first product.  With J (a render kept for the backward pass), also the
+// colour's derivative with respect to the unit view direction (x, y, z):
+// J[3 ch + c] = sum_k sh[k][ch] dY_k/ddir_c, from the derivatives of the
+// basis polynomials above.
 template <int kNB>
 __device__ __forceinline__ void sh_colour(const float* __restrict__ sh, int64_t n, int64_t i, const float* basis,
-                                          float col[3]) {
+                                          float col[3], float x = 0.f, float y = 0.f, float z = 0.f,
+                                          float* J = nullptr) {
     float v[kNB][3];
 #pragma unroll
     for (int k = 0; k < kNB; ++k)
@@ -69,9 +73,44 @@ __device__ __forceinline__ void sh_colour(const float* __restrict__ sh, int64_t 
     for (int k = 0; k < kNB; ++k)
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) col[ch] += basis[k] * v[k][ch];
+    if (!J) return;  // uniform
+#pragma unroll
+    for (int e = 0; e < 9; ++e) J[e] = 0.0f;
+    // add coefficient k's term d * dY_k/ddir_c to every channel
+    const auto add = [&](int k, int c, float d) {
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) J[3 * ch + c] += v[k][ch] * d;
+    };
+    if constexpr (kNB > 1) {
+        add(1, 1, -kY1);
+        add(2, 2, kY1);
+        add(3, 0, -kY1);
+    }
+    if constexpr (kNB > 4) {
+        add(4, 0, kY2a * y); add(4, 1, kY2a * x);
+        add(5, 1, -kY2a * z); add(5, 2, -kY2a * y);
+        add(6, 0, -2.0f * kY2b * x); add(6, 1, -2.0f * kY2b * y); add(6, 2, 4.0f * kY2b * z);
+        add(7, 0, -kY2a * z); add(7, 2, -kY2a * x);
+        add(8, 0, 2.0f * kY2c * x); add(8, 1, -2.0f * kY2c * y);
+    }
+    if constexpr (kNB > 9) {
+        const float xx = x * x, yy = y * y, zz = z * z;
+        add(9, 0, -6.0f * kY3a * x * y); add(9, 1, -3.0f * kY3a * (xx - yy));
+        add(10, 0, kY3b * y * z); add(10, 1, kY3b * x * z); add(10, 2, kY3b * x * y);
+        add(11, 0, 2.0f * kY3c * x * y); add(11, 1, -kY3c * (4.0f * zz - xx - 3.0f * yy));
+        add(11, 2, -8.0f * kY3c * y * z);
+        add(12, 0, -6.0f * kY3d * x * z); add(12, 1, -6.0f * kY3d * y * z);
+        add(12, 2, kY3d * (6.0f * zz - 3.0f * xx - 3.0f * yy));
+        add(13, 0, -kY3c * (4.0f * zz - 3.0f * xx - yy)); add(13, 1, 2.0f * kY3c * x * y);
+        add(13, 2, -8.0f * kY3c * x * z);
+        add(14, 0, 2.0f * kY3e * x * z); add(14, 1, -2.0f * kY3e * y * z); add(14, 2, kY3e * (xx - yy));
+        add(15, 0, -3.0f * kY3a * (xx - yy)); add(15, 1, 6.0f * kY3a * x * y);
+    }
 }
 
-// Gaussian i of a scene with P.n Gaussians; outputs go to slot `o` of O.
+// Gaussian i of a scene with P.n Gaussians; outputs go to slot `o` of O
+// (with kJac also the colour's direction derivative, planes O.jac[9][n]).
+template <bool kJac = false>
 __device__ __forceinline__ void preprocess_one(const ProjParams& P, const SceneParams& S, int64_t i,
                                                const SplatBuffers& O, int64_t o) {
     const int64_t n = P.n;
@@ -187,13 +226,21 @@ __device__ __forceinline__ void preprocess_one(const ProjParams& P, const SceneP
     double dx = m0 - P.campos[0], dy = m1 - P.campos[1], dz = m2 - P.campos[2];
     const double dl = sqrt(dx * dx + dy * dy + dz * dz);
     float basis[16];
-    sh_basis_f32((float)(dx / dl), (float)(dy / dl), (float)(dz / dl), P.sh_degree, basis);
+    const float ux = (float)(dx / dl), uy = (float)(dy / dl), uz = (float)(dz / dl);
+    sh_basis_f32(ux, uy, uz, P.sh_degree, basis);
     float col[3] = {0.f, 0.f, 0.f};
+    float J[9];
+    float* const jp = kJac ? J : nullptr;
     switch (P.sh_degree) {  // uniform
         case 0: sh_colour<1>(S.sh, n, i, basis, col); break;
-        case 1: sh_colour<4>(S.sh, n, i, basis, col); break;
-        case 2: sh_colour<9>(S.sh, n, i, basis, col); break;
-        default: sh_colour<16>(S.sh, n, i, basis, col); break;
+        case 1: sh_colour<4>(S.sh, n, i, basis, col, ux, uy, uz, jp); break;
+        case 2: sh_colour<9>(S.sh, n, i, basis, col, ux, uy, uz, jp); break;
+        default: sh_colour<16>(S.sh, n, i, basis, col, ux, uy, uz, jp); break;
+    }
+    if constexpr (kJac) {
+        if (P.sh_degree > 0)  // uniform
+#pragma unroll
+            for (int e = 0; e < 9; ++e) O.jac[(int64_t)e * n + o] = J[e];
     }
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
@@ -215,10 +262,11 @@ __device__ __forceinline__ void preprocess_one(const ProjParams& P, const SceneP
     O.clamp_flags[o] = flags;
 }
 
+template <bool kJac>
 __global__ __launch_bounds__(256) void k_preprocess(ProjParams P, SceneParams S, SplatBuffers O) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= P.n) return;
-    preprocess_one(P, S, i, O, i);
+    preprocess_one<kJac>(P, S, i, O, i);
 }
 
 // Several scenes at once: global index g over the concatenated scenes of a
@@ -255,7 +303,10 @@ hipError_t launch_preprocess(const ProjParams& p, const SceneParams& s, const Sp
     if (p.n == 0) return hipSuccess;
     const int nt = 256;
     const int64_t nb = (p.n + nt - 1) / nt;
-    hipLaunchKernelGGL(k_preprocess, dim3((unsigned)nb), dim3(nt), 0, stream, p, s, out);
+    if (out.jac && p.sh_degree > 0)
+        hipLaunchKernelGGL(k_preprocess<true>, dim3((unsigned)nb), dim3(nt), 0, stream, p, s, out);
+    else
+        hipLaunchKernelGGL(k_preprocess<false>, dim3((unsigned)nb), dim3(nt), 0, stream, p, s, out);
     return hipGetLastError();
 }
 

@@ -46,6 +46,7 @@ __device__ __forceinline__ void sh_weighted_grad64(double x, double y, double z,
            + k3e * (xx - yy) * w[14];
 }
 
+template <bool kJac>
 __global__ __launch_bounds__(256) void k_preprocess_bwd(ProjParams P, SceneParams S, PreBwdArgs A) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= P.n) return;
@@ -205,12 +206,22 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(ProjParams P, SceneParam
 #pragma unroll
                 for (int ch = 0; ch < 3; ++ch) {
                     put(&A.g_sh[((int64_t)k * 3 + ch) * n + i], Y[k] * grgb[ch]);
-                    wsum[k] += (double)cf[(int64_t)ch * n] * grgb[ch];
+                    if constexpr (!kJac) wsum[k] += (double)cf[(int64_t)ch * n] * grgb[ch];
                 }
             }
         }
+        // dL/ddir = sum_ch dL/drgb_ch drgb_ch/ddir: from the forward's
+        // derivative (kJac) or from the coefficients
         double gdir[3];
-        sh_weighted_grad64(dx, dy, dz, wsum, gdir);
+        if constexpr (kJac) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                gdir[c] = grgb[0] * (double)A.jac[(int64_t)c * n + i] +
+                          grgb[1] * (double)A.jac[(int64_t)(3 + c) * n + i] +
+                          grgb[2] * (double)A.jac[(int64_t)(6 + c) * n + i];
+        } else {
+            sh_weighted_grad64(dx, dy, dz, wsum, gdir);
+        }
         const double dd = dx * gdir[0] + dy * gdir[1] + dz * gdir[2];
         gm[0] = (gdir[0] - dx * dd) * ivl;
         gm[1] = (gdir[1] - dy * dd) * ivl;
@@ -227,7 +238,10 @@ hipError_t launch_preprocess_backward(const ProjParams& p, const SceneParams& s,
                                       hipStream_t stream) {
     if (p.n == 0) return hipSuccess;
     const int64_t nb = (p.n + 255) / 256;
-    hipLaunchKernelGGL(k_preprocess_bwd, dim3((unsigned)nb), dim3(256), 0, stream, p, s, a);
+    if (a.jac && p.sh_degree > 0)
+        hipLaunchKernelGGL(k_preprocess_bwd<true>, dim3((unsigned)nb), dim3(256), 0, stream, p, s, a);
+    else
+        hipLaunchKernelGGL(k_preprocess_bwd<false>, dim3((unsigned)nb), dim3(256), 0, stream, p, s, a);
     return hipGetLastError();
 }
 

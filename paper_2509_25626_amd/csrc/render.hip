@@ -37,7 +37,7 @@ void for_each_frame_buffer(cds_frame* f, F&& fn) {
                       &f->rp_small, &f->rp_rowent,
                       &f->keys0, &f->keys1, &f->tk0, &f->tk1, &f->vals0, &f->vals1, &f->sort.hist,
                       &f->sort.status, &f->sort.counters, &f->sort.part_hist, &f->sort.bases,
-                      &f->sort.scan_sums, &f->sort.scan_total, &f->ranges, &f->grad2d};
+                      &f->sort.scan_sums, &f->sort.scan_total, &f->ranges, &f->grad2d, &f->jac};
     for (DevBuf* b : bufs) fn(*b);
 }
 
@@ -161,7 +161,15 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
     sb.rect = (uint2*)f->rect.p;
     sb.touched = (uint32_t*)f->touched.p;
     sb.clamp_flags = (uint8_t*)f->clampf.p;
+    // a render kept for the backward pass stores the colour's direction
+    // derivative, which the backward then reads instead of the SH coefficients
+    f->jac_valid = false;
+    if (f->keep_jac && scene->sh_degree > 0) {
+        CDS_TRY(ensure(ctx, f->jac, sizeof(float) * 9 * nn, 1.1));
+        sb.jac = (float*)f->jac.p;
+    }
     CDS_HIP(launch_preprocess(P, make_scene(scene), sb, stream), "preprocess kernel");
+    f->jac_valid = sb.jac != nullptr;
     CDS_TRY(f->record(kEvPreprocess, stream));
 
     uint64_t* d_total = (uint64_t*)f->total.p;  // [0] = n_vis (variant 2), [1] = K
@@ -494,6 +502,7 @@ cds_status render_backward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* sce
     pa.radius = (const int32_t*)f->radius.p;
     pa.clamp_flags = (const uint8_t*)f->clampf.p;
     pa.grad2d = (const float*)f->grad2d.p;
+    pa.jac = f->jac_valid ? (const float*)f->jac.p : nullptr;
     pa.g_means = g->means;
     pa.g_log_scales = g->log_scales;
     pa.g_quats = g->quats;

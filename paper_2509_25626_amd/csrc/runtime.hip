@@ -261,7 +261,8 @@ cds_status cds_render_forward_ex(cds_ctx* ctx, cds_frame* f, const cds_scene* sc
     bool timing = false;
     SortAlgo algo = SortAlgo::kAuto;
     if (opts) {
-        if (opts->flags & ~(CDS_OPT_STAGE_TIMING | CDS_OPT_SORT_ONESWEEP | CDS_OPT_SORT_REDUCE_SCAN))
+        if (opts->flags &
+            ~(CDS_OPT_STAGE_TIMING | CDS_OPT_SORT_ONESWEEP | CDS_OPT_SORT_REDUCE_SCAN | CDS_OPT_KEEP_FOR_BACKWARD))
             return fail(CDS_ERR_INVALID_ARG, "unknown option flags");
         if ((opts->flags & CDS_OPT_SORT_ONESWEEP) && (opts->flags & CDS_OPT_SORT_REDUCE_SCAN))
             return fail(CDS_ERR_INVALID_ARG, "choose one radix-sort pass algorithm");
@@ -279,6 +280,7 @@ cds_status cds_render_forward_ex(cds_ctx* ctx, cds_frame* f, const cds_scene* sc
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     f->valid = false;
     f->timing = timing;
+    f->keep_jac = opts && (opts->flags & CDS_OPT_KEEP_FOR_BACKWARD) != 0;
     return render_forward_impl(ctx, f, scene, cam, variant, sort_variant, algo, out_rgb, out_T, out_ncontrib,
                                out_invdepth, stream);
 }

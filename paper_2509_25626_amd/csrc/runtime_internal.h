@@ -68,6 +68,8 @@ struct cds_frame {
     cds::DevBuf ranges;
     // backward
     cds::DevBuf grad2d;
+    cds::DevBuf jac;  // [9][n] colour direction derivative (renders kept for the backward pass)
+    bool keep_jac = false, jac_valid = false;
     int64_t n = 0, n_vis = 0, K = 0;
     int64_t row_entries = 0;  // variant 4: entries of the per-tile-row lists
     int32_t width = 0, height = 0, tiles_x = 0, tiles_y = 0, passes = 0, sort_variant = 0;

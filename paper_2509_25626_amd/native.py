@@ -74,6 +74,7 @@ class CdsStageTimes(ctypes.Structure):
 CDS_OPT_STAGE_TIMING = 1
 CDS_OPT_SORT_ONESWEEP = 2
 CDS_OPT_SORT_REDUCE_SCAN = 4
+CDS_OPT_KEEP_FOR_BACKWARD = 8
 CDS_NOALLOC_MAX_PAIRS = 1048576
 
 

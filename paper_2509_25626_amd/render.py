@@ -208,10 +208,12 @@ class Renderer:
 
     def forward(self, scene: GaussianScene, cam, frame: Frame | None = None, blend_variant: int = 0,
                 out=None, timing: bool = False, sort_variant: int = 0, sort_algo: str = "auto",
-                invdepth=None):
+                invdepth=None, for_backward: bool = False):
         """Render; returns (rgb [3,H,W], final_T [H,W], n_contrib [H,W] int32 view of uint32, frame).
         With `invdepth` (True, or an [H,W] float32 tensor to fill) the expected
-        inverse depth is rendered too and returned as a fifth element."""
+        inverse depth is rendered too and returned as a fifth element.
+        `for_backward`: the render will be differentiated (CDS_OPT_KEEP_FOR_BACKWARD:
+        the frame keeps the colour's direction derivative for the backward pass)."""
         cs = native.camera_struct(cam)
         H, W = cs.height, cs.width
         if out is None:
@@ -221,7 +223,8 @@ class Renderer:
         else:
             rgb, T, nc = out
         frame = frame or self.acquire_frame()
-        flags = (native.CDS_OPT_STAGE_TIMING if timing else 0) | _sort_flag(sort_algo)
+        flags = ((native.CDS_OPT_STAGE_TIMING if timing else 0) | _sort_flag(sort_algo) |
+                 (native.CDS_OPT_KEEP_FOR_BACKWARD if for_backward else 0))
         opts = native.CdsRenderOpts(flags, int(blend_variant), int(sort_variant), 0)
         sst = scene.struct()
         if invdepth is None:
@@ -293,7 +296,7 @@ class RenderFn(torch.autograd.Function):
     def forward(ctx, renderer, cam, means, log_scales, quats, opacity_logits, sh):
         scene = GaussianScene(means.detach(), log_scales.detach(), quats.detach(),
                               opacity_logits.detach(), sh.detach())
-        rgb, T, nc, frame = renderer.forward(scene, cam)
+        rgb, T, nc, frame = renderer.forward(scene, cam, for_backward=True)
         ctx.renderer, ctx.cam, ctx.scene, ctx.frame = renderer, cam, scene, frame
         ctx.save_for_backward(T, nc)
         return rgb
@@ -315,7 +318,7 @@ class RenderDepthFn(torch.autograd.Function):
     def forward(ctx, renderer, cam, means, log_scales, quats, opacity_logits, sh):
         scene = GaussianScene(means.detach(), log_scales.detach(), quats.detach(),
                               opacity_logits.detach(), sh.detach())
-        rgb, T, nc, frame, invd = renderer.forward(scene, cam, invdepth=True)
+        rgb, T, nc, frame, invd = renderer.forward(scene, cam, invdepth=True, for_backward=True)
         ctx.renderer, ctx.cam, ctx.scene, ctx.frame = renderer, cam, scene, frame
         ctx.save_for_backward(T, nc)
         return rgb, invd

@@ -45,7 +45,8 @@ def test_full_size_forward_parity(R, name):
 
 
 @pytest.mark.timeout(900)
-def test_full_size_backward_parity_c4(R):
+@pytest.mark.parametrize("for_backward", [True, False])
+def test_full_size_backward_parity_c4(R, for_backward):
     """Differentiable render at full size: 1M Gaussians (SH3), 1280x720, L1
     loss against the seeded U(0,1) target (seed 40).  The loss gradient is
     taken once from the GPU image and fed to both sides; flip-eligible pixels
@@ -60,7 +61,7 @@ def test_full_size_backward_parity_c4(R):
     H, W = cam.height, cam.width
     gs = GaussianScene.from_numpy(scene)
     target = torch.from_numpy(S.target_image(40, W, H)).cuda()
-    rgb, T, nc, frame = R.forward(gs, cam)
+    rgb, T, nc, frame = R.forward(gs, cam, for_backward=for_backward)
     dl, loss = R.l1_loss_grad(rgb, target)
     torch.cuda.synchronize()
     o = O.render(scene, cam, round_f32=True)
@@ -86,7 +87,7 @@ def test_full_size_backward_parity_c4(R):
         rel = np.linalg.norm(gg - oo) / max(np.linalg.norm(oo), 1e-30)
         elem_ok = np.abs(gg - oo) <= 1e-3 * np.abs(oo) + 1e-6 * np.abs(oo).max()
         report[k] = (float(rel), float(elem_ok.mean()))
-    print(f"c4 backward: loss={loss.item():.6f} flip-eligible pixels={nflip} replaced={replaced} "
+    print(f"c4 backward (kept colour derivative: {for_backward}): loss={loss.item():.6f} flip-eligible pixels={nflip} replaced={replaced} "
           + " ".join(f"{k}: rel={r:.2e} within={w:.5f}" for k, (r, w) in report.items()), flush=True)
     for k, (rel, within) in report.items():
         assert rel <= 1e-4, (k, rel)

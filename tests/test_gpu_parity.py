@@ -373,12 +373,12 @@ def test_exclusive_scan(R, count):
 
 # ---------------------------------------------------------------- backward
 
-def _grad_check(R, scene, cam, seed):
+def _grad_check(R, scene, cam, seed, for_backward=False):
     from paper_2509_25626_amd.render import GaussianScene
     H, W = cam.height, cam.width
     dl = np.random.default_rng(seed).normal(size=(3, H, W)).astype(np.float32)
     gs = GaussianScene.from_numpy(scene)
-    rgb, T, nc, frame = R.forward(gs, cam)
+    rgb, T, nc, frame = R.forward(gs, cam, for_backward=for_backward)
     grads = R.backward(frame, gs, cam, T, nc, torch.from_numpy(dl).cuda())
     torch.cuda.synchronize()
     R.release_frame(frame)
@@ -396,16 +396,31 @@ def _grad_check(R, scene, cam, seed):
     return report
 
 
-def test_backward_matches_oracle_gradients(R):
+# for_backward: the forward keeps the colour's direction derivative and the
+# backward reads it instead of the SH coefficients (SH degree > 0)
+@pytest.mark.parametrize("for_backward", [False, True])
+def test_backward_matches_oracle_gradients(R, for_backward):
     scene = S.scene_fd_subcase(41, 500)
     cam = S.orbit_camera(64, 64, 4.0, 20.0, 5.0, bg=(0.1, 0.2, 0.3))
-    print(_grad_check(R, scene, cam, 1))
+    print(_grad_check(R, scene, cam, 1, for_backward))
 
 
-def test_backward_outdoor_ragged(R):
+@pytest.mark.parametrize("for_backward", [False, True])
+def test_backward_outdoor_ragged(R, for_backward):
     scene = S.scene_outdoor(14, 4000)
     cam = S.orbit_camera(120, 72, 4.0, 60.0, -8.0, bg=(0.5, 0.5, 0.5))
-    print(_grad_check(R, scene, cam, 2))
+    print(_grad_check(R, scene, cam, 2, for_backward))
+
+
+@pytest.mark.parametrize("deg", [1, 2])
+def test_backward_low_sh_degrees(R, deg):
+    """SH degrees 1 and 2, with and without the kept colour derivative."""
+    scene = S.scene_outdoor(15 + deg, 2000)
+    nb = (deg + 1) ** 2
+    scene = dict(scene, sh=np.ascontiguousarray(scene["sh"][:nb]), sh_degree=deg)
+    cam = S.orbit_camera(96, 80, 4.0, 110.0, 12.0, bg=(0.2, 0.1, 0.0))
+    for fb in (False, True):
+        print(deg, fb, _grad_check(R, scene, cam, 3 + deg, fb))
 
 
 def test_l1_loss_grad_kernel(R):
