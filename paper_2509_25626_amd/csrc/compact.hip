@@ -156,6 +156,8 @@ __global__ __launch_bounds__(kCT) void k_vis_scatter(int64_t n, const uint32_t* 
 }  // namespace
 
 int64_t compact_sums_size(int64_t n) { return (n + kCTile - 1) / kCTile + 1; }
+int64_t compact_tiles(int64_t n) { return (n + kCTile - 1) / kCTile; }
+int compact_tile_groups() { return (int)(kCTile / 256); }
 
 hipError_t launch_compact_visible(int64_t n, const uint32_t* touched, const uint2* rect, const uint32_t* depth_bits,
                                   uint64_t* vis_sums, uint64_t* key_sums, uint64_t* totals, uint32_t* dkey,
@@ -186,6 +188,33 @@ hipError_t launch_compact_visible(int64_t n, const uint32_t* touched, const uint
     if (tiles > 0) {
         hipLaunchKernelGGL(k_vis_scatter, dim3((unsigned)tiles), dim3(kCT), 0, stream, n, touched, rect, depth_bits,
                            vis_sums, dkey, rec, depth_hist, (uint32_t)tiles_x, items, nitems);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+hipError_t launch_compact_counted(int64_t n, const PreCounts& c, const uint32_t* touched, const uint2* rect,
+                                  const uint32_t* depth_bits, uint64_t* vis_sums, uint64_t* key_sums,
+                                  uint64_t* h_sums, uint64_t* totals, uint64_t* sum_h, uint32_t* dkey, uint4* rec,
+                                  uint32_t* depth_hist, hipStream_t stream, int tiles_x, uint64_t* host_totals) {
+    static_assert(kCTile % 256 == 0, "a compaction tile spans whole preprocess workgroups");
+    const int64_t tiles = (n + kCTile - 1) / kCTile;
+    if ((sum_h != nullptr) != (h_sums != nullptr) || (sum_h && !c.h) || !c.vis || !c.keys ||
+        c.group != (int)(kCTile / 256) || c.stride != tiles)
+        return hipErrorInvalidValue;
+    ScanGroups g;
+    g.src_a = c.vis;
+    g.src_b = c.keys;
+    g.src_c = c.h;
+    g.src_count = preprocess_blocks(n);
+    g.group = (int)(kCTile / 256);
+    hipError_t e = launch_scan_u64_pair(vis_sums, key_sums, tiles, totals, totals + 1, stream, h_sums, sum_h,
+                                        host_totals, host_totals ? host_totals + 1 : nullptr,
+                                        host_totals ? host_totals + 3 : nullptr, &g);
+    if (e != hipSuccess) return e;
+    if (tiles > 0) {
+        hipLaunchKernelGGL(k_vis_scatter, dim3((unsigned)tiles), dim3(kCT), 0, stream, n, touched, rect, depth_bits,
+                           vis_sums, dkey, rec, depth_hist, (uint32_t)tiles_x, nullptr, 0);
         e = hipGetLastError();
     }
     return e;

@@ -99,6 +99,13 @@ __device__ __forceinline__ float wave_reduce_scatter8(const float (&v)[8]) {
     return c;
 }
 
+// Sum across the 64 lanes of a wave (every lane gets it).
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
 __device__ __forceinline__ uint32_t wave_max(uint32_t v) {
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) {

@@ -95,10 +95,21 @@ hipError_t launch_preprocess_batch(const BatchItem* items, int nitems, int64_t t
 
 // Two (or, with c, three) exclusive in-place scans of `count` uint64 values
 // each (one workgroup per array, one launch); the totals go to *total_a,
-// *total_b (and *total_c).
+// *total_b (and *total_c).  With `groups` (group <= 16), value i of a (b, c)
+// is instead the sum of src_a (src_b, src_c) items i * group + j below
+// src_count, item i * group + j stored at index j * count + i, and the scans
+// are written to a (b, c).
+struct ScanGroups {
+    const uint64_t* src_a = nullptr;
+    const uint64_t* src_b = nullptr;
+    const uint64_t* src_c = nullptr;
+    int64_t src_count = 0;
+    int group = 1;
+};
 hipError_t launch_scan_u64_pair(uint64_t* a, uint64_t* b, int64_t count, uint64_t* total_a, uint64_t* total_b,
                                 hipStream_t stream, uint64_t* c = nullptr, uint64_t* total_c = nullptr,
-                                uint64_t* host_a = nullptr, uint64_t* host_b = nullptr, uint64_t* host_c = nullptr);
+                                uint64_t* host_a = nullptr, uint64_t* host_b = nullptr, uint64_t* host_c = nullptr,
+                                const ScanGroups* groups = nullptr);
 
 // Tile record of a visible splat (16 B): its rectangle of tiles as runs of
 // tile ids, (width | height << 16, row stride, Gaussian index, id of the first
@@ -127,11 +138,41 @@ struct BatchItem;
 // given, is recorded once they are, before the scatter kernel runs (else the
 // caller records its own event after the compaction).
 int64_t compact_sums_size(int64_t n);
+int64_t compact_tiles(int64_t n);  // compaction tiles over n Gaussians
+int compact_tile_groups();         // preprocess workgroups per compaction tile
 struct ZeroSpan {
     uint32_t* p = nullptr;
     int64_t n = 0;
 };
 constexpr int kZeroSpans = 2;
+
+// Per-workgroup counts of the single-render preprocess (one per 256
+// Gaussians): visible splats, their tiles touched and (h, when not null)
+// their rectangle heights in tiles.  Workgroup b's counts are stored at
+// (b % group) * stride + b / group, with group = the workgroups per
+// compaction tile and stride = the number of compaction tiles (so the scan
+// reads them coalesced).  The kernel also clears the word ranges in `clear`
+// (the visible compaction's depth histograms and whatever the caller adds).
+struct PreCounts {
+    uint64_t* vis = nullptr;
+    uint64_t* keys = nullptr;
+    uint64_t* h = nullptr;
+    int64_t stride = 0;
+    int group = 1;
+    ZeroSpan clear[1 + kZeroSpans];
+};
+inline int64_t preprocess_blocks(int64_t n) { return (n + 255) / 256; }
+hipError_t launch_preprocess_counted(const ProjParams& p, const SceneParams& s, const SplatBuffers& out,
+                                     const PreCounts& c, hipStream_t stream);
+// The visible compaction after launch_preprocess_counted: its per-256 counts
+// (c.vis, c.keys, c.h) are summed per compaction tile and scanned into
+// vis_sums / key_sums (compact_sums_size(n) each), then the splats are
+// compacted as by launch_compact_visible (which this replaces, counting pass
+// included).  depth_hist must have been cleared (c.clear).
+hipError_t launch_compact_counted(int64_t n, const PreCounts& c, const uint32_t* touched, const uint2* rect,
+                                  const uint32_t* depth_bits, uint64_t* vis_sums, uint64_t* key_sums,
+                                  uint64_t* h_sums, uint64_t* totals, uint64_t* sum_h, uint32_t* dkey, uint4* rec,
+                                  uint32_t* depth_hist, hipStream_t stream, int tiles_x, uint64_t* host_totals);
 hipError_t launch_compact_visible(int64_t n, const uint32_t* touched, const uint2* rect, const uint32_t* depth_bits,
                                   uint64_t* vis_sums, uint64_t* key_sums, uint64_t* totals, uint32_t* dkey,
                                   uint4* rec, uint32_t* depth_hist, hipStream_t stream, int tiles_x,

@@ -60,58 +60,68 @@ __device__ __forceinline__ void sh_basis_f32(float x, float y, float z, int degr
 // colour's derivative with respect to the unit view direction (x, y, z):
 // J[3 ch + c] = sum_k sh[k][ch] dY_k/ddir_c, from the derivatives of the
 // basis polynomials above.
-template <int kNB>
+template <int kNB, bool kJac>
 __device__ __forceinline__ void sh_colour(const float* __restrict__ sh, int64_t n, int64_t i, const float* basis,
-                                          float col[3], float x = 0.f, float y = 0.f, float z = 0.f,
-                                          float* J = nullptr) {
+                                          float col[3], float x, float y, float z, float (&J)[9]) {
     float v[kNB][3];
 #pragma unroll
     for (int k = 0; k < kNB; ++k)
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) v[k][ch] = sh[((int64_t)k * 3 + ch) * n + i];
 #pragma unroll
-    for (int k = 0; k < kNB; ++k)
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) col[ch] += basis[k] * v[k][ch];
-    if (!J) return;  // uniform
-#pragma unroll
     for (int e = 0; e < 9; ++e) J[e] = 0.0f;
-    // add coefficient k's term d * dY_k/ddir_c to every channel
+    const float xx = x * x, yy = y * y, zz = z * z;
+    // coefficient k's term d * dY_k/ddir_c, every channel
     const auto add = [&](int k, int c, float d) {
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) J[3 * ch + c] += v[k][ch] * d;
     };
-    if constexpr (kNB > 1) {
-        add(1, 1, -kY1);
-        add(2, 2, kY1);
-        add(3, 0, -kY1);
-    }
-    if constexpr (kNB > 4) {
-        add(4, 0, kY2a * y); add(4, 1, kY2a * x);
-        add(5, 1, -kY2a * z); add(5, 2, -kY2a * y);
-        add(6, 0, -2.0f * kY2b * x); add(6, 1, -2.0f * kY2b * y); add(6, 2, 4.0f * kY2b * z);
-        add(7, 0, -kY2a * z); add(7, 2, -kY2a * x);
-        add(8, 0, 2.0f * kY2c * x); add(8, 1, -2.0f * kY2c * y);
-    }
-    if constexpr (kNB > 9) {
-        const float xx = x * x, yy = y * y, zz = z * z;
-        add(9, 0, -6.0f * kY3a * x * y); add(9, 1, -3.0f * kY3a * (xx - yy));
-        add(10, 0, kY3b * y * z); add(10, 1, kY3b * x * z); add(10, 2, kY3b * x * y);
-        add(11, 0, 2.0f * kY3c * x * y); add(11, 1, -kY3c * (4.0f * zz - xx - 3.0f * yy));
-        add(11, 2, -8.0f * kY3c * y * z);
-        add(12, 0, -6.0f * kY3d * x * z); add(12, 1, -6.0f * kY3d * y * z);
-        add(12, 2, kY3d * (6.0f * zz - 3.0f * xx - 3.0f * yy));
-        add(13, 0, -kY3c * (4.0f * zz - 3.0f * xx - yy)); add(13, 1, 2.0f * kY3c * x * y);
-        add(13, 2, -8.0f * kY3c * x * z);
-        add(14, 0, 2.0f * kY3e * x * z); add(14, 1, -2.0f * kY3e * y * z); add(14, 2, kY3e * (xx - yy));
-        add(15, 0, -3.0f * kY3a * (xx - yy)); add(15, 1, 6.0f * kY3a * x * y);
+    // one pass over the coefficients, each used once for the colour and
+    // once for the derivative, so none has to stay live (or be loaded again)
+#pragma unroll
+    for (int k = 0; k < kNB; ++k) {
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) col[ch] += basis[k] * v[k][ch];
+        if constexpr (!kJac) continue;
+        switch (k) {
+            case 1: add(1, 1, -kY1); break;
+            case 2: add(2, 2, kY1); break;
+            case 3: add(3, 0, -kY1); break;
+            case 4: add(4, 0, kY2a * y); add(4, 1, kY2a * x); break;
+            case 5: add(5, 1, -kY2a * z); add(5, 2, -kY2a * y); break;
+            case 6:
+                add(6, 0, -2.0f * kY2b * x); add(6, 1, -2.0f * kY2b * y); add(6, 2, 4.0f * kY2b * z);
+                break;
+            case 7: add(7, 0, -kY2a * z); add(7, 2, -kY2a * x); break;
+            case 8: add(8, 0, 2.0f * kY2c * x); add(8, 1, -2.0f * kY2c * y); break;
+            case 9: add(9, 0, -6.0f * kY3a * x * y); add(9, 1, -3.0f * kY3a * (xx - yy)); break;
+            case 10: add(10, 0, kY3b * y * z); add(10, 1, kY3b * x * z); add(10, 2, kY3b * x * y); break;
+            case 11:
+                add(11, 0, 2.0f * kY3c * x * y); add(11, 1, -kY3c * (4.0f * zz - xx - 3.0f * yy));
+                add(11, 2, -8.0f * kY3c * y * z);
+                break;
+            case 12:
+                add(12, 0, -6.0f * kY3d * x * z); add(12, 1, -6.0f * kY3d * y * z);
+                add(12, 2, kY3d * (6.0f * zz - 3.0f * xx - 3.0f * yy));
+                break;
+            case 13:
+                add(13, 0, -kY3c * (4.0f * zz - 3.0f * xx - yy)); add(13, 1, 2.0f * kY3c * x * y);
+                add(13, 2, -8.0f * kY3c * x * z);
+                break;
+            case 14:
+                add(14, 0, 2.0f * kY3e * x * z); add(14, 1, -2.0f * kY3e * y * z); add(14, 2, kY3e * (xx - yy));
+                break;
+            case 15: add(15, 0, -3.0f * kY3a * (xx - yy)); add(15, 1, 6.0f * kY3a * x * y); break;
+            default: break;
+        }
     }
 }
 
 // Gaussian i of a scene with P.n Gaussians; outputs go to slot `o` of O
 // (with kJac also the colour's direction derivative, planes O.jac[9][n]).
+// Returns (tiles touched, rectangle height in tiles), both 0 when culled.
 template <bool kJac = false>
-__device__ __forceinline__ void preprocess_one(const ProjParams& P, const SceneParams& S, int64_t i,
+__device__ __forceinline__ uint2 preprocess_one(const ProjParams& P, const SceneParams& S, int64_t i,
                                                const SplatBuffers& O, int64_t o) {
     const int64_t n = P.n;
 
@@ -217,7 +227,7 @@ __device__ __forceinline__ void preprocess_one(const ProjParams& P, const SceneP
         O.rect[o] = make_uint2(0u, 0u);
         O.touched[o] = 0u;
         O.clamp_flags[o] = 0;
-        return;
+        return make_uint2(0u, 0u);
     }
 
     const float opacity = (float)(1.0 / (1.0 + exp(-(double)olog)));
@@ -230,12 +240,11 @@ __device__ __forceinline__ void preprocess_one(const ProjParams& P, const SceneP
     sh_basis_f32(ux, uy, uz, P.sh_degree, basis);
     float col[3] = {0.f, 0.f, 0.f};
     float J[9];
-    float* const jp = kJac ? J : nullptr;
     switch (P.sh_degree) {  // uniform
-        case 0: sh_colour<1>(S.sh, n, i, basis, col); break;
-        case 1: sh_colour<4>(S.sh, n, i, basis, col, ux, uy, uz, jp); break;
-        case 2: sh_colour<9>(S.sh, n, i, basis, col, ux, uy, uz, jp); break;
-        default: sh_colour<16>(S.sh, n, i, basis, col, ux, uy, uz, jp); break;
+        case 0: sh_colour<1, false>(S.sh, n, i, basis, col, ux, uy, uz, J); break;
+        case 1: sh_colour<4, kJac>(S.sh, n, i, basis, col, ux, uy, uz, J); break;
+        case 2: sh_colour<9, kJac>(S.sh, n, i, basis, col, ux, uy, uz, J); break;
+        default: sh_colour<16, kJac>(S.sh, n, i, basis, col, ux, uy, uz, J); break;
     }
     if constexpr (kJac) {
         if (P.sh_degree > 0)  // uniform
@@ -258,8 +267,10 @@ __device__ __forceinline__ void preprocess_one(const ProjParams& P, const SceneP
     O.depth_bits[o] = __float_as_uint(dzf);
     O.radius[o] = radius;
     O.rect[o] = make_uint2(tx0 | (ty0 << 16), tx1 | (ty1 << 16));
-    O.touched[o] = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+    const uint32_t touched = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+    O.touched[o] = touched;
     O.clamp_flags[o] = flags;
+    return make_uint2(touched, ty1 - ty0 + 1);
 }
 
 template <bool kJac>
@@ -267,6 +278,40 @@ __global__ __launch_bounds__(256) void k_preprocess(ProjParams P, SceneParams S,
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= P.n) return;
     preprocess_one<kJac>(P, S, i, O, i);
+}
+
+// The same, and per workgroup of 256 Gaussians the number of visible splats,
+// the sum of their tiles touched and of their rectangle heights (the inputs
+// of the visible compaction's scan), and the clearing of C's word ranges.
+template <bool kJac>
+__global__ __launch_bounds__(256) void k_preprocess_counted(ProjParams P, SceneParams S, SplatBuffers O,
+                                                            PreCounts C) {
+    __shared__ uint32_t s_part[3][256 / kWave];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < 1 + kZeroSpans; ++j)
+        for (int64_t k = i; k < C.clear[j].n; k += (int64_t)gridDim.x * blockDim.x) C.clear[j].p[k] = 0u;
+    uint2 r = make_uint2(0u, 0u);
+    if (i < P.n) r = preprocess_one<kJac>(P, S, i, O, i);
+    // a block's sums fit 32 bits (at most 256 splats of at most 2^24 tiles each)
+    uint32_t v = r.x ? 1u : 0u, k = r.x, h = r.y;
+    v = wave_sum_u32(v);
+    k = wave_sum_u32(k);
+    h = wave_sum_u32(h);
+    const int w = threadIdx.x / kWave;
+    if (lane_id() == 0) {
+        s_part[0][w] = v;
+        s_part[1][w] = k;
+        s_part[2][w] = h;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        uint64_t t = 0;
+#pragma unroll
+        for (int q = 0; q < 256 / kWave; ++q) t += s_part[threadIdx.x][q];
+        uint64_t* dst = threadIdx.x == 0 ? C.vis : threadIdx.x == 1 ? C.keys : C.h;
+        if (dst) dst[(int64_t)(blockIdx.x % C.group) * C.stride + blockIdx.x / C.group] = t;
+    }
 }
 
 // Several scenes at once: global index g over the concatenated scenes of a
@@ -295,6 +340,23 @@ hipError_t launch_preprocess_batch(const BatchItem* items, int nitems, int64_t t
     if (total == 0) return hipSuccess;
     const int64_t nb = (total + 255) / 256;
     hipLaunchKernelGGL(k_preprocess_batch, dim3((unsigned)nb), dim3(256), 0, stream, items, nitems, total, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_preprocess_counted(const ProjParams& p, const SceneParams& s, const SplatBuffers& out,
+                                     const PreCounts& c, hipStream_t stream) {
+    const int64_t nb = preprocess_blocks(p.n);
+    if (nb == 0) {  // nothing to count: only the clearing
+        for (int j = 0; j < 1 + kZeroSpans; ++j) {
+            const hipError_t e = launch_fill_u32(c.clear[j].p, c.clear[j].n, 0u, stream);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    if (out.jac && p.sh_degree > 0)
+        hipLaunchKernelGGL(k_preprocess_counted<true>, dim3((unsigned)nb), dim3(256), 0, stream, p, s, out, c);
+    else
+        hipLaunchKernelGGL(k_preprocess_counted<false>, dim3((unsigned)nb), dim3(256), 0, stream, p, s, out, c);
     return hipGetLastError();
 }
 

@@ -37,7 +37,8 @@ void for_each_frame_buffer(cds_frame* f, F&& fn) {
                       &f->rp_small, &f->rp_rowent,
                       &f->keys0, &f->keys1, &f->tk0, &f->tk1, &f->vals0, &f->vals1, &f->sort.hist,
                       &f->sort.status, &f->sort.counters, &f->sort.part_hist, &f->sort.bases,
-                      &f->sort.scan_sums, &f->sort.scan_total, &f->ranges, &f->grad2d, &f->jac};
+                      &f->sort.scan_sums, &f->sort.scan_total, &f->ranges, &f->grad2d, &f->jac,
+                      &f->pvis, &f->pkeys, &f->ph};
     for (DevBuf* b : bufs) fn(*b);
 }
 
@@ -168,7 +169,28 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
         CDS_TRY(ensure(ctx, f->jac, sizeof(float) * 9 * nn, 1.1));
         sb.jac = (float*)f->jac.p;
     }
-    CDS_HIP(launch_preprocess(P, make_scene(scene), sb, stream), "preprocess kernel");
+    SortWorkspace wd = (compact || binned) ? sort_ws(ctx, f->sort_d) : SortWorkspace{};
+    PreCounts pc;
+    if (compact) {
+        // the preprocess also counts the visible splats per workgroup (the
+        // compaction's scan input) and clears the depth histograms and the
+        // depth sort's look-back status and id counters
+        pc.group = compact_tile_groups();
+        pc.stride = compact_tiles(n);
+        const size_t nblk = (size_t)std::max<int64_t>(pc.stride * pc.group, 1);
+        CDS_TRY(ensure(ctx, f->pvis, sizeof(uint64_t) * nblk, 1.1));
+        CDS_TRY(ensure(ctx, f->pkeys, sizeof(uint64_t) * nblk, 1.1));
+        if (rowplace) CDS_TRY(ensure(ctx, f->ph, sizeof(uint64_t) * nblk, 1.1));
+        pc.vis = (uint64_t*)f->pvis.p;
+        pc.keys = (uint64_t*)f->pkeys.p;
+        pc.h = rowplace ? (uint64_t*)f->ph.p : nullptr;
+        pc.clear[0].p = wd.hist;
+        pc.clear[0].n = 4 * 256;
+        if (n > 0 && sort_uses_onesweep(n, algo)) sort_prepare_spans(wd, n, 4, 4, pc.clear + 1);
+        CDS_HIP(launch_preprocess_counted(P, make_scene(scene), sb, pc, stream), "preprocess kernel");
+    } else {
+        CDS_HIP(launch_preprocess(P, make_scene(scene), sb, stream), "preprocess kernel");
+    }
     f->jac_valid = sb.jac != nullptr;
     CDS_TRY(f->record(kEvPreprocess, stream));
 
@@ -184,21 +206,16 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
             if (armed) (void)hipStreamWaitEvent(stream, join, 0);
         }
     } side_join{stream, nullptr, false};
-    SortWorkspace wd = (compact || binned) ? sort_ws(ctx, f->sort_d) : SortWorkspace{};
     const uint32_t* order = nullptr;
     if (compact) {
         // visible splats compacted in index order, with the depth histograms; n_vis and K
-        // (row-wise placement: also the sum of the rectangle heights, d_total[3]).  The
-        // counting kernel also clears the depth sort's look-back status and counters.
-        CDS_TRY(f->side_stream());  // its events too: f->copied is recorded by the compaction
-        ZeroSpan depth_prep[kZeroSpans];
-        const bool depth_onesweep = n > 0 && sort_uses_onesweep(n, algo);
-        if (depth_onesweep) sort_prepare_spans(wd, n, 4, 4, depth_prep);
-        CDS_HIP(launch_compact_visible(n, sb.touched, sb.rect, sb.depth_bits, (uint64_t*)f->vsums.p,
-                                       (uint64_t*)f->ksums.p, d_total, (uint32_t*)f->dkeyc.p, (uint4*)f->recc.p,
-                                       wd.hist, stream, P.tiles_x, nullptr, 0,
-                                       rowplace ? (uint64_t*)f->hsums.p : nullptr, rowplace ? d_total + 3 : nullptr,
-                                       depth_onesweep ? depth_prep : nullptr, ctx->host_pinned_dev, nullptr),
+        // (row-wise placement: also the sum of the rectangle heights, d_total[3]) from the
+        // preprocess's per-workgroup counts
+        CDS_TRY(f->side_stream());  // its events too: f->copied is recorded after the compaction
+        CDS_HIP(launch_compact_counted(n, pc, sb.touched, sb.rect, sb.depth_bits, (uint64_t*)f->vsums.p,
+                                       (uint64_t*)f->ksums.p, rowplace ? (uint64_t*)f->hsums.p : nullptr, d_total,
+                                       rowplace ? d_total + 3 : nullptr, (uint32_t*)f->dkeyc.p, (uint4*)f->recc.p,
+                                       wd.hist, stream, P.tiles_x, ctx->host_pinned_dev),
                 "visible compaction");
     } else if (binned) {
         // depth order of all N Gaussians: 4 passes, result in (dkey1, order1)

@@ -57,6 +57,7 @@ struct cds_frame {
     cds::DevBuf dkeyc, recc, recv, vsums, ksums;  // compacted visible splats (variant 2)
     cds::DevBuf kowner;                        // record owning every 1024th key (variant 2)
     cds::DevBuf hsums;                         // per-tile rectangle-height sums (variant 4)
+    cds::DevBuf pvis, pkeys, ph;               // per-preprocess-workgroup counts (compacting variants)
     cds::DevBuf rp_ha, rp_hb, rp_small, rp_rowent;  // row-wise tile placement (variant 4)
     cds::SortState sort_d;
     // per key

@@ -47,13 +47,23 @@ __global__ __launch_bounds__(kNT) void k_scan_reduce(ScanSrc src, int64_t n, uin
 // a second and a third block, when launched, do the same for sums2 / total2
 // and sums3 / total3.  A block whose host word (host_totals[block], pinned
 // host memory) is given writes its total there too.
+// With grouped sources (src[block] not null), value idx is instead the sum of
+// src[j * count + idx] over j < group (at most 16), where entry (idx, j) is
+// source item idx * group + j and items at or past src_count read as 0; the
+// scan is written to sums.
 struct HostTotals {
     uint64_t* p[3];
+};
+struct ScanSources {
+    const uint64_t* src[3];
+    int64_t src_count;
+    int group;
 };
 __global__ __launch_bounds__(1024) void k_scan_sums(uint64_t* __restrict__ sums, int64_t count,
                                                     uint64_t* __restrict__ total, uint64_t* __restrict__ sums2,
                                                     uint64_t* __restrict__ total2, uint64_t* __restrict__ sums3,
-                                                    uint64_t* __restrict__ total3, HostTotals host) {
+                                                    uint64_t* __restrict__ total3, HostTotals host,
+                                                    ScanSources srcs) {
     uint64_t* host_total = host.p[0];
     if (blockIdx.x == 1) {  // uniform
         sums = sums2;
@@ -64,13 +74,25 @@ __global__ __launch_bounds__(1024) void k_scan_sums(uint64_t* __restrict__ sums,
         total = total3;
         host_total = host.p[2];
     }
+    const uint64_t* src = srcs.src[blockIdx.x];
     __shared__ uint64_t wsum[1024 / kWave];
     __shared__ uint64_t carry;
     if (threadIdx.x == 0) carry = 0;
     __syncthreads();
     for (int64_t base = 0; base < count; base += 1024) {
         const int64_t idx = base + threadIdx.x;
-        const uint64_t v = idx < count ? sums[idx] : 0;
+        uint64_t v = 0;
+        if (!src) {  // uniform
+            v = idx < count ? sums[idx] : 0;
+        } else if (idx < count) {
+            // entry j of output idx's group is at j * count + idx: every load coalesced
+            uint64_t x[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                x[j] = j < srcs.group && idx * srcs.group + j < srcs.src_count ? src[j * count + idx] : 0;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) v += x[j];
+        }
         // inclusive wave scan in 64 bits
         uint64_t inc = v;
         const uint32_t l = lane_id();
@@ -135,11 +157,18 @@ int64_t scan_block_sums_size(int64_t n) { return (n + kTileItems - 1) / kTileIte
 
 hipError_t launch_scan_u64_pair(uint64_t* a, uint64_t* b, int64_t count, uint64_t* total_a, uint64_t* total_b,
                                 hipStream_t stream, uint64_t* c, uint64_t* total_c, uint64_t* host_a,
-                                uint64_t* host_b, uint64_t* host_c) {
+                                uint64_t* host_b, uint64_t* host_c, const ScanGroups* groups) {
     if ((c != nullptr) != (total_c != nullptr)) return hipErrorInvalidValue;
     const HostTotals host{{host_a, host_b, c ? host_c : nullptr}};
+    ScanSources srcs{{nullptr, nullptr, nullptr}, 0, 1};
+    if (groups) {
+        srcs = ScanSources{{groups->src_a, groups->src_b, c ? groups->src_c : nullptr}, groups->src_count,
+                           groups->group};
+        if (srcs.group < 1 || srcs.group > 16 || !srcs.src[0] || !srcs.src[1] || (c && !srcs.src[2]))
+            return hipErrorInvalidValue;
+    }
     hipLaunchKernelGGL(k_scan_sums, dim3(c ? 3 : 2), dim3(1024), 0, stream, a, count, total_a, b, total_b, c,
-                       total_c, host);
+                       total_c, host, srcs);
     return hipGetLastError();
 }
 
@@ -156,7 +185,8 @@ hipError_t launch_exclusive_scan(const uint32_t* in, const uint32_t* gather, uin
                            count_dev);
     }
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, stream, block_sums, tiles, total, nullptr, nullptr,
-                       nullptr, nullptr, HostTotals{{nullptr, nullptr, nullptr}});
+                       nullptr, nullptr, HostTotals{{nullptr, nullptr, nullptr}},
+                       ScanSources{{nullptr, nullptr, nullptr}, 0, 1});
     if (tiles > 0) {
         hipLaunchKernelGGL(k_scan_down, dim3((unsigned)tiles), dim3(kNT), 0, stream, src, n, block_sums, out, owner,
                            count_dev);
