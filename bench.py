@@ -84,10 +84,13 @@ def roofline(stages, scene, K, passes, info, first_pass_ms, variant, algo):
     word = 4 if packed else 8
     table = {
         # kernel, launches per frame, algorithmic bytes per launch
-        # preprocess: 40 B of geometry + SH in, 61 B of splat state out per Gaussian
-        "preprocess_ms": ("k_preprocess", 1, (40 + sh_bytes + 61) * n),
+        # preprocess: 40 B of geometry + SH in, 61 B of splat state out per Gaussian,
+        # 24 B of visible counts per workgroup of 256, and the depth sort's
+        # look-back words it clears (4 passes x 256 digits per 4096 Gaussians)
+        "preprocess_ms": ("k_preprocess_counted<false>", 1,
+                          (40 + sh_bytes + 61) * n + 24 * (-(-n // 256)) + 4 * 4 * 256 * (-(-n // 4096))),
         # compaction of the visible splats: 16 B read per Gaussian, 20 B written per visible one
-        "scan_ms": ("k_vis_count + k_vis_scatter", 1, 16 * n + 20 * nvis),
+        "scan_ms": ("k_scan_sums + k_vis_scatter", 1, 16 * n + 20 * nvis),
         # depth order: 4 onesweep passes over (u32 depth, u32 position) of the visible splats
         "depth_order_ms": ("k_sort_pass_onesweep<u32,8> (depth digits)", 4, 16 * nvis),
         # duplicate: 8 B per key (tile id, value) + 24 B per Gaussian read
