@@ -93,7 +93,8 @@ __global__ __launch_bounds__(kCT) void k_vis_scatter(int64_t n, const uint32_t* 
                                                      const uint64_t* __restrict__ vis_base,
                                                      uint32_t* __restrict__ dkey, uint4* __restrict__ rec,
                                                      uint32_t* __restrict__ hist, uint32_t tiles_x,
-                                                     const BatchItem* __restrict__ items, int nitems) {
+                                                     const BatchItem* __restrict__ items, int nitems,
+                                                     int hist_reps) {
     __shared__ uint32_t s_hist[4 * 256];
     __shared__ uint32_t s_wtot[kCWaves];
     const int t = threadIdx.x;
@@ -147,9 +148,10 @@ __global__ __launch_bounds__(kCT) void k_vis_scatter(int64_t n, const uint32_t* 
         slot += (uint32_t)__popcll(m);
     }
     __syncthreads();
+    uint32_t* const rep = hist + (size_t)(blockIdx.x % (uint32_t)hist_reps) * (4 * 256);
     for (int k = t; k < 4 * 256; k += kCT) {
         const uint32_t v = s_hist[k];
-        if (v) atomicAdd(&hist[k], v);
+        if (v) atomicAdd(&rep[k], v);
     }
 }
 
@@ -187,7 +189,7 @@ hipError_t launch_compact_visible(int64_t n, const uint32_t* touched, const uint
     if (totals_ready && (e = hipEventRecord(totals_ready, stream)) != hipSuccess) return e;
     if (tiles > 0) {
         hipLaunchKernelGGL(k_vis_scatter, dim3((unsigned)tiles), dim3(kCT), 0, stream, n, touched, rect, depth_bits,
-                           vis_sums, dkey, rec, depth_hist, (uint32_t)tiles_x, items, nitems);
+                           vis_sums, dkey, rec, depth_hist, (uint32_t)tiles_x, items, nitems, 1);
         e = hipGetLastError();
     }
     return e;
@@ -214,7 +216,7 @@ hipError_t launch_compact_counted(int64_t n, const PreCounts& c, const uint32_t*
     if (e != hipSuccess) return e;
     if (tiles > 0) {
         hipLaunchKernelGGL(k_vis_scatter, dim3((unsigned)tiles), dim3(kCT), 0, stream, n, touched, rect, depth_bits,
-                           vis_sums, dkey, rec, depth_hist, (uint32_t)tiles_x, nullptr, 0);
+                           vis_sums, dkey, rec, depth_hist, (uint32_t)tiles_x, nullptr, 0, kDepthHistReps);
         e = hipGetLastError();
     }
     return e;

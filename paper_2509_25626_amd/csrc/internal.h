@@ -168,7 +168,8 @@ hipError_t launch_preprocess_counted(const ProjParams& p, const SceneParams& s, 
 // (c.vis, c.keys, c.h) are summed per compaction tile and scanned into
 // vis_sums / key_sums (compact_sums_size(n) each), then the splats are
 // compacted as by launch_compact_visible (which this replaces, counting pass
-// included).  depth_hist must have been cleared (c.clear).
+// included), with the depth histograms in kDepthHistReps replicas
+// (depth_hist [kDepthHistReps][4][256], cleared by c.clear).
 hipError_t launch_compact_counted(int64_t n, const PreCounts& c, const uint32_t* touched, const uint2* rect,
                                   const uint32_t* depth_bits, uint64_t* vis_sums, uint64_t* key_sums,
                                   uint64_t* h_sums, uint64_t* totals, uint64_t* sum_h, uint32_t* dkey, uint4* rec,
@@ -243,8 +244,14 @@ hipError_t launch_make_keys(const uint32_t* tiles, const uint32_t* values, const
 // between (ka, va) and (kb, vb): the result is in (ka, va) after an odd
 // number of passes, in (kb, vb) after an even number.  kin may alias kb.
 enum class SortAlgo { kAuto, kOnesweep, kReduceScan };
+// Replicas of the depth sort's digit histograms: the compaction adds each
+// workgroup's counts into copy (workgroup % kDepthHistReps), so that fewer
+// workgroups' atomics meet on one counter; the passes sum the copies.
+constexpr int kDepthHistReps = 4;
 struct SortWorkspace {
-    uint32_t* hist;       // onesweep: [passes][256] digit counts of all keys
+    uint32_t* hist;       // onesweep: [passes][256] digit counts of all keys (replica 0)
+    int hist_reps = 1;    // replicas of hist, hist_rep_stride words apart
+    int64_t hist_rep_stride = 0;
     uint32_t* status;     // onesweep: [passes][partitions][256]
     uint32_t* counters;   // onesweep: [passes]
     uint32_t* part_hist;  // reduce-then-scan: [256][partitions]

@@ -185,7 +185,9 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
         pc.keys = (uint64_t*)f->pkeys.p;
         pc.h = rowplace ? (uint64_t*)f->ph.p : nullptr;
         pc.clear[0].p = wd.hist;
-        pc.clear[0].n = 4 * 256;
+        pc.clear[0].n = 4 * 256 * kDepthHistReps;
+        wd.hist_reps = kDepthHistReps;  // as the compaction fills them
+        wd.hist_rep_stride = 4 * 256;
         if (n > 0 && sort_uses_onesweep(n, algo)) sort_prepare_spans(wd, n, 4, 4, pc.clear + 1);
         CDS_HIP(launch_preprocess_counted(P, make_scene(scene), sb, pc, stream), "preprocess kernel");
     } else {

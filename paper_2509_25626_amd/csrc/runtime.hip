@@ -130,7 +130,7 @@ SceneParams make_scene(const cds_scene* s) {
 cds_status ensure_sort_workspace(cds_ctx* ctx, SortState& s, int64_t count, int passes) {
     const int64_t parts = std::max<int64_t>(sort_partitions(count), 1);
     cds_status st;
-    if ((st = ensure(ctx, s.hist, sizeof(uint32_t) * 256 * 8)) != CDS_OK) return st;
+    if ((st = ensure(ctx, s.hist, sizeof(uint32_t) * 256 * 8 * kDepthHistReps)) != CDS_OK) return st;
     if ((st = ensure(ctx, s.counters, sizeof(uint32_t) * 8)) != CDS_OK) return st;
     if ((st = ensure(ctx, s.status, sizeof(uint32_t) * 256 * (size_t)parts * passes, 1.25)) != CDS_OK) return st;
     if ((st = ensure(ctx, s.part_hist, sizeof(uint32_t) * 256 * (size_t)parts, 1.25)) != CDS_OK) return st;

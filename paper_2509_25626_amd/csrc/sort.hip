@@ -137,7 +137,9 @@ struct PassArgs {
     int shift;
     int bits;               // digit bits of this pass (1..8): key bits [shift, shift + bits)
     uint32_t dmask;         // (1 << bits) - 1
-    const uint32_t* hist;   // onesweep: [256] digit counts of all keys
+    const uint32_t* hist;   // onesweep: [256] digit counts of all keys (summed over replicas)
+    int hist_reps;          // replicas of the histogram, hist_rep_stride words apart
+    int64_t hist_rep_stride;
     uint32_t* status;       // onesweep: [partitions][256]
     uint32_t* counter;      // onesweep: partition-id counter
     const uint32_t* bases;  // reduce-then-scan: [256][partitions] exclusive bases
@@ -158,6 +160,19 @@ struct PassArgs {
     // and the workspace) is read here on the device
     const uint64_t* count_dev;
 };
+
+// Digit t's count over all keys: the sum of the histogram's replicas (the
+// counting kernel spreads its atomics over several copies of each counter).
+template <typename Key>
+__device__ __forceinline__ uint32_t hist_total(const PassArgs<Key>& a, int t) {
+    uint32_t x[kDepthHistReps];  // the loads issued together (one latency)
+#pragma unroll
+    for (int r = 0; r < kDepthHistReps; ++r) x[r] = r < a.hist_reps ? a.hist[r * a.hist_rep_stride + t] : 0u;
+    uint32_t v = 0;
+#pragma unroll
+    for (int r = 0; r < kDepthHistReps; ++r) v += x[r];
+    return v;
+}
 
 // Generated keys (duplication fused into the first tile pass).  Key p
 // belongs to the record j with off[j] <= p < off[j + 1]; its key is the
@@ -717,7 +732,7 @@ __device__ __forceinline__ void sort_pass_kernel(const PassArgs<Key>& a_in) {
     // id, so the serialized id atomics are only the needed ones
     if ((int64_t)blockIdx.x * kP >= a.count) return;  // uniform
     if (t == 0) s_pid = kOnesweep ? atomicAdd(a.counter, 1u) : blockIdx.x;
-    const uint32_t hist_t = (kOnesweep && t < 256) ? a.hist[t] : 0u;
+    const uint32_t hist_t = (kOnesweep && t < 256) ? hist_total(a, t) : 0u;
     for (int k = t; k < kWaves * 256; k += kNT) (&s_whist[0][0])[k] = 0;
     __syncthreads();
     const uint32_t pid = s_pid;
@@ -772,7 +787,7 @@ __global__ __launch_bounds__(kNT, kMinBlocks<kNT>) void k_sort_pass_packed(PassA
     const int t = threadIdx.x;
     if ((int64_t)blockIdx.x * kP >= a.count) return;  // uniform: as in sort_pass_kernel
     if (t == 0) s_pid = atomicAdd(a.counter, 1u);
-    const uint32_t hist_t = t < 256 ? a.hist[t] : 0u;
+    const uint32_t hist_t = t < 256 ? hist_total(a, t) : 0u;
     for (int k = t; k < kWaves * 256; k += kNT) (&s_whist[0][0])[k] = 0;
     __syncthreads();
     const uint32_t pid = s_pid;
@@ -895,6 +910,8 @@ hipError_t sort_passes_impl(const Key* kin, const uint32_t* vin, Key* ka, uint32
         a.bits = plan.bits[p];
         a.dmask = (1u << a.bits) - 1u;
         a.hist = ws.hist + (size_t)p * 256;
+        a.hist_reps = ws.hist_reps;
+        a.hist_rep_stride = ws.hist_rep_stride;
         a.status = ws.status + (size_t)p * parts * 256;
         a.counter = ws.counters + p;
         a.bases = ws.bases;
