@@ -67,7 +67,7 @@ __device__ __forceinline__ void sh_colour(const float* __restrict__ sh, int64_t 
 #pragma unroll
     for (int k = 0; k < kNB; ++k)
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) v[k][ch] = sh[((int64_t)k * 3 + ch) * n + i];
+        for (int ch = 0; ch < 3; ++ch) v[k][ch] = __builtin_nontemporal_load(&sh[((int64_t)k * 3 + ch) * n + i]);
 #pragma unroll
     for (int e = 0; e < 9; ++e) J[e] = 0.0f;
     const float xx = x * x, yy = y * y, zz = z * z;
@@ -125,12 +125,18 @@ __device__ __forceinline__ uint2 preprocess_one(const ProjParams& P, const Scene
                                                const SplatBuffers& O, int64_t o) {
     const int64_t n = P.n;
 
-    const double m0 = S.means[i], m1 = S.means[n + i], m2 = S.means[2 * n + i];
+    // The scene's parameters are read once per render: non-temporal loads, so
+    // that they do not displace this render's intermediate arrays from the
+    // last-level cache.
+    const double m0 = __builtin_nontemporal_load(&S.means[i]), m1 = __builtin_nontemporal_load(&S.means[n + i]),
+                 m2 = __builtin_nontemporal_load(&S.means[2 * n + i]);
     // the other per-Gaussian inputs load with the means (one memory latency);
     // a line holds culled and visible Gaussians alike
-    const float ls0 = S.log_scales[i], ls1 = S.log_scales[n + i], ls2 = S.log_scales[2 * n + i];
-    const float q0 = S.quats[i], q1 = S.quats[n + i], q2 = S.quats[2 * n + i], q3 = S.quats[3 * n + i];
-    const float olog = S.opacity_logits[i];
+    const float ls0 = __builtin_nontemporal_load(&S.log_scales[i]), ls1 = __builtin_nontemporal_load(&S.log_scales[n + i]),
+                ls2 = __builtin_nontemporal_load(&S.log_scales[2 * n + i]);
+    const float q0 = __builtin_nontemporal_load(&S.quats[i]), q1 = __builtin_nontemporal_load(&S.quats[n + i]),
+                q2 = __builtin_nontemporal_load(&S.quats[2 * n + i]), q3 = __builtin_nontemporal_load(&S.quats[3 * n + i]);
+    const float olog = __builtin_nontemporal_load(&S.opacity_logits[i]);
     const double tx = P.R[0] * m0 + P.R[1] * m1 + P.R[2] * m2 + P.t[0];
     const double ty = P.R[3] * m0 + P.R[4] * m1 + P.R[5] * m2 + P.t[1];
     const double tz = P.R[6] * m0 + P.R[7] * m1 + P.R[8] * m2 + P.t[2];

@@ -62,15 +62,18 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(ProjParams P, SceneParam
     if (!__any(live)) {  // the whole wave is culled: zeros, still one full-wave store per plane
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            A.g_means[k * n + i] = 0.f;
-            A.g_log_scales[k * n + i] = 0.f;
+            __builtin_nontemporal_store(0.f, &A.g_means[k * n + i]);
+            __builtin_nontemporal_store(0.f, &A.g_log_scales[k * n + i]);
         }
-        for (int k = 0; k < 4; ++k) A.g_quats[k * n + i] = 0.f;
-        A.g_opacity_logits[i] = 0.f;
-        for (int k = 0; k < nb * 3; ++k) A.g_sh[(int64_t)k * n + i] = 0.f;
+        for (int k = 0; k < 4; ++k) __builtin_nontemporal_store(0.f, &A.g_quats[k * n + i]);
+        __builtin_nontemporal_store(0.f, &A.g_opacity_logits[i]);
+        for (int k = 0; k < nb * 3; ++k) __builtin_nontemporal_store(0.f, &A.g_sh[(int64_t)k * n + i]);
         return;
     }
-    auto put = [live](float* dst, double v) { *dst = live ? (float)v : 0.0f; };
+    // The gradients are written once and not read again by this library; they
+    // go out non-temporal so that they do not fill the last-level cache with
+    // dirty lines that the next forward pass would have to write back.
+    auto put = [live](float* dst, double v) { __builtin_nontemporal_store(live ? (float)v : 0.0f, dst); };
     const uint8_t flags = A.clamp_flags[i];
     const float* G2 = A.grad2d + (size_t)i * kGrad2d;
 

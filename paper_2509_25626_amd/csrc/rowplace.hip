@@ -50,6 +50,7 @@ constexpr uint32_t kErrRowPlace = 32u;
 // resource is given (at most 2^31 bytes), and the hardware range check drops
 // its store; a slot past the output is dropped the same way.
 constexpr uint32_t kDropOffset = 0x80000000u;
+constexpr int kCachePolicyNt = 2;  // buffer store cache policy: non-temporal
 constexpr uint32_t kBufferDword3 = 0x00020000u;  // raw 32-bit buffer access (gfx9 family)
 typedef int int32x2_t __attribute__((ext_vector_type(2)));
 
@@ -379,8 +380,13 @@ __device__ __forceinline__ void place_bins(const uint32_t (&cm)[kColBatch], cons
                 const uint32_t off =
                     l < run - (uint32_t)(t * kWave) ? voff + (uint32_t)(t * kWave * 4 * W) : kDropOffset;
                 if constexpr (W == 1) {
+                    // the tile lists: written once and, past each list's first
+                    // few hundred entries, not read again this frame, so they
+                    // go out non-temporal (cache policy bit 1: nt) rather than
+                    // fill the last-level cache with dirty lines that the next
+                    // frame's preprocessing would have to write back
                     const uint32_t v = st[t * kWave + l];
-                    __builtin_amdgcn_raw_buffer_store_b32((int)v, out, (int)off, 0, 0);
+                    __builtin_amdgcn_raw_buffer_store_b32((int)v, out, (int)off, 0, kCachePolicyNt);
                 } else {
                     const u32x2 v = st[t * kWave + l];
                     __builtin_amdgcn_raw_buffer_store_b64(int32x2_t{(int)v.x, (int)v.y}, out, (int)off, 0, 0);
