@@ -66,3 +66,18 @@ def test_create_reports_missing_device_as_status(lib):
     st = lib.cds_create(ctypes.byref(h), 0, None)
     assert st in (native.CDS_ERR_DEVICE, native.CDS_ERR_INVALID_ARG)
     assert not h.value
+
+
+def test_header_constants_match_the_binding():
+    """Every #define CDS_* integer in the header has the same value in the
+    Python binding (option flags, status codes, limits)."""
+    text = open(HEADER).read()
+    defs = dict((k, int(v.rstrip("uU"), 0)) for k, v in
+                re.findall(r"#define\s+(CDS_[A-Z0-9_]+)\s+(0x[0-9a-fA-F]+|\d+)u?\b", text))
+    assert "CDS_OPT_KEEP_FOR_BACKWARD" in defs
+    mismatched = {k: (v, getattr(native, k)) for k, v in defs.items()
+                  if hasattr(native, k) and getattr(native, k) != v}
+    assert not mismatched, mismatched
+    for k in ("CDS_OPT_STAGE_TIMING", "CDS_OPT_SORT_ONESWEEP", "CDS_OPT_SORT_REDUCE_SCAN",
+              "CDS_OPT_KEEP_FOR_BACKWARD"):
+        assert hasattr(native, k), k
