@@ -228,14 +228,18 @@ hipError_t launch_duplicate(int64_t n, const uint32_t* order, const uint32_t* of
                             int nitems = 0, const uint4* rec = nullptr);
 // Per-tile key counts from the rectangles: ranges [ntiles] of the sorted
 // list, the tile-digit histograms hist [plan.passes][256] (written, not
-// accumulated; may be null) and *total = K (may be null).  diff: ntiles + 1
-// ints of workspace.  Batched renders pass their items (global tile ids).
+// accumulated; may be null) and *total = K (may be null).  diff: reps *
+// (ntiles + 1) ints of workspace: with reps > 1 the workgroups of the LDS
+// counting kernel add into copy (workgroup % reps), so that fewer of them
+// meet on one counter, and the ranges kernel sums the copies (reps <=
+// kTileDiffMaxReps).  Batched renders pass their items (global tile ids).
 constexpr int kTileCountBlocks = 512;
 constexpr int64_t kTileDiffLdsMaxTiles = 16383;  // ntiles + 1 ints fit 64 KiB of LDS
+constexpr int kTileDiffMaxReps = 4;
 hipError_t launch_tile_counts(int64_t n, const uint32_t* touched, const uint2* rect, int tiles_x, int64_t ntiles,
                               int* diff, uint2* ranges, uint32_t* hist, const DigitPlan& plan, uint64_t* total,
                               int max_blocks, hipStream_t stream, const BatchItem* items = nullptr, int nitems = 0,
-                              const uint4* rec = nullptr, const uint64_t* count_dev = nullptr);
+                              const uint4* rec = nullptr, const uint64_t* count_dev = nullptr, int reps = 1);
 hipError_t launch_make_keys(const uint32_t* tiles, const uint32_t* values, const uint32_t* depth_bits,
                             int64_t count, uint64_t* keys, hipStream_t stream);
 

@@ -127,7 +127,7 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
         CDS_TRY(ensure(ctx, f->blocksums, sizeof(uint64_t) * scan_block_sums_size(n), 1.1));
     }
     if (compact) {
-        CDS_TRY(ensure(ctx, f->tdiff, sizeof(int) * (size_t)(ntiles + 1), 1.1));
+        CDS_TRY(ensure(ctx, f->tdiff, sizeof(int) * kTileDiffMaxReps * (size_t)(ntiles + 1), 1.1));
         CDS_TRY(ensure(ctx, f->thist, sizeof(uint32_t) * 4 * 256));
         CDS_TRY(ensure(ctx, f->dkeyc, sizeof(uint32_t) * nn, 1.1));
         CDS_TRY(ensure(ctx, f->recc, sizeof(uint4) * nn, 1.1));
@@ -260,7 +260,8 @@ cds_status render_forward_impl(cds_ctx* ctx, cds_frame* f, const cds_scene* scen
         CDS_HIP(hipStreamWaitEvent(f->side, f->copied, 0), "hipStreamWaitEvent(fork)");
         CDS_HIP(launch_tile_counts(n, nullptr, nullptr, P.tiles_x, ntiles, (int*)f->tdiff.p, (uint2*)f->ranges.p,
                                    (uint32_t*)f->thist.p, digit_plan(tile_passes, 0, tile_bits), nullptr,
-                                   kTileCountBlocks, f->side, nullptr, 0, (const uint4*)f->recc.p, d_total),
+                                   kTileCountBlocks, f->side, nullptr, 0, (const uint4*)f->recc.p, d_total,
+                                   kTileDiffMaxReps),
                 "tile counts");
         CDS_HIP(hipEventRecord(f->join, f->side), "hipEventRecord(join)");
         side_join.armed = true;

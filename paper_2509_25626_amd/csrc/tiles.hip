@@ -22,7 +22,8 @@ struct DiffArgs {
     const uint2* rect;
     int tiles_x;
     int64_t ntiles;
-    int* diff;  // [ntiles + 1], zero on entry
+    int* diff;  // [reps][ntiles + 1], zero on entry
+    int reps;   // copies of diff the LDS counting kernel spreads its workgroups over
     const uint4* rec;  // tile records of the visible splats instead of touched/rect, or null
     const BatchItem* items;
     int nitems;
@@ -72,9 +73,10 @@ __global__ __launch_bounds__(kDiffThreads) void k_tile_diff(DiffArgs a) {
     }
     if (kLds) {
         __syncthreads();
+        int* const rep = a.diff + (int64_t)(blockIdx.x % (uint32_t)a.reps) * (a.ntiles + 1);
         for (int64_t k = threadIdx.x; k <= a.ntiles; k += kDiffThreads) {
             const int v = s_d[k];
-            if (v) atomicAdd(&a.diff[k], v);
+            if (v) atomicAdd(&rep[k], v);
         }
     }
 }
@@ -147,7 +149,8 @@ __global__ __launch_bounds__(kDiffThreads) void k_tile_diff_chunk(DiffArgs a, in
 constexpr int kRangeThreads = 1024;
 __global__ __launch_bounds__(kRangeThreads) void k_tile_ranges(int64_t ntiles, const int* __restrict__ diff,
                                                                uint2* __restrict__ ranges, uint32_t* __restrict__ hist,
-                                                               DigitPlan plan, uint64_t* __restrict__ total) {
+                                                               DigitPlan plan, uint64_t* __restrict__ total,
+                                                               int reps) {
     const int tile_passes = plan.passes;
     __shared__ uint32_t s_hist[4 * 256];
     __shared__ unsigned long long s_wave[kRangeThreads / kWave];
@@ -165,8 +168,14 @@ __global__ __launch_bounds__(kRangeThreads) void k_tile_ranges(int64_t ntiles, c
     __syncthreads();
     for (int64_t base = 0; base < ntiles; base += kRangeThreads) {
         const int64_t i = base + t;
-        // count = running sum of the difference array (int: entries may be negative)
-        int v = i < ntiles ? diff[i] : 0;
+        // count = running sum of the difference array (int: entries may be
+        // negative), summed over its copies (loads issued together)
+        int x[kTileDiffMaxReps];
+#pragma unroll
+        for (int r = 0; r < kTileDiffMaxReps; ++r) x[r] = r < reps && i < ntiles ? diff[r * (ntiles + 1) + i] : 0;
+        int v = 0;
+#pragma unroll
+        for (int r = 0; r < kTileDiffMaxReps; ++r) v += x[r];
 #pragma unroll
         for (int o = 1; o < kWave; o <<= 1) {
             const int u = __shfl_up(v, (unsigned)o, kWave);
@@ -220,10 +229,11 @@ __global__ __launch_bounds__(kRangeThreads) void k_tile_ranges(int64_t ntiles, c
 hipError_t launch_tile_counts(int64_t n, const uint32_t* touched, const uint2* rect, int tiles_x, int64_t ntiles,
                               int* diff, uint2* ranges, uint32_t* hist, const DigitPlan& plan, uint64_t* total,
                               int max_blocks, hipStream_t stream, const BatchItem* items, int nitems,
-                              const uint4* rec, const uint64_t* count_dev) {
+                              const uint4* rec, const uint64_t* count_dev, int reps) {
     if (ntiles <= 0) return hipSuccess;
-    if (plan.passes > 4) return hipErrorInvalidValue;
-    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(diff), ntiles + 1, 0u, stream);
+    if (plan.passes > 4 || reps < 1 || reps > kTileDiffMaxReps) return hipErrorInvalidValue;
+    if (ntiles > kTileDiffLdsMaxTiles) reps = 1;  // only the LDS kernel spreads its flushes
+    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(diff), reps * (ntiles + 1), 0u, stream);
     if (e != hipSuccess) return e;
     if (n > 0) {
         DiffArgs a;
@@ -233,6 +243,7 @@ hipError_t launch_tile_counts(int64_t n, const uint32_t* touched, const uint2* r
         a.tiles_x = tiles_x;
         a.ntiles = ntiles;
         a.diff = diff;
+        a.reps = reps;
         a.rec = rec;
         a.items = items;
         a.nitems = nitems;
@@ -253,7 +264,7 @@ hipError_t launch_tile_counts(int64_t n, const uint32_t* touched, const uint2* r
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_tile_ranges, dim3(1), dim3(kRangeThreads), 0, stream, ntiles, diff, ranges, hist, plan,
-                       total);
+                       total, reps);
     return hipGetLastError();
 }
 
