@@ -374,6 +374,14 @@ __device__ __forceinline__ void place_bins(const uint32_t (&cm)[kColBatch], cons
         // slots are below 2^29 (one word) or 2^28 (two), so a kept offset is
         // below 2^31 and the dropped lanes' 2^31 is past the buffer
         const uint32_t voff = (base + l) * (uint32_t)(4 * W);
+        // one-word runs: every round's slots are read before the first store,
+        // so the stores wait for LDS once per bin instead of once per round
+        // (slots past the run hold stale words, whose offsets are dropped)
+        uint32_t early[W == 1 ? R : 1];
+        if constexpr (W == 1) {
+#pragma unroll
+            for (int t = 0; t < R; ++t) early[t] = st[t * kWave + l];
+        }
 #pragma unroll
         for (int t = 0; t < R; ++t) {
             if ((uint32_t)(t * kWave) < run) {  // uniform
@@ -385,8 +393,7 @@ __device__ __forceinline__ void place_bins(const uint32_t (&cm)[kColBatch], cons
                     // go out non-temporal (cache policy bit 1: nt) rather than
                     // fill the last-level cache with dirty lines that the next
                     // frame's preprocessing would have to write back
-                    const uint32_t v = st[t * kWave + l];
-                    __builtin_amdgcn_raw_buffer_store_b32((int)v, out, (int)off, 0, kCachePolicyNt);
+                    __builtin_amdgcn_raw_buffer_store_b32((int)early[t], out, (int)off, 0, kCachePolicyNt);
                 } else {
                     const u32x2 v = st[t * kWave + l];
                     __builtin_amdgcn_raw_buffer_store_b64(int32x2_t{(int)v.x, (int)v.y}, out, (int)off, 0, 0);
@@ -398,7 +405,9 @@ __device__ __forceinline__ void place_bins(const uint32_t (&cm)[kColBatch], cons
     }
 }
 
-__global__ __launch_bounds__(kColMaxWaves * kWave) __attribute__((amdgpu_waves_per_eu(8)))
+// six waves per SIMD: the register budget the early reads need (the
+// kernel's LDS allows about that many anyway)
+__global__ __launch_bounds__(kColMaxWaves * kWave) __attribute__((amdgpu_waves_per_eu(6)))
 void k_rp_place_cols(RpArgs a) {
     extern __shared__ uint32_t s_mem[];
     const int nbins = (int)a.tiles_x;
@@ -440,9 +449,11 @@ void k_rp_place_cols(RpArgs a) {
 #pragma unroll
         for (int r = 0; r < kRoundsB; ++r) {
             const uint32_t x0 = ex[r] & 0xFFFFu, x1 = ex[r] >> 16;
-            const bool meets = x0 <= bh && x1 >= bl;
-            const uint64_t m = ballot(meets);
-            if (meets) {
+            // two ballots of plain compares: the mask comes straight from
+            // them, where a ballot of the combined bool is rebuilt by two
+            // more vector instructions
+            const uint64_t m = ballot(x0 <= bh) & ballot(x1 >= bl);
+            if (x0 <= bh && x1 >= bl) {
                 const uint32_t k = cnt + count_below(m);
                 const uint32_t o0 = (x0 > bl ? x0 : bl) - bl, o1 = (x1 < bh ? x1 : bh) - bl;
                 s_cx[k] = (uint8_t)(o0 | ((o1 - o0) << 4));
@@ -546,9 +557,8 @@ void k_rp_place_rows(RpArgs a) {
 #pragma unroll
         for (int r = 0; r < kRoundsA; ++r) {
             const uint32_t y0 = ey[r] & 0xFFFFu, y1 = ey[r] >> 16;
-            const bool meets = y0 <= bh && y1 >= bl;
-            const uint64_t m = ballot(meets);
-            if (meets) {
+            const uint64_t m = ballot(y0 <= bh) & ballot(y1 >= bl);
+            if (y0 <= bh && y1 >= bl) {
                 const uint32_t k = cnt + count_below(m);
                 const uint32_t o0 = (y0 > bl ? y0 : bl) - bl, o1 = (y1 < bh ? y1 : bh) - bl;
                 s_cx[k] = (uint8_t)(o0 | ((o1 - o0) << 4));
