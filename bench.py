@@ -3,8 +3,9 @@
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2]
 
 A step is one forward render (preprocess, scan, duplicate, sort, ranges,
-blend) of the configuration's synthetic scene, inputs resident in HBM.  The
-same run also times forward+backward steps (forward, L1 loss gradient,
+blend) of the configuration's synthetic scene, inputs resident in HBM, one
+frame at a time (`value`); the same frames are also timed with two in flight
+on two streams (`fwd_fps_2_in_flight`).  The run also times forward+backward steps (forward, L1 loss gradient,
 backward) and reports per-stage times from HIP events recorded on the render
 stream, the roofline position of the dominant kernel, and the CPU oracle timed
 on the host cores.  Prints one JSON line.
@@ -351,6 +352,32 @@ class Bench:
         stages = {k: v for k, v in st.items() if not k.endswith("backward_ms") and k != "sort_first_pass_ms"}
         return dt, stages, st.get("sort_first_pass_ms", 0.0)
 
+    def forward_in_flight(self, steps, warmup):
+        """Seconds per forward frame with two frames in flight: frames go in
+        turn to two streams, each with its own frame object and output
+        buffers, so one frame's preprocess runs beside the other's depth sort
+        and tile lists.  Every frame is rendered in full."""
+        import torch
+        H, W = self.cam.height, self.cam.width
+        outs = [self.out] + [(torch.empty((3, H, W), device=self.dev), torch.empty((H, W), device=self.dev),
+                              torch.empty((H, W), dtype=torch.int32, device=self.dev))]
+        streams = [torch.cuda.current_stream(self.dev), torch.cuda.Stream(self.dev)]
+        a = self.args
+
+        def render(i):
+            with torch.cuda.stream(streams[i % 2]):
+                self.R.forward(self.scene, self.cam, frame=self.frames[i % 2], blend_variant=a.blend_variant,
+                               out=outs[i % 2], sort_variant=a.sort_variant, sort_algo=a.sort_algo)
+
+        for i in range(max(2, warmup)):
+            render(i)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            render(i)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
     def forward_backward(self, steps, warmup):
         import torch
         from paper_2509_25626_amd import scenes as S
@@ -420,10 +447,13 @@ def main():
     H, W = cam.height, cam.width
     t_fwd, stages, first_pass_ms = b.forward(args.steps, args.warmup)
     info = b.frames[0].info()
+    t_fly = b.forward_in_flight(args.steps, args.warmup)
     K, passes = int(info.num_keys), int(info.sort_passes)
     roof = roofline(stages, b.scene, K, passes, info, first_pass_ms, args.sort_variant, args.sort_algo)
 
-    result_extra = {}
+    # forward frames/s with two frames in flight on two streams (a sequence of
+    # frames rendered back to back); `value` is one frame at a time
+    result_extra = {"fwd_fps_2_in_flight": round(1.0 / t_fly, 3), "fwd_ms_2_in_flight": round(t_fly * 1e3, 4)}
     bwd_stages = {}
     if not args.no_backward:
         t_fb, bwd_stages = b.forward_backward(args.steps, max(2, args.warmup // 2))

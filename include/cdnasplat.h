@@ -29,6 +29,11 @@
  *    argument returns CDS_ERR_INVALID_ARG and changes nothing.
  *  - A context (and every frame or server made from it) may be used by one
  *    host thread at a time.
+ *  - A frame owns all of a render's device state, so renders into different
+ *    frames (and different outputs) may be in flight on different streams at
+ *    once: the next frame's projection then runs beside the previous one's
+ *    sort and blend.  Successive calls on one frame must be stream-ordered
+ *    (the same stream, or ordered by the caller).
  */
 #ifndef CDNASPLAT_H
 #define CDNASPLAT_H

@@ -166,7 +166,13 @@ class Frame:
 
 
 class Renderer:
-    """A library context on one device, with a pool of frames."""
+    """A library context on one device, with a pool of frames.
+
+    Renders run on the current torch stream.  Renders into different frames
+    may be in flight on different streams at once; keep each frame on one
+    stream (or synchronise before moving it): its buffers come from torch's
+    allocator on the stream that was current when they were allocated, and
+    one that grows is handed back to that stream's pool."""
 
     def __init__(self, device: int = 0, torch_allocator: bool = True):
         self.L = native.load()

@@ -289,6 +289,42 @@ def test_forward_deterministic(R):
         assert np.array_equal(a[k], b[k]), k
 
 
+def test_frames_in_flight_on_two_streams(R):
+    """Renders into two frames on two streams, each enqueued while the other
+    is still running, give the same bits as the same renders one at a time."""
+    from paper_2509_25626_amd.render import GaussianScene
+    scene = GaussianScene.from_numpy(S.scene_outdoor(91, 150_000))
+    cams = [S.orbit_camera(640, 360, azimuth_deg=37.0 * k, elevation_deg=4.0 * k - 6.0) for k in range(4)]
+    ref = []
+    frame = R.acquire_frame()
+    for cam in cams:
+        rgb, T, nc, _ = R.forward(scene, cam, frame=frame)
+        ref.append((rgb.clone(), T.clone(), nc.clone()))
+    R.release_frame(frame)
+    torch.cuda.synchronize()
+    frames = [R.acquire_frame(), R.acquire_frame()]
+    streams = [torch.cuda.current_stream(), torch.cuda.Stream()]
+    # each frame first renders every camera on its own stream, so its buffers
+    # reach their size there (a buffer grown on a stream other than the one it
+    # was allocated on would go back to the other stream's pool)
+    for f, st in zip(frames, streams):
+        with torch.cuda.stream(st):
+            for cam in cams:
+                R.forward(scene, cam, frame=f)
+    torch.cuda.synchronize()
+    got = []
+    for i in range(12):
+        with torch.cuda.stream(streams[i % 2]):
+            rgb, T, nc, _ = R.forward(scene, cams[i % 4], frame=frames[i % 2])
+            got.append((i % 4, rgb, T, nc))
+    torch.cuda.synchronize()
+    for f in frames:
+        R.release_frame(f)
+    R.check_device()
+    for k, rgb, T, nc in got:
+        assert torch.equal(rgb, ref[k][0]) and torch.equal(T, ref[k][1]) and torch.equal(nc, ref[k][2]), k
+
+
 def test_outdoor_sh3_ragged_image(R):
     # the outdoor distribution (ball + far shell, SH degree 3) shrunk to 20k Gaussians,
     # a 203 x 117 image (ragged 16x16 tiles) seen from an orbit pose with a coloured background
