@@ -186,11 +186,13 @@ class Renderer:
         self._frames = weakref.WeakSet()
 
     def close(self):
+        if self.handle:
+            torch.cuda.synchronize(self.device)  # no render still uses a frame's buffers
         for f in list(self._frames):
             f.release()
         self._pool = []
+        self._seq = None
         if self.handle:
-            torch.cuda.synchronize(self.device)
             self.L.cds_destroy(self.handle)
             self.handle = None
 
@@ -211,6 +213,42 @@ class Renderer:
 
     def release_frame(self, frame: Frame):
         self._pool.append(frame)
+
+    def forward_sequence(self, scene: GaussianScene, cams, in_flight: int = 2, **kw):
+        """Render `cams` in order with `in_flight` renders overlapping, each on
+        a stream and frame of its own (kept by the renderer for later calls);
+        returns [(rgb, final_T, n_contrib)] in camera order, ready for work on
+        the caller's current stream.  `kw` as for forward (no frame or out)."""
+        if in_flight < 1:
+            raise ValueError("in_flight must be at least 1")
+        seq = getattr(self, "_seq", None)
+        if seq is None or len(seq) != in_flight:
+            if seq is not None:
+                torch.cuda.synchronize(self.device)  # the old streams' renders are done
+                for f, _ in seq:
+                    f.release()
+            seq = []
+            for _ in range(in_flight):
+                h = P()
+                check(self.L.cds_frame_create(self.handle, ctypes.byref(h)))
+                f = Frame(self, h)
+                self._frames.add(f)
+                seq.append((f, torch.cuda.Stream(self.device)))
+            self._seq = seq
+        cur = torch.cuda.current_stream(self.device)
+        for _, st in seq:
+            st.wait_stream(cur)  # the scene and earlier work on the caller's stream
+        outs = []
+        for i, cam in enumerate(cams):
+            f, st = seq[i % in_flight]
+            with torch.cuda.stream(st):
+                rgb, T, nc, _ = self.forward(scene, cam, frame=f, **kw)
+            for t in (rgb, T, nc):
+                t.record_stream(cur)
+            outs.append((rgb, T, nc))
+        for _, st in seq:
+            cur.wait_stream(st)
+        return outs
 
     def forward(self, scene: GaussianScene, cam, frame: Frame | None = None, blend_variant: int = 0,
                 out=None, timing: bool = False, sort_variant: int = 0, sort_algo: str = "auto",

@@ -323,6 +323,14 @@ def test_frames_in_flight_on_two_streams(R):
     R.check_device()
     for k, rgb, T, nc in got:
         assert torch.equal(rgb, ref[k][0]) and torch.equal(T, ref[k][1]) and torch.equal(nc, ref[k][2]), k
+    # the renderer's own sequence helper, three renders in flight
+    outs = R.forward_sequence(scene, cams * 2, in_flight=3)
+    torch.cuda.synchronize()
+    R.check_device()
+    assert len(outs) == 2 * len(cams)
+    for i, (rgb, T, nc) in enumerate(outs):
+        k = i % len(cams)
+        assert torch.equal(rgb, ref[k][0]) and torch.equal(T, ref[k][1]) and torch.equal(nc, ref[k][2]), i
 
 
 def test_outdoor_sh3_ragged_image(R):
