@@ -48,8 +48,10 @@ constexpr float kTMin = 0.0001f;
 
 // Staged splat, one LDS slot per splat:
 //   s_q  double4 (mean x, mean y, A', B')   s_c double C'   s_f float4 (opacity, r, g, b)
-//   s_b  the tile pixels its alpha can reach: bytes (x min, x max, y min, y max)
-//        + 1, relative to the tile origin and clamped to [-1, 16]
+//   s_b  the tile pixels its alpha can reach: 5-bit fields (x min, x max,
+//        y min, y max) + 1, relative to the tile origin and clamped to
+//        [-1, 16], and from bit 20 a mask of the tile's 4-row groups the
+//        alpha >= 1/255 ellipse itself can meet
 // with A' = -log2(e)/2 A, B' = -log2(e) B, C' = -log2(e)/2 C, so that
 // A' dx^2 + B' dx dy + C' dy^2 = log2(e) * power.
 //
@@ -60,6 +62,14 @@ constexpr float kTMin = 0.0001f;
 // product and of the log2 that gives t move the test by far less.  Splats with o < 1/255 reach no pixel
 // (alpha <= o); when M is not positive definite or anything is not finite,
 // the box is unbounded.
+//
+// Row groups: for each group of four tile rows (all 16 columns), the least
+// value of d^T M d over that rectangle of pixel centres, against 2t.  The
+// form is convex with its minimum at d = 0, so when d = 0 lies outside the
+// rectangle the least value is on an edge, at the edge's stationary point
+// clamped to the edge; a group is dropped only when that value exceeds 2t.
+// For a thin splat at an angle this drops about half of the (splat, wave)
+// pairs its box admits.
 __device__ __forceinline__ void stage_splat(const float2* __restrict__ mean2d,
                                             const float4* __restrict__ conic_opacity,
                                             const float4* __restrict__ rgb, uint32_t id, double4* s_q,
@@ -73,6 +83,7 @@ __device__ __forceinline__ void stage_splat(const float2* __restrict__ mean2d,
     s_f[k] = make_float4(co.w, c.x, c.y, c.z);
     // box relative to the tile origin, in whole pixels, clamped to [-1, 16]
     int x0 = -1, x1 = kTile, y0 = -1, y1 = kTile;  // unbounded
+    uint32_t rows = 0xFu;                          // every row group
     if (co.w < kAlphaMin) {
         x0 = kTile;  // empty
         x1 = -1;
@@ -90,17 +101,36 @@ __device__ __forceinline__ void stage_splat(const float2* __restrict__ mean2d,
             if (mx + ex < (double)kTile) x1 = mx + ex > -1.0 ? (int)ceil(mx + ex) : -1;
             if (my - ey > -1.0) y0 = my - ey < (double)kTile ? (int)floor(my - ey) : kTile;
             if (my + ey < (double)kTile) y1 = my + ey > -1.0 ? (int)ceil(my + ey) : -1;
+            if (fabs(mx) < 1e30 && fabs(my) < 1e30) {  // finite: the edge minima below
+                const double ua = mx - (kTile - 1), ub = mx;  // u = mean x - pixel x over the columns
+                const double sv = -b / cc, su = -b / a;       // stationary v for a u, u for a v
+                const auto form = [&](double u, double v) { return (a * u + 2.0 * b * v) * u + cc * v * v; };
+                const bool in_u = ua <= 0.0 && ub >= 0.0;
+#pragma unroll 1
+                for (int g = 0; g < 4; ++g) {
+                    const double va = my - (4 * g + 3), vb = my - 4 * g;
+                    const double v0 = fmin(fmax(sv * ua, va), vb), v1 = fmin(fmax(sv * ub, va), vb);
+                    const double u0 = fmin(fmax(su * va, ua), ub), u1 = fmin(fmax(su * vb, ua), ub);
+                    const double q = (in_u && va <= 0.0 && vb >= 0.0)
+                                         ? 0.0
+                                         : fmin(fmin(form(ua, v0), form(ub, v1)), fmin(form(u0, va), form(u1, vb)));
+                    if (q > 2.0 * t) rows &= ~(1u << g);
+                }
+            }
         }
     }
-    s_b[k] = (uint32_t)(x0 + 1) | ((uint32_t)(x1 + 1) << 8) | ((uint32_t)(y0 + 1) << 16) | ((uint32_t)(y1 + 1) << 24);
+    s_b[k] = (uint32_t)(x0 + 1) | ((uint32_t)(x1 + 1) << 5) | ((uint32_t)(y0 + 1) << 10) |
+             ((uint32_t)(y1 + 1) << 15) | (rows << 20);
 }
 
-// Whether a staged box (see stage_splat) meets the tile pixel rows
-// [r0, r1] (all 16 columns).
+// Whether a staged splat (see stage_splat) can reach the tile pixel rows
+// [r0, r1] (all 16 columns; r0 a multiple of 4): its box meets them and so
+// does its ellipse in one of their row groups.
 __device__ __forceinline__ bool box_meets_rows(uint32_t box, int r0, int r1) {
-    const int x0 = (int)(box & 0xFFu) - 1, x1 = (int)((box >> 8) & 0xFFu) - 1;
-    const int y0 = (int)((box >> 16) & 0xFFu) - 1, y1 = (int)(box >> 24) - 1;
-    return x1 >= 0 && x0 <= kTile - 1 && y1 >= r0 && y0 <= r1;
+    const int x0 = (int)(box & 31u) - 1, x1 = (int)((box >> 5) & 31u) - 1;
+    const int y0 = (int)((box >> 10) & 31u) - 1, y1 = (int)((box >> 15) & 31u) - 1;
+    const uint32_t groups = (box >> (20 + (r0 >> 2))) & ((2u << ((r1 >> 2) - (r0 >> 2))) - 1u);
+    return x1 >= 0 && x0 <= kTile - 1 && y1 >= r0 && y0 <= r1 && groups != 0u;
 }
 
 // The blending decision of one (pixel, splat) pair, shared by the forward
