@@ -67,7 +67,8 @@ constexpr float kTMin = 0.0001f;
 // value of d^T M d over that rectangle of pixel centres, against 2t.  The
 // form is convex with its minimum at d = 0, so when d = 0 lies outside the
 // rectangle the least value is on an edge, at the edge's stationary point
-// clamped to the edge; a group is dropped only when that value exceeds 2t.
+// clamped to the edge; a group is dropped only when that value exceeds 2t
+// by more than the float32 rounding of the form can account for.
 // For a thin splat at an angle this drops about half of the (splat, wave)
 // pairs its box admits.
 __device__ __forceinline__ void stage_splat(const float2* __restrict__ mean2d,
@@ -102,19 +103,27 @@ __device__ __forceinline__ void stage_splat(const float2* __restrict__ mean2d,
             if (my - ey > -1.0) y0 = my - ey < (double)kTile ? (int)floor(my - ey) : kTile;
             if (my + ey < (double)kTile) y1 = my + ey > -1.0 ? (int)ceil(my + ey) : -1;
             if (fabs(mx) < 1e30 && fabs(my) < 1e30) {  // finite: the edge minima below
-                const double ua = mx - (kTile - 1), ub = mx;  // u = mean x - pixel x over the columns
-                const double sv = -b / cc, su = -b / a;       // stationary v for a u, u for a v
-                const auto form = [&](double u, double v) { return (a * u + 2.0 * b * v) * u + cc * v * v; };
-                const bool in_u = ua <= 0.0 && ub >= 0.0;
+                // float32: a group is dropped only when the least value exceeds
+                // 2t by more than 1e-6 of the terms' magnitude (the float32
+                // rounding of the form is below 3e-7 of it)
+                const float af = co.x, bf = co.y, cf = co.z, t2 = (float)(2.0 * t);
+                const float mxf = (float)mx, myf = (float)my;
+                const float ua = mxf - (float)(kTile - 1), ub = mxf;
+                const float sv = -bf / cf, su = -bf / af;
+                const auto form = [&](float u, float v, float& mag) {
+                    mag = fmaxf(mag, fabsf(af) * u * u + 2.0f * fabsf(bf * u * v) + fabsf(cf) * v * v);
+                    return (af * u + 2.0f * bf * v) * u + cf * v * v;
+                };
+                const bool in_u = ua <= 0.0f && ub >= 0.0f;
 #pragma unroll 1
                 for (int g = 0; g < 4; ++g) {
-                    const double va = my - (4 * g + 3), vb = my - 4 * g;
-                    const double v0 = fmin(fmax(sv * ua, va), vb), v1 = fmin(fmax(sv * ub, va), vb);
-                    const double u0 = fmin(fmax(su * va, ua), ub), u1 = fmin(fmax(su * vb, ua), ub);
-                    const double q = (in_u && va <= 0.0 && vb >= 0.0)
-                                         ? 0.0
-                                         : fmin(fmin(form(ua, v0), form(ub, v1)), fmin(form(u0, va), form(u1, vb)));
-                    if (q > 2.0 * t) rows &= ~(1u << g);
+                    const float va = myf - (float)(4 * g + 3), vb = myf - (float)(4 * g);
+                    const float v0 = fminf(fmaxf(sv * ua, va), vb), v1 = fminf(fmaxf(sv * ub, va), vb);
+                    const float u0 = fminf(fmaxf(su * va, ua), ub), u1 = fminf(fmaxf(su * vb, ua), ub);
+                    float mag = 0.0f;
+                    const float q = fminf(fminf(form(ua, v0, mag), form(ub, v1, mag)),
+                                          fminf(form(u0, va, mag), form(u1, vb, mag)));
+                    if (!(in_u && va <= 0.0f && vb >= 0.0f) && q > t2 + 1e-6f * mag) rows &= ~(1u << g);
                 }
             }
         }
