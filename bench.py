@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-other-configs", action="store_true")
+    ap.add_argument("--no-in-flight", action="store_true",
+                    help="skip the two-frames-in-flight timing (kernel traces of one frame at a time)")
     ap.add_argument("--quick-serving", action="store_true",
                     help="300 requests per load instead of 2000")
     ap.add_argument("--cpu-budget-s", type=float, default=40.0)
@@ -447,13 +449,14 @@ def main():
     H, W = cam.height, cam.width
     t_fwd, stages, first_pass_ms = b.forward(args.steps, args.warmup)
     info = b.frames[0].info()
-    t_fly = b.forward_in_flight(args.steps, args.warmup)
+    t_fly = None if args.no_in_flight else b.forward_in_flight(args.steps, args.warmup)
     K, passes = int(info.num_keys), int(info.sort_passes)
     roof = roofline(stages, b.scene, K, passes, info, first_pass_ms, args.sort_variant, args.sort_algo)
 
     # forward frames/s with two frames in flight on two streams (a sequence of
     # frames rendered back to back); `value` is one frame at a time
-    result_extra = {"fwd_fps_2_in_flight": round(1.0 / t_fly, 3), "fwd_ms_2_in_flight": round(t_fly * 1e3, 4)}
+    result_extra = ({"fwd_fps_2_in_flight": round(1.0 / t_fly, 3), "fwd_ms_2_in_flight": round(t_fly * 1e3, 4)}
+                    if t_fly else {})
     bwd_stages = {}
     if not args.no_backward:
         t_fb, bwd_stages = b.forward_backward(args.steps, max(2, args.warmup // 2))
