@@ -105,10 +105,14 @@ __device__ __forceinline__ void stage_splat(const float2* __restrict__ mean2d,
             if (fabs(mx) < 1e30 && fabs(my) < 1e30) {  // finite: the edge minima below
                 // float32: a group is dropped only when the least value exceeds
                 // 2t by more than 1e-6 of the terms' magnitude (the float32
-                // rounding of the form is below 3e-7 of it)
+                // rounding of the form is below 3e-7 of it) plus what the
+                // rounding of the offsets to float32 (at most e per axis) can
+                // move it: |2 e^T M d| <= 2 e (|a u| + |b| (|u| + |v|) + |c v|)
                 const float af = co.x, bf = co.y, cf = co.z, t2 = (float)(2.0 * t);
                 const float mxf = (float)mx, myf = (float)my;
                 const float ua = mxf - (float)(kTile - 1), ub = mxf;
+                const float e2 = 2.4e-7f * (fabsf(mxf) + fabsf(myf) + (float)(2 * kTile));
+                const float ue = fmaxf(fabsf(ua), fabsf(ub));
                 const float sv = -bf / cf, su = -bf / af;
                 const auto form = [&](float u, float v, float& mag) {
                     mag = fmaxf(mag, fabsf(af) * u * u + 2.0f * fabsf(bf * u * v) + fabsf(cf) * v * v);
@@ -123,7 +127,9 @@ __device__ __forceinline__ void stage_splat(const float2* __restrict__ mean2d,
                     float mag = 0.0f;
                     const float q = fminf(fminf(form(ua, v0, mag), form(ub, v1, mag)),
                                           fminf(form(u0, va, mag), form(u1, vb, mag)));
-                    if (!(in_u && va <= 0.0f && vb >= 0.0f) && q > t2 + 1e-6f * mag) rows &= ~(1u << g);
+                    const float ve = fmaxf(fabsf(va), fabsf(vb));
+                    const float shift = e2 * (fabsf(af) * ue + fabsf(bf) * (ue + ve) + fabsf(cf) * ve);
+                    if (!(in_u && va <= 0.0f && vb >= 0.0f) && q > t2 + 1e-6f * mag + shift) rows &= ~(1u << g);
                 }
             }
         }
