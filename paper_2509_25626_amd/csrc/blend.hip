@@ -594,7 +594,9 @@ __global__ __launch_bounds__(256 / PPT) void k_blend_bwd(BlendBwdArgs a, uint32_
 #pragma unroll
         for (int qd = 0; qd < kBwdBatch / kWave; ++qd) {
             const int k = qd * kWave + (int)lane_id();
-            cand[qd] = ballot(k < cnt && box_meets_rows(s_b[k], wr0, wr0 + kRowsPerWave - 1));
+            // past this wave's last contributor no pixel of the wave can hit
+            cand[qd] = ballot(k < cnt && (uint32_t)(begin + k) < mylast &&
+                              box_meets_rows(s_b[k], wr0, wr0 + kRowsPerWave - 1));
         }
         for (int qd = kBwdBatch / kWave - 1; qd >= 0; --qd) {
             uint64_t m = cand[qd];
