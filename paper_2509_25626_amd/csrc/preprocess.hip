@@ -255,7 +255,10 @@ __device__ __forceinline__ uint2 preprocess_one(const ProjParams& P, const Scene
     if constexpr (kJac) {
         if (P.sh_degree > 0)  // uniform
 #pragma unroll
-            for (int e = 0; e < 9; ++e) O.jac[(int64_t)e * n + o] = J[e];
+            // read once, by the backward pass: non-temporal, like the other
+            // write-once streams, so it leaves no dirty lines in the
+            // last-level cache for the rest of the frame to write back
+            for (int e = 0; e < 9; ++e) __builtin_nontemporal_store(J[e], &O.jac[(int64_t)e * n + o]);
     }
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
